@@ -1,0 +1,177 @@
+/*
+ * wmg.h -- C ABI of the MI355X (gfx950) adaptive-multigrid solver for the
+ * Wilson-Dirac operator, after Babich, Brannick, Brower, Clark, Cohen,
+ * Osborn, Rebbi, "The role of multigrid algorithms for LQCD"
+ * (arXiv:0912.2186).
+ *
+ * Problem (Sec. 2, Eq. 2.1):  D(U) psi = b  on an L0 x L1 x L2 x L3 lattice,
+ * D the Wilson operator of Eq. 2.2 (read in its gauge-covariant form):
+ *   (D psi)(x) = (4+m) psi(x) - 1/2 sum_mu [ (1-gamma_mu) U_mu(x) psi(x+mu)
+ *                                         + (1+gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ * with periodic boundaries and the chiral gamma basis
+ *   gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] (k = 1,2,3),
+ *   gamma_4 = [[0, 1], [1, 0]],  gamma_5 = diag(1, 1, -1, -1).
+ *
+ * Canonical layouts (all fields complex128, interleaved re/im):
+ *   site      s = x + L0*(y + L1*(z + L2*t))
+ *   U         [V][4][3][3]   U[s][mu][a][b]: link s -> s+mu, row a, column b
+ *   spinor    [nrhs][V][12]  component spin*3 + colour
+ *   coarse    [nrhs][Vc][n]  n = 2*Nv, dof ordered (chirality, vector)
+ *   links     [Vc][9][n][n]  block d = 0 local, 1+mu forward, 5+mu backward
+ *   vectors   [Nv][V][dof]   null vectors / prolongator columns (dof = 12 on
+ *                            the fine lattice, n of the finer level otherwise)
+ *
+ * Every field pointer is a DEVICE pointer (hipMalloc'd memory, e.g. a torch
+ * CUDA tensor's data_ptr()).  The caller owns U, b, x and every array it
+ * passes; the library copies what it keeps, so U may be freed after
+ * mg_setup returns.  A context owns all its internal buffers until
+ * mg_destroy.  A context is not thread safe; its work runs on its own HIP
+ * stream and every call returns only after that work has finished.
+ *
+ * Return codes: 0 success, WMG_ENOTCONV (1) = not converged (x holds the
+ * last iterate, stats filled), negative = error, message via wmg_strerror().
+ */
+#ifndef WMG_H
+#define WMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WMG_OK 0
+#define WMG_ENOTCONV 1
+#define WMG_EINVAL (-1)      /* bad argument: null pointer, size, divisibility */
+#define WMG_ENOMEM (-2)      /* device allocation failed */
+#define WMG_EHIP (-3)        /* HIP runtime error */
+#define WMG_ERANK (-4)       /* block Gram-Schmidt breakdown (dependent null vectors) */
+#define WMG_EBREAKDOWN (-5)  /* NaN/Inf or Krylov breakdown */
+
+#define WMG_FP64 0   /* every step in double precision */
+#define WMG_MIXED 1  /* FP64 outer GCR + reliable updates, FP32 cycle on FP16-stored links/null vectors */
+
+#define WMG_VCYCLE 0
+#define WMG_WCYCLE 1
+
+#define WMG_X0_GIVEN 1 /* flags: x holds the initial guess on entry to mg_solve */
+
+typedef struct wmg_ctx wmg_ctx;
+
+typedef struct {
+  int L[4]; /* lattice extents, x fastest */
+} wmg_geom;
+
+/* Solver parameters.  Defaults (wmg_default_params) follow Sec. 3 of the
+ * paper: 4^4 aggregates, chirality split, 4 post-smoothing steps, GCR(8)
+ * outer solver, CG on the normal equations at the coarsest level, W-cycle
+ * when three levels are used. */
+typedef struct {
+  int levels;             /* 2 or 3 */
+  int block[2][4];        /* aggregate of level l -> l+1 (block[0] is overridden by mg_setup's block) */
+  int nvec[2];            /* null vectors of level l (nvec[0] is overridden by mg_setup's Nv) */
+  int setup_iters;        /* GCR iterations per null vector in the adaptive setup */
+  int post_smooth;        /* MR post-smoothing steps per level */
+  int gcr_restart;        /* outer GCR restart length (<= 16) */
+  int cycle;              /* WMG_VCYCLE or WMG_WCYCLE */
+  int precision;          /* WMG_FP64 or WMG_MIXED */
+  int nrhs_max;           /* largest nrhs accepted by mg_solve */
+  double coarse_tol;      /* coarsest CGNR: relative residual */
+  int coarse_maxiter;     /* coarsest CGNR: iteration cap */
+  double reliable_delta;  /* mixed: restart in FP64 when |r_inner| < delta * |r_last_update| */
+  int maxiter;            /* outer GCR iteration cap */
+  unsigned long long seed;/* Philox key of the setup's random start vectors */
+  int flags;              /* WMG_X0_GIVEN */
+} wmg_params;
+
+typedef struct {
+  int outer_iters;        /* outer GCR iterations (max over right-hand sides) */
+  int fine_matvecs;       /* fine-operator applications (any precision, per rhs block) */
+  int fine_matvecs_fp64;  /* of which FP64 (true residuals / reliable updates) */
+  int coarse_iters;       /* CGNR iterations summed over all coarse solves */
+  int reliable_updates;   /* FP64 residual recomputations */
+  int converged;          /* 1 if every rhs reached tol */
+  double true_relres;     /* max over rhs of |b - D x| / |b| in FP64 */
+  double setup_s;         /* wall time of mg_setup */
+  double solve_s;         /* wall time of this solve */
+} wmg_stats;
+
+/* Fill p with the defaults above.  Returns 0. */
+int wmg_default_params(wmg_params *p);
+
+/* Eq. 2.2: out = D(U) in, FP64, canonical layouts, one right-hand side.
+ * U: [V][4][3][3], in/out: [V][12] device pointers; in and out must not
+ * alias.  Runs on hip_stream (NULL = default stream) and returns without
+ * synchronising.  EINVAL on a null pointer or a non-positive extent. */
+int wilson_apply(const wmg_geom *g, const double *U, double m, const double *in, double *out, void *hip_stream);
+
+/* Adaptive setup (Sec. 2, Eqs. 2.6-2.7; Sec. 3): builds Nv near-null
+ * vectors by the sequential adaptive procedure, the chirality-split block
+ * orthonormal prolongator P (sigma_3 P = P gamma_5) and the Galerkin coarse
+ * operator P^dag D P, recursively for `levels` levels, at mass m.
+ * block[4] must divide the lattice; 1 <= Nv <= 6*|block|.  p may be NULL
+ * (defaults).  On success *out receives a new context. */
+int mg_setup(const wmg_geom *g, const double *U, double m, int Nv, const int block[4], const wmg_params *p,
+             wmg_ctx **out);
+
+/* MG-preconditioned flexible GCR solve of D x = b (Sec. 3) for nrhs
+ * right-hand sides b[nrhs][V][12] -> x[nrhs][V][12], each to
+ * |b - D x| / |b| <= tol in FP64.  x is output only unless
+ * params.flags & WMG_X0_GIVEN.  st may be NULL. */
+int mg_solve(wmg_ctx *ctx, const double *b, double *x, double tol, int nrhs, wmg_stats *st);
+
+/* Change the quark mass without a new setup: D_hat(m) = D_hat(m0) + (m-m0) 1
+ * exactly, since P^dag P = 1 and D(m) = D(0) + m. */
+int mg_set_mass(wmg_ctx *ctx, double m);
+
+/* Release the context and all its device memory. */
+int mg_destroy(wmg_ctx *ctx);
+
+/* Message of the last error (thread-local), or a description of `code`. */
+const char *wmg_strerror(int code);
+
+/* Unpreconditioned BiCGStab on D x = b from x = 0 (the unigrid baseline),
+ * FP64, one rhs, canonical layouts; st->outer_iters = iterations (two
+ * operator applications each). */
+int bicgstab_solve(const wmg_geom *g, const double *U, double m, const double *b, double *x, double tol, int maxiter,
+                   wmg_stats *st);
+
+/* ---- uneven batch (Sec. 4: one API over several lattices) ------------ */
+/* n independent instances with their own lattice, links and mass, the same
+ * Nv/block/params; solved back to back on the context's stream. */
+int mg_setup_batch(int n, const wmg_geom *g, const double *const *U, const double *m, int Nv, const int block[4],
+                   const wmg_params *p, wmg_ctx **out);
+int mg_solve_batch(wmg_ctx *ctx, const double *const *b, double *const *x, double tol, wmg_stats *st);
+
+/* ---- test hooks (exported for parity tests; not needed by solvers) ---- */
+/* level info: lattice extents, per-site dof, null vectors to the next level */
+int mg_level_info(wmg_ctx *ctx, int level, int L[4], int *dof, int *nv);
+/* Replace level `level`'s null vectors (canonical [Nv][V][dof]) and rebuild
+ * P and every coarser operator from them (no adaptive iteration). */
+int mg_set_null_vectors(wmg_ctx *ctx, int level, const double *vecs);
+/* Copy out the null vectors (before orthonormalisation) / the block
+ * orthonormal prolongator, canonical [Nv][V][dof]. */
+int mg_get_null_vectors(wmg_ctx *ctx, int level, double *vecs);
+int mg_get_prolongator(wmg_ctx *ctx, int level, double *P);
+/* Coarse links of level `level` (>= 1), canonical [Vc][9][n][n]. */
+int mg_get_coarse_links(wmg_ctx *ctx, int level, double *links);
+/* FP64 restriction / prolongation between level and level+1. */
+int mg_restrict(wmg_ctx *ctx, int level, const double *fine, double *coarse, int nrhs);
+int mg_prolong(wmg_ctx *ctx, int level, const double *coarse, double *fine, int nrhs);
+/* FP64 coarse operator (or its adjoint) at level >= 1. */
+int mg_coarse_apply(wmg_ctx *ctx, int level, const double *in, double *out, int dagger, int nrhs);
+/* Fine operator through the internal kernels: prec 0 FP64, 1 FP32 links and
+ * spinors, 2 FP16 links with FP32 spinors; canonical FP64 in/out. */
+int mg_apply_fine(wmg_ctx *ctx, int prec, const double *in, double *out, int nrhs);
+/* One application of the FP64 preconditioner z = M r (one MG cycle). */
+int mg_cycle(wmg_ctx *ctx, const double *r, double *z);
+/* Per-rhs outer iteration counts of the last solve (array of nrhs ints,
+ * host memory). */
+int mg_last_iters(wmg_ctx *ctx, int *iters, int nrhs);
+/* Time (ms) of `reps` back-to-back fine-operator applications on internal
+ * layouts, measured with HIP events on the context stream (Dslash
+ * bandwidth measurement).  prec as in mg_apply_fine. */
+int mg_time_dslash(wmg_ctx *ctx, int prec, int nrhs, int reps, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WMG_H */

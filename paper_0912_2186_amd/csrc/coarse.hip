@@ -1,0 +1,421 @@
+// Coarse operator of the adaptive multigrid (arXiv:0912.2186, Sec. 2-3 and
+// Sec. 4's dense N_nu x N_nu coarse-link algebra).
+//
+// Build: D_hat = P^dag D P (Galerkin, R = P^dag) stored as a 9-point stencil
+// with dense n x n complex blocks, n = 2 N_nu:
+//   out(xh) = X(xh) in(xh) + sum_mu [ Y_{+mu}(xh) in(xh+mu) + Y_{-mu}(xh) in(xh-mu) ].
+// For coarse column (chi_c, alpha) the fine vector v = Pi_chi_c P[alpha]
+// (all aggregates at once) is hit by the fine operator split by hop class
+// (0: diagonal + hops inside the target's aggregate; 1+mu / 5+mu: hops
+// across the +mu / -mu face) and each class is restricted on the target
+// aggregate.  Classes are kept by hop direction, so forward and backward
+// links stay apart even where a coarse extent is 1 or 2.
+//
+// Internal link layout (for coalesced apply): [Vc][9][col][row], i.e. the
+// element (row, col) of block d of site xh sits at ((xh*9+d)*n + col)*n + row.
+#include "wmg_internal.h"
+
+namespace wmg {
+
+static constexpr int TB = 256;
+
+struct CGeom {
+  int L[4], b[4], Lc[4];
+  long V, Vc;
+  int bs, dof, nv;
+};
+
+__device__ __forceinline__ long cg_block_site(const CGeom &g, long xh, int k, int x[4]) {
+  int xc[4];
+  site_coords(g.Lc, xh, xc);
+  int w0 = k % g.b[0], r = k / g.b[0];
+  int w1 = r % g.b[1]; r /= g.b[1];
+  int w2 = r % g.b[2]; int w3 = r / g.b[2];
+  x[0] = xc[0] * g.b[0] + w0;
+  x[1] = xc[1] * g.b[1] + w1;
+  x[2] = xc[2] * g.b[2] + w2;
+  x[3] = xc[3] * g.b[3] + w3;
+  return site_index(g.L, x);
+}
+
+// (coarse site, element-in-block k) of a fine site given its coordinates
+__device__ __forceinline__ void cg_locate(const CGeom &g, const int x[4], long &xh, int &k) {
+  int xc[4], w[4];
+  for (int i = 0; i < 4; i++) {
+    xc[i] = x[i] / g.b[i];
+    w[i] = x[i] % g.b[i];
+  }
+  xh = site_index(g.Lc, xc);
+  k = w[0] + g.b[0] * (w[1] + g.b[1] * (w[2] + g.b[2] * w[3]));
+}
+
+template <int NV>
+__device__ __forceinline__ void cg_wsum(cx<double> v[NV], double *sh, double *out) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; j++) {
+    double a = v[j].re, b = v[j].im;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_down(a, o, 64);
+      b += __shfl_down(b, o, 64);
+    }
+    if (lane == 0) {
+      sh[w * 2 * NV + 2 * j] = a;
+      sh[w * 2 * NV + 2 * j + 1] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * NV) {
+    double x = 0;
+    for (int q = 0; q < TB / 64; q++) x += sh[q * 2 * NV + threadIdx.x];
+    out[threadIdx.x] = x;
+  }
+  __syncthreads();
+}
+
+// Wilson hop (Eq. 2.2, gauge-covariant placement) written out with the full
+// gamma matrices: forward -1/2 (1-gamma_mu) U_mu(x) v(x+mu), backward
+// -1/2 (1+gamma_mu) U_mu(x-mu)^dag v(x-mu).
+__constant__ double2 c_gamma[4][4][4];
+
+__device__ __forceinline__ void wilson_hop(const double2 *U, long V, long s, long t, int mu, int sg,
+                                           const cx<double> in[12], cx<double> out[12]) {
+  cx<double> uv[4][3];
+  long ls = sg > 0 ? s : t;
+  for (int sp = 0; sp < 4; sp++)
+    for (int a = 0; a < 3; a++) {
+      cx<double> acc = czero<double>();
+      for (int b = 0; b < 3; b++) {
+        if (sg > 0) acc = cfma(ldc(U + (size_t)(mu * 9 + 3 * a + b) * V + ls), in[3 * sp + b], acc);
+        else acc = cfmac(ldc(U + (size_t)(mu * 9 + 3 * b + a) * V + ls), in[3 * sp + b], acc);
+      }
+      uv[sp][a] = acc;
+    }
+  for (int i = 0; i < 4; i++)
+    for (int a = 0; a < 3; a++) {
+      cx<double> acc = czero<double>();
+      for (int j = 0; j < 4; j++) {
+        double2 gg = c_gamma[mu][i][j];
+        cx<double> g = {(sg > 0 ? -gg.x : gg.x) + (i == j ? 1.0 : 0.0), sg > 0 ? -gg.y : gg.y};  // 1 -+ gamma
+        acc = cfma(g, uv[j][a], acc);
+      }
+      out[3 * i + a] = out[3 * i + a] + cx<double>{-0.5 * acc.re, -0.5 * acc.im};
+    }
+}
+
+// One workgroup per (coarse site xh, column); fine Wilson level, one thread
+// per fine site of the aggregate (bs <= 256).
+__global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__restrict__ U, double m,
+                                                    const double2 *__restrict__ P, double2 *__restrict__ Yc) {
+  long xh = blockIdx.x;
+  int col = blockIdx.y;
+  int nv = g.nv, n = 2 * nv;
+  int chic = col / nv, al = col % nv;
+  __shared__ double sh[4 * 2 * 16];
+  __shared__ double red[2 * 16];
+  int k = threadIdx.x;
+  bool act = k < g.bs;
+  int x[4] = {0, 0, 0, 0};
+  long s = 0;
+  if (act) s = cg_block_site(g, xh, k, x);
+  const long E = (long)g.bs * 12;
+  // v(site) = chirality chic part of P[al] at that site
+  auto loadv = [&](const int y[4], cx<double> v[12]) {
+    long yh;
+    int ky;
+    cg_locate(g, y, yh, ky);
+    for (int c = 0; c < 12; c++) {
+      v[c] = (c / 6 == chic) ? ldc(P + ((size_t)al * g.Vc + yh) * E + (size_t)c * g.bs + ky) : czero<double>();
+    }
+  };
+  for (int d = 0; d < 9; d++) {
+    cx<double> w[12];
+    for (int c = 0; c < 12; c++) w[c] = czero<double>();
+    if (act) {
+      if (d == 0) {
+        cx<double> v[12];
+        loadv(x, v);
+        for (int c = 0; c < 12; c++) w[c] = (4.0 + m) * v[c];
+      }
+      for (int mu = 0; mu < 4; mu++)
+        for (int sg = -1; sg <= 1; sg += 2) {
+          bool cross = sg > 0 ? (x[mu] % g.b[mu] == g.b[mu] - 1) : (x[mu] % g.b[mu] == 0);
+          int cls = cross ? (sg > 0 ? 1 + mu : 5 + mu) : 0;
+          if (cls != d) continue;
+          int y[4] = {x[0], x[1], x[2], x[3]};
+          y[mu] = (y[mu] + sg + g.L[mu]) % g.L[mu];
+          cx<double> v[12];
+          loadv(y, v);
+          long t = site_index(g.L, y);
+          wilson_hop(U, g.V, s, t, mu, sg, v, w);
+        }
+    }
+    // restrict w onto rows (chi_r, beta), 16 rows at a time
+    for (int r0 = 0; r0 < n; r0 += 16) {
+      cx<double> acc[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) {
+        acc[j] = czero<double>();
+        int row = r0 + j;
+        if (act && row < n) {
+          int chir = row / nv, be = row % nv;
+          for (int c = chir * 6; c < chir * 6 + 6; c++)
+            acc[j] = cfmac(ldc(P + ((size_t)be * g.Vc + xh) * E + (size_t)c * g.bs + k), w[c], acc[j]);
+        }
+      }
+      cg_wsum<16>(acc, sh, red);
+      if (threadIdx.x < 16 && r0 + (int)threadIdx.x < n) {
+        int row = r0 + threadIdx.x;
+        Yc[(((size_t)xh * 9 + d) * n + col) * n + row] = make_double2(red[2 * threadIdx.x], red[2 * threadIdx.x + 1]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Coarse level: the operator being coarsened is itself a 9-point stencil
+// with dof f (internal layout).  One thread per aggregate element (k, c).
+template <int EPT>
+__global__ void __launch_bounds__(TB) k_build_coarse(CGeom g, const double2 *__restrict__ Yf,
+                                                    const double2 *__restrict__ P, double2 *__restrict__ Yc) {
+  long xh = blockIdx.x;
+  int col = blockIdx.y;
+  int nv = g.nv, n = 2 * nv, f = g.dof, h = f / 2;
+  int chic = col / nv, al = col % nv;
+  const long E = (long)g.bs * f;
+  __shared__ double sh[4 * 2 * 16];
+  __shared__ double red[2 * 16];
+  for (int d = 0; d < 9; d++) {
+    cx<double> w[EPT];
+    int kk[EPT], cc[EPT];
+    for (int q = 0; q < EPT; q++) {
+      w[q] = czero<double>();
+      kk[q] = -1;
+      int e = threadIdx.x + q * TB;
+      if (e >= E) continue;
+      int k = e / f, c = e % f;
+      kk[q] = k;
+      cc[q] = c;
+      int x[4];
+      long s = cg_block_site(g, xh, k, x);
+      // hops of the fine stencil at x: d' = 0 local, 1+mu, 5+mu
+      for (int dd = 0; dd < 9; dd++) {
+        int cls;
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        if (dd == 0) cls = 0;
+        else {
+          int mu = (dd - 1) % 4, sg = dd <= 4 ? 1 : -1;
+          bool cross = sg > 0 ? (x[mu] % g.b[mu] == g.b[mu] - 1) : (x[mu] % g.b[mu] == 0);
+          cls = cross ? dd : 0;
+          y[mu] = (y[mu] + sg + g.L[mu]) % g.L[mu];
+        }
+        if (cls != d) continue;
+        long yh;
+        int ky;
+        cg_locate(g, y, yh, ky);
+        // sum_c' Yf[s][dd][c][c'] v(y)[c'], v = chirality chic part of P[al]
+        for (int c2 = chic * h; c2 < chic * h + h; c2++) {
+          cx<double> yv = ldc(Yf + (((size_t)s * 9 + dd) * f + c2) * f + c);
+          cx<double> pv = ldc(P + ((size_t)al * g.Vc + yh) * E + (size_t)ky * f + c2);
+          w[q] = cfma(yv, pv, w[q]);
+        }
+      }
+    }
+    for (int r0 = 0; r0 < n; r0 += 16) {
+      cx<double> acc[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) {
+        acc[j] = czero<double>();
+        int row = r0 + j;
+        if (row < n) {
+          int chir = row / nv, be = row % nv;
+          for (int q = 0; q < EPT; q++) {
+            if (kk[q] < 0 || cc[q] / h != chir) continue;
+            int e = threadIdx.x + q * TB;
+            acc[j] = cfmac(ldc(P + ((size_t)be * g.Vc + xh) * E + e), w[q], acc[j]);
+          }
+        }
+      }
+      cg_wsum<16>(acc, sh, red);
+      if (threadIdx.x < 16 && r0 + (int)threadIdx.x < n) {
+        int row = r0 + threadIdx.x;
+        Yc[(((size_t)xh * 9 + d) * n + col) * n + row] = make_double2(red[2 * threadIdx.x], red[2 * threadIdx.x + 1]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+static bool gamma_uploaded = false;
+static int upload_gamma() {
+  if (gamma_uploaded) return 0;
+  // chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = [[0,1],[1,0]]
+  double2 G[4][4][4];
+  for (int mu = 0; mu < 4; mu++)
+    for (int i = 0; i < 4; i++)
+      for (int j = 0; j < 4; j++) G[mu][i][j] = make_double2(0, 0);
+  // sigma matrices
+  const double s_re[3][2][2] = {{{0, 1}, {1, 0}}, {{0, 0}, {0, 0}}, {{1, 0}, {0, -1}}};
+  const double s_im[3][2][2] = {{{0, 0}, {0, 0}}, {{0, -1}, {1, 0}}, {{0, 0}, {0, 0}}};
+  for (int k = 0; k < 3; k++)
+    for (int i = 0; i < 2; i++)
+      for (int j = 0; j < 2; j++) {
+        // upper-right: -i sigma ; lower-left: +i sigma ;  i*(a+ib) = -b + ia
+        G[k][i][2 + j] = make_double2(s_im[k][i][j], -s_re[k][i][j]);
+        G[k][2 + i][j] = make_double2(-s_im[k][i][j], s_re[k][i][j]);
+      }
+  for (int i = 0; i < 2; i++) {
+    G[3][i][2 + i] = make_double2(1, 0);
+    G[3][2 + i][i] = make_double2(1, 0);
+  }
+  WMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gamma), G, sizeof(G)));
+  gamma_uploaded = true;
+  return 0;
+}
+
+int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf, const int b[4],
+                 int nv, const double2 *P, double2 *Yc, double2 * /*work*/, hipStream_t st) {
+  CGeom g;
+  for (int i = 0; i < 4; i++) {
+    g.L[i] = gf.L[i];
+    g.b[i] = b[i];
+    g.Lc[i] = gf.L[i] / b[i];
+  }
+  g.V = gf.V;
+  g.Vc = (long)g.Lc[0] * g.Lc[1] * g.Lc[2] * g.Lc[3];
+  g.bs = b[0] * b[1] * b[2] * b[3];
+  g.dof = fine_kind == 0 ? 12 : dof;
+  g.nv = nv;
+  dim3 grid((unsigned)g.Vc, 2 * nv);
+  if (fine_kind == 0) {
+    if (g.bs > TB) return set_error(-1, "coarse_build: aggregate of %d sites > %d", g.bs, TB);
+    int rc = upload_gamma();
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_build_wilson, grid, dim3(TB), 0, st, g, (const double2 *)U64soa, m, P, Yc);
+  } else {
+    long E = (long)g.bs * g.dof;
+    int ept = (int)((E + TB - 1) / TB);
+    if (ept <= 4) hipLaunchKernelGGL((k_build_coarse<4>), grid, dim3(TB), 0, st, g, Yf, P, Yc);
+    else if (ept <= 8) hipLaunchKernelGGL((k_build_coarse<8>), grid, dim3(TB), 0, st, g, Yf, P, Yc);
+    else if (ept <= 16) hipLaunchKernelGGL((k_build_coarse<16>), grid, dim3(TB), 0, st, g, Yf, P, Yc);
+    else return set_error(-1, "coarse_build: aggregate too large (%ld elements)", E);
+  }
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+// ------------------------------------------------------------ apply
+// One wavefront per (coarse site, rhs): lane = output row.  The nine input
+// vectors are staged in LDS (sigma_3 applied for the adjoint, which for a
+// gamma_5-hermitian coarse operator is D_hat^dag = sigma_3 D_hat sigma_3).
+template <class TY, class TV, int NMAX>
+__global__ void __launch_bounds__(TB) k_coarse_apply(const TY *__restrict__ Y, const TV *__restrict__ in,
+                                                    TV *__restrict__ out, int L0, int L1, int L2, int L3, long Vc, int n,
+                                                    int dagger, int nrhs) {
+  using R = typename store_traits<TV>::real;
+  __shared__ cx<R> vin[TB / 64][9][NMAX];
+  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  long item = (long)blockIdx.x * (TB / 64) + wv;
+  long xh = item % Vc;
+  int r = (int)(item / Vc);
+  bool act = r < nrhs;
+  const int L[4] = {L0, L1, L2, L3};
+  int x[4];
+  site_coords(L, act ? xh : 0, x);
+  long nb[9];
+  nb[0] = xh;
+  for (int mu = 0; mu < 4; mu++) {
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    y[mu] = (x[mu] + 1) % L[mu];
+    nb[1 + mu] = site_index(L, y);
+    y[mu] = (x[mu] - 1 + L[mu]) % L[mu];
+    nb[5 + mu] = site_index(L, y);
+  }
+  int h = n / 2;
+  if (act)
+    for (int d = 0; d < 9; d++)
+      for (int c = lane; c < n; c += 64) {
+        auto v = ldc(in + ((size_t)r * Vc + nb[d]) * n + c);
+        cx<R> t = {(R)v.re, (R)v.im};
+        vin[wv][d][c] = (dagger && c >= h) ? neg(t) : t;
+      }
+  __syncthreads();
+  if (!act) return;
+  for (int row = lane; row < n; row += 64) {
+    cx<R> acc = czero<R>();
+    for (int d = 0; d < 9; d++) {
+      const TY *yb = Y + ((size_t)xh * 9 + d) * n * n + row;
+      for (int c = 0; c < n; c++) {
+        auto yv = ldc(yb + (size_t)c * n);
+        acc = cfma(cx<R>{(R)yv.re, (R)yv.im}, vin[wv][d][c], acc);
+      }
+    }
+    if (dagger && row >= h) acc = neg(acc);
+    stc(out + ((size_t)r * Vc + xh) * n + row, acc);
+  }
+}
+
+int coarse_apply(const Geom &gc, int n, int yprec, const void *Y, int vprec, const void *in, void *out, int dagger,
+                 int nrhs, hipStream_t st) {
+  long items = gc.V * nrhs;
+  dim3 grid((unsigned)((items + TB / 64 - 1) / (TB / 64)));
+  if (n > 128) return set_error(-1, "coarse_apply: n=%d > 128", n);
+  if (yprec == P64 && vprec == P64)
+    hipLaunchKernelGGL((k_coarse_apply<double2, double2, 128>), grid, dim3(TB), 0, st, (const double2 *)Y,
+                       (const double2 *)in, (double2 *)out, gc.L[0], gc.L[1], gc.L[2], gc.L[3], gc.V, n, dagger, nrhs);
+  else if (yprec == P32 && vprec == P32)
+    hipLaunchKernelGGL((k_coarse_apply<float2, float2, 128>), grid, dim3(TB), 0, st, (const float2 *)Y,
+                       (const float2 *)in, (float2 *)out, gc.L[0], gc.L[1], gc.L[2], gc.L[3], gc.V, n, dagger, nrhs);
+  else
+    return set_error(-1, "coarse_apply: unsupported precision pair %d %d", yprec, vprec);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+__global__ void k_shift_diag(long Vc, int n, double2 *Y, double dm) {
+  long i = blockIdx.x * (long)TB + threadIdx.x;
+  if (i >= Vc * n) return;
+  long xh = i / n;
+  int r = (int)(i % n);
+  double2 *p = Y + (((size_t)xh * 9 + 0) * n + r) * n + r;
+  p->x += dm;
+}
+
+int coarse_shift_diag(long Vc, int n, double2 *Y, double dm, hipStream_t st) {
+  hipLaunchKernelGGL(k_shift_diag, dim3((unsigned)((Vc * n + TB - 1) / TB)), dim3(TB), 0, st, Vc, n, Y, dm);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+__global__ void k_Y_to_float(size_t cnt, const double2 *Y, float2 *Yf) {
+  size_t i = blockIdx.x * (size_t)TB + threadIdx.x;
+  if (i < cnt) Yf[i] = make_float2((float)Y[i].x, (float)Y[i].y);
+}
+
+int coarse_convert(long count, const double2 *Y64, int yprec, void *Yout, hipStream_t st) {
+  if (yprec != P32) return set_error(-1, "coarse_convert: precision %d", yprec);
+  hipLaunchKernelGGL(k_Y_to_float, dim3((unsigned)((count + TB - 1) / TB)), dim3(TB), 0, st, (size_t)count, Y64,
+                     (float2 *)Yout);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+// internal [xh][d][col][row] <-> canonical [xh][d][row][col]
+__global__ void k_Y_transpose(long nblk, int n, const double2 *a, double2 *b) {
+  size_t i = blockIdx.x * (size_t)TB + threadIdx.x;
+  size_t tot = (size_t)nblk * n * n;
+  if (i >= tot) return;
+  size_t blk = i / ((size_t)n * n);
+  int rr = (int)((i / n) % n), cc = (int)(i % n);
+  b[blk * n * n + (size_t)cc * n + rr] = a[i];
+}
+
+int coarse_transpose(long nblk, int n, const double2 *a, double2 *b, hipStream_t st) {
+  size_t tot = (size_t)nblk * n * n;
+  hipLaunchKernelGGL(k_Y_transpose, dim3((unsigned)((tot + TB - 1) / TB)), dim3(TB), 0, st, nblk, n, a, b);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+}  // namespace wmg

@@ -1,0 +1,1087 @@
+// Adaptive multigrid engine and C ABI (arXiv:0912.2186, Sec. 2-3).
+//
+// Host code drives device kernels on one HIP stream per context.  Solver
+// scalars (dot products, step lengths, masks) live in device memory and are
+// consumed by the kernels that need them; the host reads back one residual
+// norm per outer GCR iteration and a convergence flag every few coarse CGNR
+// iterations.
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wmg_internal.h"
+#include "../../include/wmg.h"
+
+namespace wmg {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+
+static constexpr int KMAX = 16;
+static size_t csize(int prec) { return prec == P64 ? 16 : 8; }
+
+// ------------------------------------------------------------ scalar kernels
+// MR step: alpha = <q,s>/|q|^2 (red[rhs*4 + 0..2]); e += alpha s; s -= alpha q
+template <class S>
+__global__ void k_mr_update(const double *__restrict__ red, S *__restrict__ e, S *__restrict__ s,
+                            const S *__restrict__ q, long n) {
+  using R = typename store_traits<S>::real;
+  int rhs = blockIdx.y;
+  const double *rd = red + rhs * 4;
+  double qq = rd[2];
+  cx<R> a = qq > 0 ? cx<R>{(R)(rd[0] / qq), (R)(rd[1] / qq)} : czero<R>();
+  size_t off = (size_t)rhs * n;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    auto sv = ldc(s + off + i);
+    auto qv = ldc(q + off + i);
+    auto ev = ldc(e + off + i);
+    stc(e + off + i, cfma(a, sv, ev));
+    stc(s + off + i, cfma(neg(a), qv, sv));
+  }
+}
+
+// CG: alpha = act ? ss/uu : 0; x += alpha p; r -= alpha u
+template <class S>
+__global__ void k_cg_step1(const double *__restrict__ cg, int ssoff, S *__restrict__ x, S *__restrict__ r,
+                           const S *__restrict__ p, const S *__restrict__ u, long n, int nrhs) {
+  using R = typename store_traits<S>::real;
+  int rhs = blockIdx.y;
+  const double *c = cg + rhs * 8;
+  double uu = c[0], ss = c[ssoff], act = c[5];
+  R a = (act > 0 && uu > 0) ? (R)(ss / uu) : R(0);
+  size_t off = (size_t)rhs * n;
+  if (a == R(0)) return;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    auto pv = ldc(p + off + i), uv = ldc(u + off + i);
+    stc(x + off + i, ldc(x + off + i) + a * pv);
+    stc(r + off + i, ldc(r + off + i) - a * uv);
+  }
+}
+
+// CG: p = s + beta p, beta = ss_new/ss_old, only while active
+template <class S>
+__global__ void k_cg_step2(const double *__restrict__ cg, int newoff, int oldoff, const S *__restrict__ s,
+                           S *__restrict__ p, long n) {
+  using R = typename store_traits<S>::real;
+  int rhs = blockIdx.y;
+  const double *c = cg + rhs * 8;
+  if (!(c[5] > 0)) return;
+  R be = c[oldoff] > 0 ? (R)(c[newoff] / c[oldoff]) : R(0);
+  size_t off = (size_t)rhs * n;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+    stc(p + off + i, ldc(s + off + i) + be * ldc(p + off + i));
+}
+
+// cg layout per rhs (8 doubles): 0 uu, 1 ss[0], 2 ss[1], 3 rr, 4 bb, 5 active, 6 iters, 7 tol^2
+__global__ void k_cg_init(double *cg, int nrhs, double tol2, const double *mask) {
+  int r = threadIdx.x;
+  if (r >= nrhs) return;
+  double *c = cg + r * 8;
+  c[5] = (c[4] > 0 && (!mask || mask[r] > 0)) ? 1.0 : 0.0;
+  c[6] = 0;
+  c[7] = tol2;
+}
+__global__ void k_cg_check(double *cg, int nrhs, int *alldone) {
+  int r = threadIdx.x;
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  if (r < nrhs) {
+    double *c = cg + r * 8;
+    if (c[5] > 0) {
+      c[6] += 1;
+      if (c[3] <= c[7] * c[4]) c[5] = 0;
+      else atomicOr(&any, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *alldone = any ? 0 : 1;
+}
+
+// GCR coefficient bookkeeping.  gcr layout per rhs (stride GS doubles):
+//   beta[K][K][2] | gamma[K] | alpha[K][2] | c[K][2] | tmp[2K] | mask
+constexpr int GK = KMAX;
+constexpr int G_BETA = 0, G_GAMMA = G_BETA + GK * GK * 2, G_ALPHA = G_GAMMA + GK, G_C = G_ALPHA + GK * 2,
+              G_TMP = G_C + GK * 2, G_MASK = G_TMP + 2 * GK, GS = G_MASK + 8;
+
+__global__ void k_gcr_negate_tmp(double *g, int k, int nrhs) {
+  int r = blockIdx.x, j = threadIdx.x;
+  if (r >= nrhs || j >= 2 * k) return;
+  g[r * GS + G_TMP + j] = -g[r * GS + G_TMP + j];
+}
+// beta[j][k] (+)= tmp[j], tmp = the projections <w_j, w> of this pass
+__global__ void k_gcr_accum_beta(double *g, int k, int nrhs, int first) {
+  int r = blockIdx.x, j = threadIdx.x;
+  if (r >= nrhs || j >= k) return;
+  double *b = g + r * GS + G_BETA + (j * GK + k) * 2;
+  double re = g[r * GS + G_TMP + 2 * j], im = g[r * GS + G_TMP + 2 * j + 1];
+  if (first) { b[0] = re; b[1] = im; }
+  else { b[0] += re; b[1] += im; }
+}
+__global__ void k_gcr_gamma(double *g, const double *red, int k, int nrhs) {
+  int r = threadIdx.x;
+  if (r >= nrhs) return;
+  g[r * GS + G_GAMMA + k] = sqrt(red[r * 4]);
+}
+__global__ void k_gcr_alpha(double *g, const double *red, const double *mask, int k, int nrhs) {
+  int r = threadIdx.x;
+  if (r >= nrhs) return;
+  double m = mask[r];
+  double gam = g[r * GS + G_GAMMA + k];
+  bool ok = m > 0 && gam > 0;
+  g[r * GS + G_ALPHA + 2 * k] = ok ? red[r * 4] : 0.0;
+  g[r * GS + G_ALPHA + 2 * k + 1] = ok ? red[r * 4 + 1] : 0.0;
+}
+// back substitution: c_j = (alpha_j - sum_{i>j} beta_ji c_i) / gamma_j
+__global__ void k_gcr_trisolve(double *g, int k, int nrhs) {
+  int r = threadIdx.x;
+  if (r >= nrhs) return;
+  double *G = g + r * GS;
+  for (int j = k - 1; j >= 0; j--) {
+    double tr = G[G_ALPHA + 2 * j], ti = G[G_ALPHA + 2 * j + 1];
+    for (int i = j + 1; i < k; i++) {
+      double br = G[G_BETA + (j * GK + i) * 2], bi = G[G_BETA + (j * GK + i) * 2 + 1];
+      double cr = G[G_C + 2 * i], ci = G[G_C + 2 * i + 1];
+      tr -= br * cr - bi * ci;
+      ti -= br * ci + bi * cr;
+    }
+    double gm = G[G_GAMMA + j];
+    G[G_C + 2 * j] = gm > 0 ? tr / gm : 0.0;
+    G[G_C + 2 * j + 1] = gm > 0 ? ti / gm : 0.0;
+  }
+}
+
+template <class S> static dim3 grid_for(long n, int nrhs) {
+  long b = (n + 255) / 256;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b, nrhs);
+}
+
+}  // namespace wmg
+
+using namespace wmg;
+
+// ------------------------------------------------------------ context
+enum { VR, VE, VT, VE2, VS, VQ, VCR, VCS, VCP, VCU, VX, NVW };
+
+struct Level {
+  Geom g;
+  int dof = 12;
+  bool fine = true;
+  long n = 0;        // complex numbers per rhs at the current Nv of the level above
+  long n_alloc = 0;  // ... at its largest Nv (allocation size)
+  // fine operator
+  void *U[3] = {nullptr, nullptr, nullptr};  // P64 / P32 / P16 SoA
+  double m = 0;
+  // coarse operator (internal layout)
+  double2 *Y64 = nullptr;
+  float2 *Y32 = nullptr;
+  // transfer to level+1
+  int b[4] = {1, 1, 1, 1};
+  int nv = 0, nv_max = 0;
+  double2 *vecs = nullptr;  // null vectors, level vector layout, FP64
+  double2 *P64 = nullptr;
+  float2 *P32 = nullptr;
+  __half2 *P16 = nullptr;
+  float *Ps = nullptr;
+  // work vectors: [prec][name] each [nrhs_alloc][n]
+  void *w[2][NVW] = {};
+  int w_nrhs = 0;
+};
+
+struct GcrBuf {
+  int prec = P64;  // inner precision
+  int nrhs = 0;
+  long n = 0;
+  void *z[KMAX] = {}, *wv[KMAX] = {};
+  void **zdev = nullptr, **wdev = nullptr;  // device arrays of the pointers
+  void *rin = nullptr;                      // inner residual (aliases r64 in FP64 mode)
+  double2 *x64 = nullptr, *r64 = nullptr, *b64 = nullptr, *t64 = nullptr;
+};
+
+struct wmg_ctx {
+  wmg_params p;
+  int nl = 2;       // levels of the final hierarchy
+  int nl_cur = 2;   // levels in use (the setup's trial schemes use fewer)
+  Level lv[3];
+  hipStream_t st = nullptr;
+  Reducer red{};
+  double *dsc = nullptr;  // device scalars
+  double *red_out = nullptr;
+  double *cg = nullptr;
+  double *gcr = nullptr;
+  double *mask = nullptr;
+  int *flag = nullptr;
+  double *hbuf = nullptr;  // pinned host mirror
+  GcrBuf gb[2];            // level 0 (solve), level 1 (setup of a third level)
+  std::vector<int> last_iters;
+  double setup_s = 0;
+  // solve statistics
+  long st_fine = 0, st_fine64 = 0, st_coarse = 0, st_rel = 0;
+  // batch
+  std::vector<wmg_ctx *> batch;
+};
+
+static int dalloc(void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return set_error(WMG_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  return 0;
+}
+#define TRY(x)            \
+  do {                    \
+    int rc_ = (x);        \
+    if (rc_) return rc_;  \
+  } while (0)
+
+static int sync(wmg_ctx *c) {
+  WMG_HIP(hipStreamSynchronize(c->st));
+  return 0;
+}
+
+static int level_vec(wmg_ctx *c, int l, int prec, int name, void **out) {
+  Level &L = c->lv[l];
+  int pi = prec == P64 ? 0 : 1;
+  if (!L.w[pi][name]) TRY(dalloc(&L.w[pi][name], csize(prec) * (size_t)L.n_alloc * L.w_nrhs));
+  *out = L.w[pi][name];
+  return 0;
+}
+
+// ------------------------------------------------------------ operators
+// op(level, prec, in, out, nrhs, lowlinks): fine Wilson (links P64 / P32 /
+// P16 when lowlinks) or coarse stencil.
+static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int nrhs, bool lowlinks, int dagger = 0) {
+  Level &L = c->lv[l];
+  if (L.fine) {
+    int lp = prec == P64 ? P64 : (lowlinks ? P16 : P32);
+    if (dagger) return set_error(-1, "fine adjoint not used");
+    c->st_fine++;
+    if (prec == P64) c->st_fine64++;
+    return wilson_soa(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, c->st);
+  }
+  int n = L.dof;
+  return coarse_apply(L.g, n, prec, prec == P64 ? (const void *)L.Y64 : (const void *)L.Y32, prec, in, out, dagger,
+                      nrhs, c->st);
+}
+
+static int transfer_restrict(wmg_ctx *c, int l, int prec, const void *fine, void *coarse, int nrhs) {
+  Level &L = c->lv[l];
+  int pp = prec == P64 ? P64 : P16;
+  const void *P = prec == P64 ? (const void *)L.P64 : (const void *)L.P16;
+  return restrict_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, fine, L.fine ? 1 : 0, coarse, nrhs, c->st);
+}
+static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, void *fine, int nrhs) {
+  Level &L = c->lv[l];
+  int pp = prec == P64 ? P64 : P16;
+  const void *P = prec == P64 ? (const void *)L.P64 : (const void *)L.P16;
+  return prolong_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, coarse, fine, L.fine ? 1 : 0, nrhs, c->st);
+}
+
+// ------------------------------------------------------------ MR smoother
+// nsteps minimal-residual steps on A e = r from e (post-smoother, Sec. 3)
+static int mr_smooth(wmg_ctx *c, int l, int prec, const void *r, void *e, int nsteps, int nrhs) {
+  Level &L = c->lv[l];
+  void *s, *q;
+  TRY(level_vec(c, l, prec, VS, &s));
+  TRY(level_vec(c, l, prec, VQ, &q));
+  TRY(apply_op(c, l, prec, e, q, nrhs, true));
+  TRY(csub(prec, r, q, s, L.n, nrhs, c->st));
+  for (int k = 0; k < nsteps; k++) {
+    TRY(apply_op(c, l, prec, s, q, nrhs, true));
+    TRY(dot_norm(c->red, prec, q, s, L.n, nrhs, c->red_out, 4, c->st));
+    dim3 g = grid_for<double2>(L.n, nrhs);
+    if (prec == P64)
+      hipLaunchKernelGGL(k_mr_update<double2>, g, dim3(256), 0, c->st, c->red_out, (double2 *)e, (double2 *)s,
+                         (const double2 *)q, L.n);
+    else
+      hipLaunchKernelGGL(k_mr_update<float2>, g, dim3(256), 0, c->st, c->red_out, (float2 *)e, (float2 *)s,
+                         (const float2 *)q, L.n);
+    WMG_HIP(hipGetLastError());
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------ CGNR
+// CG on the normal equations at the coarsest level (Sec. 3); stops per rhs
+// when |b - A x| <= tol |b| (recursively updated residual).
+static int cgnr(wmg_ctx *c, int l, int prec, const void *b, void *x, int nrhs) {
+  Level &L = c->lv[l];
+  void *r, *s, *p, *u;
+  TRY(level_vec(c, l, prec, VCR, &r));
+  TRY(level_vec(c, l, prec, VCS, &s));
+  TRY(level_vec(c, l, prec, VCP, &p));
+  TRY(level_vec(c, l, prec, VCU, &u));
+  double tol = c->p.coarse_tol;
+  TRY(zero(prec, x, L.n, nrhs, c->st));
+  TRY(copy(prec, r, prec, b, L.n, nrhs, c->st));
+  // cg[rhs*8 + 4] = |b|^2
+  TRY(norm2(c->red, prec, b, L.n, nrhs, c->cg + 4, 8, c->st));
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64), 0, c->st, c->cg, nrhs, tol * tol, (const double *)nullptr);
+  TRY(apply_op(c, l, prec, r, s, nrhs, false, 1));
+  TRY(copy(prec, p, prec, s, L.n, nrhs, c->st));
+  TRY(norm2(c->red, prec, s, L.n, nrhs, c->cg + 1, 8, c->st));
+  int cur = 1;
+  const int check = 4;
+  int it = 0;
+  dim3 g = grid_for<double2>(L.n, nrhs);
+  for (; it < c->p.coarse_maxiter; it++) {
+    TRY(apply_op(c, l, prec, p, u, nrhs, false));
+    TRY(norm2(c->red, prec, u, L.n, nrhs, c->cg + 0, 8, c->st));
+    if (prec == P64)
+      hipLaunchKernelGGL(k_cg_step1<double2>, g, dim3(256), 0, c->st, c->cg, cur, (double2 *)x, (double2 *)r,
+                         (const double2 *)p, (const double2 *)u, L.n, nrhs);
+    else
+      hipLaunchKernelGGL(k_cg_step1<float2>, g, dim3(256), 0, c->st, c->cg, cur, (float2 *)x, (float2 *)r,
+                         (const float2 *)p, (const float2 *)u, L.n, nrhs);
+    TRY(norm2(c->red, prec, r, L.n, nrhs, c->cg + 3, 8, c->st));
+    hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, c->st, c->cg, nrhs, c->flag);
+    if ((it + 1) % check == 0 || it + 1 == c->p.coarse_maxiter) {
+      int done = 0;
+      WMG_HIP(hipMemcpyAsync(&done, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+      TRY(sync(c));
+      if (done) { it++; break; }
+    }
+    TRY(apply_op(c, l, prec, r, s, nrhs, false, 1));
+    int nxt = 3 - cur;
+    TRY(norm2(c->red, prec, s, L.n, nrhs, c->cg + nxt, 8, c->st));
+    if (prec == P64)
+      hipLaunchKernelGGL(k_cg_step2<double2>, g, dim3(256), 0, c->st, c->cg, nxt, cur, (const double2 *)s,
+                         (double2 *)p, L.n);
+    else
+      hipLaunchKernelGGL(k_cg_step2<float2>, g, dim3(256), 0, c->st, c->cg, nxt, cur, (const float2 *)s,
+                         (float2 *)p, L.n);
+    cur = nxt;
+  }
+  // effective iterations (max over rhs) for the statistics
+  WMG_HIP(hipMemcpyAsync(c->hbuf, c->cg, sizeof(double) * 8 * nrhs, hipMemcpyDeviceToHost, c->st));
+  TRY(sync(c));
+  double mx = 0;
+  for (int r2 = 0; r2 < nrhs; r2++) mx = fmax(mx, c->hbuf[r2 * 8 + 6]);
+  c->st_coarse += (long)mx;
+  return 0;
+}
+
+// ------------------------------------------------------------ cycle
+// e = M_l r: restrict, coarse correction (CGNR at the coarsest level, else
+// one or two recursive cycles), prolong, post-smooth (no pre-smoothing).
+static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int nrhs) {
+  Level &C = c->lv[l + 1];
+  void *rc, *ec;
+  TRY(level_vec(c, l + 1, prec, VR, &rc));
+  TRY(level_vec(c, l + 1, prec, VE, &ec));
+  TRY(transfer_restrict(c, l, prec, r, rc, nrhs));
+  if (l + 1 == c->nl_cur - 1) {
+    TRY(cgnr(c, l + 1, prec, rc, ec, nrhs));
+  } else {
+    TRY(mg_cycle_l(c, l + 1, prec, rc, ec, nrhs));
+    if (c->p.cycle == WMG_WCYCLE) {
+      void *t, *e2;
+      TRY(level_vec(c, l + 1, prec, VT, &t));
+      TRY(level_vec(c, l + 1, prec, VE2, &e2));
+      TRY(apply_op(c, l + 1, prec, ec, t, nrhs, true));
+      TRY(csub(prec, rc, t, t, C.n, nrhs, c->st));
+      TRY(mg_cycle_l(c, l + 1, prec, t, e2, nrhs));
+      TRY(axpby(prec, 1.0, e2, 1.0, ec, C.n, nrhs, c->st));  // ec += e2
+    }
+  }
+  TRY(transfer_prolong(c, l, prec, ec, e, nrhs));
+  TRY(mr_smooth(c, l, prec, r, e, c->p.post_smooth, nrhs));
+  return 0;
+}
+
+// ------------------------------------------------------------ GCR buffers
+static int gcr_buffers(wmg_ctx *c, int l, int prec, int nrhs, GcrBuf **out) {
+  int slot = (l == 0 ? 0 : 1);
+  GcrBuf &B = c->gb[slot];
+  Level &L = c->lv[l];
+  long nalloc = L.g.V * (L.fine ? 12 : 2 * c->lv[l - 1].nv_max);
+  bool ok = B.x64 && B.prec == prec && B.nrhs >= nrhs && B.n >= nalloc;
+  if (!ok) {
+    // release and reallocate
+    for (int k = 0; k < KMAX; k++) {
+      if (B.z[k]) (void)hipFree(B.z[k]);
+      if (B.wv[k]) (void)hipFree(B.wv[k]);
+      B.z[k] = B.wv[k] = nullptr;
+    }
+    if (B.x64) (void)hipFree(B.x64);
+    if (B.r64) (void)hipFree(B.r64);
+    if (B.b64) (void)hipFree(B.b64);
+    if (B.t64) (void)hipFree(B.t64);
+    if (B.prec != P64 && B.rin) (void)hipFree(B.rin);
+    if (B.zdev) (void)hipFree(B.zdev);
+    if (B.wdev) (void)hipFree(B.wdev);
+    B = GcrBuf();
+    B.prec = prec;
+    B.nrhs = nrhs;
+    B.n = nalloc;
+    int K = c->p.gcr_restart;
+    for (int k = 0; k < K; k++) {
+      TRY(dalloc(&B.z[k], csize(prec) * nalloc * nrhs));
+      TRY(dalloc(&B.wv[k], csize(prec) * nalloc * nrhs));
+    }
+    TRY(dalloc((void **)&B.x64, 16 * nalloc * nrhs));
+    TRY(dalloc((void **)&B.r64, 16 * nalloc * nrhs));
+    TRY(dalloc((void **)&B.b64, 16 * nalloc * nrhs));
+    TRY(dalloc((void **)&B.t64, 16 * nalloc * nrhs));
+    if (prec == P64) B.rin = B.r64;
+    else TRY(dalloc(&B.rin, csize(prec) * nalloc * nrhs));
+    TRY(dalloc((void **)&B.zdev, sizeof(void *) * KMAX));
+    TRY(dalloc((void **)&B.wdev, sizeof(void *) * KMAX));
+    WMG_HIP(hipMemcpy(B.zdev, B.z, sizeof(void *) * KMAX, hipMemcpyHostToDevice));
+    WMG_HIP(hipMemcpy(B.wdev, B.wv, sizeof(void *) * KMAX, hipMemcpyHostToDevice));
+  }
+  *out = &B;
+  return 0;
+}
+
+// ------------------------------------------------------------ flexible GCR
+// Restarted flexible GCR on level l (Sec. 3 outer solver) with reliable
+// updates.  Each restart cycle works in the inner precision on r_in: z_k =
+// M(r_in), w_k = A z_k orthonormalised against w_0..w_{k-1} (classical GS
+// twice), alpha_k = <w_k, r_in>, r_in -= alpha_k w_k.  A right-hand side
+// leaves the cycle when |r_in| <= tol |b|, when |r_in| < delta |r| (mixed
+// precision) or after K steps; the FP64 solution update is recovered from
+// the triangular system A z_k = gamma_k w_k + sum_j beta_jk w_j, and the
+// residual is recomputed in FP64 (the reliable update).
+// precond: 0 = smoother only (first setup vector), 1 = multigrid cycle.
+static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int maxiter, int precond, double delta,
+                     bool x0_nonzero, std::vector<int> &iters, double *relres_out) {
+  Level &L = c->lv[l];
+  const int ip = B.prec;
+  const int K = c->p.gcr_restart;
+  const long n = L.n;
+  hipStream_t st = c->st;
+  std::vector<double> bn(nrhs), rn(nrhs), rn_last(nrhs);
+  std::vector<char> active(nrhs), frozen(nrhs);
+  iters.assign(nrhs, 0);
+  // |b|
+  TRY(norm2(c->red, P64, B.b64, n, nrhs, c->red_out, 4, st));
+  WMG_HIP(hipMemcpyAsync(c->hbuf, c->red_out, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, st));
+  TRY(sync(c));
+  for (int r = 0; r < nrhs; r++) bn[r] = sqrt(c->hbuf[4 * r]);
+  if (x0_nonzero) {
+    TRY(apply_op(c, l, P64, B.x64, B.t64, nrhs, false));
+    TRY(csub(P64, B.b64, B.t64, B.r64, n, nrhs, st));
+  } else {
+    TRY(copy(P64, B.r64, P64, B.b64, n, nrhs, st));
+  }
+  TRY(norm2(c->red, P64, B.r64, n, nrhs, c->red_out, 4, st));
+  WMG_HIP(hipMemcpyAsync(c->hbuf, c->red_out, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, st));
+  TRY(sync(c));
+  bool any = false;
+  for (int r = 0; r < nrhs; r++) {
+    rn[r] = sqrt(c->hbuf[4 * r]);
+    active[r] = !(rn[r] <= tol * bn[r]);
+    if (!std::isfinite(rn[r])) return set_error(WMG_EBREAKDOWN, "non-finite initial residual");
+    any |= active[r];
+  }
+  int total = 0;
+  std::vector<double> mask(nrhs * GS, 0.0);
+  while (any && total < maxiter) {
+    for (int r = 0; r < nrhs; r++) {
+      rn_last[r] = rn[r];
+      frozen[r] = !active[r];
+    }
+    if (ip != P64) TRY(copy(ip, B.rin, P64, B.r64, n, nrhs, st));
+    int k = 0;
+    while (k < K && total < maxiter) {
+      // per-rhs participation mask of this step
+      double *hm = c->hbuf + 2048;
+      for (int r = 0; r < nrhs; r++) hm[r] = frozen[r] ? 0.0 : 1.0;
+      WMG_HIP(hipMemcpyAsync(c->mask, hm, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+      void *z = B.z[k], *w = B.wv[k];
+      if (precond == 1) {
+        TRY(mg_cycle_l(c, l, ip, B.rin, z, nrhs));
+      } else {
+        TRY(zero(ip, z, n, nrhs, st));
+        TRY(mr_smooth(c, l, ip, B.rin, z, c->p.post_smooth, nrhs));
+      }
+      TRY(apply_op(c, l, ip, z, w, nrhs, false));
+      if (k > 0) {
+        for (int pass = 0; pass < 2; pass++) {
+          TRY(multi_dot(c->red, ip, (const void *const *)B.wdev, k, w, n, nrhs, c->gcr + G_TMP, GS, st));
+          hipLaunchKernelGGL(k_gcr_accum_beta, dim3(nrhs), dim3(KMAX), 0, st, c->gcr, k, nrhs, pass == 0 ? 1 : 0);
+          hipLaunchKernelGGL(k_gcr_negate_tmp, dim3(nrhs), dim3(2 * KMAX), 0, st, c->gcr, k, nrhs);
+          TRY(multi_caxpy(ip, w, ip, (const void *const *)B.wdev, k, c->gcr + G_TMP, GS, 1.0, 1, n, nrhs, st));
+        }
+      }
+      TRY(norm2(c->red, ip, w, n, nrhs, c->red_out, 4, st));
+      hipLaunchKernelGGL(k_gcr_gamma, dim3(1), dim3(64), 0, st, c->gcr, c->red_out, k, nrhs);
+      TRY(scale_inv_sqrt(ip, w, c->red_out, 4, n, nrhs, st));
+      TRY(dot(c->red, ip, w, B.rin, n, nrhs, c->red_out, 4, st));
+      hipLaunchKernelGGL(k_gcr_alpha, dim3(1), dim3(64), 0, st, c->gcr, c->red_out, c->mask, k, nrhs);
+      TRY(caxpy_dev(ip, c->gcr + G_ALPHA + 2 * k, GS, -1.0, w, B.rin, n, nrhs, st));
+      TRY(norm2(c->red, ip, B.rin, n, nrhs, c->red_out, 4, st));
+      WMG_HIP(hipMemcpyAsync(c->hbuf, c->red_out, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, st));
+      TRY(sync(c));
+      bool allfrozen = true;
+      for (int r = 0; r < nrhs; r++) {
+        double rin = sqrt(c->hbuf[4 * r]);
+        if (!std::isfinite(rin)) return set_error(WMG_EBREAKDOWN, "non-finite GCR residual (rhs %d)", r);
+        if (!frozen[r]) {
+          iters[r]++;
+          if (rin <= tol * bn[r] || rin < delta * rn_last[r]) frozen[r] = 1;
+        }
+        allfrozen &= (bool)frozen[r];
+      }
+      k++;
+      total++;
+      if (allfrozen) break;
+    }
+    hipLaunchKernelGGL(k_gcr_trisolve, dim3(1), dim3(64), 0, st, c->gcr, k, nrhs);
+    TRY(multi_caxpy(P64, B.x64, ip, (const void *const *)B.zdev, k, c->gcr + G_C, GS, 1.0, 1, n, nrhs, st));
+    // reliable update: true residual in FP64
+    TRY(apply_op(c, l, P64, B.x64, B.t64, nrhs, false));
+    TRY(csub(P64, B.b64, B.t64, B.r64, n, nrhs, st));
+    c->st_rel++;
+    TRY(norm2(c->red, P64, B.r64, n, nrhs, c->red_out, 4, st));
+    WMG_HIP(hipMemcpyAsync(c->hbuf, c->red_out, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, st));
+    TRY(sync(c));
+    any = false;
+    for (int r = 0; r < nrhs; r++) {
+      rn[r] = sqrt(c->hbuf[4 * r]);
+      if (!std::isfinite(rn[r])) return set_error(WMG_EBREAKDOWN, "non-finite true residual (rhs %d)", r);
+      if (active[r] && rn[r] <= tol * bn[r]) active[r] = 0;
+      any |= (bool)active[r];
+    }
+  }
+  if (relres_out) {
+    double mx = 0;
+    for (int r = 0; r < nrhs; r++) mx = fmax(mx, bn[r] > 0 ? rn[r] / bn[r] : rn[r]);
+    *relres_out = mx;
+  }
+  return any ? WMG_ENOTCONV : 0;
+}
+
+// ------------------------------------------------------------ hierarchy build
+// P_l from the first k null vectors (Eq. 2.7, chirality split) and the
+// Galerkin operator of level l+1.
+static int build_level(wmg_ctx *c, int l, int k) {
+  Level &F = c->lv[l], &C = c->lv[l + 1];
+  F.nv = k;
+  C.dof = 2 * k;
+  C.n = C.g.V * C.dof;
+  WMG_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), c->st));
+  TRY(block_orthonormalize(F.g, F.dof, F.b, k, F.vecs, F.fine ? 1 : 0, F.P64, c->flag, c->st));
+  int fail = 0;
+  WMG_HIP(hipMemcpyAsync(&fail, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  TRY(sync(c));
+  if (fail) return set_error(WMG_ERANK, "block Gram-Schmidt breakdown at level %d (null vectors dependent)", l);
+  TRY(coarse_build(F.g, F.fine ? 0 : 1, F.dof, F.U[P64], F.m, F.Y64, F.b, k, F.P64, C.Y64, nullptr, c->st));
+  return 0;
+}
+
+// reduced-precision copies used by the mixed-precision cycle
+static int make_low_precision(wmg_ctx *c) {
+  if (c->p.precision != WMG_MIXED) return 0;
+  for (int l = 0; l + 1 < c->nl; l++) {
+    Level &F = c->lv[l];
+    int bs = F.b[0] * F.b[1] * F.b[2] * F.b[3];
+    long nsites = (long)F.nv * (F.g.V / bs) * bs;
+    if (!F.P16) {
+      TRY(dalloc((void **)&F.P16, 4 * (size_t)F.nv_max * F.g.V * F.dof));
+      TRY(dalloc((void **)&F.Ps, 4 * (size_t)F.nv_max * F.g.V));
+    }
+    TRY(P_convert_half(nsites, bs, F.dof, F.fine ? 1 : 0, F.P64, F.P16, F.Ps, c->st));
+  }
+  for (int l = 1; l < c->nl; l++) {
+    Level &C = c->lv[l];
+    long cnt = C.g.V * 9L * C.dof * C.dof;
+    if (!C.Y32) TRY(dalloc((void **)&C.Y32, 8 * (size_t)C.g.V * 9 * C.dof * C.dof));
+    TRY(coarse_convert(cnt, C.Y64, P32, C.Y32, c->st));
+  }
+  return sync(c);
+}
+
+// Adaptive setup of level l (Sec. 2, Eq. 2.6): null vector k starts from a
+// Philox random vector and is relaxed on A x = 0 by setup_iters GCR steps
+// preconditioned with the trial two-level scheme built from vectors
+// 0..k-1 (the smoother alone for k = 0); it is then normalised.  After the
+// last vector the level is built from all of them.
+static int setup_level(wmg_ctx *c, int l) {
+  Level &F = c->lv[l];
+  int nv = F.nv_max;
+  c->nl_cur = l + 2;
+  GcrBuf *B;
+  TRY(gcr_buffers(c, l, P64, 1, &B));
+  long n = F.n;
+  std::vector<int> its;
+  for (int k = 0; k < nv; k++) {
+    TRY(start_vectors(F.g.V, F.dof, c->p.seed, l, k, 1, B->x64, F.fine ? 1 : 0, F.g.V, c->st));
+    if (k > 0) TRY(build_level(c, l, k));
+    TRY(zero(P64, B->b64, n, 1, c->st));
+    int rc = gcr_solve(c, l, *B, 1, 0.0, c->p.setup_iters, k > 0 ? 1 : 0, 0.0, true, its, nullptr);
+    if (rc < 0) return rc;
+    TRY(norm2(c->red, P64, B->x64, n, 1, c->red_out, 4, c->st));
+    TRY(scale_inv_sqrt(P64, B->x64, c->red_out, 4, n, 1, c->st));
+    TRY(copy(P64, F.vecs + (size_t)k * n, P64, B->x64, n, 1, c->st));
+  }
+  TRY(build_level(c, l, nv));
+  c->nl_cur = c->nl;
+  return sync(c);
+}
+
+static void free_ctx(wmg_ctx *c) {
+  if (!c) return;
+  for (auto *b : c->batch) free_ctx(b);
+  for (int l = 0; l < 3; l++) {
+    Level &L = c->lv[l];
+    for (int i = 0; i < 3; i++)
+      if (L.U[i]) (void)hipFree(L.U[i]);
+    void *ps[] = {L.Y64, L.Y32, L.vecs, L.P64, L.P32, L.P16, L.Ps};
+    for (void *p : ps)
+      if (p) (void)hipFree(p);
+    for (int a = 0; a < 2; a++)
+      for (int k = 0; k < NVW; k++)
+        if (L.w[a][k]) (void)hipFree(L.w[a][k]);
+  }
+  for (auto &B : c->gb) {
+    for (int k = 0; k < KMAX; k++) {
+      if (B.z[k]) (void)hipFree(B.z[k]);
+      if (B.wv[k]) (void)hipFree(B.wv[k]);
+    }
+    void *ps[] = {B.x64, B.r64, B.b64, B.t64, B.zdev, B.wdev};
+    for (void *p : ps)
+      if (p) (void)hipFree(p);
+    if (B.prec != P64 && B.rin) (void)hipFree(B.rin);
+  }
+  red_free(c->red);
+  if (c->dsc) (void)hipFree(c->dsc);
+  if (c->flag) (void)hipFree(c->flag);
+  if (c->hbuf) (void)hipHostFree(c->hbuf);
+  if (c->st) (void)hipStreamDestroy(c->st);
+  delete c;
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ============================================================ C ABI
+extern "C" {
+
+int wmg_default_params(wmg_params *p) {
+  if (!p) return set_error(WMG_EINVAL, "null params");
+  memset(p, 0, sizeof(*p));
+  p->levels = 2;
+  for (int l = 0; l < 2; l++)
+    for (int i = 0; i < 4; i++) p->block[l][i] = l == 0 ? 4 : 2;
+  p->nvec[0] = 24;
+  p->nvec[1] = 32;
+  p->setup_iters = 5;
+  p->post_smooth = 4;
+  p->gcr_restart = 8;
+  p->cycle = WMG_WCYCLE;
+  p->precision = WMG_FP64;
+  p->nrhs_max = 1;
+  p->coarse_tol = 1e-8;
+  p->coarse_maxiter = 500;
+  p->reliable_delta = 0.1;
+  p->maxiter = 1000;
+  p->seed = 12345;
+  p->flags = 0;
+  return 0;
+}
+
+const char *wmg_strerror(int code) {
+  if (g_err[0]) return g_err;
+  switch (code) {
+    case WMG_OK: return "ok";
+    case WMG_ENOTCONV: return "not converged";
+    case WMG_EINVAL: return "invalid argument";
+    case WMG_ENOMEM: return "out of device memory";
+    case WMG_EHIP: return "HIP runtime error";
+    case WMG_ERANK: return "block Gram-Schmidt rank breakdown";
+    case WMG_EBREAKDOWN: return "numerical breakdown";
+  }
+  return "unknown error";
+}
+
+static int check_geom(const wmg_geom *g) {
+  if (!g) return set_error(WMG_EINVAL, "null geometry");
+  for (int i = 0; i < 4; i++)
+    if (g->L[i] <= 0) return set_error(WMG_EINVAL, "lattice extent L[%d] = %d", i, g->L[i]);
+  return 0;
+}
+
+static Geom to_geom(const int L[4]) {
+  Geom g;
+  for (int i = 0; i < 4; i++) g.L[i] = L[i];
+  g.V = (long)L[0] * L[1] * L[2] * L[3];
+  return g;
+}
+
+int wilson_apply(const wmg_geom *g, const double *U, double m, const double *in, double *out, void *hip_stream) {
+  g_err[0] = 0;
+  TRY(check_geom(g));
+  if (!U || !in || !out) return set_error(WMG_EINVAL, "null field pointer");
+  if (in == out) return set_error(WMG_EINVAL, "in and out alias");
+  return wilson_canonical(to_geom(g->L), U, m, in, out, (hipStream_t)hip_stream);
+}
+
+int mg_destroy(wmg_ctx *ctx) {
+  free_ctx(ctx);
+  return 0;
+}
+
+static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, const int block[4], const wmg_params *pin,
+                      wmg_ctx **out) {
+  TRY(check_geom(g));
+  if (!U || !out || !block) return set_error(WMG_EINVAL, "null argument");
+  wmg_params p;
+  if (pin) p = *pin;
+  else wmg_default_params(&p);
+  for (int i = 0; i < 4; i++) p.block[0][i] = block[i];
+  p.nvec[0] = Nv;
+  if (p.levels < 2 || p.levels > 3) return set_error(WMG_EINVAL, "levels = %d (2 or 3)", p.levels);
+  if (p.gcr_restart < 1 || p.gcr_restart > KMAX) return set_error(WMG_EINVAL, "gcr_restart = %d", p.gcr_restart);
+  if (p.nrhs_max < 1 || p.nrhs_max > 64) return set_error(WMG_EINVAL, "nrhs_max = %d", p.nrhs_max);
+  int L[4] = {g->L[0], g->L[1], g->L[2], g->L[3]};
+  int dof = 12;
+  for (int l = 0; l + 1 < p.levels; l++) {
+    int bs = 1;
+    for (int i = 0; i < 4; i++) {
+      if (p.block[l][i] <= 0 || L[i] % p.block[l][i]) 
+        return set_error(WMG_EINVAL, "level %d: extent %d not divisible by block %d", l, L[i], p.block[l][i]);
+      bs *= p.block[l][i];
+    }
+    if (p.nvec[l] < 1 || p.nvec[l] > (dof / 2) * bs || p.nvec[l] > 64)
+      return set_error(WMG_EINVAL, "level %d: Nv = %d outside [1, %d]", l, p.nvec[l], (dof / 2) * bs < 64 ? (dof / 2) * bs : 64);
+    if (l == 0 && bs > 256) return set_error(WMG_EINVAL, "fine aggregate of %d sites > 256", bs);
+    for (int i = 0; i < 4; i++) L[i] /= p.block[l][i];
+    dof = 2 * p.nvec[l];
+  }
+  wmg_ctx *c = new wmg_ctx();
+  c->p = p;
+  c->nl = c->nl_cur = p.levels;
+  int rc = 0;
+#define CK(x)                  \
+  do {                         \
+    rc = (x);                  \
+    if (rc) goto fail;         \
+  } while (0)
+  CK(hipStreamCreate(&c->st) == hipSuccess ? 0 : set_error(WMG_EHIP, "hipStreamCreate"));
+  CK(red_init(c->red, p.nrhs_max));
+  CK(dalloc((void **)&c->dsc, sizeof(double) * ((size_t)(4 + 8 + GS + 1) * 64 + 4096)));
+  c->red_out = c->dsc;
+  c->cg = c->dsc + 4 * 64;
+  c->gcr = c->cg + 8 * 64;
+  c->mask = c->gcr + GS * 64;
+  CK(dalloc((void **)&c->flag, sizeof(int)));
+  CK(hipHostMalloc((void **)&c->hbuf, sizeof(double) * 4096) == hipSuccess ? 0 : set_error(WMG_ENOMEM, "hipHostMalloc"));
+  {
+    Level &F = c->lv[0];
+    F.g = to_geom(g->L);
+    F.fine = true;
+    F.dof = 12;
+    F.n = F.n_alloc = F.g.V * 12;
+    F.m = m;
+    F.w_nrhs = p.nrhs_max;
+    CK(dalloc(&F.U[P64], 16 * 36 * (size_t)F.g.V));
+    CK(links_to_soa(F.g, U, P64, F.U[P64], c->st));
+    CK(dalloc(&F.U[P32], 8 * 36 * (size_t)F.g.V));
+    CK(links_to_soa(F.g, U, P32, F.U[P32], c->st));
+    CK(dalloc(&F.U[P16], 4 * 36 * (size_t)F.g.V));
+    CK(links_to_soa(F.g, U, P16, F.U[P16], c->st));
+    for (int l = 0; l + 1 < c->nl; l++) {
+      Level &A = c->lv[l], &C = c->lv[l + 1];
+      for (int i = 0; i < 4; i++) A.b[i] = p.block[l][i];
+      A.nv_max = A.nv = p.nvec[l];
+      CK(dalloc((void **)&A.vecs, 16 * (size_t)A.nv_max * A.n));
+      CK(dalloc((void **)&A.P64, 16 * (size_t)A.nv_max * A.n));
+      int Lc[4];
+      for (int i = 0; i < 4; i++) Lc[i] = A.g.L[i] / A.b[i];
+      C.g = to_geom(Lc);
+      C.fine = false;
+      C.dof = 2 * A.nv_max;
+      C.n = C.n_alloc = C.g.V * C.dof;
+      C.m = m;
+      C.w_nrhs = p.nrhs_max;
+      CK(dalloc((void **)&C.Y64, 16 * (size_t)C.g.V * 9 * C.dof * C.dof));
+    }
+  }
+  *out = c;
+  return 0;
+fail:
+  free_ctx(c);
+  return rc;
+#undef CK
+}
+
+int mg_setup(const wmg_geom *g, const double *U, double m, int Nv, const int block[4], const wmg_params *p,
+             wmg_ctx **out) {
+  g_err[0] = 0;
+  double t0 = now_s();
+  wmg_ctx *c = nullptr;
+  TRY(ctx_create(g, U, m, Nv, block, p, &c));
+  int rc = 0;
+  for (int l = 0; l + 1 < c->nl && !rc; l++) rc = setup_level(c, l);
+  if (!rc) rc = make_low_precision(c);
+  if (rc) {
+    free_ctx(c);
+    return rc;
+  }
+  c->setup_s = now_s() - t0;
+  *out = c;
+  return 0;
+}
+
+int mg_set_mass(wmg_ctx *c, double m) {
+  if (!c) return set_error(WMG_EINVAL, "null context");
+  if (!c->batch.empty()) return set_error(WMG_EINVAL, "mg_set_mass on a batch context");
+  double dm = m - c->lv[0].m;
+  for (int l = 0; l < c->nl; l++) c->lv[l].m = m;
+  for (int l = 1; l < c->nl; l++) TRY(coarse_shift_diag(c->lv[l].g.V, c->lv[l].dof, c->lv[l].Y64, dm, c->st));
+  TRY(sync(c));
+  return make_low_precision(c);
+}
+
+int mg_solve(wmg_ctx *c, const double *b, double *x, double tol, int nrhs, wmg_stats *stt) {
+  g_err[0] = 0;
+  if (!c || !b || !x) return set_error(WMG_EINVAL, "null argument");
+  if (!c->batch.empty()) return set_error(WMG_EINVAL, "mg_solve on a batch context (use mg_solve_batch)");
+  if (nrhs < 1 || nrhs > c->p.nrhs_max) return set_error(WMG_EINVAL, "nrhs = %d outside [1, %d]", nrhs, c->p.nrhs_max);
+  if (!(tol > 0)) return set_error(WMG_EINVAL, "tol must be positive");
+  double t0 = now_s();
+  c->st_fine = c->st_fine64 = c->st_coarse = c->st_rel = 0;
+  int ip = c->p.precision == WMG_MIXED ? P32 : P64;
+  GcrBuf *B;
+  TRY(gcr_buffers(c, 0, ip, c->p.nrhs_max, &B));
+  Level &F = c->lv[0];
+  TRY(spinor_to_soa(F.g, b, B->b64, nrhs, c->st));
+  bool x0 = (c->p.flags & WMG_X0_GIVEN) != 0;
+  if (x0) TRY(spinor_to_soa(F.g, x, B->x64, nrhs, c->st));
+  else TRY(zero(P64, B->x64, F.n, nrhs, c->st));
+  double relres = 0;
+  double delta = c->p.precision == WMG_MIXED ? c->p.reliable_delta : 0.0;
+  int rc = gcr_solve(c, 0, *B, nrhs, tol, c->p.maxiter, 1, delta, x0, c->last_iters, &relres);
+  if (rc < 0) return rc;
+  TRY(spinor_from_soa(F.g, B->x64, x, nrhs, c->st));
+  TRY(sync(c));
+  if (stt) {
+    int mx = 0;
+    for (int v : c->last_iters) mx = v > mx ? v : mx;
+    stt->outer_iters = mx;
+    stt->fine_matvecs = (int)c->st_fine;
+    stt->fine_matvecs_fp64 = (int)c->st_fine64;
+    stt->coarse_iters = (int)c->st_coarse;
+    stt->reliable_updates = (int)c->st_rel;
+    stt->converged = rc == 0;
+    stt->true_relres = relres;
+    stt->setup_s = c->setup_s;
+    stt->solve_s = now_s() - t0;
+  }
+  return rc;
+}
+
+int mg_last_iters(wmg_ctx *c, int *iters, int nrhs) {
+  if (!c || !iters) return set_error(WMG_EINVAL, "null argument");
+  for (int r = 0; r < nrhs; r++) iters[r] = r < (int)c->last_iters.size() ? c->last_iters[r] : 0;
+  return 0;
+}
+
+int mg_level_info(wmg_ctx *c, int level, int L[4], int *dof, int *nv) {
+  if (!c || level < 0 || level >= c->nl) return set_error(WMG_EINVAL, "level %d", level);
+  for (int i = 0; i < 4; i++) L[i] = c->lv[level].g.L[i];
+  *dof = c->lv[level].dof;
+  *nv = level + 1 < c->nl ? c->lv[level].nv : 0;
+  return 0;
+}
+
+static int check_level(wmg_ctx *c, int level, bool need_coarse) {
+  if (!c) return set_error(WMG_EINVAL, "null context");
+  if (level < 0 || level >= c->nl) return set_error(WMG_EINVAL, "level %d", level);
+  if (need_coarse && level + 1 >= c->nl) return set_error(WMG_EINVAL, "level %d has no coarser level", level);
+  return 0;
+}
+
+// canonical [nrhs][V][dof] <-> level vector layout (FP64)
+static int to_internal(wmg_ctx *c, int l, const double *canon, double2 *dst, int nrhs) {
+  Level &L = c->lv[l];
+  if (L.fine) return spinor_to_soa(L.g, canon, dst, nrhs, c->st);
+  WMG_HIP(hipMemcpyAsync(dst, canon, 16 * (size_t)L.n * nrhs, hipMemcpyDeviceToDevice, c->st));
+  return 0;
+}
+static int from_internal(wmg_ctx *c, int l, const double2 *src, double *canon, int nrhs) {
+  Level &L = c->lv[l];
+  if (L.fine) return spinor_from_soa(L.g, src, canon, nrhs, c->st);
+  WMG_HIP(hipMemcpyAsync(canon, src, 16 * (size_t)L.n * nrhs, hipMemcpyDeviceToDevice, c->st));
+  return 0;
+}
+
+int mg_set_null_vectors(wmg_ctx *c, int level, const double *vecs) {
+  g_err[0] = 0;
+  TRY(check_level(c, level, true));
+  if (!vecs) return set_error(WMG_EINVAL, "null vectors");
+  Level &F = c->lv[level];
+  TRY(to_internal(c, level, vecs, F.vecs, F.nv_max));
+  TRY(build_level(c, level, F.nv_max));
+  TRY(sync(c));
+  return make_low_precision(c);
+}
+
+int mg_get_null_vectors(wmg_ctx *c, int level, double *vecs) {
+  TRY(check_level(c, level, true));
+  Level &F = c->lv[level];
+  TRY(from_internal(c, level, F.vecs, vecs, F.nv));
+  return sync(c);
+}
+
+int mg_get_prolongator(wmg_ctx *c, int level, double *P) {
+  TRY(check_level(c, level, true));
+  Level &F = c->lv[level];
+  void *tmp;
+  TRY(dalloc(&tmp, 16 * (size_t)F.nv * F.n));
+  int rc = P_block_to_vector(F.g, F.dof, F.b, F.nv, F.P64, (double2 *)tmp, F.fine ? 1 : 0, c->st);
+  if (!rc) rc = from_internal(c, level, (double2 *)tmp, P, F.nv);
+  if (!rc) rc = sync(c);
+  (void)hipFree(tmp);
+  return rc;
+}
+
+int mg_get_coarse_links(wmg_ctx *c, int level, double *links) {
+  TRY(check_level(c, level, false));
+  if (level == 0) return set_error(WMG_EINVAL, "level 0 has no coarse links");
+  Level &C = c->lv[level];
+  TRY(coarse_transpose(C.g.V * 9, C.dof, C.Y64, (double2 *)links, c->st));
+  return sync(c);
+}
+
+int mg_restrict(wmg_ctx *c, int level, const double *fine, double *coarse, int nrhs) {
+  TRY(check_level(c, level, true));
+  if (!fine || !coarse || nrhs < 1 || nrhs > c->p.nrhs_max) return set_error(WMG_EINVAL, "bad argument");
+  void *tmp;
+  TRY(level_vec(c, level, P64, VX, &tmp));
+  TRY(to_internal(c, level, fine, (double2 *)tmp, nrhs));
+  TRY(transfer_restrict(c, level, P64, tmp, coarse, nrhs));
+  return sync(c);
+}
+
+int mg_prolong(wmg_ctx *c, int level, const double *coarse, double *fine, int nrhs) {
+  TRY(check_level(c, level, true));
+  if (!fine || !coarse || nrhs < 1 || nrhs > c->p.nrhs_max) return set_error(WMG_EINVAL, "bad argument");
+  void *tmp;
+  TRY(level_vec(c, level, P64, VX, &tmp));
+  TRY(transfer_prolong(c, level, P64, coarse, tmp, nrhs));
+  TRY(from_internal(c, level, (double2 *)tmp, fine, nrhs));
+  return sync(c);
+}
+
+int mg_coarse_apply(wmg_ctx *c, int level, const double *in, double *out, int dagger, int nrhs) {
+  TRY(check_level(c, level, false));
+  if (level == 0) return set_error(WMG_EINVAL, "level 0 is the fine operator");
+  if (!in || !out || nrhs < 1 || nrhs > c->p.nrhs_max) return set_error(WMG_EINVAL, "bad argument");
+  TRY(apply_op(c, level, P64, in, out, nrhs, false, dagger));
+  return sync(c);
+}
+
+int mg_apply_fine(wmg_ctx *c, int prec, const double *in, double *out, int nrhs) {
+  if (!c || !in || !out || nrhs < 1 || nrhs > c->p.nrhs_max || prec < 0 || prec > 2)
+    return set_error(WMG_EINVAL, "bad argument");
+  Level &F = c->lv[0];
+  void *a64, *b64;
+  TRY(level_vec(c, 0, P64, VX, &a64));
+  TRY(level_vec(c, 0, P64, VT, &b64));
+  TRY(spinor_to_soa(F.g, in, (double2 *)a64, nrhs, c->st));
+  if (prec == 0) {
+    TRY(wilson_soa(F.g, P64, F.U[P64], P64, F.m, a64, b64, nrhs, c->st));
+  } else {
+    void *a32, *b32;
+    TRY(level_vec(c, 0, P32, VX, &a32));
+    TRY(level_vec(c, 0, P32, VT, &b32));
+    TRY(copy(P32, a32, P64, a64, F.n, nrhs, c->st));
+    TRY(wilson_soa(F.g, prec == 1 ? P32 : P16, F.U[prec == 1 ? P32 : P16], P32, F.m, a32, b32, nrhs, c->st));
+    TRY(copy(P64, b64, P32, b32, F.n, nrhs, c->st));
+  }
+  TRY(spinor_from_soa(F.g, (double2 *)b64, out, nrhs, c->st));
+  return sync(c);
+}
+
+int mg_cycle(wmg_ctx *c, const double *r, double *z) {
+  if (!c || !r || !z) return set_error(WMG_EINVAL, "bad argument");
+  Level &F = c->lv[0];
+  void *a, *e;
+  TRY(level_vec(c, 0, P64, VX, &a));
+  TRY(level_vec(c, 0, P64, VE2, &e));
+  TRY(spinor_to_soa(F.g, r, (double2 *)a, 1, c->st));
+  TRY(mg_cycle_l(c, 0, P64, a, e, 1));
+  TRY(spinor_from_soa(F.g, (double2 *)e, z, 1, c->st));
+  return sync(c);
+}
+
+int mg_time_dslash(wmg_ctx *c, int prec, int nrhs, int reps, double *ms) {
+  if (!c || !ms || nrhs < 1 || nrhs > c->p.nrhs_max || reps < 1 || prec < 0 || prec > 2)
+    return set_error(WMG_EINVAL, "bad argument");
+  Level &F = c->lv[0];
+  int sp = prec == 0 ? P64 : P32;
+  int lp = prec == 0 ? P64 : (prec == 1 ? P32 : P16);
+  void *a, *b;
+  TRY(level_vec(c, 0, sp, VX, &a));
+  TRY(level_vec(c, 0, sp, VT, &b));
+  void *a64;
+  TRY(level_vec(c, 0, P64, VE2, &a64));
+  TRY(start_vectors(F.g.V, 12, 99, 7, 0, 1, (double2 *)a64, 1, F.g.V, c->st));
+  for (int r = 0; r < nrhs; r++) TRY(copy(sp, (char *)a + csize(sp) * (size_t)F.n * r, P64, a64, F.n, 1, c->st));
+  TRY(wilson_soa(F.g, lp, F.U[lp], sp, F.m, a, b, nrhs, c->st));  // warm-up
+  hipEvent_t e0, e1;
+  WMG_HIP(hipEventCreate(&e0));
+  WMG_HIP(hipEventCreate(&e1));
+  WMG_HIP(hipEventRecord(e0, c->st));
+  for (int i = 0; i < reps; i++) TRY(wilson_soa(F.g, lp, F.U[lp], sp, F.m, (i & 1) ? b : a, (i & 1) ? a : b, nrhs, c->st));
+  WMG_HIP(hipEventRecord(e1, c->st));
+  WMG_HIP(hipEventSynchronize(e1));
+  float t = 0;
+  WMG_HIP(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = t / reps;
+  return 0;
+}
+
+// ------------------------------------------------------------ batch
+int mg_setup_batch(int n, const wmg_geom *g, const double *const *U, const double *m, int Nv, const int block[4],
+                   const wmg_params *p, wmg_ctx **out) {
+  g_err[0] = 0;
+  if (n < 1 || !g || !U || !m || !out) return set_error(WMG_EINVAL, "bad argument");
+  wmg_ctx *parent = new wmg_ctx();
+  if (p) parent->p = *p;
+  else wmg_default_params(&parent->p);
+  for (int i = 0; i < n; i++) {
+    wmg_ctx *c = nullptr;
+    int rc = mg_setup(&g[i], U[i], m[i], Nv, block, p, &c);
+    if (rc) {
+      free_ctx(parent);
+      return rc;
+    }
+    parent->batch.push_back(c);
+  }
+  *out = parent;
+  return 0;
+}
+
+int mg_solve_batch(wmg_ctx *c, const double *const *b, double *const *x, double tol, wmg_stats *st) {
+  if (!c || c->batch.empty() || !b || !x) return set_error(WMG_EINVAL, "not a batch context");
+  int worst = 0;
+  for (size_t i = 0; i < c->batch.size(); i++) {
+    int rc = mg_solve(c->batch[i], b[i], x[i], tol, 1, st ? &st[i] : nullptr);
+    if (rc < 0) return rc;
+    if (rc > worst) worst = rc;
+  }
+  return worst;
+}
+
+}  // extern "C"

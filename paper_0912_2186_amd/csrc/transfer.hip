@@ -1,0 +1,486 @@
+// Inter-grid transfer of the adaptive multigrid (arXiv:0912.2186, Sec. 2-3):
+//   * random start vectors of the adaptive setup (Philox4x32-10)
+//   * block orthonormalisation of the null vectors, Eq. 2.7, split by
+//     chirality so that sigma_3 P = P gamma_5 (Sec. 3)
+//   * restriction r_hat = P^dag r and prolongation e = P e_hat (Eq. 2.3)
+//
+// The prolongator is stored block-major, [alpha][xh][block element], so one
+// workgroup reads the whole aggregate of a coarse site as a contiguous slab.
+// A block element e enumerates (fine site k of the block, component c):
+//   fine lattice (SoA spinors):   e = c * bs + k   (sites fastest)
+//   coarse lattice (AoS vectors): e = k * dof + c  (components fastest)
+// Chirality of component c is c / (dof/2).  In FP16 storage every
+// (alpha, xh, k) site of P carries one FP32 scale (max |re|, |im| of its
+// components), the stored halves being the components divided by it.
+#include "wmg_internal.h"
+
+namespace wmg {
+
+static constexpr int TB = 256;
+
+// ------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+// (SC'11): 10 rounds of two 32x32->64 multiplies with the Weyl key schedule.
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Vector alpha of level lvl: component (s, c) = (int32(w0), int32(w1)) * 2^-31
+// with w = Philox(ctr = (c, s, alpha, lvl), key = seed).  Written in the
+// level's vector layout (fine: SoA [12][V]; coarse: AoS [V][dof]).
+__global__ void k_start_vectors(long nsite, int dof, uint32_t k0, uint32_t k1, int lvl, int alpha0, double2 *out,
+                                int fine_soa) {
+  long i = blockIdx.x * (long)TB + threadIdx.x;
+  int a = blockIdx.y;
+  if (i >= nsite * dof) return;
+  long s, c;
+  if (fine_soa) { c = i / nsite; s = i % nsite; }
+  else { s = i / dof; c = i % dof; }
+  uint32_t w[4] = {(uint32_t)c, (uint32_t)s, (uint32_t)(alpha0 + a), (uint32_t)lvl};
+  philox10(w, k0, k1);
+  out[(size_t)a * nsite * dof + i] = make_double2((double)(int32_t)w[0] * 0x1p-31, (double)(int32_t)w[1] * 0x1p-31);
+}
+
+int start_vectors(long nsite, int dof, uint64_t seed, int lvl, int alpha0, int count, double2 *out, int fine_soa,
+                  long /*V*/, hipStream_t st) {
+  dim3 grid((unsigned)((nsite * dof + TB - 1) / TB), count);
+  hipLaunchKernelGGL(k_start_vectors, grid, dim3(TB), 0, st, nsite, dof, (uint32_t)seed, (uint32_t)(seed >> 32), lvl,
+                     alpha0, out, fine_soa);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+// ------------------------------------------------------------ geometry help
+struct BlockGeom {
+  int L[4], b[4], Lc[4];
+  long V, Vc;
+  int bs, dof;
+};
+
+static BlockGeom make_bg(const Geom &g, int dof, const int b[4]) {
+  BlockGeom bg;
+  for (int i = 0; i < 4; i++) {
+    bg.L[i] = g.L[i];
+    bg.b[i] = b[i];
+    bg.Lc[i] = g.L[i] / b[i];
+  }
+  bg.V = g.V;
+  bg.Vc = (long)bg.Lc[0] * bg.Lc[1] * bg.Lc[2] * bg.Lc[3];
+  bg.bs = b[0] * b[1] * b[2] * b[3];
+  bg.dof = dof;
+  return bg;
+}
+
+// fine site of element k of coarse site xh
+__device__ __forceinline__ long block_site(const BlockGeom &bg, long xh, int k) {
+  int xc[4], x[4];
+  site_coords(bg.Lc, xh, xc);
+  int w0 = k % bg.b[0], r = k / bg.b[0];
+  int w1 = r % bg.b[1]; r /= bg.b[1];
+  int w2 = r % bg.b[2]; int w3 = r / bg.b[2];
+  x[0] = xc[0] * bg.b[0] + w0;
+  x[1] = xc[1] * bg.b[1] + w1;
+  x[2] = xc[2] * bg.b[2] + w2;
+  x[3] = xc[3] * bg.b[3] + w3;
+  return site_index(bg.L, x);
+}
+
+// element e -> (k, c)
+template <int FINE> __device__ __forceinline__ void elem_kc(const BlockGeom &bg, int e, int &k, int &c) {
+  if (FINE) { c = e / bg.bs; k = e % bg.bs; }
+  else { k = e / bg.dof; c = e % bg.dof; }
+}
+
+// address of component c of site s, rhs r, in a level vector
+template <int FINE> __device__ __forceinline__ size_t vec_addr(const BlockGeom &bg, int r, long s, int c) {
+  if (FINE) return ((size_t)r * 12 + c) * bg.V + s;
+  return ((size_t)r * bg.V + s) * bg.dof + c;
+}
+
+// workgroup sum of NV complex numbers held per thread; result in sh_out
+template <int NV>
+__device__ __forceinline__ void wg_csum(cx<double> v[NV], double *sh /* [4][2*NV] */, double *sh_out /* [2*NV] */) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; j++) {
+    double a = v[j].re, b = v[j].im;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_down(a, o, 64);
+      b += __shfl_down(b, o, 64);
+    }
+    if (lane == 0) {
+      sh[w * 2 * NV + 2 * j] = a;
+      sh[w * 2 * NV + 2 * j + 1] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * NV) {
+    double x = 0;
+    for (int q = 0; q < TB / 64; q++) x += sh[q * 2 * NV + threadIdx.x];
+    sh_out[threadIdx.x] = x;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ block Gram-Schmidt
+// One workgroup per (coarse site, chirality).  The nv vectors are gathered
+// into the block-major P slab, then orthonormalised in order, each against
+// the already finished ones with classical Gram-Schmidt applied twice (CGS2,
+// numerically equivalent to modified GS twice), unit norm, positive real
+// diagonal of R.  EPT = elements per thread.
+template <int FINE, int EPT>
+__global__ void __launch_bounds__(TB) k_block_gs(BlockGeom bg, int nv, const double2 *__restrict__ vecs,
+                                                double2 *__restrict__ P, int *fail) {
+  long xh = blockIdx.x;
+  int chi = blockIdx.y;
+  int h = bg.dof / 2;
+  int E = bg.bs * bg.dof;
+  __shared__ double sh[4 * 2 * 8];
+  __shared__ double red[2 * 8];
+  __shared__ double coef[2 * 64];
+  // gather: element list of this chirality for this thread
+  int my_e[EPT];
+  int nmine = 0;
+  for (int e = threadIdx.x, q = 0; q < EPT; q++, e += TB) {
+    my_e[q] = -1;
+    if (e < E) {
+      int k, c;
+      elem_kc<FINE>(bg, e, k, c);
+      if (c / h == chi) my_e[q] = e;
+    }
+  }
+  (void)nmine;
+  for (int a = 0; a < nv; a++) {
+    cx<double> v[EPT];
+    double n0loc = 0;
+#pragma unroll
+    for (int q = 0; q < EPT; q++) {
+      v[q] = czero<double>();
+      if (my_e[q] >= 0) {
+        int k, c;
+        elem_kc<FINE>(bg, my_e[q], k, c);
+        long s = block_site(bg, xh, k);
+        v[q] = ldc(vecs + (size_t)a * bg.V * bg.dof + (FINE ? (size_t)c * bg.V + s : (size_t)s * bg.dof + c));
+        n0loc += v[q].re * v[q].re + v[q].im * v[q].im;
+      }
+    }
+    {
+      cx<double> t[1] = {{n0loc, 0.0}};
+      wg_csum<1>(t, sh, red);
+    }
+    double n0 = red[0];
+    for (int pass = 0; pass < 2; pass++) {
+      // coefficients <q_j, v> for all j < a, in chunks of 8
+      for (int j0 = 0; j0 < a; j0 += 8) {
+        cx<double> d[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++) {
+          d[jj] = czero<double>();
+          int j = j0 + jj;
+          if (j < a) {
+#pragma unroll
+            for (int q = 0; q < EPT; q++)
+              if (my_e[q] >= 0) {
+                cx<double> qj = ldc(P + ((size_t)j * bg.Vc + xh) * E + my_e[q]);
+                d[jj] = cfmac(qj, v[q], d[jj]);
+              }
+          }
+        }
+        wg_csum<8>(d, sh, red);
+        if (threadIdx.x < 16 && j0 * 2 + (int)threadIdx.x < 2 * 64) coef[j0 * 2 + threadIdx.x] = red[threadIdx.x];
+        __syncthreads();
+      }
+      for (int j = 0; j < a; j++) {
+        cx<double> cj = {coef[2 * j], coef[2 * j + 1]};
+#pragma unroll
+        for (int q = 0; q < EPT; q++)
+          if (my_e[q] >= 0) {
+            cx<double> qj = ldc(P + ((size_t)j * bg.Vc + xh) * E + my_e[q]);
+            v[q] = v[q] - cj * qj;
+          }
+      }
+      __syncthreads();
+    }
+    double nl = 0;
+#pragma unroll
+    for (int q = 0; q < EPT; q++) nl += v[q].re * v[q].re + v[q].im * v[q].im;
+    {
+      cx<double> t[1] = {{nl, 0.0}};
+      wg_csum<1>(t, sh, red);
+    }
+    double nn = red[0];
+    if (!(nn > 1e-24 * n0) || n0 == 0) {
+      if (threadIdx.x == 0) atomicOr(fail, 1);
+      nn = 1;
+    }
+    double inv = 1.0 / sqrt(nn);
+#pragma unroll
+    for (int q = 0; q < EPT; q++)
+      if (my_e[q] >= 0) stc(P + ((size_t)a * bg.Vc + xh) * E + my_e[q], inv * v[q]);
+    __syncthreads();
+  }
+}
+
+int block_orthonormalize(const Geom &g, int dof, const int b[4], int nv, const double2 *vecs, int fine_soa, double2 *P,
+                         int *fail_dev, hipStream_t st) {
+  BlockGeom bg = make_bg(g, dof, b);
+  int E = bg.bs * dof;
+  int ept = (E + TB - 1) / TB;
+  if (nv > 64) return set_error(-1, "block_orthonormalize: nv=%d > 64", nv);
+  dim3 grid((unsigned)bg.Vc, 2);
+#define GS_CASE(F, N)                                                                                      \
+  if (fine_soa == F && ept <= N) {                                                                        \
+    hipLaunchKernelGGL((k_block_gs<F, N>), grid, dim3(TB), 0, st, bg, nv, vecs, P, fail_dev);             \
+    WMG_HIP(hipGetLastError());                                                                            \
+    return 0;                                                                                              \
+  }
+  GS_CASE(1, 4) GS_CASE(1, 8) GS_CASE(1, 16) GS_CASE(1, 32)
+  GS_CASE(0, 4) GS_CASE(0, 8) GS_CASE(0, 16) GS_CASE(0, 32)
+#undef GS_CASE
+  return set_error(-1, "block_orthonormalize: block too large (%d elements)", E);
+}
+
+// ------------------------------------------------------------ restriction
+template <class TP> struct pscale {
+  static __device__ __forceinline__ float get(const float *, size_t) { return 1.f; }
+};
+template <> struct pscale<__half2> {
+  static __device__ __forceinline__ float get(const float *s, size_t i) { return s[i]; }
+};
+
+// one workgroup per (coarse site, rhs); alpha processed in chunks of 8
+template <int FINE, int EPT, class TP, class TV>
+__global__ void __launch_bounds__(TB) k_restrict(BlockGeom bg, int nv, const TP *__restrict__ P,
+                                                const float *__restrict__ Pscale, const TV *__restrict__ fine,
+                                                TV *__restrict__ coarse) {
+  using R = typename store_traits<TV>::real;
+  long xh = blockIdx.x;
+  int r = blockIdx.y;
+  int E = bg.bs * bg.dof, h = bg.dof / 2;
+  __shared__ double sh[4 * 2 * 16];
+  __shared__ double red[2 * 16];
+  cx<R> v[EPT];
+  int ch[EPT];
+  size_t sidx[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; q++) {
+    int e = threadIdx.x + q * TB;
+    v[q] = czero<R>();
+    ch[q] = -1;
+    if (e < E) {
+      int k, c;
+      elem_kc<FINE>(bg, e, k, c);
+      long s = block_site(bg, xh, k);
+      auto t = ldc(fine + vec_addr<FINE>(bg, r, s, c));
+      v[q] = {(R)t.re, (R)t.im};
+      ch[q] = c / h;
+      sidx[q] = (size_t)xh * bg.bs + k;
+    }
+  }
+  for (int a0 = 0; a0 < nv; a0 += 8) {
+    cx<double> acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) acc[j] = czero<double>();
+#pragma unroll
+    for (int jj = 0; jj < 8; jj++) {
+      int a = a0 + jj;
+      if (a < nv) {
+#pragma unroll
+        for (int q = 0; q < EPT; q++) {
+          if (ch[q] < 0) continue;
+          int e = threadIdx.x + q * TB;
+          auto p = ldc(P + ((size_t)a * bg.Vc + xh) * E + e);
+          float sc = pscale<TP>::get(Pscale, (size_t)a * bg.Vc * bg.bs + sidx[q]);
+          cx<R> pv = {(R)(sc * p.re), (R)(sc * p.im)};
+          cx<R> t = cmulc(pv, v[q]);
+          if (ch[q] == 0) acc[jj] = acc[jj] + cx<double>{t.re, t.im};
+          else acc[8 + jj] = acc[8 + jj] + cx<double>{t.re, t.im};
+        }
+      }
+    }
+    wg_csum<16>(acc, sh, red);
+    if (threadIdx.x < 16) {
+      int jj = threadIdx.x & 7, chi = threadIdx.x >> 3, a = a0 + jj;
+      if (a < nv)
+        stc(coarse + ((size_t)r * bg.Vc + xh) * (2 * nv) + chi * nv + a,
+            cx<double>{red[2 * threadIdx.x], red[2 * threadIdx.x + 1]});
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ prolongation
+// one workgroup per (coarse site, rhs); one thread per block element
+template <int FINE, int EPT, class TP, class TV>
+__global__ void __launch_bounds__(TB) k_prolong(BlockGeom bg, int nv, const TP *__restrict__ P,
+                                               const float *__restrict__ Pscale, const TV *__restrict__ coarse,
+                                               TV *__restrict__ fine) {
+  using R = typename store_traits<TV>::real;
+  long xh = blockIdx.x;
+  int r = blockIdx.y;
+  int E = bg.bs * bg.dof, h = bg.dof / 2;
+  __shared__ cx<R> ch_s[2 * 64];
+  for (int i = threadIdx.x; i < 2 * nv; i += TB) {
+    auto t = ldc(coarse + ((size_t)r * bg.Vc + xh) * (2 * nv) + i);
+    ch_s[i] = {(R)t.re, (R)t.im};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < EPT; q++) {
+    int e = threadIdx.x + q * TB;
+    if (e >= E) continue;
+    int k, c;
+    elem_kc<FINE>(bg, e, k, c);
+    int chi = c / h;
+    size_t si = (size_t)xh * bg.bs + k;
+    cx<R> acc = czero<R>();
+    for (int a = 0; a < nv; a++) {
+      auto p = ldc(P + ((size_t)a * bg.Vc + xh) * E + e);
+      float sc = pscale<TP>::get(Pscale, (size_t)a * bg.Vc * bg.bs + si);
+      cx<R> pv = {(R)(sc * p.re), (R)(sc * p.im)};
+      acc = cfma(pv, ch_s[chi * nv + a], acc);
+    }
+    long s = block_site(bg, xh, k);
+    stc(fine + vec_addr<FINE>(bg, r, s, c), acc);
+  }
+}
+
+template <int FINE, class TP, class TV>
+static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, const float *Ps, const void *in,
+                           void *out, int nrhs, hipStream_t st) {
+  int E = bg.bs * bg.dof;
+  int ept = (E + TB - 1) / TB;
+  dim3 grid((unsigned)bg.Vc, nrhs);
+#define TR_CASE(N)                                                                                         \
+  if (ept <= N) {                                                                                         \
+    if (dir == 0)                                                                                          \
+      hipLaunchKernelGGL((k_restrict<FINE, N, TP, TV>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps,  \
+                         (const TV *)in, (TV *)out);                                                       \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_prolong<FINE, N, TP, TV>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps,   \
+                         (const TV *)in, (TV *)out);                                                       \
+    WMG_HIP(hipGetLastError());                                                                            \
+    return 0;                                                                                              \
+  }
+  TR_CASE(4) TR_CASE(8) TR_CASE(16) TR_CASE(32)
+#undef TR_CASE
+  return set_error(-1, "transfer: block too large (%d elements)", E);
+}
+
+static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P,
+                    const float *Ps, int vprec, const void *in, void *out, int fine_soa, int nrhs, hipStream_t st) {
+  BlockGeom bg = make_bg(g, dof, b);
+  if (nv > 64) return set_error(-1, "transfer: nv=%d > 64", nv);
+#define TP_CASE(F, TPT, TVT, PP, VP)                                                                       \
+  if (fine_soa == F && pprec == PP && vprec == VP) return launch_transfer<F, TPT, TVT>(dir, bg, nv, P, Ps, in, out, nrhs, st);
+  TP_CASE(1, double2, double2, P64, P64)
+  TP_CASE(1, float2, float2, P32, P32)
+  TP_CASE(1, __half2, float2, P16, P32)
+  TP_CASE(0, double2, double2, P64, P64)
+  TP_CASE(0, float2, float2, P32, P32)
+  TP_CASE(0, __half2, float2, P16, P32)
+#undef TP_CASE
+  return set_error(-1, "transfer: unsupported precisions P=%d v=%d", pprec, vprec);
+}
+
+int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
+                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st) {
+  return transfer(0, g, dof, b, nv, pprec, P, Pscale, vprec, fine, coarse, fine_soa, nrhs, st);
+}
+
+int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
+               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st) {
+  return transfer(1, g, dof, b, nv, pprec, P, Pscale, vprec, coarse, fine, fine_soa, nrhs, st);
+}
+
+// ------------------------------------------------------------ P precision
+// FP64 -> FP32 copy, or FP64 -> FP16 with one scale per (alpha, xh, k) site.
+// count = nv * Vc * bs sites; each has dof components at stride `cstride`
+// and site stride `sstride` in element units (fine: cstride = bs, site
+// stride 1 inside a block; coarse: cstride 1, site stride dof).
+__global__ void k_P_to_half(long nsites, int bs, int dof, int fine, const double2 *__restrict__ P,
+                            __half2 *__restrict__ Ph, float *__restrict__ scale) {
+  long i = blockIdx.x * (long)TB + threadIdx.x;
+  if (i >= nsites) return;
+  long blk = i / bs;
+  int k = (int)(i % bs);
+  size_t base = (size_t)blk * bs * dof;
+  double mx = 0;
+  for (int c = 0; c < dof; c++) {
+    size_t e = base + (fine ? (size_t)c * bs + k : (size_t)k * dof + c);
+    double2 v = P[e];
+    mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+  }
+  float sc = mx > 0 ? (float)mx : 1.f;
+  scale[i] = sc;
+  for (int c = 0; c < dof; c++) {
+    size_t e = base + (fine ? (size_t)c * bs + k : (size_t)k * dof + c);
+    double2 v = P[e];
+    Ph[e] = __floats2half2_rn((float)(v.x / sc), (float)(v.y / sc));
+  }
+}
+
+__global__ void k_P_to_float(size_t n, const double2 *__restrict__ P, float2 *__restrict__ Pf) {
+  size_t i = blockIdx.x * (size_t)TB + threadIdx.x;
+  if (i < n) Pf[i] = make_float2((float)P[i].x, (float)P[i].y);
+}
+
+int P_convert(long nsites_total, const double2 *P64, int pprec, void *Pout, float *scale, int dof, hipStream_t st) {
+  // nsites_total = nv * Vc * bs ; bs passed through `scale == nullptr` path is not needed for FP32
+  (void)dof;
+  if (pprec == P32) {
+    size_t n = (size_t)nsites_total * dof;
+    hipLaunchKernelGGL(k_P_to_float, dim3((unsigned)((n + TB - 1) / TB)), dim3(TB), 0, st, n, P64, (float2 *)Pout);
+    WMG_HIP(hipGetLastError());
+    return 0;
+  }
+  return set_error(-1, "P_convert: use P_convert_half for FP16");
+}
+
+int P_convert_half(long nsites_total, int bs, int dof, int fine, const double2 *P64, __half2 *Ph, float *scale,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_P_to_half, dim3((unsigned)((nsites_total + TB - 1) / TB)), dim3(TB), 0, st, nsites_total, bs,
+                     dof, fine, P64, Ph, scale);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+}  // namespace wmg
+
+namespace wmg {
+// block-major P -> level vector layout (fine SoA [nv][12][V] or coarse AoS
+// [nv][V][dof]) for copying the prolongator out
+__global__ void k_P_to_vec(BlockGeom bg, int nv, int fine, const double2 *__restrict__ P, double2 *__restrict__ vec) {
+  size_t E = (size_t)bg.bs * bg.dof;
+  size_t i = blockIdx.x * (size_t)TB + threadIdx.x;
+  size_t tot = (size_t)nv * bg.Vc * E;
+  if (i >= tot) return;
+  size_t a = i / (bg.Vc * E);
+  long xh = (long)((i / E) % bg.Vc);
+  int e = (int)(i % E);
+  int k, c;
+  if (fine) { c = e / bg.bs; k = e % bg.bs; }
+  else { k = e / bg.dof; c = e % bg.dof; }
+  long s = block_site(bg, xh, k);
+  size_t dst = fine ? (a * 12 + c) * bg.V + s : (a * bg.V + s) * bg.dof + c;
+  vec[dst] = P[i];
+}
+
+int P_block_to_vector(const Geom &g, int dof, const int b[4], int nv, const double2 *P, double2 *vec, int fine_soa,
+                      hipStream_t st) {
+  BlockGeom bg = make_bg(g, dof, b);
+  size_t tot = (size_t)nv * bg.Vc * bg.bs * dof;
+  hipLaunchKernelGGL(k_P_to_vec, dim3((unsigned)((tot + TB - 1) / TB)), dim3(TB), 0, st, bg, nv, fine_soa, P, vec);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+}  // namespace wmg

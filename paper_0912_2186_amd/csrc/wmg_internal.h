@@ -1,0 +1,172 @@
+// Internal declarations of the gfx950 multigrid library (not installed).
+//
+// Layouts in device memory (all chosen for coalesced, site-fastest access):
+//   fine spinor   [rhs][12][V]   complex (double2 / float2), component
+//                 c = spin*3 + colour, lexicographic site s = x+Lx(y+Ly(z+Lz t))
+//   gauge links   [4][9][V]      complex (double2 / float2 / __half2), element
+//                 (mu, 3a+b) of U_mu(s)
+//   coarse vector [rhs][Vc][n]   complex, n = 2 Nv dof per site ordered (chi, alpha)
+//   coarse links  [Vc][9][n][n]  complex, direction d = 0 local, 1+mu forward,
+//                 5+mu backward; row-major within a block
+//   prolongator   [nv][Vc][bs][h2]  block-major: for null vector alpha and
+//                 coarse site xh the bs fine sites of the block in lexicographic
+//                 order inside the block, each with its `dof` components
+//                 (12 on the fine lattice, n on a coarse one)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace wmg {
+
+// ---------------------------------------------------------------- complex
+template <class R> struct cx {
+  R re, im;
+};
+template <class R> __host__ __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R> __host__ __device__ __forceinline__ cx<R> operator*(R a, cx<R> b) { return {a * b.re, a * b.im}; }
+// conj(a) * b
+template <class R> __host__ __device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+__host__ __device__ __forceinline__ float mad(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double mad(double a, double b, double c) { return fma(a, b, c); }
+template <class R> __host__ __device__ __forceinline__ cx<R> cfma(cx<R> a, cx<R> b, cx<R> c) {  // a*b + c
+  return {mad(a.re, b.re, mad(-a.im, b.im, c.re)), mad(a.re, b.im, mad(a.im, b.re, c.im))};
+}
+template <class R> __host__ __device__ __forceinline__ cx<R> cfmac(cx<R> a, cx<R> b, cx<R> c) {  // conj(a)*b + c
+  return {mad(a.re, b.re, mad(a.im, b.im, c.re)), mad(a.re, b.im, mad(-a.im, b.re, c.im))};
+}
+template <class R> __host__ __device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> times_mi(cx<R> a) { return {a.im, -a.re}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> neg(cx<R> a) { return {-a.re, -a.im}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> czero() { return {R(0), R(0)}; }
+
+// storage element <-> arithmetic complex
+__device__ __forceinline__ cx<double> ldc(const double2 *p) { double2 v = *p; return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> ldc(const float2 *p) { float2 v = *p; return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> ldc(const __half2 *p) {
+  float2 v = __half22float2(*p);
+  return {v.x, v.y};
+}
+__device__ __forceinline__ void stc(double2 *p, cx<double> v) { *p = make_double2(v.re, v.im); }
+__device__ __forceinline__ void stc(float2 *p, cx<float> v) { *p = make_float2(v.re, v.im); }
+__device__ __forceinline__ void stc(double2 *p, cx<float> v) { *p = make_double2(v.re, v.im); }
+__device__ __forceinline__ void stc(float2 *p, cx<double> v) { *p = make_float2((float)v.re, (float)v.im); }
+
+template <class S> struct store_traits;
+template <> struct store_traits<double2> { using real = double; };
+template <> struct store_traits<float2> { using real = float; };
+template <> struct store_traits<__half2> { using real = float; };
+
+// ---------------------------------------------------------------- geometry
+struct Geom {
+  int L[4];
+  long V;
+};
+
+__host__ __device__ __forceinline__ void site_coords(const int L[4], long s, int x[4]) {
+  x[0] = (int)(s % L[0]); s /= L[0];
+  x[1] = (int)(s % L[1]); s /= L[1];
+  x[2] = (int)(s % L[2]); s /= L[2];
+  x[3] = (int)s;
+}
+__host__ __device__ __forceinline__ long site_index(const int L[4], const int x[4]) {
+  return x[0] + (long)L[0] * (x[1] + (long)L[1] * (x[2] + (long)L[2] * x[3]));
+}
+
+// Workgroup -> tile remap so that each of the 8 XCDs (which receive
+// workgroups round-robin) walks one contiguous range of tiles; neighbouring
+// tiles then share that XCD's L2.
+// Launch xcd_grid(ntiles) workgroups; tile xcd_tile(blockIdx.x) (skip if
+// >= ntiles).
+static constexpr int NXCD = 8;
+__host__ __device__ __forceinline__ long xcd_grid(long ntiles) { return (ntiles + NXCD - 1) / NXCD * NXCD; }
+__device__ __forceinline__ long xcd_tile(long bid, long grid) { return (bid % NXCD) * (grid / NXCD) + bid / NXCD; }
+
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+
+// ---------------------------------------------------------------- errors
+int set_error(int code, const char *fmt, ...);
+#define WMG_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) return ::wmg::set_error(-3, "%s:%d %s: %s", __FILE__, __LINE__, #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- kernels
+// dslash.hip
+int wilson_canonical(const Geom &g, const double *U, double m, const double *in, double *out, hipStream_t st);
+int wilson_soa(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
+               hipStream_t st);
+int links_to_soa(const Geom &g, const double *Ucanon, int lprec, void *Usoa, hipStream_t st);
+int spinor_to_soa(const Geom &g, const double *canon, double2 *soa, int nrhs, hipStream_t st);
+int spinor_from_soa(const Geom &g, const double2 *soa, double *canon, int nrhs, hipStream_t st);
+
+// blas.hip -- flat complex vectors [nrhs][n]
+struct Reducer {
+  double *partial;    // [nrhs][maxblk][4]
+  unsigned *counter;  // [nrhs]
+  int maxblk;
+  int nrhs_max;
+};
+int red_init(Reducer &r, int nrhs_max);
+void red_free(Reducer &r);
+// out[rhs*stride + 0..1] = <x,y> (re, im)
+int dot(Reducer &R, int prec, const void *x, const void *y, long n, int nrhs, double *out, int out_stride, hipStream_t st);
+int norm2(Reducer &R, int prec, const void *x, long n, int nrhs, double *out, int out_stride, hipStream_t st);
+// out[rhs*stride+0..1] = <x,y>, out[rhs*stride+2] = |x|^2
+int dot_norm(Reducer &R, int prec, const void *x, const void *y, long n, int nrhs, double *out, int out_stride,
+             hipStream_t st);
+int copy(int pdst, void *dst, int psrc, const void *src, long n, int nrhs, hipStream_t st);
+int zero(int prec, void *x, long n, int nrhs, hipStream_t st);
+// y[rhs] += sgn * a[rhs] x[rhs]   (a complex, read from device: a[rhs*astride + 0..1])
+int caxpy_dev(int prec, const double *a, int astride, double sgn, const void *x, void *y, long n, int nrhs,
+              hipStream_t st);
+// y = x + sgn*a*y   (xpay)
+int cxpay_dev(int prec, const void *x, const double *a, int astride, double sgn, void *y, long n, int nrhs,
+              hipStream_t st);
+// y[rhs] = sum_j c[rhs][j] x_j[rhs]  + (accumulate ? y : 0),  x_j given by pointer list (device array)
+int multi_caxpy(int py, void *y, int px, const void *const *xs_dev, int k, const double *c, int cstride, double sgn,
+                int accumulate, long n, int nrhs, hipStream_t st);
+// y = a x + b y (host scalars)
+int axpby(int prec, double a, const void *x, double b, void *y, long n, int nrhs, hipStream_t st);
+// out[rhs][j] = <x_j, y> for j < k
+int multi_dot(Reducer &R, int prec, const void *const *xs_dev, int k, const void *y, long n, int nrhs, double *out,
+              int out_stride, hipStream_t st);
+// y = a - b
+int csub(int prec, const void *a, const void *b, void *y, long n, int nrhs, hipStream_t st);
+// x *= 1/sqrt(nrm2[rhs])  (nrm2 device)
+int scale_inv_sqrt(int prec, void *x, const double *nrm2, int stride, long n, int nrhs, hipStream_t st);
+int sigma3(int prec, void *x, long nsite, int dof, int nrhs, hipStream_t st);
+
+// transfer.hip
+int start_vectors(long nsite, int dof, uint64_t seed, int lvl, int alpha0, int count, double2 *out_soa_or_aos,
+                  int fine_soa, long V, hipStream_t st);
+int block_orthonormalize(const Geom &g, int dof, const int b[4], int nv, const double2 *vecs, int fine_soa,
+                         double2 *P, int *fail_dev, hipStream_t st);
+int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
+                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st);
+int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
+               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st);
+int P_convert(long count, const double2 *P64, int pprec, void *Pout, float *scale, int dof, hipStream_t st);
+int P_convert_half(long nsites_total, int bs, int dof, int fine, const double2 *P64, __half2 *Ph, float *scale,
+                   hipStream_t st);
+int P_block_to_vector(const Geom &g, int dof, const int b[4], int nv, const double2 *P, double2 *vec, int fine_soa,
+                      hipStream_t st);
+
+// coarse.hip
+int coarse_build(const Geom &g, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf, const int b[4],
+                 int nv, const double2 *P, double2 *Yc, double2 *work, hipStream_t st);
+int coarse_apply(const Geom &gc, int n, int yprec, const void *Y, int vprec, const void *in, void *out, int dagger,
+                 int nrhs, hipStream_t st);
+int coarse_shift_diag(long Vc, int n, double2 *Y, double dm, hipStream_t st);
+int coarse_convert(long count, const double2 *Y64, int yprec, void *Yout, hipStream_t st);
+int coarse_transpose(long nblk, int n, const double2 *a, double2 *b, hipStream_t st);
+
+}  // namespace wmg
