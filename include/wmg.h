@@ -122,6 +122,10 @@ int mg_solve(wmg_ctx *ctx, const double *b, double *x, double tol, int nrhs, wmg
  * exactly, since P^dag P = 1 and D(m) = D(0) + m. */
 int mg_set_mass(wmg_ctx *ctx, double m);
 
+/* Switch the solve precision (WMG_FP64 / WMG_MIXED) of a context without
+ * a new setup; the hierarchy is always built in FP64. */
+int mg_set_precision(wmg_ctx *ctx, int precision);
+
 /* Release the context and all its device memory. */
 int mg_destroy(wmg_ctx *ctx);
 
@@ -170,6 +174,22 @@ int mg_last_iters(wmg_ctx *ctx, int *iters, int nrhs);
  * layouts, measured with HIP events on the context stream (Dslash
  * bandwidth measurement).  prec as in mg_apply_fine. */
 int mg_time_dslash(wmg_ctx *ctx, int prec, int nrhs, int reps, double *ms);
+
+/* ---- measurement hooks --------------------------------------------- */
+/* Kernel classes timed by mg_profile. */
+#define WMG_K_DSLASH_CYCLE 0   /* fine operator inside the cycle (FP16 links, FP32 spinors) */
+#define WMG_K_DSLASH_OUTER32 1 /* fine operator of the inner GCR (FP32) */
+#define WMG_K_DSLASH_64 2      /* fine operator in FP64 */
+#define WMG_K_COARSE32 3       /* coarse stencil, FP32 */
+#define WMG_K_COARSE64 4       /* coarse stencil, FP64 */
+#define WMG_K_RESTRICT 5       /* fine -> first coarse level */
+#define WMG_K_PROLONG 6        /* first coarse level -> fine */
+/* enable != 0: from now on record a HIP event pair on the context stream
+ * around every launch of the classes above; resets the accumulators. */
+int mg_profile(wmg_ctx *ctx, int enable);
+/* Launch count, summed event time (ms) and summed algorithmic bytes of one
+ * class since the last mg_profile call. */
+int mg_profile_get(wmg_ctx *ctx, int kind, int *launches, double *total_ms, double *total_bytes);
 
 #ifdef __cplusplus
 }

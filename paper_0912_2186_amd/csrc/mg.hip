@@ -197,9 +197,9 @@ struct Level {
   float2 *P32 = nullptr;
   __half2 *P16 = nullptr;
   float *Ps = nullptr;
-  // work vectors: [prec][name] each [nrhs_alloc][n]
+  // work vectors: [prec][name] each [cap][n_alloc], cap = largest nrhs asked for
   void *w[2][NVW] = {};
-  int w_nrhs = 0;
+  int w_cap[2][NVW] = {};
 };
 
 struct GcrBuf {
@@ -226,14 +226,63 @@ struct wmg_ctx {
   double *mask = nullptr;
   int *flag = nullptr;
   double *hbuf = nullptr;  // pinned host mirror
-  GcrBuf gb[2];            // level 0 (solve), level 1 (setup of a third level)
+  GcrBuf gb[2][2];         // [level 0 / level 1][FP64 / FP32 inner precision]
   std::vector<int> last_iters;
   double setup_s = 0;
   // solve statistics
   long st_fine = 0, st_fine64 = 0, st_coarse = 0, st_rel = 0;
   // batch
   std::vector<wmg_ctx *> batch;
+  // per-kernel-class event timing (mg_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;  // kind of each recorded pair
+  std::vector<double> ev_bytes;
+  int ev_used = 0;           // pairs recorded and not yet resolved
+  double prof_ms[8] = {0}, prof_bytes[8] = {0};
+  long prof_n[8] = {0};
 };
+
+// kernel classes timed by mg_profile
+enum { K_DSLASH_CYCLE = 0, K_DSLASH_OUTER32 = 1, K_DSLASH_64 = 2, K_COARSE32 = 3, K_COARSE64 = 4, K_RESTRICT = 5,
+       K_PROLONG = 6, K_NKIND = 7 };
+static const int EV_CAP = 2048;
+
+static int prof_resolve(wmg_ctx *c) {
+  if (!c->ev_used) return 0;
+  WMG_HIP(hipStreamSynchronize(c->st));
+  for (int i = 0; i < c->ev_used; i++) {
+    float t = 0;
+    WMG_HIP(hipEventElapsedTime(&t, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
+    int k = c->ev_kind[i];
+    c->prof_ms[k] += t;
+    c->prof_bytes[k] += c->ev_bytes[i];
+    c->prof_n[k]++;
+  }
+  c->ev_used = 0;
+  return 0;
+}
+
+// record the start event of a timed launch; returns the pair slot or -1
+static int prof_begin(wmg_ctx *c, int kind, double bytes) {
+  if (!c->prof) return -1;
+  if (c->ev_pool.empty()) {
+    c->ev_pool.resize(2 * EV_CAP);
+    c->ev_kind.resize(EV_CAP);
+    c->ev_bytes.resize(EV_CAP);
+    for (auto &e : c->ev_pool)
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+  }
+  if (c->ev_used == EV_CAP && prof_resolve(c)) return -1;
+  int i = c->ev_used++;
+  c->ev_kind[i] = kind;
+  c->ev_bytes[i] = bytes;
+  (void)hipEventRecord(c->ev_pool[2 * i], c->st);
+  return i;
+}
+static void prof_end(wmg_ctx *c, int slot) {
+  if (slot >= 0) (void)hipEventRecord(c->ev_pool[2 * slot + 1], c->st);
+}
 
 static int dalloc(void **p, size_t bytes) {
   *p = nullptr;
@@ -253,10 +302,18 @@ static int sync(wmg_ctx *c) {
   return 0;
 }
 
-static int level_vec(wmg_ctx *c, int l, int prec, int name, void **out) {
+// work vector `name` of level l for nrhs right-hand sides (grown on demand;
+// a solve uses one nrhs throughout, so pointers stay valid within it)
+static int level_vec(wmg_ctx *c, int l, int prec, int name, void **out, int nrhs) {
   Level &L = c->lv[l];
   int pi = prec == P64 ? 0 : 1;
-  if (!L.w[pi][name]) TRY(dalloc(&L.w[pi][name], csize(prec) * (size_t)L.n_alloc * L.w_nrhs));
+  if (L.w_cap[pi][name] < nrhs) {
+    if (L.w[pi][name]) (void)hipFree(L.w[pi][name]);
+    L.w[pi][name] = nullptr;
+    L.w_cap[pi][name] = 0;
+    TRY(dalloc(&L.w[pi][name], csize(prec) * (size_t)L.n_alloc * nrhs));
+    L.w_cap[pi][name] = nrhs;
+  }
   *out = L.w[pi][name];
   return 0;
 }
@@ -271,24 +328,49 @@ static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int 
     if (dagger) return set_error(-1, "fine adjoint not used");
     c->st_fine++;
     if (prec == P64) c->st_fine64++;
-    return wilson_soa(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, c->st);
+    // algorithmic bytes: 4 links per site + one spinor in and out per rhs
+    double lb = lp == P64 ? 16 : (lp == P32 ? 8 : 4), sb = prec == P64 ? 16 : 8;
+    int kind = prec == P64 ? K_DSLASH_64 : (lowlinks ? K_DSLASH_CYCLE : K_DSLASH_OUTER32);
+    int slot = prof_begin(c, kind, (double)L.g.V * (36 * lb + 24.0 * sb * nrhs));
+    int rc = wilson_soa(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, c->st);
+    prof_end(c, slot);
+    return rc;
   }
   int n = L.dof;
-  return coarse_apply(L.g, n, prec, prec == P64 ? (const void *)L.Y64 : (const void *)L.Y32, prec, in, out, dagger,
-                      nrhs, c->st);
+  double yb = prec == P64 ? 16 : 8;
+  int slot = prof_begin(c, prec == P64 ? K_COARSE64 : K_COARSE32,
+                        (double)L.g.V * (9.0 * n * n * yb + 2.0 * n * yb * nrhs));
+  int rc = coarse_apply(L.g, n, prec, prec == P64 ? (const void *)L.Y64 : (const void *)L.Y32, prec, in, out, dagger,
+                        nrhs, c->st);
+  prof_end(c, slot);
+  return rc;
 }
 
+// algorithmic bytes of one transfer: P once (plus FP16 scales) and the fine
+// vectors of every rhs (coarse vectors are negligible)
+static double transfer_bytes(const Level &L, int prec, int nrhs) {
+  double pb = prec == P64 ? 16 : 4, vb = prec == P64 ? 16 : 8;
+  double b = (double)L.nv * L.n * pb + (double)L.n * vb * nrhs;
+  if (prec != P64) b += 4.0 * L.nv * L.g.V;
+  return b;
+}
 static int transfer_restrict(wmg_ctx *c, int l, int prec, const void *fine, void *coarse, int nrhs) {
   Level &L = c->lv[l];
   int pp = prec == P64 ? P64 : P16;
   const void *P = prec == P64 ? (const void *)L.P64 : (const void *)L.P16;
-  return restrict_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, fine, L.fine ? 1 : 0, coarse, nrhs, c->st);
+  int slot = l == 0 ? prof_begin(c, K_RESTRICT, transfer_bytes(L, prec, nrhs)) : -1;
+  int rc = restrict_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, fine, L.fine ? 1 : 0, coarse, nrhs, c->st);
+  prof_end(c, slot);
+  return rc;
 }
 static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, void *fine, int nrhs) {
   Level &L = c->lv[l];
   int pp = prec == P64 ? P64 : P16;
   const void *P = prec == P64 ? (const void *)L.P64 : (const void *)L.P16;
-  return prolong_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, coarse, fine, L.fine ? 1 : 0, nrhs, c->st);
+  int slot = l == 0 ? prof_begin(c, K_PROLONG, transfer_bytes(L, prec, nrhs)) : -1;
+  int rc = prolong_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, coarse, fine, L.fine ? 1 : 0, nrhs, c->st);
+  prof_end(c, slot);
+  return rc;
 }
 
 // ------------------------------------------------------------ MR smoother
@@ -296,8 +378,8 @@ static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, voi
 static int mr_smooth(wmg_ctx *c, int l, int prec, const void *r, void *e, int nsteps, int nrhs) {
   Level &L = c->lv[l];
   void *s, *q;
-  TRY(level_vec(c, l, prec, VS, &s));
-  TRY(level_vec(c, l, prec, VQ, &q));
+  TRY(level_vec(c, l, prec, VS, &s, nrhs));
+  TRY(level_vec(c, l, prec, VQ, &q, nrhs));
   TRY(apply_op(c, l, prec, e, q, nrhs, true));
   TRY(csub(prec, r, q, s, L.n, nrhs, c->st));
   for (int k = 0; k < nsteps; k++) {
@@ -321,10 +403,10 @@ static int mr_smooth(wmg_ctx *c, int l, int prec, const void *r, void *e, int ns
 static int cgnr(wmg_ctx *c, int l, int prec, const void *b, void *x, int nrhs) {
   Level &L = c->lv[l];
   void *r, *s, *p, *u;
-  TRY(level_vec(c, l, prec, VCR, &r));
-  TRY(level_vec(c, l, prec, VCS, &s));
-  TRY(level_vec(c, l, prec, VCP, &p));
-  TRY(level_vec(c, l, prec, VCU, &u));
+  TRY(level_vec(c, l, prec, VCR, &r, nrhs));
+  TRY(level_vec(c, l, prec, VCS, &s, nrhs));
+  TRY(level_vec(c, l, prec, VCP, &p, nrhs));
+  TRY(level_vec(c, l, prec, VCU, &u, nrhs));
   double tol = c->p.coarse_tol;
   TRY(zero(prec, x, L.n, nrhs, c->st));
   TRY(copy(prec, r, prec, b, L.n, nrhs, c->st));
@@ -381,8 +463,8 @@ static int cgnr(wmg_ctx *c, int l, int prec, const void *b, void *x, int nrhs) {
 static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int nrhs) {
   Level &C = c->lv[l + 1];
   void *rc, *ec;
-  TRY(level_vec(c, l + 1, prec, VR, &rc));
-  TRY(level_vec(c, l + 1, prec, VE, &ec));
+  TRY(level_vec(c, l + 1, prec, VR, &rc, nrhs));
+  TRY(level_vec(c, l + 1, prec, VE, &ec, nrhs));
   TRY(transfer_restrict(c, l, prec, r, rc, nrhs));
   if (l + 1 == c->nl_cur - 1) {
     TRY(cgnr(c, l + 1, prec, rc, ec, nrhs));
@@ -390,8 +472,8 @@ static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int n
     TRY(mg_cycle_l(c, l + 1, prec, rc, ec, nrhs));
     if (c->p.cycle == WMG_WCYCLE) {
       void *t, *e2;
-      TRY(level_vec(c, l + 1, prec, VT, &t));
-      TRY(level_vec(c, l + 1, prec, VE2, &e2));
+      TRY(level_vec(c, l + 1, prec, VT, &t, nrhs));
+      TRY(level_vec(c, l + 1, prec, VE2, &e2, nrhs));
       TRY(apply_op(c, l + 1, prec, ec, t, nrhs, true));
       TRY(csub(prec, rc, t, t, C.n, nrhs, c->st));
       TRY(mg_cycle_l(c, l + 1, prec, t, e2, nrhs));
@@ -406,7 +488,7 @@ static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int n
 // ------------------------------------------------------------ GCR buffers
 static int gcr_buffers(wmg_ctx *c, int l, int prec, int nrhs, GcrBuf **out) {
   int slot = (l == 0 ? 0 : 1);
-  GcrBuf &B = c->gb[slot];
+  GcrBuf &B = c->gb[slot][prec == P64 ? 0 : 1];
   Level &L = c->lv[l];
   long nalloc = L.g.V * (L.fine ? 12 : 2 * c->lv[l - 1].nv_max);
   bool ok = B.x64 && B.prec == prec && B.nrhs >= nrhs && B.n >= nalloc;
@@ -649,7 +731,8 @@ static void free_ctx(wmg_ctx *c) {
       for (int k = 0; k < NVW; k++)
         if (L.w[a][k]) (void)hipFree(L.w[a][k]);
   }
-  for (auto &B : c->gb) {
+  for (auto &Bl : c->gb)
+  for (auto &B : Bl) {
     for (int k = 0; k < KMAX; k++) {
       if (B.z[k]) (void)hipFree(B.z[k]);
       if (B.wv[k]) (void)hipFree(B.wv[k]);
@@ -659,6 +742,7 @@ static void free_ctx(wmg_ctx *c) {
       if (p) (void)hipFree(p);
     if (B.prec != P64 && B.rin) (void)hipFree(B.rin);
   }
+  for (auto &e : c->ev_pool) (void)hipEventDestroy(e);
   red_free(c->red);
   if (c->dsc) (void)hipFree(c->dsc);
   if (c->flag) (void)hipFree(c->flag);
@@ -790,7 +874,6 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
     F.dof = 12;
     F.n = F.n_alloc = F.g.V * 12;
     F.m = m;
-    F.w_nrhs = p.nrhs_max;
     CK(dalloc(&F.U[P64], 16 * 36 * (size_t)F.g.V));
     CK(links_to_soa(F.g, U, P64, F.U[P64], c->st));
     CK(dalloc(&F.U[P32], 8 * 36 * (size_t)F.g.V));
@@ -810,7 +893,6 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
       C.dof = 2 * A.nv_max;
       C.n = C.n_alloc = C.g.V * C.dof;
       C.m = m;
-      C.w_nrhs = p.nrhs_max;
       CK(dalloc((void **)&C.Y64, 16 * (size_t)C.g.V * 9 * C.dof * C.dof));
     }
   }
@@ -860,7 +942,7 @@ int mg_solve(wmg_ctx *c, const double *b, double *x, double tol, int nrhs, wmg_s
   c->st_fine = c->st_fine64 = c->st_coarse = c->st_rel = 0;
   int ip = c->p.precision == WMG_MIXED ? P32 : P64;
   GcrBuf *B;
-  TRY(gcr_buffers(c, 0, ip, c->p.nrhs_max, &B));
+  TRY(gcr_buffers(c, 0, ip, nrhs, &B));
   Level &F = c->lv[0];
   TRY(spinor_to_soa(F.g, b, B->b64, nrhs, c->st));
   bool x0 = (c->p.flags & WMG_X0_GIVEN) != 0;
@@ -965,7 +1047,7 @@ int mg_restrict(wmg_ctx *c, int level, const double *fine, double *coarse, int n
   TRY(check_level(c, level, true));
   if (!fine || !coarse || nrhs < 1 || nrhs > c->p.nrhs_max) return set_error(WMG_EINVAL, "bad argument");
   void *tmp;
-  TRY(level_vec(c, level, P64, VX, &tmp));
+  TRY(level_vec(c, level, P64, VX, &tmp, nrhs));
   TRY(to_internal(c, level, fine, (double2 *)tmp, nrhs));
   TRY(transfer_restrict(c, level, P64, tmp, coarse, nrhs));
   return sync(c);
@@ -975,7 +1057,7 @@ int mg_prolong(wmg_ctx *c, int level, const double *coarse, double *fine, int nr
   TRY(check_level(c, level, true));
   if (!fine || !coarse || nrhs < 1 || nrhs > c->p.nrhs_max) return set_error(WMG_EINVAL, "bad argument");
   void *tmp;
-  TRY(level_vec(c, level, P64, VX, &tmp));
+  TRY(level_vec(c, level, P64, VX, &tmp, nrhs));
   TRY(transfer_prolong(c, level, P64, coarse, tmp, nrhs));
   TRY(from_internal(c, level, (double2 *)tmp, fine, nrhs));
   return sync(c);
@@ -994,15 +1076,15 @@ int mg_apply_fine(wmg_ctx *c, int prec, const double *in, double *out, int nrhs)
     return set_error(WMG_EINVAL, "bad argument");
   Level &F = c->lv[0];
   void *a64, *b64;
-  TRY(level_vec(c, 0, P64, VX, &a64));
-  TRY(level_vec(c, 0, P64, VT, &b64));
+  TRY(level_vec(c, 0, P64, VX, &a64, nrhs));
+  TRY(level_vec(c, 0, P64, VT, &b64, nrhs));
   TRY(spinor_to_soa(F.g, in, (double2 *)a64, nrhs, c->st));
   if (prec == 0) {
     TRY(wilson_soa(F.g, P64, F.U[P64], P64, F.m, a64, b64, nrhs, c->st));
   } else {
     void *a32, *b32;
-    TRY(level_vec(c, 0, P32, VX, &a32));
-    TRY(level_vec(c, 0, P32, VT, &b32));
+    TRY(level_vec(c, 0, P32, VX, &a32, nrhs));
+    TRY(level_vec(c, 0, P32, VT, &b32, nrhs));
     TRY(copy(P32, a32, P64, a64, F.n, nrhs, c->st));
     TRY(wilson_soa(F.g, prec == 1 ? P32 : P16, F.U[prec == 1 ? P32 : P16], P32, F.m, a32, b32, nrhs, c->st));
     TRY(copy(P64, b64, P32, b32, F.n, nrhs, c->st));
@@ -1015,8 +1097,8 @@ int mg_cycle(wmg_ctx *c, const double *r, double *z) {
   if (!c || !r || !z) return set_error(WMG_EINVAL, "bad argument");
   Level &F = c->lv[0];
   void *a, *e;
-  TRY(level_vec(c, 0, P64, VX, &a));
-  TRY(level_vec(c, 0, P64, VE2, &e));
+  TRY(level_vec(c, 0, P64, VX, &a, 1));
+  TRY(level_vec(c, 0, P64, VE2, &e, 1));
   TRY(spinor_to_soa(F.g, r, (double2 *)a, 1, c->st));
   TRY(mg_cycle_l(c, 0, P64, a, e, 1));
   TRY(spinor_from_soa(F.g, (double2 *)e, z, 1, c->st));
@@ -1030,10 +1112,10 @@ int mg_time_dslash(wmg_ctx *c, int prec, int nrhs, int reps, double *ms) {
   int sp = prec == 0 ? P64 : P32;
   int lp = prec == 0 ? P64 : (prec == 1 ? P32 : P16);
   void *a, *b;
-  TRY(level_vec(c, 0, sp, VX, &a));
-  TRY(level_vec(c, 0, sp, VT, &b));
+  TRY(level_vec(c, 0, sp, VX, &a, nrhs));
+  TRY(level_vec(c, 0, sp, VT, &b, nrhs));
   void *a64;
-  TRY(level_vec(c, 0, P64, VE2, &a64));
+  TRY(level_vec(c, 0, P64, VE2, &a64, 1));
   TRY(start_vectors(F.g.V, 12, 99, 7, 0, 1, (double2 *)a64, 1, F.g.V, c->st));
   for (int r = 0; r < nrhs; r++) TRY(copy(sp, (char *)a + csize(sp) * (size_t)F.n * r, P64, a64, F.n, 1, c->st));
   TRY(wilson_soa(F.g, lp, F.U[lp], sp, F.m, a, b, nrhs, c->st));  // warm-up
@@ -1049,6 +1131,33 @@ int mg_time_dslash(wmg_ctx *c, int prec, int nrhs, int reps, double *ms) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *ms = t / reps;
+  return 0;
+}
+
+int mg_set_precision(wmg_ctx *c, int precision) {
+  if (!c || (precision != WMG_FP64 && precision != WMG_MIXED)) return set_error(WMG_EINVAL, "bad argument");
+  c->p.precision = precision;
+  return make_low_precision(c);
+}
+
+int mg_profile(wmg_ctx *c, int enable) {
+  if (!c) return set_error(WMG_EINVAL, "null context");
+  TRY(prof_resolve(c));
+  c->prof = enable != 0;
+  for (int k = 0; k < 8; k++) {
+    c->prof_ms[k] = c->prof_bytes[k] = 0;
+    c->prof_n[k] = 0;
+  }
+  return 0;
+}
+
+int mg_profile_get(wmg_ctx *c, int kind, int *launches, double *total_ms, double *total_bytes) {
+  if (!c || kind < 0 || kind >= K_NKIND || !launches || !total_ms || !total_bytes)
+    return set_error(WMG_EINVAL, "bad argument");
+  TRY(prof_resolve(c));
+  *launches = (int)c->prof_n[kind];
+  *total_ms = c->prof_ms[kind];
+  *total_bytes = c->prof_bytes[kind];
   return 0;
 }
 

@@ -92,6 +92,7 @@ _sig = {
     "mg_setup": (_i, [_P(Geom), _vp, _d, _i, _P(ctypes.c_int * 4), _P(Params), _P(_vp)]),
     "mg_solve": (_i, [_vp, _vp, _vp, _d, _i, _P(Stats)]),
     "mg_set_mass": (_i, [_vp, _d]),
+    "mg_set_precision": (_i, [_vp, _i]),
     "mg_destroy": (_i, [_vp]),
     "bicgstab_solve": (_i, [_P(Geom), _vp, _d, _vp, _vp, _d, _i, _P(Stats)]),
     "mg_setup_batch": (_i, [_i, _P(Geom), _P(_vp), _P(_d), _i, _P(ctypes.c_int * 4), _P(Params), _P(_vp)]),
@@ -108,7 +109,11 @@ _sig = {
     "mg_cycle": (_i, [_vp, _vp, _vp]),
     "mg_last_iters": (_i, [_vp, _P(_i), _i]),
     "mg_time_dslash": (_i, [_vp, _i, _i, _i, _P(_d)]),
+    "mg_profile": (_i, [_vp, _i]),
+    "mg_profile_get": (_i, [_vp, _i, _P(_i), _P(_d), _P(_d)]),
 }
+KERNEL_KINDS = {"dslash_cycle": 0, "dslash_outer32": 1, "dslash_fp64": 2, "coarse_fp32": 3, "coarse_fp64": 4,
+                "restrict": 5, "prolong": 6}
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
@@ -208,6 +213,9 @@ class MG:
     def mg_set_mass(self, m: float) -> None:
         _check(_lib.mg_set_mass(self.h, float(m)))
 
+    def mg_set_precision(self, precision: int) -> None:
+        _check(_lib.mg_set_precision(self.h, int(precision)))
+
     def level_info(self, level: int):
         L = (ctypes.c_int * 4)()
         dof = ctypes.c_int()
@@ -256,6 +264,16 @@ class MG:
         arr = (ctypes.c_int * nrhs)()
         _check(_lib.mg_last_iters(self.h, arr, int(nrhs)))
         return list(arr)
+
+    def mg_profile(self, enable: bool) -> None:
+        _check(_lib.mg_profile(self.h, int(bool(enable))))
+
+    def mg_profile_get(self, kind: int):
+        n = ctypes.c_int()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(_lib.mg_profile_get(self.h, int(kind), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value
 
     def mg_time_dslash(self, prec: int, nrhs: int = 1, reps: int = 20) -> float:
         ms = ctypes.c_double()
