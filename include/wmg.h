@@ -162,6 +162,9 @@ int mg_restrict(wmg_ctx *ctx, int level, const double *fine, double *coarse, int
 int mg_prolong(wmg_ctx *ctx, int level, const double *coarse, double *fine, int nrhs);
 /* FP64 coarse operator (or its adjoint) at level >= 1. */
 int mg_coarse_apply(wmg_ctx *ctx, int level, const double *in, double *out, int dagger, int nrhs);
+/* The same through the FP32 coarse operator of a mixed-precision context
+ * (matrix-core kernel for n <= 64); canonical FP64 in/out. */
+int mg_coarse_apply_f32(wmg_ctx *ctx, int level, const double *in, double *out, int dagger, int nrhs);
 /* Fine operator through the internal kernels: prec 0 FP64, 1 FP32 links and
  * spinors, 2 FP16 links with FP32 spinors; canonical FP64 in/out. */
 int mg_apply_fine(wmg_ctx *ctx, int prec, const double *in, double *out, int nrhs);

@@ -418,4 +418,143 @@ int coarse_transpose(long nblk, int n, const double2 *a, double2 *b, hipStream_t
   return 0;
 }
 
+
+// ------------------------------------------------------------ MFMA apply
+// Multi-RHS coarse stencil on the matrix cores.  Per coarse site and
+// direction the complex block product C = Y B (Y: n x n link block, B: the
+// neighbour's n x R vectors of R right-hand sides) is written as one real
+// GEMM without duplicating the links:
+//   [Cr | Ci] (n x 2R) = [Yr | Yi] (n x 2n) . [[Br, Bi], [-Bi, Br]] (2n x 2R)
+// and accumulated over the nine directions with v_mfma_f32_16x16x4f32.  One
+// workgroup per site, one wavefront per 16-row tile of the output.  The A
+// operand streams from a pre-swizzled FP32 copy of the links laid out
+// [site][d][k-step][row tile][lane] (one coalesced 256-byte load per
+// wavefront and k-step, every link byte read once); the B operand of each
+// direction is staged in LDS.  Lane layout of the 16x16x4 instruction: lane
+// l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register v of lane
+// l holds C[4*(l/16)+v][l%16].
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__global__ void k_Y_to_mfma(long Vc, int n, int MT, const double2 *__restrict__ Y, float *__restrict__ Ym) {
+  size_t i = blockIdx.x * (size_t)TB + threadIdx.x;
+  size_t per_site_d = (size_t)(n / 2) * MT * 64;
+  size_t tot = (size_t)Vc * 9 * per_site_d;
+  if (i >= tot) return;
+  size_t sd = i / per_site_d;  // site*9 + d
+  size_t rem = i % per_site_d;
+  int ks = (int)(rem / (MT * 64)), mt = (int)((rem / 64) % MT), lane = (int)(rem % 64);
+  int row = mt * 16 + lane % 16, kk = ks * 4 + lane / 16;
+  float v = 0.f;
+  if (row < n) {
+    int col = kk < n ? kk : kk - n;
+    double2 y = Y[(sd * n + col) * n + row];  // internal [site][d][col][row]
+    v = (float)(kk < n ? y.x : y.y);
+  }
+  Ym[i] = v;
+}
+
+int coarse_to_mfma(long Vc, int n, const double2 *Y64, float *Ym, hipStream_t st) {
+  int MT = (n + 15) / 16;
+  size_t tot = (size_t)Vc * 9 * (n / 2) * MT * 64;
+  hipLaunchKernelGGL(k_Y_to_mfma, dim3((unsigned)((tot + TB - 1) / TB)), dim3(TB), 0, st, Vc, n, MT, Y64, Ym);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+size_t coarse_mfma_floats(long Vc, int n) { return (size_t)Vc * 9 * (n / 2) * ((n + 15) / 16) * 64; }
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_coarse_apply_mfma(const float *__restrict__ Ym, const float2 *__restrict__ in,
+                                                          float2 *__restrict__ out, int L0, int L1, int L2, int L3,
+                                                          long Vc, int n, int nrhs, int dagger) {
+  constexpr int LD = NT * 16 + ((NT % 2 == 0) ? 16 : 0);  // LDS row stride (bank spread)
+  extern __shared__ float Bs[];                            // [2n][LD]
+  const int MT = (n + 15) / 16;
+  long xh = blockIdx.x;
+  int r0 = blockIdx.y * 32;
+  int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
+  int mt = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int L[4] = {L0, L1, L2, L3};
+  int x[4];
+  site_coords(L, xh, x);
+  long nb[9];
+  nb[0] = xh;
+  for (int mu = 0; mu < 4; mu++) {
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    y[mu] = (x[mu] + 1) % L[mu];
+    nb[1 + mu] = site_index(L, y);
+    y[mu] = (x[mu] - 1 + L[mu]) % L[mu];
+    nb[5 + mu] = site_index(L, y);
+  }
+  const int h = n / 2, K = 2 * n, NC = NT * 16;
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int d = 0; d < 9; d++) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < K * NC; idx += blockDim.x) {
+      int kk = idx / NC, j = idx % NC;
+      float val = 0.f;
+      if (j < 2 * R) {
+        int col = kk < n ? kk : kk - n;
+        int r = j < R ? j : j - R;
+        float2 v = in[((size_t)(r0 + r) * Vc + nb[d]) * n + col];
+        if (dagger && col >= h) { v.x = -v.x; v.y = -v.y; }
+        if (kk < n) val = j < R ? v.x : v.y;
+        else val = j < R ? -v.y : v.x;
+      }
+      Bs[kk * LD + j] = val;
+    }
+    __syncthreads();
+    if (mt < MT) {
+      const float *Ad = Ym + ((size_t)xh * 9 + d) * (size_t)(n / 2) * MT * 64;
+      const int krow = lane >> 4, jc = lane & 15;
+      for (int ks = 0; ks < n / 2; ks++) {
+        float a = Ad[((size_t)ks * MT + mt) * 64 + lane];
+        const float *brow = Bs + (ks * 4 + krow) * LD + jc;
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, brow[t * 16], acc[t], 0, 0, 0);
+      }
+    }
+  }
+  if (mt >= MT) return;
+  float *of = (float *)out;
+#pragma unroll
+  for (int t = 0; t < NT; t++)
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      int row = mt * 16 + 4 * (lane >> 4) + v, j = t * 16 + (lane & 15);
+      if (row < n && j < 2 * R) {
+        int r = j < R ? j : j - R;
+        float val = acc[t][v];
+        if (dagger && row >= h) val = -val;
+        of[2 * (((size_t)(r0 + r) * Vc + xh) * n + row) + (j < R ? 0 : 1)] = val;
+      }
+    }
+}
+
+int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, float2 *out, int dagger, int nrhs,
+                      hipStream_t st) {
+  if (n > 64 || (n & 1)) return set_error(-1, "coarse_apply_mfma: n=%d (even, <= 64)", n);
+  int MT = (n + 15) / 16;
+  int rmax = nrhs < 32 ? nrhs : 32;
+  int NT = (2 * rmax + 15) / 16;
+  dim3 grid((unsigned)gc.V, (nrhs + 31) / 32);
+  dim3 blk(64 * MT);
+  int LD = NT * 16 + ((NT % 2 == 0) ? 16 : 0);
+  size_t lds = sizeof(float) * 2 * n * LD;
+  switch (NT) {
+#define NT_CASE(N)                                                                                              \
+  case N:                                                                                                      \
+    hipLaunchKernelGGL((k_coarse_apply_mfma<N>), grid, blk, lds, st, Ym, in, out, gc.L[0], gc.L[1], gc.L[2],    \
+                       gc.L[3], gc.V, n, nrhs, dagger);                                                       \
+    break;
+    NT_CASE(1) NT_CASE(2) NT_CASE(3) NT_CASE(4)
+#undef NT_CASE
+    default: return set_error(-1, "coarse_apply_mfma: NT=%d", NT);
+  }
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
 }  // namespace wmg

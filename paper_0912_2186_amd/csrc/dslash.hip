@@ -70,12 +70,15 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
                                                    float diagf, double diagd, int nrhs) {
   using R = typename store_traits<TS>::real;
   const R diag = sizeof(R) == 8 ? (R)diagd : (R)diagf;
-  long ntile = (V + 255) / 256;
+  // tiles = (site tile, rhs tile) with the rhs tile fastest, so the rhs
+  // tiles of one site tile run back to back on one XCD and share its links
+  int nrt = (nrhs + RT - 1) / RT;
+  long ntile = (V + 255) / 256 * nrt;
   long tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntile) return;
-  long s = tile * 256 + threadIdx.x;
+  long s = (tile / nrt) * 256 + threadIdx.x;
   if (s >= V) return;
-  int r0 = blockIdx.y * RT;
+  int r0 = (int)(tile % nrt) * RT;
   const int L[4] = {L0, L1, L2, L3};
   int x[4];
   site_coords(L, s, x);
@@ -146,9 +149,9 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
 
 template <class TL, class TS>
 static void launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, hipStream_t st) {
-  long ntile = (g.V + 255) / 256;
   constexpr int RT = sizeof(TS) == 16 ? 1 : 2;
-  dim3 grid((unsigned)xcd_grid(ntile), (nrhs + RT - 1) / RT);
+  long ntile = (g.V + 255) / 256 * ((nrhs + RT - 1) / RT);
+  dim3 grid((unsigned)xcd_grid(ntile));
   hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT>), grid, dim3(256), 0, st, (const TL *)U, (const TS *)in, (TS *)out,
                      g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs);
 }

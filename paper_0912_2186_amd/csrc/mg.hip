@@ -188,7 +188,9 @@ struct Level {
   double m = 0;
   // coarse operator (internal layout)
   double2 *Y64 = nullptr;
-  float2 *Y32 = nullptr;
+  float2 *Y32 = nullptr;  // FP32 copy for the vector-FMA stencil (n > 64)
+  float *Ym = nullptr;    // FP32 copy swizzled for the MFMA stencil (n <= 64)
+  int dof_max = 0;
   // transfer to level+1
   int b[4] = {1, 1, 1, 1};
   int nv = 0, nv_max = 0;
@@ -340,8 +342,12 @@ static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int 
   double yb = prec == P64 ? 16 : 8;
   int slot = prof_begin(c, prec == P64 ? K_COARSE64 : K_COARSE32,
                         (double)L.g.V * (9.0 * n * n * yb + 2.0 * n * yb * nrhs));
-  int rc = coarse_apply(L.g, n, prec, prec == P64 ? (const void *)L.Y64 : (const void *)L.Y32, prec, in, out, dagger,
-                        nrhs, c->st);
+  int rc;
+  if (prec == P32 && L.Ym)
+    rc = coarse_apply_mfma(L.g, n, L.Ym, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st);
+  else
+    rc = coarse_apply(L.g, n, prec, prec == P64 ? (const void *)L.Y64 : (const void *)L.Y32, prec, in, out, dagger,
+                      nrhs, c->st);
   prof_end(c, slot);
   return rc;
 }
@@ -682,9 +688,14 @@ static int make_low_precision(wmg_ctx *c) {
   }
   for (int l = 1; l < c->nl; l++) {
     Level &C = c->lv[l];
-    long cnt = C.g.V * 9L * C.dof * C.dof;
-    if (!C.Y32) TRY(dalloc((void **)&C.Y32, 8 * (size_t)C.g.V * 9 * C.dof * C.dof));
-    TRY(coarse_convert(cnt, C.Y64, P32, C.Y32, c->st));
+    if (C.dof_max <= 64) {
+      if (!C.Ym) TRY(dalloc((void **)&C.Ym, sizeof(float) * coarse_mfma_floats(C.g.V, C.dof_max)));
+      TRY(coarse_to_mfma(C.g.V, C.dof, C.Y64, C.Ym, c->st));
+    } else {
+      long cnt = C.g.V * 9L * C.dof * C.dof;
+      if (!C.Y32) TRY(dalloc((void **)&C.Y32, 8 * (size_t)C.g.V * 9 * C.dof_max * C.dof_max));
+      TRY(coarse_convert(cnt, C.Y64, P32, C.Y32, c->st));
+    }
   }
   return sync(c);
 }
@@ -724,7 +735,7 @@ static void free_ctx(wmg_ctx *c) {
     Level &L = c->lv[l];
     for (int i = 0; i < 3; i++)
       if (L.U[i]) (void)hipFree(L.U[i]);
-    void *ps[] = {L.Y64, L.Y32, L.vecs, L.P64, L.P32, L.P16, L.Ps};
+    void *ps[] = {L.Y64, L.Y32, L.Ym, L.vecs, L.P64, L.P32, L.P16, L.Ps};
     for (void *p : ps)
       if (p) (void)hipFree(p);
     for (int a = 0; a < 2; a++)
@@ -890,7 +901,7 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
       for (int i = 0; i < 4; i++) Lc[i] = A.g.L[i] / A.b[i];
       C.g = to_geom(Lc);
       C.fine = false;
-      C.dof = 2 * A.nv_max;
+      C.dof = C.dof_max = 2 * A.nv_max;
       C.n = C.n_alloc = C.g.V * C.dof;
       C.m = m;
       CK(dalloc((void **)&C.Y64, 16 * (size_t)C.g.V * 9 * C.dof * C.dof));
@@ -1068,6 +1079,21 @@ int mg_coarse_apply(wmg_ctx *c, int level, const double *in, double *out, int da
   if (level == 0) return set_error(WMG_EINVAL, "level 0 is the fine operator");
   if (!in || !out || nrhs < 1 || nrhs > c->p.nrhs_max) return set_error(WMG_EINVAL, "bad argument");
   TRY(apply_op(c, level, P64, in, out, nrhs, false, dagger));
+  return sync(c);
+}
+
+int mg_coarse_apply_f32(wmg_ctx *c, int level, const double *in, double *out, int dagger, int nrhs) {
+  TRY(check_level(c, level, false));
+  if (level == 0) return set_error(WMG_EINVAL, "level 0 is the fine operator");
+  if (!in || !out || nrhs < 1 || nrhs > c->p.nrhs_max) return set_error(WMG_EINVAL, "bad argument");
+  if (c->p.precision != WMG_MIXED) return set_error(WMG_EINVAL, "FP32 coarse operator exists in mixed precision only");
+  Level &C = c->lv[level];
+  void *a, *b;
+  TRY(level_vec(c, level, P32, VX, &a, nrhs));
+  TRY(level_vec(c, level, P32, VT, &b, nrhs));
+  TRY(copy(P32, a, P64, in, C.n, nrhs, c->st));
+  TRY(apply_op(c, level, P32, a, b, nrhs, false, dagger));
+  TRY(copy(P64, out, P32, b, C.n, nrhs, c->st));
   return sync(c);
 }
 

@@ -261,10 +261,12 @@ template <> struct pscale<__half2> {
 template <int FINE, int EPT, class TP, class TV>
 __global__ void __launch_bounds__(TB) k_restrict(BlockGeom bg, int nv, const TP *__restrict__ P,
                                                 const float *__restrict__ Pscale, const TV *__restrict__ fine,
-                                                TV *__restrict__ coarse) {
+                                                TV *__restrict__ coarse, int nrhs) {
   using R = typename store_traits<TV>::real;
-  long xh = blockIdx.x;
-  int r = blockIdx.y;
+  // workgroups of one aggregate (all rhs) are adjacent: its P is re-read
+  // from cache, not HBM
+  long xh = blockIdx.x / nrhs;
+  int r = (int)(blockIdx.x % nrhs);
   int E = bg.bs * bg.dof, h = bg.dof / 2;
   __shared__ double sh[4 * 2 * 16];
   __shared__ double red[2 * 16];
@@ -323,10 +325,10 @@ __global__ void __launch_bounds__(TB) k_restrict(BlockGeom bg, int nv, const TP 
 template <int FINE, int EPT, class TP, class TV>
 __global__ void __launch_bounds__(TB) k_prolong(BlockGeom bg, int nv, const TP *__restrict__ P,
                                                const float *__restrict__ Pscale, const TV *__restrict__ coarse,
-                                               TV *__restrict__ fine) {
+                                               TV *__restrict__ fine, int nrhs) {
   using R = typename store_traits<TV>::real;
-  long xh = blockIdx.x;
-  int r = blockIdx.y;
+  long xh = blockIdx.x / nrhs;
+  int r = (int)(blockIdx.x % nrhs);
   int E = bg.bs * bg.dof, h = bg.dof / 2;
   __shared__ cx<R> ch_s[2 * 64];
   for (int i = threadIdx.x; i < 2 * nv; i += TB) {
@@ -359,15 +361,15 @@ static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, 
                            void *out, int nrhs, hipStream_t st) {
   int E = bg.bs * bg.dof;
   int ept = (E + TB - 1) / TB;
-  dim3 grid((unsigned)bg.Vc, nrhs);
+  dim3 grid((unsigned)(bg.Vc * nrhs));
 #define TR_CASE(N)                                                                                         \
   if (ept <= N) {                                                                                         \
     if (dir == 0)                                                                                          \
       hipLaunchKernelGGL((k_restrict<FINE, N, TP, TV>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps,  \
-                         (const TV *)in, (TV *)out);                                                       \
+                         (const TV *)in, (TV *)out, nrhs);                                                 \
     else                                                                                                   \
       hipLaunchKernelGGL((k_prolong<FINE, N, TP, TV>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps,   \
-                         (const TV *)in, (TV *)out);                                                       \
+                         (const TV *)in, (TV *)out, nrhs);                                                 \
     WMG_HIP(hipGetLastError());                                                                            \
     return 0;                                                                                              \
   }

@@ -168,5 +168,10 @@ int coarse_apply(const Geom &gc, int n, int yprec, const void *Y, int vprec, con
 int coarse_shift_diag(long Vc, int n, double2 *Y, double dm, hipStream_t st);
 int coarse_convert(long count, const double2 *Y64, int yprec, void *Yout, hipStream_t st);
 int coarse_transpose(long nblk, int n, const double2 *a, double2 *b, hipStream_t st);
+// multi-RHS FP32 coarse stencil on the matrix cores (links pre-swizzled)
+int coarse_to_mfma(long Vc, int n, const double2 *Y64, float *Ym, hipStream_t st);
+size_t coarse_mfma_floats(long Vc, int n);
+int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, float2 *out, int dagger, int nrhs,
+                      hipStream_t st);
 
 }  // namespace wmg

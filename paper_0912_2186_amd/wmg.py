@@ -105,6 +105,7 @@ _sig = {
     "mg_restrict": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_prolong": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_coarse_apply": (_i, [_vp, _i, _vp, _vp, _i, _i]),
+    "mg_coarse_apply_f32": (_i, [_vp, _i, _vp, _vp, _i, _i]),
     "mg_apply_fine": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_cycle": (_i, [_vp, _vp, _vp]),
     "mg_last_iters": (_i, [_vp, _P(_i), _i]),
@@ -251,6 +252,11 @@ class MG:
                         nrhs: int = 1) -> None:
         torch.cuda.synchronize()
         _check(_lib.mg_coarse_apply(self.h, int(level), _ptr(inp), _ptr(out), int(bool(dagger)), int(nrhs)))
+
+    def mg_coarse_apply_f32(self, level: int, inp: torch.Tensor, out: torch.Tensor, dagger: bool = False,
+                            nrhs: int = 1) -> None:
+        torch.cuda.synchronize()
+        _check(_lib.mg_coarse_apply_f32(self.h, int(level), _ptr(inp), _ptr(out), int(bool(dagger)), int(nrhs)))
 
     def mg_apply_fine(self, prec: int, inp: torch.Tensor, out: torch.Tensor, nrhs: int = 1) -> None:
         torch.cuda.synchronize()

@@ -117,6 +117,35 @@ def test_transfer_and_galerkin_from_given_vectors(wmg, L, block):
         assert relerr(host(o), oracle.coarse_apply(Lc, n, Y_ref, c_ref, dagger=dag)) < 1e-13
 
 
+@pytest.mark.parametrize("nv,nrhs", [(5, 1), (8, 7), (24, 28), (24, 40), (32, 3)])
+def test_mfma_coarse_apply_multi_rhs(wmg, nv, nrhs):
+    """FP32 matrix-core coarse stencil (and its sigma_3 adjoint) for many
+    right-hand sides against the oracle's FP64 stencil."""
+    L = (8, 8, 8, 16) if nv <= 8 else (8, 8, 8, 8)
+    block = (4, 4, 4, 4) if nv <= 8 else (2, 2, 4, 4)
+    say("mfma coarse", nv, nrhs, L, block)
+    V = vol(L)
+    m = -0.1
+    U = inputs.gauge_field(L, 0.5, 307)
+    p = wmg.default_params(setup_iters=0, seed=2, nrhs_max=nrhs, precision=wmg.WMG_MIXED)
+    mg = wmg.MG(L, dev(U), m, nv, block, p)
+    vecs = rand_vecs(nv, V, 12, 81)
+    mg.mg_set_null_vectors(0, dev(vecs))
+    P = oracle.block_orthonormalize(L, 12, block, vecs)
+    Y = oracle.coarse_build_wilson(L, U, m, block, P)
+    Lc = oracle.coarse_dims(L, block)
+    Vc = vol(Lc)
+    n = 2 * nv
+    v = rand_vecs(nrhs, Vc, n, 82)
+    for dag in (False, True):
+        o = empty((nrhs, Vc, n))
+        mg.mg_coarse_apply_f32(1, dev(v), o, dagger=dag, nrhs=nrhs)
+        ref = np.stack([oracle.coarse_apply(Lc, n, Y, v[r], dagger=dag) for r in range(nrhs)])
+        e = relerr(host(o), ref)
+        say("  dagger", dag, "relerr", e)
+        assert e < 2e-6
+
+
 def test_three_level_galerkin_from_given_vectors(wmg):
     L = (8, 8, 8, 8)
     say("three-level galerkin", L)
