@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_FP32_PEAK_TF = 157.3
 
 WORKLOADS = {
     # name: lattice, eps, mass, Nv, nrhs (point + Z4), precision, setup iterations
@@ -57,7 +58,7 @@ def make_rhs(inputs, L, w):
 
 def cpu_baseline(w):
     """The FP64 oracle, as it stands, on a bounded sample of the same
-    workload: setup + one-RHS MG-GCR solve on an 8^3 x 16 sub-volume with
+    workload: setup + one-RHS MG-GCR solves on a 16^4 sub-volume with
     the same parameters; its solve time is scaled to the full volume (the
     iteration count is volume independent, the cost per iteration linear)."""
     import numpy as np
@@ -65,7 +66,7 @@ def cpu_baseline(w):
     import oracle
     from paper_0912_2186_amd import inputs
 
-    Ls = (8, 8, 8, 16)
+    Ls = (16, 16, 16, 16)
     Vs = Ls[0] * Ls[1] * Ls[2] * Ls[3]
     V = w["L"][0] * w["L"][1] * w["L"][2] * w["L"][3]
     U = inputs.gauge_field(Ls, w["eps"], w["seed_cfg"] * 100 + 1)
@@ -75,7 +76,7 @@ def cpu_baseline(w):
     t0 = time.time()
     mg.setup()
     ts = time.time() - t0
-    nsample = 8
+    nsample = 4
     bs = inputs.gaussian_rhs(Ls, 7, nsample)
     t0 = time.time()
     for k in range(nsample):
@@ -86,7 +87,7 @@ def cpu_baseline(w):
         "unit": "s/RHS",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": "FP64 oracle MG-GCR (same N_nu, blocks, eps, m, tol 1e-10) on an 8^3x16 sub-volume, "
+        "sample": "FP64 oracle MG-GCR (same N_nu, blocks, eps, m, tol 1e-10) on a 16^4 sub-volume, "
                   "%d Gaussian RHS solved one by one: %.2f s/RHS (%d outer iterations; setup %.1f s not counted), "
                   "scaled by the volume ratio %d" % (nsample, t, st["outer_iters"], ts, V // Vs),
     }
@@ -100,6 +101,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-RHS comparison solve")
+    ap.add_argument("--only", choices=["dslash", "copy"], default=None,
+                    help="counter runs: only the fine-operator kernels (FP64, FP32, FP16-link) on the workload "
+                         "lattice, or only a 1 GiB device copy (bytes reference for the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -114,6 +118,26 @@ def main():
     w = WORKLOADS[args.workload]
     L = w["L"]
     V = L[0] * L[1] * L[2] * L[3]
+    if args.only == "copy":
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copies": 5}))
+        return
+    if args.only == "dslash":
+        U = inputs.gauge_field(L, w["eps"], w["seed_cfg"] * 100 + 1)
+        Ud = torch.from_numpy(U).cuda()
+        p = wmg.default_params(setup_iters=0, nrhs_max=1)
+        mg = wmg.MG(L, Ud, w["m"], 4, (4, 4, 4, 4), p)
+        res = {}
+        for prec, name, lb, sb in [(0, "fp64", 16, 16), (1, "fp32", 8, 8), (2, "fp16links_fp32spinor", 4, 8)]:
+            ms = mg.mg_time_dslash(prec, 1, 10)
+            res[name] = {"ms": round(ms, 4), "alg_bytes": V * (36 * lb + 24 * sb),
+                         "GB/s": round(V * (36 * lb + 24 * sb) / (ms * 1e-3) / 1e9, 1)}
+        print(json.dumps({"workload": args.workload, "dslash": res, "launches_each": 11}))
+        return
     t0 = time.time()
     U = inputs.gauge_field(L, w["eps"], w["seed_cfg"] * 100 + 1)
     b = make_rhs(inputs, L, w)
@@ -156,6 +180,17 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "launches": n_l, "avg_launch_ms": round(avg_ms, 4),
                 "share_of_step": round(ms_l / max(el * 1e3, 1e-9), 3)}
+    if dom.startswith("coarse") and n_l:
+        # the multi-RHS coarse stencil is a dense contraction: 8 real flops per
+        # complex multiply-add, 9 n^2 per site and rhs; take whichever
+        # roofline binds (FP32 matrix peak vs HBM)
+        n = 2 * w["nv"]
+        flops = (V // 256) * 9 * n * n * 8.0 * nrhs
+        by_launch = by_l / n_l
+        if flops / (MFMA_FP32_PEAK_TF * 1e12) > by_launch / (HBM_PEAK_GBS * 1e9):
+            tf = flops / (avg_ms * 1e-3) / 1e12
+            roofline.update({"bound": "mfma", "achieved": round(tf, 2), "peak": MFMA_FP32_PEAK_TF, "unit": "TFLOP/s",
+                             "frac": round(tf / MFMA_FP32_PEAK_TF, 4)})
     kernels = {k: {"launches": v[0], "ms": round(v[1], 2),
                    "GB/s": round(v[2] / max(v[0], 1) / (v[1] / max(v[0], 1) * 1e-3) / 1e9, 1) if v[0] else None}
                for k, v in prof.items()}

@@ -63,7 +63,10 @@ template <int NC> __device__ __forceinline__ void wg_sum(double v[NC]) {
   }
 }
 
-// store the workgroup partial; the last workgroup of this rhs finalises
+// store the workgroup partial; the last workgroup of this rhs finalises:
+// thread t sums partial slots t, t+RB, ... in order, then a fixed-shape
+// workgroup tree combines the threads, so the result does not depend on
+// which workgroup finished last and is bitwise reproducible.
 template <int NC>
 __device__ __forceinline__ void wg_finish(double v[NC], double *partial, unsigned *counter, int rhs, double *out,
                                           int out_stride) {
@@ -77,15 +80,17 @@ __device__ __forceinline__ void wg_finish(double v[NC], double *partial, unsigne
     last = (t == gridDim.x - 1);
   }
   __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    double acc[NC];
+  if (!last) return;
+  __threadfence();
+  const volatile double *p = partial + (size_t)rhs * RMAXBLK * RSLOT;
+  double acc[NC];
 #pragma unroll
-    for (int c = 0; c < NC; c++) acc[c] = 0;
-    const volatile double *p = partial + (size_t)rhs * RMAXBLK * RSLOT;
-    for (unsigned b = 0; b < gridDim.x; b++)
+  for (int c = 0; c < NC; c++) acc[c] = 0;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += RB)
 #pragma unroll
-      for (int c = 0; c < NC; c++) acc[c] += p[b * RSLOT + c];
+    for (int c = 0; c < NC; c++) acc[c] += p[b * RSLOT + c];
+  wg_sum<NC>(acc);
+  if (threadIdx.x == 0) {
 #pragma unroll
     for (int c = 0; c < NC; c++) out[(size_t)rhs * out_stride + c] = acc[c];
     counter[rhs] = 0;
@@ -198,16 +203,36 @@ __global__ void __launch_bounds__(RB) k_multi_dot(const S *const *__restrict__ x
     last = (t == gridDim.x - 1);
   }
   __syncthreads();
-  if (last) {
-    __threadfence();
-    if (threadIdx.x < 2 * k) {
-      const volatile double *p = partial + (size_t)rhs * RMAXBLK * RSLOT;
-      double acc = 0;
-      for (unsigned b = 0; b < gridDim.x; b++) acc += p[b * RSLOT + threadIdx.x];
-      out[(size_t)rhs * out_stride + threadIdx.x] = acc;
-    }
-    if (threadIdx.x == 0) counter[rhs] = 0;
+  if (!last) return;
+  __threadfence();
+  // finalise 2k values: thread t sums slots t, t+RB, ... of every value, then
+  // a fixed-shape workgroup tree (same as the workgroup partials)
+  const volatile double *p = partial + (size_t)rhs * RMAXBLK * RSLOT;
+#pragma unroll
+  for (int c = 0; c < 32; c++) v[c] = 0;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += RB)
+#pragma unroll
+    for (int c = 0; c < 32; c++)
+      if (c < 2 * k) v[c] += p[b * RSLOT + c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 32; c++) {
+    double x = v[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    v[c] = x;
   }
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 32; c++)
+      if (c < 2 * k) sh[c][w] = v[c];
+  __syncthreads();
+  if (threadIdx.x < 2 * k) {
+    double x = 0;
+    for (int q = 0; q < RB / 64; q++) x += sh[threadIdx.x][q];
+    out[(size_t)rhs * out_stride + threadIdx.x] = x;
+  }
+  if (threadIdx.x == 0) counter[rhs] = 0;
 }
 
 int multi_dot(Reducer &R, int prec, const void *const *xs_dev, int k, const void *y, long n, int nrhs, double *out,

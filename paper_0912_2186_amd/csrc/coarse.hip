@@ -463,12 +463,16 @@ int coarse_to_mfma(long Vc, int n, const double2 *Y64, float *Ym, hipStream_t st
 
 size_t coarse_mfma_floats(long Vc, int n) { return (size_t)Vc * 9 * (n / 2) * ((n + 15) / 16) * 64; }
 
+// LDS row stride of the transposed B tile: a multiple of 32 plus 4, so the
+// 16 columns x 4 k-rows read by one MFMA B fragment spread over all banks
+__host__ __device__ __forceinline__ int mfma_ldk(int n) { return (2 * n + 31) / 32 * 32 + 4; }
+
 template <int NT>
 __global__ void __launch_bounds__(256) k_coarse_apply_mfma(const float *__restrict__ Ym, const float2 *__restrict__ in,
                                                           float2 *__restrict__ out, int L0, int L1, int L2, int L3,
                                                           long Vc, int n, int nrhs, int dagger) {
-  constexpr int LD = NT * 16 + ((NT % 2 == 0) ? 16 : 0);  // LDS row stride (bank spread)
-  extern __shared__ float Bs[];                            // [2n][LD]
+  extern __shared__ float Bt[];  // B transposed: [NT*16 columns][LDK], column j, k-row kk at j*LDK + kk
+  const int LDK = mfma_ldk(n);
   const int MT = (n + 15) / 16;
   long xh = blockIdx.x;
   int r0 = blockIdx.y * 32;
@@ -486,34 +490,44 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(const float *__restri
     y[mu] = (x[mu] - 1 + L[mu]) % L[mu];
     nb[5 + mu] = site_index(L, y);
   }
-  const int h = n / 2, K = 2 * n, NC = NT * 16;
+  const int h = n / 2, NC = NT * 16;
+  // padding columns 2R..NC-1 stay zero for every direction
+  for (int idx = threadIdx.x; idx < (NC - 2 * R) * LDK; idx += blockDim.x) Bt[2 * R * LDK + idx] = 0.f;
   floatx4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int KS = n / 2;
   for (int d = 0; d < 9; d++) {
+    // issue this direction's link loads first: they fly while B is staged
+    float a[32];
+    {
+      const float *Ad = Ym + ((size_t)xh * 9 + d) * (size_t)KS * MT * 64 + (mt < MT ? mt : 0) * 64 + lane;
+#pragma unroll
+      for (int ks = 0; ks < 32; ks++) a[ks] = (ks < KS && mt < MT) ? Ad[(size_t)ks * MT * 64] : 0.f;
+    }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < K * NC; idx += blockDim.x) {
-      int kk = idx / NC, j = idx % NC;
-      float val = 0.f;
-      if (j < 2 * R) {
-        int col = kk < n ? kk : kk - n;
-        int r = j < R ? j : j - R;
-        float2 v = in[((size_t)(r0 + r) * Vc + nb[d]) * n + col];
-        if (dagger && col >= h) { v.x = -v.x; v.y = -v.y; }
-        if (kk < n) val = j < R ? v.x : v.y;
-        else val = j < R ? -v.y : v.x;
-      }
-      Bs[kk * LD + j] = val;
+    // B = [[Br, Bi], [-Bi, Br]]: each coalesced load of in[r][nb][col] fills
+    // four entries (col fastest across threads: conflict-free LDS writes)
+    for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
+      int r = idx / n, col = idx % n;
+      float2 v = in[((size_t)(r0 + r) * Vc + nb[d]) * n + col];
+      if (dagger && col >= h) { v.x = -v.x; v.y = -v.y; }
+      Bt[r * LDK + col] = v.x;
+      Bt[(R + r) * LDK + col] = v.y;
+      Bt[r * LDK + n + col] = -v.y;
+      Bt[(R + r) * LDK + n + col] = v.x;
     }
     __syncthreads();
     if (mt < MT) {
-      const float *Ad = Ym + ((size_t)xh * 9 + d) * (size_t)(n / 2) * MT * 64;
       const int krow = lane >> 4, jc = lane & 15;
-      for (int ks = 0; ks < n / 2; ks++) {
-        float a = Ad[((size_t)ks * MT + mt) * 64 + lane];
-        const float *brow = Bs + (ks * 4 + krow) * LD + jc;
 #pragma unroll
-        for (int t = 0; t < NT; t++) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, brow[t * 16], acc[t], 0, 0, 0);
+      for (int ks = 0; ks < 32; ks++) {
+        if (ks < KS) {
+          const float *bcol = Bt + jc * LDK + ks * 4 + krow;
+#pragma unroll
+          for (int t = 0; t < NT; t++)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], bcol[t * 16 * LDK], acc[t], 0, 0, 0);
+        }
       }
     }
   }
@@ -541,8 +555,7 @@ int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, 
   int NT = (2 * rmax + 15) / 16;
   dim3 grid((unsigned)gc.V, (nrhs + 31) / 32);
   dim3 blk(64 * MT);
-  int LD = NT * 16 + ((NT % 2 == 0) ? 16 : 0);
-  size_t lds = sizeof(float) * 2 * n * LD;
+  size_t lds = sizeof(float) * NT * 16 * mfma_ldk(n);
   switch (NT) {
 #define NT_CASE(N)                                                                                              \
   case N:                                                                                                      \

@@ -30,6 +30,17 @@ template <int MU, int S, class R> __device__ __forceinline__ void project(const 
   }
 }
 
+// one colour of the projection: h0 = p0 - S (A p_down)_0, h1 = p1 - S (A p_down)_1
+template <int MU, int S, class R> __device__ __forceinline__ void proj_pair(const cx<R> p[4], cx<R> &h0, cx<R> &h1) {
+  cx<R> a0, a1;
+  if (MU == 0) { a0 = times_mi(p[3]); a1 = times_mi(p[2]); }
+  if (MU == 1) { a0 = neg(p[3]); a1 = p[2]; }
+  if (MU == 2) { a0 = times_mi(p[2]); a1 = times_i(p[3]); }
+  if (MU == 3) { a0 = p[2]; a1 = p[3]; }
+  if (S > 0) { h0 = p[0] - a0; h1 = p[1] - a1; }
+  else { h0 = p[0] + a0; h1 = p[1] + a1; }
+}
+
 // acc_up += g; acc_down += -S * A_mu^dag g
 template <int MU, int S, class R> __device__ __forceinline__ void reconstruct(const cx<R> g[6], cx<R> acc[12]) {
 #pragma unroll
@@ -63,25 +74,98 @@ template <int DAG, class R> __device__ __forceinline__ void su3_mul(const cx<R> 
     }
 }
 
+// ---------------------------------------------------------------- work order
+// Each XCD has its own 4 MB L2 and receives workgroups round-robin.  The
+// lattice is cut into slabs (y and z split into ny x nz pieces, a multiple of
+// 8 of them when possible) whose cross-section at fixed t is small.  Tiles
+// of 256 sites are numbered slab by slab, inside a slab x fastest and t
+// slowest, and XCD k takes the k-th contiguous eighth of that sequence: it
+// sweeps its slabs in t order, so the previous and next t-slices of a site
+// (and its y and z neighbours inside the slab) are in that XCD's L2 when
+// they are needed.
+struct SweepMap {
+  int ny, nz;     // slab split of y and z
+  int dy, dz;     // slab extents
+  long vd;        // sites per slab
+  long td;        // tiles per slab
+  long per_xcd;   // tiles per XCD
+  long nblocks;   // grid size (multiple of 8)
+};
+
+static SweepMap make_sweep(const int L[4], int bytes_per_site) {
+  // among splits whose t-slice takes at most ~1 MB of L2, the one with the
+  // smallest y/z face fraction (neighbours outside the slab); the largest
+  // cross-section breaks ties.  If none fits, the smallest cross-section.
+  const long budget = 1L << 20;
+  SweepMap best{};
+  best.ny = best.nz = 1;
+  bool have = false, bfits = false;
+  double bface = 0;
+  long bcs = 0;
+  for (int ny = 1; ny <= L[1]; ny++) {
+    if (L[1] % ny) continue;
+    for (int nz = 1; nz <= L[2]; nz++) {
+      if (L[2] % nz || (ny * nz) % NXCD) continue;
+      int dy = L[1] / ny, dz = L[2] / nz;
+      long cs = (long)L[0] * dy * dz;
+      bool fits = cs * bytes_per_site <= budget;
+      double face = (dy < L[1] ? 1.0 / dy : 0.0) + (dz < L[2] ? 1.0 / dz : 0.0);
+      bool better;
+      if (!have) better = true;
+      else if (fits != bfits) better = fits;
+      else if (fits) better = face < bface - 1e-12 || (face < bface + 1e-12 && cs > bcs);
+      else better = cs < bcs;
+      if (better) {
+        have = true;
+        bfits = fits;
+        bface = face;
+        bcs = cs;
+        best.ny = ny;
+        best.nz = nz;
+      }
+    }
+  }
+  best.dy = L[1] / best.ny;
+  best.dz = L[2] / best.nz;
+  best.vd = (long)L[0] * best.dy * best.dz * L[3];
+  best.td = (best.vd + 255) / 256;
+  long ntile = (long)best.ny * best.nz * best.td;
+  best.per_xcd = (ntile + NXCD - 1) / NXCD;
+  best.nblocks = best.per_xcd * NXCD;
+  return best;
+}
+
+// site handled by (workgroup b, thread t); false for padding slots
+__device__ __forceinline__ bool sweep_site(const SweepMap &sm, const int L[4], long b, int t, int x[4], long &s) {
+  long g = (b % NXCD) * sm.per_xcd + b / NXCD;  // tile in slab-major order
+  long slab = g / sm.td;
+  if (slab >= (long)sm.ny * sm.nz) return false;
+  long q = (g % sm.td) * 256 + t;
+  if (q >= sm.vd) return false;
+  int iy = (int)(slab % sm.ny), iz = (int)(slab / sm.ny);
+  x[0] = (int)(q % L[0]);
+  q /= L[0];
+  x[1] = (int)(q % sm.dy) + iy * sm.dy;
+  q /= sm.dy;
+  x[2] = (int)(q % sm.dz) + iz * sm.dz;
+  x[3] = (int)(q / sm.dz);
+  s = site_index(L, x);
+  return true;
+}
+
 // ---------------------------------------------------------------- SoA
 template <class TL, class TS, int RT>
 __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, const TS *__restrict__ in,
                                                    TS *__restrict__ out, int L0, int L1, int L2, int L3, long V,
-                                                   float diagf, double diagd, int nrhs) {
+                                                   float diagf, double diagd, int nrhs, SweepMap sm) {
   using R = typename store_traits<TS>::real;
   const R diag = sizeof(R) == 8 ? (R)diagd : (R)diagf;
-  // tiles = (site tile, rhs tile) with the rhs tile fastest, so the rhs
-  // tiles of one site tile run back to back on one XCD and share its links
-  int nrt = (nrhs + RT - 1) / RT;
-  long ntile = (V + 255) / 256 * nrt;
-  long tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile >= ntile) return;
-  long s = (tile / nrt) * 256 + threadIdx.x;
-  if (s >= V) return;
-  int r0 = (int)(tile % nrt) * RT;
+  // one sweep over the lattice per tile of RT right-hand sides (grid.y)
   const int L[4] = {L0, L1, L2, L3};
   int x[4];
-  site_coords(L, s, x);
+  long s;
+  if (!sweep_site(sm, L, blockIdx.x, threadIdx.x, x, s)) return;
+  int r0 = blockIdx.y * RT;
   long stride[4] = {1, (long)L0, (long)L0 * L1, (long)L0 * L1 * L2};
   cx<R> acc[RT][12];
 #pragma unroll
@@ -104,16 +188,29 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
     }
   };
 
+  // half spinor of the neighbour, projected colour by colour straight from
+  // the loads, then the link applied row by row (few live registers)
+  auto hop_half = [&](int r, long site, auto proj, cx<R> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      cx<R> p4[4];
+#pragma unroll
+      for (int sp = 0; sp < 4; sp++) {
+        auto v = ldc(in + ((size_t)r * 12 + sp * 3 + c) * V + site);
+        p4[sp] = {(R)v.re, (R)v.im};
+      }
+      proj(p4, h[c], h[3 + c]);
+    }
+  };
 #define WILSON_DIR(MU)                                                                         \
   {                                                                                            \
     long fw = x[MU] == L[MU] - 1 ? s - (long)(L[MU] - 1) * stride[MU] : s + stride[MU];        \
     long bw = x[MU] == 0 ? s + (long)(L[MU] - 1) * stride[MU] : s - stride[MU];                \
-    cx<R> u[9], p[12], h[6], g[6];                                                             \
+    cx<R> u[9], h[6], g[6];                                                                    \
     load_link(MU, s, u);                                                                       \
     _Pragma("unroll") for (int t = 0; t < RT; t++) {                                           \
       if (r0 + t < nrhs) {                                                                     \
-        load_psi(r0 + t, fw, p);                                                               \
-        project<MU, 1>(p, h);                                                                  \
+        hop_half(r0 + t, fw, proj_pair<MU, 1, R>, h);                                          \
         su3_mul<0>(u, h, g);                                                                   \
         reconstruct<MU, 1>(g, acc[t]);                                                         \
       }                                                                                        \
@@ -121,8 +218,7 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
     load_link(MU, bw, u);                                                                      \
     _Pragma("unroll") for (int t = 0; t < RT; t++) {                                           \
       if (r0 + t < nrhs) {                                                                     \
-        load_psi(r0 + t, bw, p);                                                               \
-        project<MU, -1>(p, h);                                                                 \
+        hop_half(r0 + t, bw, proj_pair<MU, -1, R>, h);                                         \
         su3_mul<1>(u, h, g);                                                                   \
         reconstruct<MU, -1>(g, acc[t]);                                                        \
       }                                                                                        \
@@ -150,10 +246,11 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
 template <class TL, class TS>
 static void launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, hipStream_t st) {
   constexpr int RT = sizeof(TS) == 16 ? 1 : 2;
-  long ntile = (g.V + 255) / 256 * ((nrhs + RT - 1) / RT);
-  dim3 grid((unsigned)xcd_grid(ntile));
+  // bytes a site brings into L2 during one sweep: its links and RT spinors
+  SweepMap sm = make_sweep(g.L, 36 * (int)sizeof(TL) + 24 * (int)sizeof(TS) / 2 * RT);
+  dim3 grid((unsigned)sm.nblocks, (nrhs + RT - 1) / RT);
   hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT>), grid, dim3(256), 0, st, (const TL *)U, (const TS *)in, (TS *)out,
-                     g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs);
+                     g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm);
 }
 
 int wilson_soa(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,

@@ -1082,6 +1082,38 @@ int mg_coarse_apply(wmg_ctx *c, int level, const double *in, double *out, int da
   return sync(c);
 }
 
+// restriction (dir 0) or prolongation (dir 1) through the FP32 vectors and
+// FP16-stored prolongator of a mixed-precision context
+static int transfer_f32(wmg_ctx *c, int level, int dir, const double *in, double *out, int nrhs) {
+  TRY(check_level(c, level, true));
+  if (!in || !out || nrhs < 1 || nrhs > c->p.nrhs_max) return set_error(WMG_EINVAL, "bad argument");
+  if (c->p.precision != WMG_MIXED) return set_error(WMG_EINVAL, "FP16 prolongator exists in mixed precision only");
+  Level &F = c->lv[level], &C = c->lv[level + 1];
+  void *f32, *c32, *f64;
+  TRY(level_vec(c, level, P32, VX, &f32, nrhs));
+  TRY(level_vec(c, level + 1, P32, VX, &c32, nrhs));
+  TRY(level_vec(c, level, P64, VX, &f64, nrhs));
+  if (dir == 0) {
+    TRY(to_internal(c, level, in, (double2 *)f64, nrhs));
+    TRY(copy(P32, f32, P64, f64, F.n, nrhs, c->st));
+    TRY(transfer_restrict(c, level, P32, f32, c32, nrhs));
+    TRY(copy(P64, out, P32, c32, C.n, nrhs, c->st));
+  } else {
+    TRY(copy(P32, c32, P64, in, C.n, nrhs, c->st));
+    TRY(transfer_prolong(c, level, P32, c32, f32, nrhs));
+    TRY(copy(P64, f64, P32, f32, F.n, nrhs, c->st));
+    TRY(from_internal(c, level, (double2 *)f64, out, nrhs));
+  }
+  return sync(c);
+}
+
+int mg_restrict_f32(wmg_ctx *c, int level, const double *fine, double *coarse, int nrhs) {
+  return transfer_f32(c, level, 0, fine, coarse, nrhs);
+}
+int mg_prolong_f32(wmg_ctx *c, int level, const double *coarse, double *fine, int nrhs) {
+  return transfer_f32(c, level, 1, coarse, fine, nrhs);
+}
+
 int mg_coarse_apply_f32(wmg_ctx *c, int level, const double *in, double *out, int dagger, int nrhs) {
   TRY(check_level(c, level, false));
   if (level == 0) return set_error(WMG_EINVAL, "level 0 is the fine operator");

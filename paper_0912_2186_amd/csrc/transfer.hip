@@ -321,38 +321,135 @@ __global__ void __launch_bounds__(TB) k_restrict(BlockGeom bg, int nv, const TP 
 }
 
 // ------------------------------------------------------------ prolongation
-// one workgroup per (coarse site, rhs); one thread per block element
-template <int FINE, int EPT, class TP, class TV>
+// One workgroup per coarse site (XCD-contiguous order).  The coarse values of
+// RC right-hand sides are staged in LDS; every thread takes its aggregate
+// elements, reads each P entry once and applies it to all RC right-hand
+// sides held in registers (one pass over P per chunk of RC).
+template <int FINE, int EPT, int RC, class TP, class TV>
 __global__ void __launch_bounds__(TB) k_prolong(BlockGeom bg, int nv, const TP *__restrict__ P,
                                                const float *__restrict__ Pscale, const TV *__restrict__ coarse,
                                                TV *__restrict__ fine, int nrhs) {
   using R = typename store_traits<TV>::real;
-  long xh = blockIdx.x / nrhs;
-  int r = (int)(blockIdx.x % nrhs);
-  int E = bg.bs * bg.dof, h = bg.dof / 2;
-  __shared__ cx<R> ch_s[2 * 64];
-  for (int i = threadIdx.x; i < 2 * nv; i += TB) {
-    auto t = ldc(coarse + ((size_t)r * bg.Vc + xh) * (2 * nv) + i);
-    ch_s[i] = {(R)t.re, (R)t.im};
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < EPT; q++) {
-    int e = threadIdx.x + q * TB;
-    if (e >= E) continue;
-    int k, c;
-    elem_kc<FINE>(bg, e, k, c);
-    int chi = c / h;
-    size_t si = (size_t)xh * bg.bs + k;
-    cx<R> acc = czero<R>();
-    for (int a = 0; a < nv; a++) {
-      auto p = ldc(P + ((size_t)a * bg.Vc + xh) * E + e);
-      float sc = pscale<TP>::get(Pscale, (size_t)a * bg.Vc * bg.bs + si);
-      cx<R> pv = {(R)(sc * p.re), (R)(sc * p.im)};
-      acc = cfma(pv, ch_s[chi * nv + a], acc);
+  long xh = xcd_tile(blockIdx.x, gridDim.x);
+  if (xh >= bg.Vc) return;
+  const int E = bg.bs * bg.dof, h = bg.dof / 2, n = 2 * nv;
+  __shared__ cx<R> cs[RC * 128];
+  for (int r0 = 0; r0 < nrhs; r0 += RC) {
+    int rc = nrhs - r0 < RC ? nrhs - r0 : RC;
+    __syncthreads();
+    for (int i = threadIdx.x; i < rc * n; i += TB) {
+      int r = i / n, j = i % n;
+      auto t = ldc(coarse + ((size_t)(r0 + r) * bg.Vc + xh) * n + j);
+      cs[r * n + j] = {(R)t.re, (R)t.im};
     }
-    long s = block_site(bg, xh, k);
-    stc(fine + vec_addr<FINE>(bg, r, s, c), acc);
+    __syncthreads();
+#pragma unroll 1
+    for (int q = 0; q < EPT; q++) {
+      int e = threadIdx.x + q * TB;
+      if (e >= E) break;
+      int k, c;
+      elem_kc<FINE>(bg, e, k, c);
+      const int off = (c / h) * nv;
+      const size_t si = (size_t)xh * bg.bs + k;
+      cx<R> acc[RC];
+#pragma unroll
+      for (int r = 0; r < RC; r++) acc[r] = czero<R>();
+      for (int a = 0; a < nv; a++) {
+        auto pv0 = ldc(P + ((size_t)a * bg.Vc + xh) * E + e);
+        float sc = pscale<TP>::get(Pscale, (size_t)a * bg.Vc * bg.bs + si);
+        cx<R> pv = {(R)(sc * pv0.re), (R)(sc * pv0.im)};
+#pragma unroll
+        for (int r = 0; r < RC; r++)
+          if (r < rc) acc[r] = cfma(pv, cs[r * n + off + a], acc[r]);
+      }
+      long s = block_site(bg, xh, k);
+#pragma unroll
+      for (int r = 0; r < RC; r++)
+        if (r < rc) stc(fine + vec_addr<FINE>(bg, r0 + r, s, c), acc[r]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ MFMA restriction
+// Fine-level restriction of many right-hand sides on the matrix cores.  Per
+// aggregate xh and chirality chi the complex product
+//   O[alpha][r] = sum_e conj(P[alpha][e]) v[r][e]      (e: elements of chi)
+// is the real GEMM [Or | Oi] = [Pr | Pi] . [[vr, vi], [vi, -vr]] (M = Nv,
+// N = 2R, K = 2 x elements), streamed in chunks of CH elements: the chunk of
+// P (FP16 with its per-site scale, expanded to FP32) and of all R vectors is
+// staged in LDS, so P and the vectors are each read once.  Both LDS tiles are
+// kept k-contiguous with a row stride of 2*CH+4 floats, which spreads the 16
+// rows x 4 k of an MFMA fragment over all banks.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+static constexpr int RCH = 64;            // elements per chunk
+static constexpr int RLD = 2 * RCH + 4;   // LDS row stride
+
+__global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, const __half2 *__restrict__ P,
+                                                     const float *__restrict__ Pscale, const float2 *__restrict__ fine,
+                                                     float2 *__restrict__ coarse, int nrhs) {
+  __shared__ float As[32 * RLD];
+  __shared__ float Bt[64 * RLD];
+  long xh = xcd_tile(blockIdx.x, gridDim.x);
+  if (xh >= bg.Vc) return;
+  const int r0 = blockIdx.y * 32;
+  const int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
+  const int E = bg.bs * 12, H = bg.bs * 6;
+  const int MTr = (nv + 15) / 16, NTr = (2 * R + 15) / 16, ntile = MTr * NTr;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // zero the padding rows once (rows nv..31 of A, columns 2R..63 of B)
+  for (int i = threadIdx.x; i < (32 - nv) * RLD; i += TB) As[nv * RLD + i] = 0.f;
+  for (int i = threadIdx.x; i < (64 - 2 * R) * RLD; i += TB) Bt[2 * R * RLD + i] = 0.f;
+  for (int chi = 0; chi < 2; chi++) {
+    floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+    for (int e0 = 0; e0 < H; e0 += RCH) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < nv * RCH; i += TB) {
+        int a = i / RCH, e = i % RCH;
+        int ee = chi * H + e0 + e;
+        float2 pv = __half22float2(P[((size_t)a * bg.Vc + xh) * E + ee]);
+        float sc = Pscale[((size_t)a * bg.Vc + xh) * bg.bs + ee % bg.bs];
+        As[a * RLD + e] = sc * pv.x;
+        As[a * RLD + RCH + e] = sc * pv.y;
+      }
+      for (int i = threadIdx.x; i < R * RCH; i += TB) {
+        int r = i / RCH, e = i % RCH;
+        int ee = chi * H + e0 + e;
+        int c = ee / bg.bs, k = ee % bg.bs;
+        long st = block_site(bg, xh, k);
+        float2 v = fine[((size_t)(r0 + r) * 12 + c) * bg.V + st];
+        Bt[r * RLD + e] = v.x;
+        Bt[(R + r) * RLD + e] = v.y;
+        Bt[r * RLD + RCH + e] = v.y;
+        Bt[(R + r) * RLD + RCH + e] = -v.x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 2; i++) {
+        int tt = w + 4 * i;
+        if (tt < ntile) {
+          int mt = tt / NTr, nt = tt % NTr;
+          const float *ar = As + (mt * 16 + (lane & 15)) * RLD + (lane >> 4);
+          const float *br = Bt + (nt * 16 + (lane & 15)) * RLD + (lane >> 4);
+          for (int ks = 0; ks < 2 * RCH / 4; ks++)
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ks * 4], br[ks * 4], acc[i], 0, 0, 0);
+        }
+      }
+    }
+    float *of = (float *)coarse;
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      int tt = w + 4 * i;
+      if (tt >= ntile) continue;
+      int mt = tt / NTr, nt = tt % NTr;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        int a = mt * 16 + 4 * (lane >> 4) + v, j = nt * 16 + (lane & 15);
+        if (a < nv && j < 2 * R) {
+          int r = j < R ? j : j - R;
+          of[2 * (((size_t)(r0 + r) * bg.Vc + xh) * (2 * nv) + chi * nv + a) + (j < R ? 0 : 1)] = acc[i][v];
+        }
+      }
+    }
   }
 }
 
@@ -368,8 +465,8 @@ static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, 
       hipLaunchKernelGGL((k_restrict<FINE, N, TP, TV>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps,  \
                          (const TV *)in, (TV *)out, nrhs);                                                 \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_prolong<FINE, N, TP, TV>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps,   \
-                         (const TV *)in, (TV *)out, nrhs);                                                 \
+      hipLaunchKernelGGL((k_prolong<FINE, N, sizeof(TV) == 16 ? 4 : 16, TP, TV>), dim3((unsigned)xcd_grid(bg.Vc)), \
+                         dim3(TB), 0, st, bg, nv, (const TP *)P, Ps, (const TV *)in, (TV *)out, nrhs);       \
     WMG_HIP(hipGetLastError());                                                                            \
     return 0;                                                                                              \
   }
@@ -382,6 +479,13 @@ static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int
                     const float *Ps, int vprec, const void *in, void *out, int fine_soa, int nrhs, hipStream_t st) {
   BlockGeom bg = make_bg(g, dof, b);
   if (nv > 64) return set_error(-1, "transfer: nv=%d > 64", nv);
+  if (dir == 0 && fine_soa && pprec == P16 && vprec == P32 && nv <= 32 && (bg.bs * 6) % RCH == 0) {
+    dim3 grid((unsigned)xcd_grid(bg.Vc), (nrhs + 31) / 32);
+    hipLaunchKernelGGL(k_restrict_mfma, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps, (const float2 *)in,
+                       (float2 *)out, nrhs);
+    WMG_HIP(hipGetLastError());
+    return 0;
+  }
 #define TP_CASE(F, TPT, TVT, PP, VP)                                                                       \
   if (fine_soa == F && pprec == PP && vprec == VP) return launch_transfer<F, TPT, TVT>(dir, bg, nv, P, Ps, in, out, nrhs, st);
   TP_CASE(1, double2, double2, P64, P64)
