@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-RHS comparison solve")
+    ap.add_argument("--delta", type=float, default=None, help="reliable-update threshold (default: library's)")
+    ap.add_argument("--coarse-tol", type=float, default=None, help="coarsest CGNR tolerance (mixed default 1e-5)")
     ap.add_argument("--only", choices=["dslash", "copy"], default=None,
                     help="counter runs: only the fine-operator kernels (FP64, FP32, FP16-link) on the workload "
                          "lattice, or only a 1 GiB device copy (bytes reference for the HBM counters)")
@@ -150,6 +152,10 @@ def main():
     p = wmg.default_params(setup_iters=w["setup_iters"], seed=w["seed_cfg"] * 100 + 50, nrhs_max=nrhs,
                            precision=wmg.WMG_MIXED if w["mixed"] else wmg.WMG_FP64,
                            coarse_tol=1e-5 if w["mixed"] else 1e-8)
+    if args.delta is not None:
+        p.reliable_delta = args.delta
+    if args.coarse_tol is not None:
+        p.coarse_tol = args.coarse_tol
     torch.cuda.synchronize()
     t0 = time.time()
     mg = wmg.MG(L, Ud, w["m"], w["nv"], (4, 4, 4, 4), p)

@@ -162,6 +162,10 @@ int mg_restrict(wmg_ctx *ctx, int level, const double *fine, double *coarse, int
 int mg_prolong(wmg_ctx *ctx, int level, const double *coarse, double *fine, int nrhs);
 /* FP64 coarse operator (or its adjoint) at level >= 1. */
 int mg_coarse_apply(wmg_ctx *ctx, int level, const double *in, double *out, int dagger, int nrhs);
+/* Restriction / prolongation through the FP32 vectors and the FP16-stored
+ * prolongator of a mixed-precision context; canonical FP64 in/out. */
+int mg_restrict_f32(wmg_ctx *ctx, int level, const double *fine, double *coarse, int nrhs);
+int mg_prolong_f32(wmg_ctx *ctx, int level, const double *coarse, double *fine, int nrhs);
 /* The same through the FP32 coarse operator of a mixed-precision context
  * (matrix-core kernel for n <= 64); canonical FP64 in/out. */
 int mg_coarse_apply_f32(wmg_ctx *ctx, int level, const double *in, double *out, int dagger, int nrhs);

@@ -30,7 +30,8 @@ extern "C" int bicgstab_solve(const wmg_geom *gg, const double *U, double m, con
     g.L[i] = gg->L[i];
   }
   g.V = (long)g.L[0] * g.L[1] * g.L[2] * g.L[3];
-  long n = g.V * 12;
+  g.Vs = fine_stride(g.V);
+  long n = g.Vs * 12;
   hipStream_t s;
   WMG_HIP(hipStreamCreate(&s));
   Reducer R{};
@@ -41,9 +42,10 @@ extern "C" int bicgstab_solve(const wmg_geom *gg, const double *U, double m, con
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
     bufs.push_back(p);
+    if (hipMemset(p, 0, bytes) != hipSuccess) return nullptr;  // padding sites stay zero
     return p;
   };
-  void *Us = alloc(16 * 36 * (size_t)g.V);
+  void *Us = alloc(16 * 36 * (size_t)g.Vs);
   double2 *x = (double2 *)alloc(16 * n), *b = (double2 *)alloc(16 * n), *r = (double2 *)alloc(16 * n),
           *rh = (double2 *)alloc(16 * n), *p = (double2 *)alloc(16 * n), *v = (double2 *)alloc(16 * n),
           *sv = (double2 *)alloc(16 * n), *t = (double2 *)alloc(16 * n);

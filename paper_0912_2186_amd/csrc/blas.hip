@@ -250,6 +250,175 @@ int multi_dot(Reducer &R, int prec, const void *const *xs_dev, int k, const void
   return 0;
 }
 
+// ---------------------------------------------------------------- GCR fusions
+// Projection step of classical Gram-Schmidt against unnormalised basis
+// vectors w_j (|w_j|^2 kept in wn2): b_j = d_j / |w_j|^2, w <- w - sum b_j w_j,
+// b_j recorded in beta[j][k] (PASS 1: =, PASS 2: +=).  PASS 1 then reduces
+// the new projections <w_j, w> (2k values, the dots of the second pass);
+// PASS 2 reduces <w, r> and |w|^2.  One read of every w_j, w (and r).
+template <class S, int PASS>
+__global__ void __launch_bounds__(RB) k_gcr_proj(const S *const *__restrict__ W, int k, S *__restrict__ w,
+                                                const S *__restrict__ r, const double *__restrict__ d, int dstride,
+                                                const double *__restrict__ wn2, int wstride, double *__restrict__ beta,
+                                                int bstride, int kcol, long n, double *partial, unsigned *counter,
+                                                double *out, int out_stride) {
+  using R = typename store_traits<S>::real;
+  int rhs = blockIdx.y;
+  cx<R> b[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    double q = j < k ? wn2[(size_t)rhs * wstride + j] : 0.0;
+    double br = (j < k && q > 0) ? d[(size_t)rhs * dstride + 2 * j] / q : 0.0;
+    double bi = (j < k && q > 0) ? d[(size_t)rhs * dstride + 2 * j + 1] / q : 0.0;
+    b[j] = {(R)br, (R)bi};
+    if (blockIdx.x == 0 && threadIdx.x == 0 && j < k) {
+      double *bb = beta + (size_t)rhs * bstride + (j * 16 + kcol) * 2;
+      if (PASS == 1) { bb[0] = br; bb[1] = bi; }
+      else { bb[0] += br; bb[1] += bi; }
+    }
+  }
+  constexpr int NV = PASS == 1 ? 32 : 3;
+  double v[NV];
+#pragma unroll
+  for (int c = 0; c < NV; c++) v[c] = 0;
+  size_t off = (size_t)rhs * n;
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) {
+    cx<R> wj[16];
+    cx<R> x = ldc(w + off + i);
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      if (j < k) {
+        auto t = ldc(W[j] + off + i);
+        wj[j] = {(R)t.re, (R)t.im};
+        x = x - b[j] * wj[j];
+      }
+    stc(w + off + i, x);
+    if (PASS == 1) {
+#pragma unroll
+      for (int j = 0; j < 16; j++)
+        if (j < k) {
+          v[2 * j] += (double)wj[j].re * x.re + (double)wj[j].im * x.im;
+          v[2 * j + 1] += (double)wj[j].re * x.im - (double)wj[j].im * x.re;
+        }
+    } else {
+      auto rr = ldc(r + off + i);
+      v[0] += (double)x.re * rr.re + (double)x.im * rr.im;
+      v[1] += (double)x.re * rr.im - (double)x.im * rr.re;
+      v[2] += (double)x.re * x.re + (double)x.im * x.im;
+    }
+  }
+  if (PASS == 2) {
+    double t3[3] = {v[0], v[1], v[2]};
+    wg_sum<3>(t3);
+    wg_finish<3>(t3, partial, counter, rhs, out, out_stride);
+  } else {
+    // 2k values: workgroup tree, slot, last-workgroup finalise
+    __shared__ double sh[32][RB / 64];
+    __shared__ bool last;
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 32; c++) {
+      double x = v[c];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+      v[c] = x;
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int c = 0; c < 32; c++)
+        if (c < 2 * k) sh[c][wv] = v[c];
+    __syncthreads();
+    if (threadIdx.x < 2 * k) {
+      double x = 0;
+      for (int q = 0; q < RB / 64; q++) x += sh[threadIdx.x][q];
+      partial[((size_t)rhs * RMAXBLK + blockIdx.x) * RSLOT + threadIdx.x] = x;
+      __threadfence();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      unsigned t = atomicAdd(counter + rhs, 1u);
+      last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const volatile double *p = partial + (size_t)rhs * RMAXBLK * RSLOT;
+#pragma unroll
+    for (int c = 0; c < 32; c++) v[c] = 0;
+    for (unsigned bb = threadIdx.x; bb < gridDim.x; bb += RB)
+#pragma unroll
+      for (int c = 0; c < 32; c++)
+        if (c < 2 * k) v[c] += p[bb * RSLOT + c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 32; c++) {
+      double x = v[c];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+      v[c] = x;
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int c = 0; c < 32; c++)
+        if (c < 2 * k) sh[c][wv] = v[c];
+    __syncthreads();
+    if (threadIdx.x < 2 * k) {
+      double x = 0;
+      for (int q = 0; q < RB / 64; q++) x += sh[threadIdx.x][q];
+      out[(size_t)rhs * out_stride + threadIdx.x] = x;
+    }
+    if (threadIdx.x == 0) counter[rhs] = 0;
+  }
+}
+
+int gcr_project(Reducer &R, int prec, int pass, const void *const *W, int k, void *w, const void *r, const double *d,
+                int dstride, const double *wn2, int wstride, double *beta, int bstride, int kcol, long n, int nrhs,
+                double *out, int out_stride, hipStream_t st) {
+  if (k < 1 || k > 16 || nrhs > R.nrhs_max) return set_error(-1, "gcr_project k=%d", k);
+  dim3 grid(red_blocks(n), nrhs);
+#define GP(S, P)                                                                                                \
+  hipLaunchKernelGGL((k_gcr_proj<S, P>), grid, dim3(RB), 0, st, (const S *const *)W, k, (S *)w, (const S *)r, d,  \
+                     dstride, wn2, wstride, beta, bstride, kcol, n, R.partial, R.counter, out, out_stride)
+  if (prec == P64) { if (pass == 1) GP(double2, 1); else GP(double2, 2); }
+  else { if (pass == 1) GP(float2, 1); else GP(float2, 2); }
+#undef GP
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+// y -= a x (a complex on the device, masked by the caller) and |y|^2
+template <class S>
+__global__ void __launch_bounds__(RB) k_caxpy_norm(const double *__restrict__ a, int astride, const S *__restrict__ x,
+                                                  S *__restrict__ y, long n, double *partial, unsigned *counter,
+                                                  double *out, int out_stride) {
+  using R = typename store_traits<S>::real;
+  int rhs = blockIdx.y;
+  cx<R> c = {(R)(-a[(size_t)rhs * astride]), (R)(-a[(size_t)rhs * astride + 1])};
+  size_t off = (size_t)rhs * n;
+  double v[1] = {0};
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) {
+    auto yv = cfma(c, ldc(x + off + i), ldc(y + off + i));
+    stc(y + off + i, yv);
+    v[0] += (double)yv.re * yv.re + (double)yv.im * yv.im;
+  }
+  wg_sum<1>(v);
+  wg_finish<1>(v, partial, counter, rhs, out, out_stride);
+}
+
+int caxpy_norm(Reducer &R, int prec, const double *a, int astride, const void *x, void *y, long n, int nrhs,
+               double *out, int out_stride, hipStream_t st) {
+  dim3 grid(red_blocks(n), nrhs);
+  if (prec == P64)
+    hipLaunchKernelGGL((k_caxpy_norm<double2>), grid, dim3(RB), 0, st, a, astride, (const double2 *)x, (double2 *)y, n,
+                       R.partial, R.counter, out, out_stride);
+  else
+    hipLaunchKernelGGL((k_caxpy_norm<float2>), grid, dim3(RB), 0, st, a, astride, (const float2 *)x, (float2 *)y, n,
+                       R.partial, R.counter, out, out_stride);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
 // ---------------------------------------------------------------- elementwise
 static dim3 ew_grid(long n, int nrhs) {
   long b = (n + 255) / 256;
@@ -444,7 +613,7 @@ int scale_inv_sqrt(int prec, void *x, const double *nrm2, int stride, long n, in
 
 // sigma_3 (coarse) / gamma_5 (fine, AoS view): negate the second half of
 // every site's components.  For SoA fine spinors the caller passes nsite=1
-// and dof = 12*V, which negates components 6..11 of every site.
+// and dof = 12*Vs, which negates components 6..11 of every site.
 template <class S> __global__ void k_sigma3(S *x, long nsite, int dof) {
   long n = nsite * dof;
   size_t off = (size_t)blockIdx.y * n;

@@ -22,6 +22,7 @@ static constexpr int TB = 256;
 struct CGeom {
   int L[4], b[4], Lc[4];
   long V, Vc;
+  long Vs;  // fine-lattice site stride of the links
   int bs, dof, nv;
 };
 
@@ -148,7 +149,7 @@ __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__r
           cx<double> v[12];
           loadv(y, v);
           long t = site_index(g.L, y);
-          wilson_hop(U, g.V, s, t, mu, sg, v, w);
+          wilson_hop(U, g.Vs, s, t, mu, sg, v, w);
         }
     }
     // restrict w onto rows (chi_r, beta), 16 rows at a time
@@ -283,6 +284,7 @@ int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, dou
     g.Lc[i] = gf.L[i] / b[i];
   }
   g.V = gf.V;
+  g.Vs = gf.Vs;
   g.Vc = (long)g.Lc[0] * g.Lc[1] * g.Lc[2] * g.Lc[3];
   g.bs = b[0] * b[1] * b[2] * b[3];
   g.dof = fine_kind == 0 ? 12 : dof;

@@ -154,18 +154,28 @@ __device__ __forceinline__ bool sweep_site(const SweepMap &sm, const int L[4], l
 }
 
 // ---------------------------------------------------------------- SoA
-template <class TL, class TS, int RT>
+// Optional fusions for the smoother: bsub != nullptr gives out = bsub - D in
+// (residual); RED != 0 also reduces <out, in> and |out|^2 over the
+// workgroup into red[(rhs * gridDim.x + block) * 3 + 0..2] for a
+// fixed-order finalisation by k_dslash_red_finalize.
+template <class TL, class TS, int RT, int RED>
 __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, const TS *__restrict__ in,
                                                    TS *__restrict__ out, int L0, int L1, int L2, int L3, long V,
-                                                   float diagf, double diagd, int nrhs, SweepMap sm) {
+                                                   float diagf, double diagd, int nrhs, SweepMap sm, long Vs,
+                                                   const TS *__restrict__ bsub, double *__restrict__ red) {
   using R = typename store_traits<TS>::real;
   const R diag = sizeof(R) == 8 ? (R)diagd : (R)diagf;
   // one sweep over the lattice per tile of RT right-hand sides (grid.y)
   const int L[4] = {L0, L1, L2, L3};
   int x[4];
-  long s;
-  if (!sweep_site(sm, L, blockIdx.x, threadIdx.x, x, s)) return;
+  long s = 0;
+  const bool valid = sweep_site(sm, L, blockIdx.x, threadIdx.x, x, s);
+  if (!RED && !valid) return;
   int r0 = blockIdx.y * RT;
+  double rs[RT][3];
+#pragma unroll
+  for (int t = 0; t < RT; t++) rs[t][0] = rs[t][1] = rs[t][2] = 0.0;
+  if (valid) {
   long stride[4] = {1, (long)L0, (long)L0 * L1, (long)L0 * L1 * L2};
   cx<R> acc[RT][12];
 #pragma unroll
@@ -176,14 +186,14 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
   auto load_link = [&](int mu, long site, cx<R> u[9]) {
 #pragma unroll
     for (int e = 0; e < 9; e++) {
-      auto v = ldc(U + ((size_t)(mu * 9 + e)) * V + site);
+      auto v = ldc(U + ((size_t)(mu * 9 + e)) * Vs + site);
       u[e] = {(R)v.re, (R)v.im};
     }
   };
   auto load_psi = [&](int r, long site, cx<R> p[12]) {
 #pragma unroll
     for (int c = 0; c < 12; c++) {
-      auto v = ldc(in + ((size_t)r * 12 + c) * V + site);
+      auto v = ldc(in + ((size_t)r * 12 + c) * Vs + site);
       p[c] = {(R)v.re, (R)v.im};
     }
   };
@@ -196,7 +206,7 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
       cx<R> p4[4];
 #pragma unroll
       for (int sp = 0; sp < 4; sp++) {
-        auto v = ldc(in + ((size_t)r * 12 + sp * 3 + c) * V + site);
+        auto v = ldc(in + ((size_t)r * 12 + sp * 3 + c) * Vs + site);
         p4[sp] = {(R)v.re, (R)v.im};
       }
       proj(p4, h[c], h[3 + c]);
@@ -238,29 +248,106 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
 #pragma unroll
     for (int c = 0; c < 12; c++) {
       cx<R> o = {diag * p[c].re - R(0.5) * acc[t][c].re, diag * p[c].im - R(0.5) * acc[t][c].im};
-      stc(out + ((size_t)(r0 + t) * 12 + c) * V + s, o);
+      if (bsub) {
+        auto bv = ldc(bsub + ((size_t)(r0 + t) * 12 + c) * Vs + s);
+        o = cx<R>{(R)bv.re - o.re, (R)bv.im - o.im};
+      }
+      stc(out + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
+      if (RED) {
+        rs[t][0] += (double)o.re * p[c].re + (double)o.im * p[c].im;
+        rs[t][1] += (double)o.re * p[c].im - (double)o.im * p[c].re;
+        rs[t][2] += (double)o.re * o.re + (double)o.im * o.im;
+      }
+    }
+  }
+  }  // valid
+  if (RED) {
+    __shared__ double sh[RT][3][4];
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < RT; t++)
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        double v = rs[t][q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) sh[t][q][wv] = v;
+      }
+    __syncthreads();
+    if (threadIdx.x < RT * 3) {
+      int t = threadIdx.x / 3, q = threadIdx.x % 3;
+      if (r0 + t < nrhs)
+        red[((size_t)(r0 + t) * gridDim.x + blockIdx.x) * 3 + q] = sh[t][q][0] + sh[t][q][1] + sh[t][q][2] + sh[t][q][3];
     }
   }
 }
 
+// out[rhs*stride + 0..2] = sum over blocks of red[(rhs*nblk + b)*3 + 0..2],
+// summed in a fixed order (one workgroup per rhs)
+__global__ void __launch_bounds__(256) k_dslash_red_finalize(const double *__restrict__ red, long nblk,
+                                                            double *__restrict__ out, int stride) {
+  int rhs = blockIdx.x;
+  double v[3] = {0, 0, 0};
+  for (long b = threadIdx.x; b < nblk; b += 256)
+#pragma unroll
+    for (int q = 0; q < 3; q++) v[q] += red[((size_t)rhs * nblk + b) * 3 + q];
+  __shared__ double sh[3][4];
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    double x = v[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) sh[q][wv] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) out[(size_t)rhs * stride + threadIdx.x] = sh[threadIdx.x][0] + sh[threadIdx.x][1] +
+                                                                   sh[threadIdx.x][2] + sh[threadIdx.x][3];
+}
+
 template <class TL, class TS>
-static void launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, hipStream_t st) {
+static void launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, const void *bsub,
+                       double *red, double *red_out, int red_stride, hipStream_t st) {
   constexpr int RT = sizeof(TS) == 16 ? 1 : 2;
   // bytes a site brings into L2 during one sweep: its links and RT spinors
   SweepMap sm = make_sweep(g.L, 36 * (int)sizeof(TL) + 24 * (int)sizeof(TS) / 2 * RT);
   dim3 grid((unsigned)sm.nblocks, (nrhs + RT - 1) / RT);
-  hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT>), grid, dim3(256), 0, st, (const TL *)U, (const TS *)in, (TS *)out,
-                     g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm);
+  if (red) {
+    hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT, 1>), grid, dim3(256), 0, st, (const TL *)U, (const TS *)in,
+                       (TS *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
+                       (const TS *)bsub, red);
+    hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
+                       red_stride);
+  } else {
+    hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT, 0>), grid, dim3(256), 0, st, (const TL *)U, (const TS *)in,
+                       (TS *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
+                       (const TS *)bsub, (double *)nullptr);
+  }
+}
+
+long wilson_red_blocks(const Geom &g) {
+  SweepMap a = make_sweep(g.L, 36 * 16 + 24 * 8), b = make_sweep(g.L, 36 * 8 + 24 * 4 * 2),
+           c = make_sweep(g.L, 36 * 4 + 24 * 4 * 2);
+  long m = a.nblocks > b.nblocks ? a.nblocks : b.nblocks;
+  return m > c.nblocks ? m : c.nblocks;
+}
+
+int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
+                     const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st) {
+  if (sprec == P64 && lprec == P64)
+    launch_soa<double2, double2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st);
+  else if (sprec == P32 && lprec == P32)
+    launch_soa<float2, float2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st);
+  else if (sprec == P32 && lprec == P16)
+    launch_soa<__half2, float2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st);
+  else return set_error(-1, "wilson_soa: unsupported precision pair link=%d spinor=%d", lprec, sprec);
+  WMG_HIP(hipGetLastError());
+  return 0;
 }
 
 int wilson_soa(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
                hipStream_t st) {
-  if (sprec == P64 && lprec == P64) launch_soa<double2, double2>(g, U, m, in, out, nrhs, st);
-  else if (sprec == P32 && lprec == P32) launch_soa<float2, float2>(g, U, m, in, out, nrhs, st);
-  else if (sprec == P32 && lprec == P16) launch_soa<__half2, float2>(g, U, m, in, out, nrhs, st);
-  else return set_error(-1, "wilson_soa: unsupported precision pair link=%d spinor=%d", lprec, sprec);
-  WMG_HIP(hipGetLastError());
-  return 0;
+  return wilson_soa_fused(g, lprec, U, sprec, m, in, out, nrhs, nullptr, nullptr, nullptr, 0, st);
 }
 
 // ---------------------------------------------------------------- canonical
@@ -314,13 +401,14 @@ int wilson_canonical(const Geom &g, const double *U, double m, const double *in,
 }
 
 // ---------------------------------------------------------------- layouts
-template <class TL> __global__ void k_links_to_soa(const double2 *__restrict__ Uc, TL *__restrict__ Us, long V) {
+template <class TL>
+__global__ void k_links_to_soa(const double2 *__restrict__ Uc, TL *__restrict__ Us, long V, long Vs) {
   long s = blockIdx.x * 256L + threadIdx.x;
   if (s >= V) return;
   for (int mu = 0; mu < 4; mu++)
     for (int e = 0; e < 9; e++) {
       double2 v = Uc[(s * 4 + mu) * 9 + e];
-      TL *d = Us + (size_t)(mu * 9 + e) * V + s;
+      TL *d = Us + (size_t)(mu * 9 + e) * Vs + s;
       if constexpr (sizeof(TL) == 16) *d = v;
       else if constexpr (sizeof(TL) == 8) *d = make_float2((float)v.x, (float)v.y);
       else *d = __floats2half2_rn((float)v.x, (float)v.y);
@@ -330,37 +418,37 @@ template <class TL> __global__ void k_links_to_soa(const double2 *__restrict__ U
 int links_to_soa(const Geom &g, const double *Ucanon, int lprec, void *Usoa, hipStream_t st) {
   dim3 grid((unsigned)((g.V + 255) / 256));
   if (lprec == P64)
-    hipLaunchKernelGGL((k_links_to_soa<double2>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (double2 *)Usoa, g.V);
+    hipLaunchKernelGGL((k_links_to_soa<double2>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (double2 *)Usoa, g.V, g.Vs);
   else if (lprec == P32)
-    hipLaunchKernelGGL((k_links_to_soa<float2>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (float2 *)Usoa, g.V);
+    hipLaunchKernelGGL((k_links_to_soa<float2>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (float2 *)Usoa, g.V, g.Vs);
   else
-    hipLaunchKernelGGL((k_links_to_soa<__half2>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (__half2 *)Usoa, g.V);
+    hipLaunchKernelGGL((k_links_to_soa<__half2>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (__half2 *)Usoa, g.V, g.Vs);
   WMG_HIP(hipGetLastError());
   return 0;
 }
 
-__global__ void k_spinor_to_soa(const double2 *__restrict__ c, double2 *__restrict__ s, long V) {
+__global__ void k_spinor_to_soa(const double2 *__restrict__ c, double2 *__restrict__ s, long V, long Vs) {
   long i = blockIdx.x * 256L + threadIdx.x;
   int r = blockIdx.y;
   if (i >= V) return;
-  for (int k = 0; k < 12; k++) s[((size_t)r * 12 + k) * V + i] = c[((size_t)r * V + i) * 12 + k];
+  for (int k = 0; k < 12; k++) s[((size_t)r * 12 + k) * Vs + i] = c[((size_t)r * V + i) * 12 + k];
 }
-__global__ void k_spinor_from_soa(const double2 *__restrict__ s, double2 *__restrict__ c, long V) {
+__global__ void k_spinor_from_soa(const double2 *__restrict__ s, double2 *__restrict__ c, long V, long Vs) {
   long i = blockIdx.x * 256L + threadIdx.x;
   int r = blockIdx.y;
   if (i >= V) return;
-  for (int k = 0; k < 12; k++) c[((size_t)r * V + i) * 12 + k] = s[((size_t)r * 12 + k) * V + i];
+  for (int k = 0; k < 12; k++) c[((size_t)r * V + i) * 12 + k] = s[((size_t)r * 12 + k) * Vs + i];
 }
 
 int spinor_to_soa(const Geom &g, const double *canon, double2 *soa, int nrhs, hipStream_t st) {
   dim3 grid((unsigned)((g.V + 255) / 256), nrhs);
-  hipLaunchKernelGGL(k_spinor_to_soa, grid, dim3(256), 0, st, (const double2 *)canon, soa, g.V);
+  hipLaunchKernelGGL(k_spinor_to_soa, grid, dim3(256), 0, st, (const double2 *)canon, soa, g.V, g.Vs);
   WMG_HIP(hipGetLastError());
   return 0;
 }
 int spinor_from_soa(const Geom &g, const double2 *soa, double *canon, int nrhs, hipStream_t st) {
   dim3 grid((unsigned)((g.V + 255) / 256), nrhs);
-  hipLaunchKernelGGL(k_spinor_from_soa, grid, dim3(256), 0, st, soa, (double2 *)canon, g.V);
+  hipLaunchKernelGGL(k_spinor_from_soa, grid, dim3(256), 0, st, soa, (double2 *)canon, g.V, g.Vs);
   WMG_HIP(hipGetLastError());
   return 0;
 }

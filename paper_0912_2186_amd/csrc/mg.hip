@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "wmg_internal.h"
@@ -111,41 +112,25 @@ __global__ void k_cg_check(double *cg, int nrhs, int *alldone) {
 }
 
 // GCR coefficient bookkeeping.  gcr layout per rhs (stride GS doubles):
-//   beta[K][K][2] | gamma[K] | alpha[K][2] | c[K][2] | tmp[2K] | mask
+//   beta[K][K][2] | wn2[K] (|w_k|^2 of the unnormalised basis) | alpha[K][2] |
+//   c[K][2] | tmp[2K] (first-pass projections) | tmp2[2K] (second pass)
 constexpr int GK = KMAX;
 constexpr int G_BETA = 0, G_GAMMA = G_BETA + GK * GK * 2, G_ALPHA = G_GAMMA + GK, G_C = G_ALPHA + GK * 2,
-              G_TMP = G_C + GK * 2, G_MASK = G_TMP + 2 * GK, GS = G_MASK + 8;
-
-__global__ void k_gcr_negate_tmp(double *g, int k, int nrhs) {
-  int r = blockIdx.x, j = threadIdx.x;
-  if (r >= nrhs || j >= 2 * k) return;
-  g[r * GS + G_TMP + j] = -g[r * GS + G_TMP + j];
-}
-// beta[j][k] (+)= tmp[j], tmp = the projections <w_j, w> of this pass
-__global__ void k_gcr_accum_beta(double *g, int k, int nrhs, int first) {
-  int r = blockIdx.x, j = threadIdx.x;
-  if (r >= nrhs || j >= k) return;
-  double *b = g + r * GS + G_BETA + (j * GK + k) * 2;
-  double re = g[r * GS + G_TMP + 2 * j], im = g[r * GS + G_TMP + 2 * j + 1];
-  if (first) { b[0] = re; b[1] = im; }
-  else { b[0] += re; b[1] += im; }
-}
-__global__ void k_gcr_gamma(double *g, const double *red, int k, int nrhs) {
+              G_TMP = G_C + GK * 2, G_TMP2 = G_TMP + 2 * GK, GS = G_TMP2 + 2 * GK + 8;
+// wn2[k] = |w_k|^2; alpha_k = <w_k, r>/|w_k|^2 for participating rhs, else 0
+// (red holds <w_k, r> in slots 0,1 and |w_k|^2 in slot 2)
+__global__ void k_gcr_alpha2(double *g, const double *red, const double *mask, int k, int nrhs) {
   int r = threadIdx.x;
   if (r >= nrhs) return;
-  g[r * GS + G_GAMMA + k] = sqrt(red[r * 4]);
+  double q = red[r * 4 + 2];
+  g[r * GS + G_GAMMA + k] = q;
+  bool ok = mask[r] > 0 && q > 0;
+  g[r * GS + G_ALPHA + 2 * k] = ok ? red[r * 4] / q : 0.0;
+  g[r * GS + G_ALPHA + 2 * k + 1] = ok ? red[r * 4 + 1] / q : 0.0;
 }
-__global__ void k_gcr_alpha(double *g, const double *red, const double *mask, int k, int nrhs) {
-  int r = threadIdx.x;
-  if (r >= nrhs) return;
-  double m = mask[r];
-  double gam = g[r * GS + G_GAMMA + k];
-  bool ok = m > 0 && gam > 0;
-  g[r * GS + G_ALPHA + 2 * k] = ok ? red[r * 4] : 0.0;
-  g[r * GS + G_ALPHA + 2 * k + 1] = ok ? red[r * 4 + 1] : 0.0;
-}
-// back substitution: c_j = (alpha_j - sum_{i>j} beta_ji c_i) / gamma_j
-__global__ void k_gcr_trisolve(double *g, int k, int nrhs) {
+// back substitution for A z_k = w_k + sum_{j<k} beta_jk w_j:
+//   c_j = alpha_j - sum_{i>j} beta_ji c_i   (c_j = 0 where w_j vanished)
+__global__ void k_gcr_trisolve2(double *g, int k, int nrhs) {
   int r = threadIdx.x;
   if (r >= nrhs) return;
   double *G = g + r * GS;
@@ -157,9 +142,9 @@ __global__ void k_gcr_trisolve(double *g, int k, int nrhs) {
       tr -= br * cr - bi * ci;
       ti -= br * ci + bi * cr;
     }
-    double gm = G[G_GAMMA + j];
-    G[G_C + 2 * j] = gm > 0 ? tr / gm : 0.0;
-    G[G_C + 2 * j + 1] = gm > 0 ? ti / gm : 0.0;
+    bool ok = G[G_GAMMA + j] > 0;
+    G[G_C + 2 * j] = ok ? tr : 0.0;
+    G[G_C + 2 * j + 1] = ok ? ti : 0.0;
   }
 }
 
@@ -226,6 +211,7 @@ struct wmg_ctx {
   double *cg = nullptr;
   double *gcr = nullptr;
   double *mask = nullptr;
+  double *dred = nullptr;  // per-workgroup partials of the fused Dslash reductions
   int *flag = nullptr;
   double *hbuf = nullptr;  // pinned host mirror
   GcrBuf gb[2][2];         // [level 0 / level 1][FP64 / FP32 inner precision]
@@ -291,6 +277,10 @@ static int dalloc(void **p, size_t bytes) {
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) return set_error(WMG_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  // zero-filled: the site padding of fine-lattice fields must read as zero
+  // in every vector kernel that sweeps whole arrays
+  e = hipMemset(*p, 0, bytes);
+  if (e != hipSuccess) return set_error(WMG_EHIP, "hipMemset: %s", hipGetErrorString(e));
   return 0;
 }
 #define TRY(x)            \
@@ -379,18 +369,44 @@ static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, voi
   return rc;
 }
 
+// fine operator with the smoother's fusions: out = [bsub -] D in, and with
+// reduce also <out, in>, |out|^2 -> red_out (cycle links)
+static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int nrhs, const void *bsub, bool reduce) {
+  Level &L = c->lv[0];
+  int lp = prec == P64 ? P64 : P16;
+  c->st_fine++;
+  if (prec == P64) c->st_fine64++;
+  double lb = lp == P64 ? 16 : 4, sb = prec == P64 ? 16 : 8;
+  int slot = prof_begin(c, prec == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE,
+                        (double)L.g.V * (36 * lb + (bsub ? 36.0 : 24.0) * sb * nrhs));
+  int rc = wilson_soa_fused(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, bsub, reduce ? c->dred : nullptr, c->red_out,
+                            4, c->st);
+  prof_end(c, slot);
+  return rc;
+}
+
 // ------------------------------------------------------------ MR smoother
-// nsteps minimal-residual steps on A e = r from e (post-smoother, Sec. 3)
+// nsteps minimal-residual steps on A e = r from e (post-smoother, Sec. 3).
+// On the fine level the residual and the two step reductions are fused into
+// the operator's kernel.
 static int mr_smooth(wmg_ctx *c, int l, int prec, const void *r, void *e, int nsteps, int nrhs) {
   Level &L = c->lv[l];
   void *s, *q;
   TRY(level_vec(c, l, prec, VS, &s, nrhs));
   TRY(level_vec(c, l, prec, VQ, &q, nrhs));
-  TRY(apply_op(c, l, prec, e, q, nrhs, true));
-  TRY(csub(prec, r, q, s, L.n, nrhs, c->st));
+  if (L.fine) {
+    TRY(fine_apply_fused(c, prec, e, s, nrhs, r, false));
+  } else {
+    TRY(apply_op(c, l, prec, e, q, nrhs, true));
+    TRY(csub(prec, r, q, s, L.n, nrhs, c->st));
+  }
   for (int k = 0; k < nsteps; k++) {
-    TRY(apply_op(c, l, prec, s, q, nrhs, true));
-    TRY(dot_norm(c->red, prec, q, s, L.n, nrhs, c->red_out, 4, c->st));
+    if (L.fine) {
+      TRY(fine_apply_fused(c, prec, s, q, nrhs, nullptr, true));
+    } else {
+      TRY(apply_op(c, l, prec, s, q, nrhs, true));
+      TRY(dot_norm(c->red, prec, q, s, L.n, nrhs, c->red_out, 4, c->st));
+    }
     dim3 g = grid_for<double2>(L.n, nrhs);
     if (prec == P64)
       hipLaunchKernelGGL(k_mr_update<double2>, g, dim3(256), 0, c->st, c->red_out, (double2 *)e, (double2 *)s,
@@ -496,7 +512,7 @@ static int gcr_buffers(wmg_ctx *c, int l, int prec, int nrhs, GcrBuf **out) {
   int slot = (l == 0 ? 0 : 1);
   GcrBuf &B = c->gb[slot][prec == P64 ? 0 : 1];
   Level &L = c->lv[l];
-  long nalloc = L.g.V * (L.fine ? 12 : 2 * c->lv[l - 1].nv_max);
+  long nalloc = L.n_alloc;
   bool ok = B.x64 && B.prec == prec && B.nrhs >= nrhs && B.n >= nalloc;
   if (!ok) {
     // release and reallocate
@@ -599,21 +615,20 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
         TRY(mr_smooth(c, l, ip, B.rin, z, c->p.post_smooth, nrhs));
       }
       TRY(apply_op(c, l, ip, z, w, nrhs, false));
-      if (k > 0) {
-        for (int pass = 0; pass < 2; pass++) {
-          TRY(multi_dot(c->red, ip, (const void *const *)B.wdev, k, w, n, nrhs, c->gcr + G_TMP, GS, st));
-          hipLaunchKernelGGL(k_gcr_accum_beta, dim3(nrhs), dim3(KMAX), 0, st, c->gcr, k, nrhs, pass == 0 ? 1 : 0);
-          hipLaunchKernelGGL(k_gcr_negate_tmp, dim3(nrhs), dim3(2 * KMAX), 0, st, c->gcr, k, nrhs);
-          TRY(multi_caxpy(ip, w, ip, (const void *const *)B.wdev, k, c->gcr + G_TMP, GS, 1.0, 1, n, nrhs, st));
-        }
+      // classical Gram-Schmidt twice against the unnormalised w_j, fused:
+      // dots | project + new dots | project + <w, r> + |w|^2
+      if (k == 0) {
+        TRY(dot_norm(c->red, ip, w, B.rin, n, nrhs, c->red_out, 4, st));
+      } else {
+        TRY(multi_dot(c->red, ip, (const void *const *)B.wdev, k, w, n, nrhs, c->gcr + G_TMP, GS, st));
+        TRY(gcr_project(c->red, ip, 1, (const void *const *)B.wdev, k, w, nullptr, c->gcr + G_TMP, GS,
+                        c->gcr + G_GAMMA, GS, c->gcr + G_BETA, GS, k, n, nrhs, c->gcr + G_TMP2, GS, st));
+        TRY(gcr_project(c->red, ip, 2, (const void *const *)B.wdev, k, w, B.rin, c->gcr + G_TMP2, GS,
+                        c->gcr + G_GAMMA, GS, c->gcr + G_BETA, GS, k, n, nrhs, c->red_out, 4, st));
       }
-      TRY(norm2(c->red, ip, w, n, nrhs, c->red_out, 4, st));
-      hipLaunchKernelGGL(k_gcr_gamma, dim3(1), dim3(64), 0, st, c->gcr, c->red_out, k, nrhs);
-      TRY(scale_inv_sqrt(ip, w, c->red_out, 4, n, nrhs, st));
-      TRY(dot(c->red, ip, w, B.rin, n, nrhs, c->red_out, 4, st));
-      hipLaunchKernelGGL(k_gcr_alpha, dim3(1), dim3(64), 0, st, c->gcr, c->red_out, c->mask, k, nrhs);
-      TRY(caxpy_dev(ip, c->gcr + G_ALPHA + 2 * k, GS, -1.0, w, B.rin, n, nrhs, st));
-      TRY(norm2(c->red, ip, B.rin, n, nrhs, c->red_out, 4, st));
+      hipLaunchKernelGGL(k_gcr_alpha2, dim3(1), dim3(64), 0, st, c->gcr, c->red_out, c->mask, k, nrhs);
+      // r_in -= alpha_k w_k and |r_in|^2
+      TRY(caxpy_norm(c->red, ip, c->gcr + G_ALPHA + 2 * k, GS, w, B.rin, n, nrhs, c->red_out, 4, st));
       WMG_HIP(hipMemcpyAsync(c->hbuf, c->red_out, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, st));
       TRY(sync(c));
       bool allfrozen = true;
@@ -630,7 +645,7 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
       total++;
       if (allfrozen) break;
     }
-    hipLaunchKernelGGL(k_gcr_trisolve, dim3(1), dim3(64), 0, st, c->gcr, k, nrhs);
+    hipLaunchKernelGGL(k_gcr_trisolve2, dim3(1), dim3(64), 0, st, c->gcr, k, nrhs);
     TRY(multi_caxpy(P64, B.x64, ip, (const void *const *)B.zdev, k, c->gcr + G_C, GS, 1.0, 1, n, nrhs, st));
     // reliable update: true residual in FP64
     TRY(apply_op(c, l, P64, B.x64, B.t64, nrhs, false));
@@ -714,7 +729,7 @@ static int setup_level(wmg_ctx *c, int l) {
   long n = F.n;
   std::vector<int> its;
   for (int k = 0; k < nv; k++) {
-    TRY(start_vectors(F.g.V, F.dof, c->p.seed, l, k, 1, B->x64, F.fine ? 1 : 0, F.g.V, c->st));
+    TRY(start_vectors(F.g.V, F.dof, c->p.seed, l, k, 1, B->x64, F.fine ? 1 : 0, F.g.Vs, c->st));
     if (k > 0) TRY(build_level(c, l, k));
     TRY(zero(P64, B->b64, n, 1, c->st));
     int rc = gcr_solve(c, l, *B, 1, 0.0, c->p.setup_iters, k > 0 ? 1 : 0, 0.0, true, its, nullptr);
@@ -756,6 +771,7 @@ static void free_ctx(wmg_ctx *c) {
   for (auto &e : c->ev_pool) (void)hipEventDestroy(e);
   red_free(c->red);
   if (c->dsc) (void)hipFree(c->dsc);
+  if (c->dred) (void)hipFree(c->dred);
   if (c->flag) (void)hipFree(c->flag);
   if (c->hbuf) (void)hipHostFree(c->hbuf);
   if (c->st) (void)hipStreamDestroy(c->st);
@@ -817,6 +833,7 @@ static Geom to_geom(const int L[4]) {
   Geom g;
   for (int i = 0; i < 4; i++) g.L[i] = L[i];
   g.V = (long)L[0] * L[1] * L[2] * L[3];
+  g.Vs = g.V;
   return g;
 }
 
@@ -881,15 +898,17 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
   {
     Level &F = c->lv[0];
     F.g = to_geom(g->L);
+    F.g.Vs = fine_stride(F.g.V);
     F.fine = true;
     F.dof = 12;
-    F.n = F.n_alloc = F.g.V * 12;
+    F.n = F.n_alloc = F.g.Vs * 12;
     F.m = m;
-    CK(dalloc(&F.U[P64], 16 * 36 * (size_t)F.g.V));
+    CK(dalloc((void **)&c->dred, sizeof(double) * 3 * (size_t)p.nrhs_max * wilson_red_blocks(F.g)));
+    CK(dalloc(&F.U[P64], 16 * 36 * (size_t)F.g.Vs));
     CK(links_to_soa(F.g, U, P64, F.U[P64], c->st));
-    CK(dalloc(&F.U[P32], 8 * 36 * (size_t)F.g.V));
+    CK(dalloc(&F.U[P32], 8 * 36 * (size_t)F.g.Vs));
     CK(links_to_soa(F.g, U, P32, F.U[P32], c->st));
-    CK(dalloc(&F.U[P16], 4 * 36 * (size_t)F.g.V));
+    CK(dalloc(&F.U[P16], 4 * 36 * (size_t)F.g.Vs));
     CK(links_to_soa(F.g, U, P16, F.U[P16], c->st));
     for (int l = 0; l + 1 < c->nl; l++) {
       Level &A = c->lv[l], &C = c->lv[l + 1];
@@ -1174,7 +1193,7 @@ int mg_time_dslash(wmg_ctx *c, int prec, int nrhs, int reps, double *ms) {
   TRY(level_vec(c, 0, sp, VT, &b, nrhs));
   void *a64;
   TRY(level_vec(c, 0, P64, VE2, &a64, 1));
-  TRY(start_vectors(F.g.V, 12, 99, 7, 0, 1, (double2 *)a64, 1, F.g.V, c->st));
+  TRY(start_vectors(F.g.V, 12, 99, 7, 0, 1, (double2 *)a64, 1, F.g.Vs, c->st));
   for (int r = 0; r < nrhs; r++) TRY(copy(sp, (char *)a + csize(sp) * (size_t)F.n * r, P64, a64, F.n, 1, c->st));
   TRY(wilson_soa(F.g, lp, F.U[lp], sp, F.m, a, b, nrhs, c->st));  // warm-up
   hipEvent_t e0, e1;
@@ -1220,33 +1239,60 @@ int mg_profile_get(wmg_ctx *c, int kind, int *launches, double *total_ms, double
 }
 
 // ------------------------------------------------------------ batch
+// Uneven batch: one context (own stream, own buffers) per instance; setup
+// and solve of all instances are driven from one host thread each, so the
+// instances' kernels run concurrently on the device and small lattices
+// fill the GPU together.
 int mg_setup_batch(int n, const wmg_geom *g, const double *const *U, const double *m, int Nv, const int block[4],
                    const wmg_params *p, wmg_ctx **out) {
   g_err[0] = 0;
-  if (n < 1 || !g || !U || !m || !out) return set_error(WMG_EINVAL, "bad argument");
+  if (n < 1 || n > 256 || !g || !U || !m || !out || !block) return set_error(WMG_EINVAL, "bad argument");
   wmg_ctx *parent = new wmg_ctx();
   if (p) parent->p = *p;
   else wmg_default_params(&parent->p);
+  std::vector<wmg_ctx *> ctx(n, nullptr);
+  std::vector<int> rcs(n, 0);
+  std::vector<std::string> msgs(n);
+  std::vector<std::thread> th;
+  for (int i = 0; i < n; i++)
+    th.emplace_back([&, i]() {
+      rcs[i] = mg_setup(&g[i], U[i], m[i], Nv, block, p, &ctx[i]);
+      if (rcs[i]) msgs[i] = g_err;
+    });
+  for (auto &t : th) t.join();
+  int rc = 0;
   for (int i = 0; i < n; i++) {
-    wmg_ctx *c = nullptr;
-    int rc = mg_setup(&g[i], U[i], m[i], Nv, block, p, &c);
-    if (rc) {
-      free_ctx(parent);
-      return rc;
+    if (ctx[i]) parent->batch.push_back(ctx[i]);
+    if (rcs[i] && !rc) {
+      rc = rcs[i];
+      set_error(rc, "instance %d: %s", i, msgs[i].c_str());
     }
-    parent->batch.push_back(c);
+  }
+  if (rc) {
+    free_ctx(parent);
+    return rc;
   }
   *out = parent;
   return 0;
 }
 
 int mg_solve_batch(wmg_ctx *c, const double *const *b, double *const *x, double tol, wmg_stats *st) {
+  g_err[0] = 0;
   if (!c || c->batch.empty() || !b || !x) return set_error(WMG_EINVAL, "not a batch context");
+  int n = (int)c->batch.size();
+  std::vector<int> rcs(n, 0);
+  std::vector<std::string> msgs(n);
+  std::vector<std::thread> th;
+  for (int i = 0; i < n; i++)
+    th.emplace_back([&, i]() {
+      rcs[i] = mg_solve(c->batch[i], b[i], x[i], tol, 1, st ? &st[i] : nullptr);
+      if (rcs[i]) msgs[i] = g_err;
+    });
+  for (auto &t : th) t.join();
   int worst = 0;
-  for (size_t i = 0; i < c->batch.size(); i++) {
-    int rc = mg_solve(c->batch[i], b[i], x[i], tol, 1, st ? &st[i] : nullptr);
-    if (rc < 0) return rc;
-    if (rc > worst) worst = rc;
+  for (int i = 0; i < n; i++) {
+    if (rcs[i] < 0) return set_error(rcs[i], "instance %d: %s", i, msgs[i].c_str());
+    if (rcs[i] > worst) worst = rcs[i];
   }
   return worst;
 }

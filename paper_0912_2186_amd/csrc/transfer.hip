@@ -37,23 +37,31 @@ __device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1
 // with w = Philox(ctr = (c, s, alpha, lvl), key = seed).  Written in the
 // level's vector layout (fine: SoA [12][V]; coarse: AoS [V][dof]).
 __global__ void k_start_vectors(long nsite, int dof, uint32_t k0, uint32_t k1, int lvl, int alpha0, double2 *out,
-                                int fine_soa) {
+                                int fine_soa, long Vs) {
   long i = blockIdx.x * (long)TB + threadIdx.x;
   int a = blockIdx.y;
   if (i >= nsite * dof) return;
   long s, c;
-  if (fine_soa) { c = i / nsite; s = i % nsite; }
-  else { s = i / dof; c = i % dof; }
+  size_t dst;
+  if (fine_soa) {
+    c = i / nsite;
+    s = i % nsite;
+    dst = (size_t)a * 12 * Vs + (size_t)c * Vs + s;
+  } else {
+    s = i / dof;
+    c = i % dof;
+    dst = (size_t)a * nsite * dof + i;
+  }
   uint32_t w[4] = {(uint32_t)c, (uint32_t)s, (uint32_t)(alpha0 + a), (uint32_t)lvl};
   philox10(w, k0, k1);
-  out[(size_t)a * nsite * dof + i] = make_double2((double)(int32_t)w[0] * 0x1p-31, (double)(int32_t)w[1] * 0x1p-31);
+  out[dst] = make_double2((double)(int32_t)w[0] * 0x1p-31, (double)(int32_t)w[1] * 0x1p-31);
 }
 
 int start_vectors(long nsite, int dof, uint64_t seed, int lvl, int alpha0, int count, double2 *out, int fine_soa,
-                  long /*V*/, hipStream_t st) {
+                  long Vs, hipStream_t st) {
   dim3 grid((unsigned)((nsite * dof + TB - 1) / TB), count);
   hipLaunchKernelGGL(k_start_vectors, grid, dim3(TB), 0, st, nsite, dof, (uint32_t)seed, (uint32_t)(seed >> 32), lvl,
-                     alpha0, out, fine_soa);
+                     alpha0, out, fine_soa, Vs);
   WMG_HIP(hipGetLastError());
   return 0;
 }
@@ -62,6 +70,7 @@ int start_vectors(long nsite, int dof, uint64_t seed, int lvl, int alpha0, int c
 struct BlockGeom {
   int L[4], b[4], Lc[4];
   long V, Vc;
+  long Vs;  // fine-lattice site stride
   int bs, dof;
 };
 
@@ -73,6 +82,7 @@ static BlockGeom make_bg(const Geom &g, int dof, const int b[4]) {
     bg.Lc[i] = g.L[i] / b[i];
   }
   bg.V = g.V;
+  bg.Vs = g.Vs;
   bg.Vc = (long)bg.Lc[0] * bg.Lc[1] * bg.Lc[2] * bg.Lc[3];
   bg.bs = b[0] * b[1] * b[2] * b[3];
   bg.dof = dof;
@@ -101,7 +111,7 @@ template <int FINE> __device__ __forceinline__ void elem_kc(const BlockGeom &bg,
 
 // address of component c of site s, rhs r, in a level vector
 template <int FINE> __device__ __forceinline__ size_t vec_addr(const BlockGeom &bg, int r, long s, int c) {
-  if (FINE) return ((size_t)r * 12 + c) * bg.V + s;
+  if (FINE) return ((size_t)r * 12 + c) * bg.Vs + s;
   return ((size_t)r * bg.V + s) * bg.dof + c;
 }
 
@@ -169,7 +179,8 @@ __global__ void __launch_bounds__(TB) k_block_gs(BlockGeom bg, int nv, const dou
         int k, c;
         elem_kc<FINE>(bg, my_e[q], k, c);
         long s = block_site(bg, xh, k);
-        v[q] = ldc(vecs + (size_t)a * bg.V * bg.dof + (FINE ? (size_t)c * bg.V + s : (size_t)s * bg.dof + c));
+        v[q] = ldc(vecs + (FINE ? (size_t)a * 12 * bg.Vs + (size_t)c * bg.Vs + s
+                                : (size_t)a * bg.V * bg.dof + (size_t)s * bg.dof + c));
         n0loc += v[q].re * v[q].re + v[q].im * v[q].im;
       }
     }
@@ -416,7 +427,7 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, cons
         int ee = chi * H + e0 + e;
         int c = ee / bg.bs, k = ee % bg.bs;
         long st = block_site(bg, xh, k);
-        float2 v = fine[((size_t)(r0 + r) * 12 + c) * bg.V + st];
+        float2 v = fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + st];
         Bt[r * RLD + e] = v.x;
         Bt[(R + r) * RLD + e] = v.y;
         Bt[r * RLD + RCH + e] = v.y;
@@ -577,7 +588,7 @@ __global__ void k_P_to_vec(BlockGeom bg, int nv, int fine, const double2 *__rest
   if (fine) { c = e / bg.bs; k = e % bg.bs; }
   else { k = e / bg.dof; c = e % bg.dof; }
   long s = block_site(bg, xh, k);
-  size_t dst = fine ? (a * 12 + c) * bg.V + s : (a * bg.V + s) * bg.dof + c;
+  size_t dst = fine ? (a * 12 + c) * bg.Vs + s : (a * bg.V + s) * bg.dof + c;
   vec[dst] = P[i];
 }
 

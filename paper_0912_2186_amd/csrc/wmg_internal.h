@@ -1,9 +1,10 @@
 // Internal declarations of the gfx950 multigrid library (not installed).
 //
 // Layouts in device memory (all chosen for coalesced, site-fastest access):
-//   fine spinor   [rhs][12][V]   complex (double2 / float2), component
-//                 c = spin*3 + colour, lexicographic site s = x+Lx(y+Ly(z+Lz t))
-//   gauge links   [4][9][V]      complex (double2 / float2 / __half2), element
+//   fine spinor   [rhs][12][Vs]  complex (double2 / float2), component
+//                 c = spin*3 + colour, lexicographic site s = x+Lx(y+Ly(z+Lz t)),
+//                 Vs = fine_stride(V) (padding entries are zero)
+//   gauge links   [4][9][Vs]     complex (double2 / float2 / __half2), element
 //                 (mu, 3a+b) of U_mu(s)
 //   coarse vector [rhs][Vc][n]   complex, n = 2 Nv dof per site ordered (chi, alpha)
 //   coarse links  [Vc][9][n][n]  complex, direction d = 0 local, 1+mu forward,
@@ -67,8 +68,15 @@ template <> struct store_traits<__half2> { using real = float; };
 // ---------------------------------------------------------------- geometry
 struct Geom {
   int L[4];
-  long V;
+  long V;   // sites
+  long Vs;  // site stride of fine-lattice SoA arrays (>= V, see fine_stride)
 };
+
+// Fine-lattice SoA fields keep their components fine_stride(V) sites apart
+// rather than V: with V a power of two every component of a site would sit
+// at the same offset modulo the cache-set period and the 12 spinor and 36
+// link components of one site would compete for the same L2 sets.
+__host__ __device__ __forceinline__ long fine_stride(long V) { return (V + 63) / 64 * 64 + 320; }
 
 __host__ __device__ __forceinline__ void site_coords(const int L[4], long s, int x[4]) {
   x[0] = (int)(s % L[0]); s /= L[0];
@@ -104,6 +112,11 @@ int set_error(int code, const char *fmt, ...);
 int wilson_canonical(const Geom &g, const double *U, double m, const double *in, double *out, hipStream_t st);
 int wilson_soa(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
                hipStream_t st);
+// out = [bsub -] D in; with red != nullptr also <out, in>, |out|^2 per rhs ->
+// red_out[rhs * red_stride + 0..2] (red: scratch of nrhs * wilson_red_blocks * 3)
+int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
+                     const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st);
+long wilson_red_blocks(const Geom &g);
 int links_to_soa(const Geom &g, const double *Ucanon, int lprec, void *Usoa, hipStream_t st);
 int spinor_to_soa(const Geom &g, const double *canon, double2 *soa, int nrhs, hipStream_t st);
 int spinor_from_soa(const Geom &g, const double2 *soa, double *canon, int nrhs, hipStream_t st);
@@ -139,6 +152,13 @@ int axpby(int prec, double a, const void *x, double b, void *y, long n, int nrhs
 // out[rhs][j] = <x_j, y> for j < k
 int multi_dot(Reducer &R, int prec, const void *const *xs_dev, int k, const void *y, long n, int nrhs, double *out,
               int out_stride, hipStream_t st);
+// GCR Gram-Schmidt pass against unnormalised w_j (see blas.hip)
+int gcr_project(Reducer &R, int prec, int pass, const void *const *W, int k, void *w, const void *r, const double *d,
+                int dstride, const double *wn2, int wstride, double *beta, int bstride, int kcol, long n, int nrhs,
+                double *out, int out_stride, hipStream_t st);
+// y -= a x and |y|^2 -> out
+int caxpy_norm(Reducer &R, int prec, const double *a, int astride, const void *x, void *y, long n, int nrhs,
+               double *out, int out_stride, hipStream_t st);
 // y = a - b
 int csub(int prec, const void *a, const void *b, void *y, long n, int nrhs, hipStream_t st);
 // x *= 1/sqrt(nrm2[rhs])  (nrm2 device)
@@ -146,8 +166,10 @@ int scale_inv_sqrt(int prec, void *x, const double *nrm2, int stride, long n, in
 int sigma3(int prec, void *x, long nsite, int dof, int nrhs, hipStream_t st);
 
 // transfer.hip
+// count vectors; fine (SoA): component stride Vs, vector stride 12*Vs;
+// coarse (AoS): vector stride nsite*dof
 int start_vectors(long nsite, int dof, uint64_t seed, int lvl, int alpha0, int count, double2 *out_soa_or_aos,
-                  int fine_soa, long V, hipStream_t st);
+                  int fine_soa, long Vs, hipStream_t st);
 int block_orthonormalize(const Geom &g, int dof, const int b[4], int nv, const double2 *vecs, int fine_soa,
                          double2 *P, int *fail_dev, hipStream_t st);
 int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,

@@ -106,6 +106,8 @@ _sig = {
     "mg_prolong": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_coarse_apply": (_i, [_vp, _i, _vp, _vp, _i, _i]),
     "mg_coarse_apply_f32": (_i, [_vp, _i, _vp, _vp, _i, _i]),
+    "mg_restrict_f32": (_i, [_vp, _i, _vp, _vp, _i]),
+    "mg_prolong_f32": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_apply_fine": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_cycle": (_i, [_vp, _vp, _vp]),
     "mg_last_iters": (_i, [_vp, _P(_i), _i]),
@@ -252,6 +254,14 @@ class MG:
                         nrhs: int = 1) -> None:
         torch.cuda.synchronize()
         _check(_lib.mg_coarse_apply(self.h, int(level), _ptr(inp), _ptr(out), int(bool(dagger)), int(nrhs)))
+
+    def mg_restrict_f32(self, level: int, fine: torch.Tensor, coarse: torch.Tensor, nrhs: int = 1) -> None:
+        torch.cuda.synchronize()
+        _check(_lib.mg_restrict_f32(self.h, int(level), _ptr(fine), _ptr(coarse), int(nrhs)))
+
+    def mg_prolong_f32(self, level: int, coarse: torch.Tensor, fine: torch.Tensor, nrhs: int = 1) -> None:
+        torch.cuda.synchronize()
+        _check(_lib.mg_prolong_f32(self.h, int(level), _ptr(coarse), _ptr(fine), int(nrhs)))
 
     def mg_coarse_apply_f32(self, level: int, inp: torch.Tensor, out: torch.Tensor, dagger: bool = False,
                             nrhs: int = 1) -> None:

@@ -81,3 +81,12 @@ def test_default_params(lib):
     # Sec. 3: 4^4 aggregates, 4 post-smoothing steps, GCR(8), W-cycle
     assert list(p.block)[:4] == [4, 4, 4, 4]
     assert p.post_smooth == 4 and p.gcr_restart == 8 and p.cycle == 1
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr

@@ -146,6 +146,35 @@ def test_mfma_coarse_apply_multi_rhs(wmg, nv, nrhs):
         assert e < 2e-6
 
 
+@pytest.mark.parametrize("L,block,nv,nrhs", [((8, 8, 8, 16), (4, 4, 4, 4), 24, 28), ((8, 8, 8, 8), (4, 4, 4, 4), 6, 1),
+                                             ((8, 8, 8, 8), (4, 4, 4, 4), 8, 37), ((8, 4, 4, 8), (2, 2, 2, 4), 5, 3)])
+def test_low_precision_transfers_multi_rhs(wmg, L, block, nv, nrhs):
+    """Restriction (matrix cores where the aggregate allows) and
+    prolongation with FP32 vectors and the FP16-stored prolongator, many
+    right-hand sides, against the oracle's FP64 P^dag and P."""
+    say("lowprec transfers", L, block, nv, nrhs)
+    V = vol(L)
+    U = inputs.gauge_field(L, 0.5, 308)
+    p = wmg.default_params(setup_iters=0, seed=2, nrhs_max=nrhs, precision=wmg.WMG_MIXED)
+    mg = wmg.MG(L, dev(U), -0.1, nv, block, p)
+    vecs = rand_vecs(nv, V, 12, 91)
+    mg.mg_set_null_vectors(0, dev(vecs))
+    P = oracle.block_orthonormalize(L, 12, block, vecs)
+    Vc = vol(oracle.coarse_dims(L, block))
+    f = inputs.gaussian_rhs(L, 92, nrhs)
+    c = empty((nrhs, Vc, 2 * nv))
+    mg.mg_restrict_f32(0, dev(f), c, nrhs)
+    ref = np.stack([oracle.restrict(L, 12, block, P, f[r]) for r in range(nrhs)])
+    e1 = relerr(host(c), ref)
+    cr = rand_vecs(nrhs, Vc, 2 * nv, 93)
+    fo = empty((nrhs, V, 12))
+    mg.mg_prolong_f32(0, dev(cr), fo, nrhs)
+    ref2 = np.stack([oracle.prolong(L, 12, block, P, cr[r]) for r in range(nrhs)])
+    e2 = relerr(host(fo), ref2)
+    say("  restrict relerr", e1, "prolong relerr", e2)
+    assert e1 < 2e-3 and e2 < 2e-3
+
+
 def test_three_level_galerkin_from_given_vectors(wmg):
     L = (8, 8, 8, 8)
     say("three-level galerkin", L)
@@ -330,3 +359,31 @@ def test_bicgstab_matches_oracle(wmg):
     say("  gpu", st, "oracle", it, rr)
     assert st["converged"] and abs(st["outer_iters"] - it) <= 2
     assert np.linalg.norm(b - oracle.wilson(L, U, 0.0, host(x))) <= 1e-10 * np.linalg.norm(b) * 1.0001
+
+
+def test_uneven_batch_matches_single_instances(wmg):
+    """Uneven batch: instances of different shapes, links and masses
+    (eps_k = 0.3 + 0.1k, m_k = -0.1 - 0.2k/3) set up and solved together;
+    every solution meets the oracle's residual and equals the standalone
+    solve of the same instance."""
+    shapes = [(8, 8, 8, 8), (8, 8, 8, 12), (12, 8, 8, 8), (8, 8, 12, 16)]
+    say("uneven batch", shapes)
+    Us, ms, bs = [], [], []
+    for k, L in enumerate(shapes):
+        Us.append(inputs.gauge_field(L, 0.3 + 0.1 * k, 1000 + 10 * k))
+        ms.append(-0.1 - 0.2 * k / 3)
+        bs.append(inputs.gaussian_rhs(L, 2000 + k))
+    p = wmg.default_params(setup_iters=4, seed=77)
+    batch = wmg.MGBatch(shapes, [dev(U) for U in Us], ms, 6, (4, 4, 4, 4), p)
+    xs = [empty((1, vol(L), 12)) for L in shapes]
+    sts = batch.mg_solve_batch([dev(b) for b in bs], xs, 1e-10)
+    for k, L in enumerate(shapes):
+        xh = host(xs[k])[0]
+        res = np.linalg.norm(bs[k][0] - oracle.wilson(L, Us[k], ms[k], xh)) / np.linalg.norm(bs[k][0])
+        say("  instance", k, L, sts[k]["outer_iters"], res)
+        assert sts[k]["converged"] and res <= 1e-10 * 1.0001
+        single = wmg.MG(L, dev(Us[k]), ms[k], 6, (4, 4, 4, 4), p)
+        x1 = empty((1, vol(L), 12))
+        s1 = single.mg_solve(dev(bs[k]), x1, 1e-10)
+        assert s1["outer_iters"] == sts[k]["outer_iters"]
+        assert relerr(host(x1)[0], xh) < 1e-12
