@@ -3,10 +3,12 @@
 //
 // Reductions are two-stage and order-fixed: every workgroup reduces its
 // grid-stride slice (FP64 accumulation whatever the storage precision) into
-// a partial slot; the last workgroup to finish (atomic ticket) sums the
+// a partial slot; a second small kernel (one workgroup per rhs) sums the
 // partials in slot order and writes the result to device memory, so the
 // result is bitwise reproducible for a given n and launch shape, and the
-// solvers can consume it on the device without a host round trip.
+// solvers can consume it on the device without a host round trip.  The
+// kernel boundary orders the two stages: no device-scope fences or
+// same-address atomics, which are expensive across the XCDs' separate L2s.
 #include "wmg_internal.h"
 
 namespace wmg {
@@ -19,16 +21,12 @@ int red_init(Reducer &r, int nrhs_max) {
   r.maxblk = RMAXBLK;
   r.nrhs_max = nrhs_max;
   WMG_HIP(hipMalloc(&r.partial, sizeof(double) * RSLOT * RMAXBLK * (size_t)nrhs_max));
-  WMG_HIP(hipMalloc(&r.counter, sizeof(unsigned) * (size_t)nrhs_max));
-  WMG_HIP(hipMemset(r.counter, 0, sizeof(unsigned) * (size_t)nrhs_max));
   return 0;
 }
 
 void red_free(Reducer &r) {
   if (r.partial) (void)hipFree(r.partial);
-  if (r.counter) (void)hipFree(r.counter);
   r.partial = nullptr;
-  r.counter = nullptr;
 }
 
 static int red_blocks(long n) {
@@ -63,44 +61,56 @@ template <int NC> __device__ __forceinline__ void wg_sum(double v[NC]) {
   }
 }
 
-// store the workgroup partial; the last workgroup of this rhs finalises:
-// thread t sums partial slots t, t+RB, ... in order, then a fixed-shape
-// workgroup tree combines the threads, so the result does not depend on
-// which workgroup finished last and is bitwise reproducible.
-template <int NC>
-__device__ __forceinline__ void wg_finish(double v[NC], double *partial, unsigned *counter, int rhs, double *out,
-                                          int out_stride) {
-  __shared__ bool last;
+// store the workgroup partial (valid in thread 0) into its slot
+template <int NC> __device__ __forceinline__ void wg_store(const double v[NC], double *partial, int rhs) {
   if (threadIdx.x == 0) {
     double *p = partial + ((size_t)rhs * RMAXBLK + blockIdx.x) * RSLOT;
 #pragma unroll
     for (int c = 0; c < NC; c++) p[c] = v[c];
-    __threadfence();
-    unsigned t = atomicAdd(counter + rhs, 1u);
-    last = (t == gridDim.x - 1);
+  }
+}
+
+// second stage, one workgroup per rhs: thread t sums slots t, t+RB, ... in
+// order for each of the nc values, then a fixed-shape workgroup tree
+// combines the threads
+__global__ void __launch_bounds__(RB) k_red_final(const double *__restrict__ partial, int nblk, int nc,
+                                                 double *__restrict__ out, int out_stride) {
+  int rhs = blockIdx.x;
+  const double *p = partial + (size_t)rhs * RMAXBLK * RSLOT;
+  double v[RSLOT];
+#pragma unroll
+  for (int c = 0; c < RSLOT; c++) v[c] = 0;
+  for (int b = threadIdx.x; b < nblk; b += RB)
+#pragma unroll
+    for (int c = 0; c < RSLOT; c++)
+      if (c < nc) v[c] += p[(size_t)b * RSLOT + c];
+  __shared__ double sh[RSLOT][RB / 64];
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < RSLOT; c++) {
+    double x = v[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0 && c < nc) sh[c][w] = x;
   }
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const volatile double *p = partial + (size_t)rhs * RMAXBLK * RSLOT;
-  double acc[NC];
-#pragma unroll
-  for (int c = 0; c < NC; c++) acc[c] = 0;
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += RB)
-#pragma unroll
-    for (int c = 0; c < NC; c++) acc[c] += p[b * RSLOT + c];
-  wg_sum<NC>(acc);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int c = 0; c < NC; c++) out[(size_t)rhs * out_stride + c] = acc[c];
-    counter[rhs] = 0;
+  if (threadIdx.x < nc) {
+    double x = 0;
+    for (int q = 0; q < RB / 64; q++) x += sh[threadIdx.x][q];
+    out[(size_t)rhs * out_stride + threadIdx.x] = x;
   }
+}
+
+static int red_final(Reducer &R, int nblk, int nc, int nrhs, double *out, int out_stride, hipStream_t st) {
+  hipLaunchKernelGGL(k_red_final, dim3(nrhs), dim3(RB), 0, st, (const double *)R.partial, nblk, nc, out, out_stride);
+  WMG_HIP(hipGetLastError());
+  return 0;
 }
 
 // MODE 0: <x,y> (2), 1: |x|^2 (1), 2: <x,y>,|x|^2 (3)
 template <int MODE, class S>
-__global__ void __launch_bounds__(RB) k_reduce(const S *__restrict__ x, const S *__restrict__ y, long n, double *partial,
-                                              unsigned *counter, double *out, int out_stride) {
+__global__ void __launch_bounds__(RB) k_reduce(const S *__restrict__ x, const S *__restrict__ y, long n,
+                                              double *partial) {
   constexpr int NC = MODE == 0 ? 2 : (MODE == 1 ? 1 : 3);
   int rhs = blockIdx.y;
   const S *xr = x + (size_t)rhs * n;
@@ -122,7 +132,7 @@ __global__ void __launch_bounds__(RB) k_reduce(const S *__restrict__ x, const S 
     }
   }
   wg_sum<NC>(v);
-  wg_finish<NC>(v, partial, counter, rhs, out, out_stride);
+  wg_store<NC>(v, partial, rhs);
 }
 
 template <int MODE>
@@ -132,12 +142,12 @@ static int launch_reduce(Reducer &R, int prec, const void *x, const void *y, lon
   if (nrhs > R.nrhs_max) return set_error(-1, "reduction nrhs %d > %d", nrhs, R.nrhs_max);
   if (prec == P64)
     hipLaunchKernelGGL((k_reduce<MODE, double2>), grid, dim3(RB), 0, st, (const double2 *)x, (const double2 *)y, n,
-                       R.partial, R.counter, out, out_stride);
+                       R.partial);
   else
     hipLaunchKernelGGL((k_reduce<MODE, float2>), grid, dim3(RB), 0, st, (const float2 *)x, (const float2 *)y, n,
-                       R.partial, R.counter, out, out_stride);
+                       R.partial);
   WMG_HIP(hipGetLastError());
-  return 0;
+  return red_final(R, (int)grid.x, MODE == 0 ? 2 : (MODE == 1 ? 1 : 3), nrhs, out, out_stride, st);
 }
 
 int dot(Reducer &R, int prec, const void *x, const void *y, long n, int nrhs, double *out, int out_stride,
@@ -154,10 +164,29 @@ int dot_norm(Reducer &R, int prec, const void *x, const void *y, long n, int nrh
 
 // ---------------------------------------------------------------- multi-dot
 // out[rhs][j] = <x_j, y>, j < k (k <= 16), one pass over y
+// workgroup sums of nv (<= 32) values into this workgroup's partial slot
+template <int NMAX>
+__device__ __forceinline__ void wg_store_n(double v[NMAX], int nv, double *partial, int rhs) {
+  __shared__ double sh[NMAX][RB / 64];
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NMAX; c++) {
+    double x = v[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0 && c < nv) sh[c][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double x = 0;
+    for (int q = 0; q < RB / 64; q++) x += sh[threadIdx.x][q];
+    partial[((size_t)rhs * RMAXBLK + blockIdx.x) * RSLOT + threadIdx.x] = x;
+  }
+}
+
 template <class S>
 __global__ void __launch_bounds__(RB) k_multi_dot(const S *const *__restrict__ xs, int k, const S *__restrict__ y,
-                                                 long n, double *partial, unsigned *counter, double *out,
-                                                 int out_stride) {
+                                                 long n, double *partial) {
   int rhs = blockIdx.y;
   double v[32];
 #pragma unroll
@@ -175,64 +204,7 @@ __global__ void __launch_bounds__(RB) k_multi_dot(const S *const *__restrict__ x
       }
     }
   }
-  __shared__ double sh[32][RB / 64];
-#pragma unroll
-  for (int c = 0; c < 32; c++) {
-    double x = v[c];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    v[c] = x;
-  }
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int c = 0; c < 32; c++)
-      if (c < 2 * k) sh[c][w] = v[c];
-  __syncthreads();
-  __shared__ bool last;
-  if (threadIdx.x < 2 * k) {
-    double x = 0;
-    for (int q = 0; q < RB / 64; q++) x += sh[threadIdx.x][q];
-    partial[((size_t)rhs * RMAXBLK + blockIdx.x) * RSLOT + threadIdx.x] = x;
-    __threadfence();
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = atomicAdd(counter + rhs, 1u);
-    last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // finalise 2k values: thread t sums slots t, t+RB, ... of every value, then
-  // a fixed-shape workgroup tree (same as the workgroup partials)
-  const volatile double *p = partial + (size_t)rhs * RMAXBLK * RSLOT;
-#pragma unroll
-  for (int c = 0; c < 32; c++) v[c] = 0;
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += RB)
-#pragma unroll
-    for (int c = 0; c < 32; c++)
-      if (c < 2 * k) v[c] += p[b * RSLOT + c];
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 32; c++) {
-    double x = v[c];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    v[c] = x;
-  }
-  if (lane == 0)
-#pragma unroll
-    for (int c = 0; c < 32; c++)
-      if (c < 2 * k) sh[c][w] = v[c];
-  __syncthreads();
-  if (threadIdx.x < 2 * k) {
-    double x = 0;
-    for (int q = 0; q < RB / 64; q++) x += sh[threadIdx.x][q];
-    out[(size_t)rhs * out_stride + threadIdx.x] = x;
-  }
-  if (threadIdx.x == 0) counter[rhs] = 0;
+  wg_store_n<32>(v, 2 * k, partial, rhs);
 }
 
 int multi_dot(Reducer &R, int prec, const void *const *xs_dev, int k, const void *y, long n, int nrhs, double *out,
@@ -242,12 +214,12 @@ int multi_dot(Reducer &R, int prec, const void *const *xs_dev, int k, const void
   dim3 grid(red_blocks(n), nrhs);
   if (prec == P64)
     hipLaunchKernelGGL((k_multi_dot<double2>), grid, dim3(RB), 0, st, (const double2 *const *)xs_dev, k,
-                       (const double2 *)y, n, R.partial, R.counter, out, out_stride);
+                       (const double2 *)y, n, R.partial);
   else
     hipLaunchKernelGGL((k_multi_dot<float2>), grid, dim3(RB), 0, st, (const float2 *const *)xs_dev, k,
-                       (const float2 *)y, n, R.partial, R.counter, out, out_stride);
+                       (const float2 *)y, n, R.partial);
   WMG_HIP(hipGetLastError());
-  return 0;
+  return red_final(R, (int)grid.x, 2 * k, nrhs, out, out_stride, st);
 }
 
 // ---------------------------------------------------------------- GCR fusions
@@ -260,8 +232,7 @@ template <class S, int PASS>
 __global__ void __launch_bounds__(RB) k_gcr_proj(const S *const *__restrict__ W, int k, S *__restrict__ w,
                                                 const S *__restrict__ r, const double *__restrict__ d, int dstride,
                                                 const double *__restrict__ wn2, int wstride, double *__restrict__ beta,
-                                                int bstride, int kcol, long n, double *partial, unsigned *counter,
-                                                double *out, int out_stride) {
+                                                int bstride, int kcol, long n, double *partial) {
   using R = typename store_traits<S>::real;
   int rhs = blockIdx.y;
   cx<R> b[16];
@@ -310,65 +281,9 @@ __global__ void __launch_bounds__(RB) k_gcr_proj(const S *const *__restrict__ W,
   if (PASS == 2) {
     double t3[3] = {v[0], v[1], v[2]};
     wg_sum<3>(t3);
-    wg_finish<3>(t3, partial, counter, rhs, out, out_stride);
+    wg_store<3>(t3, partial, rhs);
   } else {
-    // 2k values: workgroup tree, slot, last-workgroup finalise
-    __shared__ double sh[32][RB / 64];
-    __shared__ bool last;
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < 32; c++) {
-      double x = v[c];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-      v[c] = x;
-    }
-    if (lane == 0)
-#pragma unroll
-      for (int c = 0; c < 32; c++)
-        if (c < 2 * k) sh[c][wv] = v[c];
-    __syncthreads();
-    if (threadIdx.x < 2 * k) {
-      double x = 0;
-      for (int q = 0; q < RB / 64; q++) x += sh[threadIdx.x][q];
-      partial[((size_t)rhs * RMAXBLK + blockIdx.x) * RSLOT + threadIdx.x] = x;
-      __threadfence();
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      unsigned t = atomicAdd(counter + rhs, 1u);
-      last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    const volatile double *p = partial + (size_t)rhs * RMAXBLK * RSLOT;
-#pragma unroll
-    for (int c = 0; c < 32; c++) v[c] = 0;
-    for (unsigned bb = threadIdx.x; bb < gridDim.x; bb += RB)
-#pragma unroll
-      for (int c = 0; c < 32; c++)
-        if (c < 2 * k) v[c] += p[bb * RSLOT + c];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 32; c++) {
-      double x = v[c];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-      v[c] = x;
-    }
-    if (lane == 0)
-#pragma unroll
-      for (int c = 0; c < 32; c++)
-        if (c < 2 * k) sh[c][wv] = v[c];
-    __syncthreads();
-    if (threadIdx.x < 2 * k) {
-      double x = 0;
-      for (int q = 0; q < RB / 64; q++) x += sh[threadIdx.x][q];
-      out[(size_t)rhs * out_stride + threadIdx.x] = x;
-    }
-    if (threadIdx.x == 0) counter[rhs] = 0;
+    wg_store_n<32>(v, 2 * k, partial, rhs);
   }
 }
 
@@ -379,19 +294,18 @@ int gcr_project(Reducer &R, int prec, int pass, const void *const *W, int k, voi
   dim3 grid(red_blocks(n), nrhs);
 #define GP(S, P)                                                                                                \
   hipLaunchKernelGGL((k_gcr_proj<S, P>), grid, dim3(RB), 0, st, (const S *const *)W, k, (S *)w, (const S *)r, d,  \
-                     dstride, wn2, wstride, beta, bstride, kcol, n, R.partial, R.counter, out, out_stride)
+                     dstride, wn2, wstride, beta, bstride, kcol, n, R.partial)
   if (prec == P64) { if (pass == 1) GP(double2, 1); else GP(double2, 2); }
   else { if (pass == 1) GP(float2, 1); else GP(float2, 2); }
 #undef GP
   WMG_HIP(hipGetLastError());
-  return 0;
+  return red_final(R, (int)grid.x, pass == 1 ? 2 * k : 3, nrhs, out, out_stride, st);
 }
 
 // y -= a x (a complex on the device, masked by the caller) and |y|^2
 template <class S>
 __global__ void __launch_bounds__(RB) k_caxpy_norm(const double *__restrict__ a, int astride, const S *__restrict__ x,
-                                                  S *__restrict__ y, long n, double *partial, unsigned *counter,
-                                                  double *out, int out_stride) {
+                                                  S *__restrict__ y, long n, double *partial) {
   using R = typename store_traits<S>::real;
   int rhs = blockIdx.y;
   cx<R> c = {(R)(-a[(size_t)rhs * astride]), (R)(-a[(size_t)rhs * astride + 1])};
@@ -403,7 +317,7 @@ __global__ void __launch_bounds__(RB) k_caxpy_norm(const double *__restrict__ a,
     v[0] += (double)yv.re * yv.re + (double)yv.im * yv.im;
   }
   wg_sum<1>(v);
-  wg_finish<1>(v, partial, counter, rhs, out, out_stride);
+  wg_store<1>(v, partial, rhs);
 }
 
 int caxpy_norm(Reducer &R, int prec, const double *a, int astride, const void *x, void *y, long n, int nrhs,
@@ -411,12 +325,12 @@ int caxpy_norm(Reducer &R, int prec, const double *a, int astride, const void *x
   dim3 grid(red_blocks(n), nrhs);
   if (prec == P64)
     hipLaunchKernelGGL((k_caxpy_norm<double2>), grid, dim3(RB), 0, st, a, astride, (const double2 *)x, (double2 *)y, n,
-                       R.partial, R.counter, out, out_stride);
+                       R.partial);
   else
     hipLaunchKernelGGL((k_caxpy_norm<float2>), grid, dim3(RB), 0, st, a, astride, (const float2 *)x, (float2 *)y, n,
-                       R.partial, R.counter, out, out_stride);
+                       R.partial);
   WMG_HIP(hipGetLastError());
-  return 0;
+  return red_final(R, (int)grid.x, 1, nrhs, out, out_stride, st);
 }
 
 // ---------------------------------------------------------------- elementwise

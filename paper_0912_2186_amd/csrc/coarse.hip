@@ -430,24 +430,31 @@ int coarse_transpose(long nblk, int n, const double2 *a, double2 *b, hipStream_t
 // and accumulated over the nine directions with v_mfma_f32_16x16x4f32.  One
 // workgroup per site, one wavefront per 16-row tile of the output.  The A
 // operand streams from a pre-swizzled FP32 copy of the links laid out
-// [site][d][k-step][row tile][lane] (one coalesced 256-byte load per
-// wavefront and k-step, every link byte read once); the B operand of each
+// [site][d][row tile][k-step/4][lane][k-step%4] with the k-steps padded to a
+// multiple of 8 by zeros (each lane reads four k-steps with one 16-byte
+// load, a wavefront 1 KB contiguous; every link byte is read once); the B operand of each
 // direction is staged in LDS.  Lane layout of the 16x16x4 instruction: lane
 // l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register v of lane
 // l holds C[4*(l/16)+v][l%16].
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__global__ void k_Y_to_mfma(long Vc, int n, int MT, const double2 *__restrict__ Y, float *__restrict__ Ym) {
+// k-steps of the MFMA link layout for n x n blocks: n/2 rounded up to 8
+__host__ __device__ __forceinline__ int mfma_km(int n) { return (n / 2 + 7) / 8 * 8; }
+
+__global__ void k_Y_to_mfma(long Vc, int n, int MT, int KM, const double2 *__restrict__ Y, float *__restrict__ Ym) {
   size_t i = blockIdx.x * (size_t)TB + threadIdx.x;
-  size_t per_site_d = (size_t)(n / 2) * MT * 64;
+  size_t per_site_d = (size_t)MT * KM * 64;
   size_t tot = (size_t)Vc * 9 * per_site_d;
   if (i >= tot) return;
   size_t sd = i / per_site_d;  // site*9 + d
   size_t rem = i % per_site_d;
-  int ks = (int)(rem / (MT * 64)), mt = (int)((rem / 64) % MT), lane = (int)(rem % 64);
+  int mt = (int)(rem / ((size_t)KM * 64));
+  int q = (int)(rem % ((size_t)KM * 64));  // (kq*64 + lane)*4 + e
+  int e = q % 4, lane = (q / 4) % 64, kq = q / 256;
+  int ks = kq * 4 + e;
   int row = mt * 16 + lane % 16, kk = ks * 4 + lane / 16;
   float v = 0.f;
-  if (row < n) {
+  if (row < n && kk < 2 * n) {
     int col = kk < n ? kk : kk - n;
     double2 y = Y[(sd * n + col) * n + row];  // internal [site][d][col][row]
     v = (float)(kk < n ? y.x : y.y);
@@ -456,21 +463,27 @@ __global__ void k_Y_to_mfma(long Vc, int n, int MT, const double2 *__restrict__ 
 }
 
 int coarse_to_mfma(long Vc, int n, const double2 *Y64, float *Ym, hipStream_t st) {
-  int MT = (n + 15) / 16;
-  size_t tot = (size_t)Vc * 9 * (n / 2) * MT * 64;
-  hipLaunchKernelGGL(k_Y_to_mfma, dim3((unsigned)((tot + TB - 1) / TB)), dim3(TB), 0, st, Vc, n, MT, Y64, Ym);
+  int MT = (n + 15) / 16, KM = mfma_km(n);
+  size_t tot = (size_t)Vc * 9 * MT * KM * 64;
+  hipLaunchKernelGGL(k_Y_to_mfma, dim3((unsigned)((tot + TB - 1) / TB)), dim3(TB), 0, st, Vc, n, MT, KM, Y64, Ym);
   WMG_HIP(hipGetLastError());
   return 0;
 }
 
-size_t coarse_mfma_floats(long Vc, int n) { return (size_t)Vc * 9 * (n / 2) * ((n + 15) / 16) * 64; }
+size_t coarse_mfma_floats(long Vc, int n) { return (size_t)Vc * 9 * ((n + 15) / 16) * mfma_km(n) * 64; }
 
 // LDS row stride of the transposed B tile: a multiple of 32 plus 4, so the
 // 16 columns x 4 k-rows read by one MFMA B fragment spread over all banks
 __host__ __device__ __forceinline__ int mfma_ldk(int n) { return (2 * n + 31) / 32 * 32 + 4; }
 
-template <int NT>
-__global__ void __launch_bounds__(256) k_coarse_apply_mfma(const float *__restrict__ Ym, const float2 *__restrict__ in,
+// One workgroup per (coarse site, tile of up to 32 right-hand sides); wave mt
+// owns rows 16mt..16mt+15 of the n x n blocks and all NT column tiles.  The
+// loop over the 9 stencil directions is software pipelined: while the MFMAs
+// of direction d run, the link fragments of direction d+1 (registers) and
+// its neighbour vectors (registers, written to LDS after the next barrier)
+// are already in flight, so no direction waits for a cold load.
+template <int NT, int KM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_coarse_apply_mfma(const float *__restrict__ Ym, const float2 *__restrict__ in,
                                                           float2 *__restrict__ out, int L0, int L1, int L2, int L3,
                                                           long Vc, int n, int nrhs, int dagger) {
   extern __shared__ float Bt[];  // B transposed: [NT*16 columns][LDK], column j, k-row kk at j*LDK + kk
@@ -483,55 +496,91 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(const float *__restri
   const int L[4] = {L0, L1, L2, L3};
   int x[4];
   site_coords(L, xh, x);
-  long nb[9];
-  nb[0] = xh;
-  for (int mu = 0; mu < 4; mu++) {
+  // neighbour site of direction d (0: the site, 1+mu: +mu, 5+mu: -mu)
+  auto nbr = [&](int d) -> long {
+    if (d == 0) return xh;
+    int mu = (d - 1) & 3;
     int y[4] = {x[0], x[1], x[2], x[3]};
-    y[mu] = (x[mu] + 1) % L[mu];
-    nb[1 + mu] = site_index(L, y);
-    y[mu] = (x[mu] - 1 + L[mu]) % L[mu];
-    nb[5 + mu] = site_index(L, y);
-  }
-  const int h = n / 2, NC = NT * 16;
-  // padding columns 2R..NC-1 stay zero for every direction
+    y[mu] = d < 5 ? (x[mu] + 1) % L[mu] : (x[mu] - 1 + L[mu]) % L[mu];
+    return site_index(L, y);
+  };
+  const int h = n / 2, NC = NT * 16, KS = n / 2;
+  // padding columns 2R..NC-1 and padding k-rows 2n..4KM-1 stay zero for
+  // every direction (4KM <= LDK - 4)
   for (int idx = threadIdx.x; idx < (NC - 2 * R) * LDK; idx += blockDim.x) Bt[2 * R * LDK + idx] = 0.f;
+  for (int idx = threadIdx.x; idx < 2 * R * (4 * KM - 2 * n); idx += blockDim.x) {
+    int j = idx / (4 * KM - 2 * n), kk = 2 * n + idx % (4 * KM - 2 * n);
+    Bt[j * LDK + kk] = 0.f;
+  }
+  // staging map: thread -> (column col, rows rg, rg + tpr, ...); tpr >= 4
+  // row groups fit in 64*MT threads, so 8 rounds cover R <= 32 rows
+  const int tpr = (int)blockDim.x / n;
+  const int col = threadIdx.x % n, rg = threadIdx.x / n;
+  const bool stager = rg < tpr;
+  const bool neg = dagger && col >= h;
+  float2 stg[8];
+  auto stage_load = [&](int d) {
+    const float2 *src = in + ((size_t)(r0 + rg) * Vc + nbr(d)) * n + col;
+    const size_t step = (size_t)tpr * Vc * n;
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (stager && rg + q * tpr < R) stg[q] = src[q * step];
+  };
+  // B = [[Br, Bi], [-Bi, Br]] (col fastest across threads: conflict-free writes)
+  auto stage_store = [&]() {
+    float *dst = Bt + rg * LDK + col;
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (stager && rg + q * tpr < R) {
+        float2 v = stg[q];
+        if (neg) { v.x = -v.x; v.y = -v.y; }
+        float *p = dst + q * tpr * LDK;
+        p[0] = v.x;
+        p[R * LDK] = v.y;
+        p[n] = -v.y;
+        p[R * LDK + n] = v.x;
+      }
+  };
+  const int mts = mt < MT ? mt : 0;
+  auto a_load = [&](float *a, int d) {
+    const float4 *Ad = (const float4 *)(Ym + (((size_t)xh * 9 + d) * MT + mts) * KM * 64) + lane;
+#pragma unroll
+    for (int kq = 0; kq < KM / 4; kq++) {
+      float4 v = Ad[kq * 64];
+      a[4 * kq] = v.x;
+      a[4 * kq + 1] = v.y;
+      a[4 * kq + 2] = v.z;
+      a[4 * kq + 3] = v.w;
+    }
+  };
   floatx4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int KS = n / 2;
+  float a_cur[KM], a_nxt[KM];
+  stage_load(0);
+  a_load(a_cur, 0);
   for (int d = 0; d < 9; d++) {
-    // issue this direction's link loads first: they fly while B is staged
-    float a[32];
-    {
-      const float *Ad = Ym + ((size_t)xh * 9 + d) * (size_t)KS * MT * 64 + (mt < MT ? mt : 0) * 64 + lane;
-#pragma unroll
-      for (int ks = 0; ks < 32; ks++) a[ks] = (ks < KS && mt < MT) ? Ad[(size_t)ks * MT * 64] : 0.f;
-    }
+    __syncthreads();  // every wave is done reading B of direction d-1
+    stage_store();
     __syncthreads();
-    // B = [[Br, Bi], [-Bi, Br]]: each coalesced load of in[r][nb][col] fills
-    // four entries (col fastest across threads: conflict-free LDS writes)
-    for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
-      int r = idx / n, col = idx % n;
-      float2 v = in[((size_t)(r0 + r) * Vc + nb[d]) * n + col];
-      if (dagger && col >= h) { v.x = -v.x; v.y = -v.y; }
-      Bt[r * LDK + col] = v.x;
-      Bt[(R + r) * LDK + col] = v.y;
-      Bt[r * LDK + n + col] = -v.y;
-      Bt[(R + r) * LDK + n + col] = v.x;
+    if (d + 1 < 9) {
+      stage_load(d + 1);
+      a_load(a_nxt, d + 1);
     }
-    __syncthreads();
     if (mt < MT) {
       const int krow = lane >> 4, jc = lane & 15;
 #pragma unroll
-      for (int ks = 0; ks < 32; ks++) {
-        if (ks < KS) {
-          const float *bcol = Bt + jc * LDK + ks * 4 + krow;
+      for (int ks = 0; ks < KM; ks++) {
+        // k-steps KS..KM-1 multiply zero link fragments with zero B rows:
+        // a fixed trip count keeps the accumulators in place
+        const float *bcol = Bt + jc * LDK + ks * 4 + krow;
 #pragma unroll
-          for (int t = 0; t < NT; t++)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], bcol[t * 16 * LDK], acc[t], 0, 0, 0);
-        }
+        for (int t = 0; t < NT; t++)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[ks], bcol[t * 16 * LDK], acc[t], 0, 0, 0);
       }
     }
+#pragma unroll
+    for (int ks = 0; ks < KM; ks++) a_cur[ks] = a_nxt[ks];
   }
   if (mt >= MT) return;
   float *of = (float *)out;
@@ -558,16 +607,17 @@ int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, 
   dim3 grid((unsigned)gc.V, (nrhs + 31) / 32);
   dim3 blk(64 * MT);
   size_t lds = sizeof(float) * NT * 16 * mfma_ldk(n);
-  switch (NT) {
-#define NT_CASE(N)                                                                                              \
-  case N:                                                                                                      \
-    hipLaunchKernelGGL((k_coarse_apply_mfma<N>), grid, blk, lds, st, Ym, in, out, gc.L[0], gc.L[1], gc.L[2],    \
+  const int KM = mfma_km(n);  // 8, 16, 24 or 32
+#define NT_CASE(N, K)                                                                                           \
+  if (NT == N && KM == K) {                                                                                    \
+    hipLaunchKernelGGL((k_coarse_apply_mfma<N, K>), grid, blk, lds, st, Ym, in, out, gc.L[0], gc.L[1], gc.L[2], \
                        gc.L[3], gc.V, n, nrhs, dagger);                                                       \
-    break;
-    NT_CASE(1) NT_CASE(2) NT_CASE(3) NT_CASE(4)
+  } else
+#define NT_ALL(N) NT_CASE(N, 8) NT_CASE(N, 16) NT_CASE(N, 24) NT_CASE(N, 32)
+  NT_ALL(1) NT_ALL(2) NT_ALL(3) NT_ALL(4)
+  return set_error(-1, "coarse_apply_mfma: NT=%d KM=%d", NT, KM);
+#undef NT_ALL
 #undef NT_CASE
-    default: return set_error(-1, "coarse_apply_mfma: NT=%d", NT);
-  }
   WMG_HIP(hipGetLastError());
   return 0;
 }

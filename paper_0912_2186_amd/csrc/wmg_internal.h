@@ -123,8 +123,7 @@ int spinor_from_soa(const Geom &g, const double2 *soa, double *canon, int nrhs, 
 
 // blas.hip -- flat complex vectors [nrhs][n]
 struct Reducer {
-  double *partial;    // [nrhs][maxblk][4]
-  unsigned *counter;  // [nrhs]
+  double *partial;  // [nrhs][maxblk][32] per-workgroup partial sums
   int maxblk;
   int nrhs_max;
 };

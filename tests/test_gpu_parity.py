@@ -117,7 +117,7 @@ def test_transfer_and_galerkin_from_given_vectors(wmg, L, block):
         assert relerr(host(o), oracle.coarse_apply(Lc, n, Y_ref, c_ref, dagger=dag)) < 1e-13
 
 
-@pytest.mark.parametrize("nv,nrhs", [(5, 1), (8, 7), (24, 28), (24, 40), (32, 3)])
+@pytest.mark.parametrize("nv,nrhs", [(5, 1), (8, 7), (20, 28), (24, 28), (24, 40), (32, 3)])
 def test_mfma_coarse_apply_multi_rhs(wmg, nv, nrhs):
     """FP32 matrix-core coarse stencil (and its sigma_3 adjoint) for many
     right-hand sides against the oracle's FP64 stencil."""
