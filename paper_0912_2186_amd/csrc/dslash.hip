@@ -9,8 +9,11 @@
 // One thread per site (and per tile of RT right-hand sides, which then share
 // every link load).  Links and spinors are stored component-major with sites
 // fastest, so each load instruction of a wavefront reads consecutive
-// addresses; neighbour reuse is left to L2/MALL, with workgroups mapped so
-// that each XCD sweeps one contiguous range of sites.
+// addresses.  A workgroup first copies the spinors of its own 256-site tile
+// into LDS with one burst of coalesced loads; every hop whose neighbour lies
+// in the tile (and the diagonal term) then reads LDS, and only neighbours in
+// other tiles go to L2.  Reuse across tiles is left to L2/MALL, with
+// workgroups mapped so that each XCD sweeps one contiguous range of sites.
 #include "wmg_internal.h"
 
 namespace wmg {
@@ -170,8 +173,29 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
   int x[4];
   long s = 0;
   const bool valid = sweep_site(sm, L, blockIdx.x, threadIdx.x, x, s);
-  if (!RED && !valid) return;
   int r0 = blockIdx.y * RT;
+  // the tile's own spinors, [t][c][thread] (sized for the right-hand sides
+  // this launch has, at most RT)
+  extern __shared__ unsigned char dsm[];
+  TS *Sh = (TS *)dsm;
+  if (valid) {
+#pragma unroll
+    for (int t = 0; t < RT; t++)
+      if (r0 + t < nrhs)
+#pragma unroll
+        for (int c = 0; c < 12; c++) Sh[(t * 12 + c) * 256 + threadIdx.x] = in[((size_t)(r0 + t) * 12 + c) * Vs + s];
+  }
+  __syncthreads();
+  // tile-local slot of a neighbour site, -1 when it lies in another tile
+  const long gtile = (blockIdx.x % NXCD) * sm.per_xcd + blockIdx.x / NXCD;
+  const long ttile = gtile % sm.td, slab = gtile / sm.td;
+  const int iy = (int)(slab % sm.ny), iz = (int)(slab / sm.ny);
+  auto local_of = [&](const int y[4]) -> int {
+    int ly = y[1] - iy * sm.dy, lz = y[2] - iz * sm.dz;
+    if (ly < 0 || ly >= sm.dy || lz < 0 || lz >= sm.dz) return -1;
+    long q = y[0] + (long)L0 * (ly + (long)sm.dy * (lz + (long)sm.dz * y[3]));
+    return q / 256 == ttile ? (int)(q % 256) : -1;
+  };
   double rs[RT][3];
 #pragma unroll
   for (int t = 0; t < RT; t++) rs[t][0] = rs[t][1] = rs[t][2] = 0.0;
@@ -190,23 +214,16 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
       u[e] = {(R)v.re, (R)v.im};
     }
   };
-  auto load_psi = [&](int r, long site, cx<R> p[12]) {
-#pragma unroll
-    for (int c = 0; c < 12; c++) {
-      auto v = ldc(in + ((size_t)r * 12 + c) * Vs + site);
-      p[c] = {(R)v.re, (R)v.im};
-    }
-  };
-
   // half spinor of the neighbour, projected colour by colour straight from
   // the loads, then the link applied row by row (few live registers)
-  auto hop_half = [&](int r, long site, auto proj, cx<R> h[6]) {
+  auto hop_half = [&](int r, long site, int loc, auto proj, cx<R> h[6]) {
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       cx<R> p4[4];
 #pragma unroll
       for (int sp = 0; sp < 4; sp++) {
-        auto v = ldc(in + ((size_t)r * 12 + sp * 3 + c) * Vs + site);
+        auto v = loc >= 0 ? ldc(Sh + ((r - r0) * 12 + sp * 3 + c) * 256 + loc)
+                          : ldc(in + ((size_t)r * 12 + sp * 3 + c) * Vs + site);
         p4[sp] = {(R)v.re, (R)v.im};
       }
       proj(p4, h[c], h[3 + c]);
@@ -216,11 +233,15 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
   {                                                                                            \
     long fw = x[MU] == L[MU] - 1 ? s - (long)(L[MU] - 1) * stride[MU] : s + stride[MU];        \
     long bw = x[MU] == 0 ? s + (long)(L[MU] - 1) * stride[MU] : s - stride[MU];                \
+    int yf[4] = {x[0], x[1], x[2], x[3]}, yb[4] = {x[0], x[1], x[2], x[3]};                    \
+    yf[MU] = x[MU] == L[MU] - 1 ? 0 : x[MU] + 1;                                               \
+    yb[MU] = x[MU] == 0 ? L[MU] - 1 : x[MU] - 1;                                               \
+    const int lf = local_of(yf), lb = local_of(yb);                                            \
     cx<R> u[9], h[6], g[6];                                                                    \
     load_link(MU, s, u);                                                                       \
     _Pragma("unroll") for (int t = 0; t < RT; t++) {                                           \
       if (r0 + t < nrhs) {                                                                     \
-        hop_half(r0 + t, fw, proj_pair<MU, 1, R>, h);                                          \
+        hop_half(r0 + t, fw, lf, proj_pair<MU, 1, R>, h);                                          \
         su3_mul<0>(u, h, g);                                                                   \
         reconstruct<MU, 1>(g, acc[t]);                                                         \
       }                                                                                        \
@@ -228,7 +249,7 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
     load_link(MU, bw, u);                                                                      \
     _Pragma("unroll") for (int t = 0; t < RT; t++) {                                           \
       if (r0 + t < nrhs) {                                                                     \
-        hop_half(r0 + t, bw, proj_pair<MU, -1, R>, h);                                         \
+        hop_half(r0 + t, bw, lb, proj_pair<MU, -1, R>, h);                                         \
         su3_mul<1>(u, h, g);                                                                   \
         reconstruct<MU, -1>(g, acc[t]);                                                        \
       }                                                                                        \
@@ -244,7 +265,11 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
   for (int t = 0; t < RT; t++) {
     if (r0 + t >= nrhs) continue;
     cx<R> p[12];
-    load_psi(r0 + t, s, p);
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+      auto v = ldc(Sh + (t * 12 + c) * 256 + threadIdx.x);
+      p[c] = {(R)v.re, (R)v.im};
+    }
 #pragma unroll
     for (int c = 0; c < 12; c++) {
       cx<R> o = {diag * p[c].re - R(0.5) * acc[t][c].re, diag * p[c].im - R(0.5) * acc[t][c].im};
@@ -312,14 +337,15 @@ static void launch_soa(const Geom &g, const void *U, double m, const void *in, v
   // bytes a site brings into L2 during one sweep: its links and RT spinors
   SweepMap sm = make_sweep(g.L, 36 * (int)sizeof(TL) + 24 * (int)sizeof(TS) / 2 * RT);
   dim3 grid((unsigned)sm.nblocks, (nrhs + RT - 1) / RT);
+  const size_t lds = (size_t)(nrhs < RT ? nrhs : RT) * 12 * 256 * sizeof(TS);
   if (red) {
-    hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT, 1>), grid, dim3(256), 0, st, (const TL *)U, (const TS *)in,
+    hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT, 1>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
                        (TS *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
                        (const TS *)bsub, red);
     hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
                        red_stride);
   } else {
-    hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT, 0>), grid, dim3(256), 0, st, (const TL *)U, (const TS *)in,
+    hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT, 0>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
                        (TS *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
                        (const TS *)bsub, (double *)nullptr);
   }
