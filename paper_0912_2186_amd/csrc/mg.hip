@@ -53,6 +53,45 @@ __global__ void k_mr_update(const double *__restrict__ red, S *__restrict__ e, S
   }
 }
 
+// MR with the solution update deferred (fine level): step k only forms the
+// next residual s_{k+1} = s_k - alpha_k q_k; after the last step
+// e += sum_k alpha_k s_k in one pass.  alpha_k = <q_k,s_k>/|q_k|^2 from
+// red[(k*64 + rhs)*4 + 0..2].
+template <class R> __device__ __forceinline__ cx<R> mr_alpha(const double *red, int k, int rhs) {
+  const double *rd = red + ((size_t)k * 64 + rhs) * 4;
+  double qq = rd[2];
+  return qq > 0 ? cx<R>{(R)(rd[0] / qq), (R)(rd[1] / qq)} : czero<R>();
+}
+template <class S>
+__global__ void k_mr_next(const double *__restrict__ red, int k, const S *__restrict__ s, const S *__restrict__ q,
+                          S *__restrict__ snext, long n) {
+  using R = typename store_traits<S>::real;
+  int rhs = blockIdx.y;
+  cx<R> a = mr_alpha<R>(red, k, rhs);
+  size_t off = (size_t)rhs * n;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+    stc(snext + off + i, cfma(neg(a), ldc(q + off + i), ldc(s + off + i)));
+}
+struct MrVecs {
+  const void *s[4];
+};
+template <class S>
+__global__ void k_mr_accum(const double *__restrict__ red, int nsteps, MrVecs v, S *__restrict__ e, long n) {
+  using R = typename store_traits<S>::real;
+  int rhs = blockIdx.y;
+  cx<R> a[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) a[k] = k < nsteps ? mr_alpha<R>(red, k, rhs) : czero<R>();
+  size_t off = (size_t)rhs * n;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    cx<R> acc = ldc(e + off + i);
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (k < nsteps) acc = cfma(a[k], ldc((const S *)v.s[k] + off + i), acc);
+    stc(e + off + i, acc);
+  }
+}
+
 // CG: alpha = act ? ss/uu : 0; x += alpha p; r -= alpha u
 template <class S>
 __global__ void k_cg_step1(const double *__restrict__ cg, int ssoff, S *__restrict__ x, S *__restrict__ r,
@@ -160,7 +199,7 @@ template <class S> static dim3 grid_for(long n, int nrhs) {
 using namespace wmg;
 
 // ------------------------------------------------------------ context
-enum { VR, VE, VT, VE2, VS, VQ, VCR, VCS, VCP, VCU, VX, NVW };
+enum { VR, VE, VT, VE2, VS, VQ, VCR, VCS, VCP, VCU, VX, VS1, VS2, VS3, NVW };
 
 struct Level {
   Geom g;
@@ -208,6 +247,7 @@ struct wmg_ctx {
   Reducer red{};
   double *dsc = nullptr;  // device scalars
   double *red_out = nullptr;
+  double *mr_red = nullptr;  // fused MR step reductions, [step][rhs][4]
   double *cg = nullptr;
   double *gcr = nullptr;
   double *mask = nullptr;
@@ -371,7 +411,8 @@ static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, voi
 
 // fine operator with the smoother's fusions: out = [bsub -] D in, and with
 // reduce also <out, in>, |out|^2 -> red_out (cycle links)
-static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int nrhs, const void *bsub, bool reduce) {
+static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int nrhs, const void *bsub, bool reduce,
+                            double *red_dst = nullptr) {
   Level &L = c->lv[0];
   int lp = prec == P64 ? P64 : P16;
   c->st_fine++;
@@ -379,8 +420,8 @@ static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int
   double lb = lp == P64 ? 16 : 4, sb = prec == P64 ? 16 : 8;
   int slot = prof_begin(c, prec == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE,
                         (double)L.g.V * (36 * lb + (bsub ? 36.0 : 24.0) * sb * nrhs));
-  int rc = wilson_soa_fused(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, bsub, reduce ? c->dred : nullptr, c->red_out,
-                            4, c->st);
+  int rc = wilson_soa_fused(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, bsub, reduce ? c->dred : nullptr,
+                            red_dst ? red_dst : c->red_out, 4, c->st);
   prof_end(c, slot);
   return rc;
 }
@@ -394,6 +435,34 @@ static int mr_smooth(wmg_ctx *c, int l, int prec, const void *r, void *e, int ns
   void *s, *q;
   TRY(level_vec(c, l, prec, VS, &s, nrhs));
   TRY(level_vec(c, l, prec, VQ, &q, nrhs));
+  if (L.fine && nsteps >= 1 && nsteps <= 4 && nrhs <= 64) {
+    // s_0 = r - A e; q_k = A s_k with <q_k,s_k>, |q_k|^2 fused;
+    // s_{k+1} = s_k - alpha_k q_k; finally e += sum_k alpha_k s_k
+    void *sv[4] = {s, nullptr, nullptr, nullptr};
+    const int names[4] = {VS, VS1, VS2, VS3};
+    for (int k = 1; k < nsteps; k++) TRY(level_vec(c, l, prec, names[k], &sv[k], nrhs));
+    TRY(fine_apply_fused(c, prec, e, s, nrhs, r, false));
+    dim3 g = grid_for<double2>(L.n, nrhs);
+    for (int k = 0; k < nsteps; k++) {
+      TRY(fine_apply_fused(c, prec, sv[k], q, nrhs, nullptr, true, c->mr_red + (size_t)k * 64 * 4));
+      if (k + 1 < nsteps) {
+        if (prec == P64)
+          hipLaunchKernelGGL(k_mr_next<double2>, g, dim3(256), 0, c->st, c->mr_red, k, (const double2 *)sv[k],
+                             (const double2 *)q, (double2 *)sv[k + 1], L.n);
+        else
+          hipLaunchKernelGGL(k_mr_next<float2>, g, dim3(256), 0, c->st, c->mr_red, k, (const float2 *)sv[k],
+                             (const float2 *)q, (float2 *)sv[k + 1], L.n);
+        WMG_HIP(hipGetLastError());
+      }
+    }
+    MrVecs mv{{sv[0], sv[1], sv[2], sv[3]}};
+    if (prec == P64)
+      hipLaunchKernelGGL(k_mr_accum<double2>, g, dim3(256), 0, c->st, c->mr_red, nsteps, mv, (double2 *)e, L.n);
+    else
+      hipLaunchKernelGGL(k_mr_accum<float2>, g, dim3(256), 0, c->st, c->mr_red, nsteps, mv, (float2 *)e, L.n);
+    WMG_HIP(hipGetLastError());
+    return 0;
+  }
   if (L.fine) {
     TRY(fine_apply_fused(c, prec, e, s, nrhs, r, false));
   } else {
@@ -801,7 +870,7 @@ int wmg_default_params(wmg_params *p) {
   p->nrhs_max = 1;
   p->coarse_tol = 1e-8;
   p->coarse_maxiter = 500;
-  p->reliable_delta = 0.1;
+  p->reliable_delta = 0.01;
   p->maxiter = 1000;
   p->seed = 12345;
   p->flags = 0;
@@ -893,6 +962,7 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
   c->cg = c->dsc + 4 * 64;
   c->gcr = c->cg + 8 * 64;
   c->mask = c->gcr + GS * 64;
+  c->mr_red = c->mask + 64;  // [4 steps][64 rhs][4]
   CK(dalloc((void **)&c->flag, sizeof(int)));
   CK(hipHostMalloc((void **)&c->hbuf, sizeof(double) * 4096) == hipSuccess ? 0 : set_error(WMG_ENOMEM, "hipHostMalloc"));
   {
