@@ -43,6 +43,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM traffic per launch of a kernel class, from the rocprofv3 counter runs
+# summarised in profiles/ (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
+# what the same counters read for a plain device copy of known size).  A row
+# counts only while the kernel's source file still has the hash it had when
+# the counters were taken.
+TRAFFIC_FILE = {"32^3x64-28rhs-mixed": "hbm_traffic_dominant_kernels_32x32x32x64_28rhs_mixed.md"}
+
+
+def measured_traffic(workload, kernel_class):
+    import hashlib
+
+    name = TRAFFIC_FILE.get(workload)
+    if not name or not os.path.exists(os.path.join(ROOT, "profiles", name)):
+        return None
+    for line in open(os.path.join(ROOT, "profiles", name)):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) < 7 or cells[0] != kernel_class:
+            continue
+        # | class | symbol | FETCH KiB | WRITE KiB | bytes per launch | source | sha256 |
+        src, sha = cells[5].strip("`"), cells[6].strip("`")
+        try:
+            cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        except OSError:
+            return None
+        return float(cells[4]) if cur == sha else None
+    return None
+
+
 def make_rhs(inputs, L, w):
     import numpy as np
 
@@ -186,6 +214,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "launches": n_l, "avg_launch_ms": round(avg_ms, 4),
                 "share_of_step": round(ms_l / max(el * 1e3, 1e-9), 3)}
+    tr = measured_traffic(args.workload, dom)
+    roofline["traffic"] = tr
     if dom.startswith("coarse") and n_l:
         # the multi-RHS coarse stencil is a dense contraction: 8 real flops per
         # complex multiply-add, 9 n^2 per site and rhs; take whichever

@@ -184,13 +184,14 @@ int mg_time_dslash(wmg_ctx *ctx, int prec, int nrhs, int reps, double *ms);
 
 /* ---- measurement hooks --------------------------------------------- */
 /* Kernel classes timed by mg_profile. */
-#define WMG_K_DSLASH_CYCLE 0   /* fine operator inside the cycle (FP16 links, FP32 spinors) */
+#define WMG_K_DSLASH_CYCLE 0   /* fine operator of the cycle's MR steps (FP16 links, FP32 spinors) */
 #define WMG_K_DSLASH_OUTER32 1 /* fine operator of the inner GCR (FP32) */
 #define WMG_K_DSLASH_64 2      /* fine operator in FP64 */
 #define WMG_K_COARSE32 3       /* coarse stencil, FP32 */
 #define WMG_K_COARSE64 4       /* coarse stencil, FP64 */
 #define WMG_K_RESTRICT 5       /* fine -> first coarse level */
 #define WMG_K_PROLONG 6        /* first coarse level -> fine */
+#define WMG_K_DSLASH_RES 7     /* smoother residual r - A e in the cycle (FP16 links, FP32 spinors) */
 /* enable != 0: from now on record a HIP event pair on the context stream
  * around every launch of the classes above; resets the accumulators. */
 int mg_profile(wmg_ctx *ctx, int enable);

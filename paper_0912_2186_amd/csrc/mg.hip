@@ -273,7 +273,7 @@ struct wmg_ctx {
 
 // kernel classes timed by mg_profile
 enum { K_DSLASH_CYCLE = 0, K_DSLASH_OUTER32 = 1, K_DSLASH_64 = 2, K_COARSE32 = 3, K_COARSE64 = 4, K_RESTRICT = 5,
-       K_PROLONG = 6, K_NKIND = 7 };
+       K_PROLONG = 6, K_DSLASH_RES = 7, K_NKIND = 8 };
 static const int EV_CAP = 2048;
 
 static int prof_resolve(wmg_ctx *c) {
@@ -418,7 +418,7 @@ static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int
   c->st_fine++;
   if (prec == P64) c->st_fine64++;
   double lb = lp == P64 ? 16 : 4, sb = prec == P64 ? 16 : 8;
-  int slot = prof_begin(c, prec == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE,
+  int slot = prof_begin(c, prec == P64 ? K_DSLASH_64 : (bsub ? K_DSLASH_RES : K_DSLASH_CYCLE),
                         (double)L.g.V * (36 * lb + (bsub ? 36.0 : 24.0) * sb * nrhs));
   int rc = wilson_soa_fused(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, bsub, reduce ? c->dred : nullptr,
                             red_dst ? red_dst : c->red_out, 4, c->st);

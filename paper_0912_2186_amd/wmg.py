@@ -116,7 +116,7 @@ _sig = {
     "mg_profile_get": (_i, [_vp, _i, _P(_i), _P(_d), _P(_d)]),
 }
 KERNEL_KINDS = {"dslash_cycle": 0, "dslash_outer32": 1, "dslash_fp64": 2, "coarse_fp32": 3, "coarse_fp64": 4,
-                "restrict": 5, "prolong": 6}
+                "restrict": 5, "prolong": 6, "dslash_residual": 7}
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
