@@ -161,11 +161,12 @@ __device__ __forceinline__ bool sweep_site(const SweepMap &sm, const int L[4], l
 // (residual); RED != 0 also reduces <out, in> and |out|^2 over the
 // workgroup into red[(rhs * gridDim.x + block) * 3 + 0..2] for a
 // fixed-order finalisation by k_dslash_red_finalize.
-template <class TL, class TS, int RT, int RED>
+template <class TL, class TS, class TO, int RT, int RED>
 __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, const TS *__restrict__ in,
-                                                   TS *__restrict__ out, int L0, int L1, int L2, int L3, long V,
+                                                   TO *__restrict__ out, int L0, int L1, int L2, int L3, long V,
                                                    float diagf, double diagd, int nrhs, SweepMap sm, long Vs,
-                                                   const TS *__restrict__ bsub, double *__restrict__ red) {
+                                                   const TS *__restrict__ bsub, const double *__restrict__ bnrm2,
+                                                   int bstride, double *__restrict__ red) {
   using R = typename store_traits<TS>::real;
   const R diag = sizeof(R) == 8 ? (R)diagd : (R)diagf;
   // one sweep over the lattice per tile of RT right-hand sides (grid.y)
@@ -275,9 +276,15 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
       cx<R> o = {diag * p[c].re - R(0.5) * acc[t][c].re, diag * p[c].im - R(0.5) * acc[t][c].im};
       if (bsub) {
         auto bv = ldc(bsub + ((size_t)(r0 + t) * 12 + c) * Vs + s);
-        o = cx<R>{(R)bv.re - o.re, (R)bv.im - o.im};
+        R bs = R(1);
+        if (bnrm2) {
+          double q = bnrm2[(size_t)(r0 + t) * bstride];
+          bs = q > 0 ? (R)(1.0 / sqrt(q)) : R(0);
+        }
+        o = cx<R>{bs * (R)bv.re - o.re, bs * (R)bv.im - o.im};
       }
       stc(out + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
+      if (RED) o = as_stored(out, o);
       if (RED) {
         rs[t][0] += (double)o.re * p[c].re + (double)o.im * p[c].im;
         rs[t][1] += (double)o.re * p[c].im - (double)o.im * p[c].re;
@@ -330,32 +337,37 @@ __global__ void __launch_bounds__(256) k_dslash_red_finalize(const double *__res
                                                                    sh[threadIdx.x][2] + sh[threadIdx.x][3];
 }
 
-template <class TL, class TS>
+template <class TL, class TS, class TO = TS>
 static void launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, const void *bsub,
-                       double *red, double *red_out, int red_stride, hipStream_t st) {
+                       double *red, double *red_out, int red_stride, hipStream_t st, const double *bnrm2 = nullptr,
+                       int bstride = 0) {
   constexpr int RT = sizeof(TS) == 16 ? 1 : 2;
   // bytes a site brings into L2 during one sweep: its links and RT spinors
   SweepMap sm = make_sweep(g.L, 36 * (int)sizeof(TL) + 24 * (int)sizeof(TS) / 2 * RT);
   dim3 grid((unsigned)sm.nblocks, (nrhs + RT - 1) / RT);
   const size_t lds = (size_t)(nrhs < RT ? nrhs : RT) * 12 * 256 * sizeof(TS);
   if (red) {
-    hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT, 1>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
-                       (TS *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                       (const TS *)bsub, red);
+    hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
+                       (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
+                       (const TS *)bsub, bnrm2, bstride, red);
     hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
                        red_stride);
   } else {
-    hipLaunchKernelGGL((k_wilson_soa<TL, TS, RT, 0>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
-                       (TS *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                       (const TS *)bsub, (double *)nullptr);
+    hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
+                       (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
+                       (const TS *)bsub, bnrm2, bstride, (double *)nullptr);
   }
 }
 
 long wilson_red_blocks(const Geom &g) {
-  SweepMap a = make_sweep(g.L, 36 * 16 + 24 * 8), b = make_sweep(g.L, 36 * 8 + 24 * 4 * 2),
-           c = make_sweep(g.L, 36 * 4 + 24 * 4 * 2);
-  long m = a.nblocks > b.nblocks ? a.nblocks : b.nblocks;
-  return m > c.nblocks ? m : c.nblocks;
+  // every (link, spinor) storage pair launch_soa instantiates
+  const int bps[4] = {36 * 16 + 24 * 8, 36 * 8 + 24 * 4 * 2, 36 * 4 + 24 * 4 * 2, 36 * 4 + 24 * 2 * 2};
+  long m = 0;
+  for (int i = 0; i < 4; i++) {
+    long nb = make_sweep(g.L, bps[i]).nblocks;
+    m = nb > m ? nb : m;
+  }
+  return m;
 }
 
 int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
@@ -367,6 +379,18 @@ int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double 
   else if (sprec == P32 && lprec == P16)
     launch_soa<__half2, float2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st);
   else return set_error(-1, "wilson_soa: unsupported precision pair link=%d spinor=%d", lprec, sprec);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
+                   const void *bsub, const double *bnrm2, int bstride, double *red, double *red_out, int red_stride,
+                   hipStream_t st) {
+  if (iprec == P32)
+    launch_soa<__half2, float2, __half2>(g, U16, m, in, out, nrhs, bsub, red, red_out, red_stride, st, bnrm2, bstride);
+  else if (iprec == P16 && !bsub)
+    launch_soa<__half2, __half2, __half2>(g, U16, m, in, out, nrhs, nullptr, red, red_out, red_stride, st);
+  else return set_error(-1, "wilson_soa_h16: input precision %d%s", iprec, bsub ? " with bsub" : "");
   WMG_HIP(hipGetLastError());
   return 0;
 }

@@ -31,7 +31,7 @@ int set_error(int code, const char *fmt, ...) {
 
 
 static constexpr int KMAX = 16;
-static size_t csize(int prec) { return prec == P64 ? 16 : 8; }
+static size_t csize(int prec) { return prec == P64 ? 16 : (prec == P16 ? 4 : 8); }
 
 // ------------------------------------------------------------ scalar kernels
 // MR step: alpha = <q,s>/|q|^2 (red[rhs*4 + 0..2]); e += alpha s; s -= alpha q
@@ -75,7 +75,7 @@ __global__ void k_mr_next(const double *__restrict__ red, int k, const S *__rest
 struct MrVecs {
   const void *s[4];
 };
-template <class S>
+template <class S, class SS = S>
 __global__ void k_mr_accum(const double *__restrict__ red, int nsteps, MrVecs v, S *__restrict__ e, long n) {
   using R = typename store_traits<S>::real;
   int rhs = blockIdx.y;
@@ -87,7 +87,7 @@ __global__ void k_mr_accum(const double *__restrict__ red, int nsteps, MrVecs v,
     cx<R> acc = ldc(e + off + i);
 #pragma unroll
     for (int k = 0; k < 4; k++)
-      if (k < nsteps) acc = cfma(a[k], ldc((const S *)v.s[k] + off + i), acc);
+      if (k < nsteps) acc = cfma(a[k], ldc((const SS *)v.s[k] + off + i), acc);
     stc(e + off + i, acc);
   }
 }
@@ -224,8 +224,8 @@ struct Level {
   __half2 *P16 = nullptr;
   float *Ps = nullptr;
   // work vectors: [prec][name] each [cap][n_alloc], cap = largest nrhs asked for
-  void *w[2][NVW] = {};
-  int w_cap[2][NVW] = {};
+  void *w[3][NVW] = {};  // work vectors by storage precision (P64, P32, P16)
+  int w_cap[3][NVW] = {};
 };
 
 struct GcrBuf {
@@ -248,6 +248,7 @@ struct wmg_ctx {
   double *dsc = nullptr;  // device scalars
   double *red_out = nullptr;
   double *mr_red = nullptr;  // fused MR step reductions, [step][rhs][4]
+  double *cyc_nrm = nullptr;  // |r|^2 of the cycle input per rhs, [rhs][4]
   double *cg = nullptr;
   double *gcr = nullptr;
   double *mask = nullptr;
@@ -338,7 +339,7 @@ static int sync(wmg_ctx *c) {
 // a solve uses one nrhs throughout, so pointers stay valid within it)
 static int level_vec(wmg_ctx *c, int l, int prec, int name, void **out, int nrhs) {
   Level &L = c->lv[l];
-  int pi = prec == P64 ? 0 : 1;
+  int pi = prec == P64 ? 0 : (prec == P16 ? 2 : 1);
   if (L.w_cap[pi][name] < nrhs) {
     if (L.w[pi][name]) (void)hipFree(L.w[pi][name]);
     L.w[pi][name] = nullptr;
@@ -427,6 +428,43 @@ static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int
 }
 
 // ------------------------------------------------------------ MR smoother
+// Fine-level smoother of the mixed-precision cycle with the MR residuals
+// s_k and q_k = A s_k stored in FP16 (FP32 arithmetic, FP16 links).  The
+// cycle input r is used as r/|r| (|r|^2 per rhs in rn2, stride 4): the cycle
+// is homogeneous in r, the restricted residual was scaled the same way, so
+// e here belongs to r/|r| and every stored residual is O(1).
+static int mr_smooth_h16(wmg_ctx *c, const void *r, const double *rn2, void *e, int nsteps, int nrhs) {
+  Level &L = c->lv[0];
+  void *sv[4] = {nullptr, nullptr, nullptr, nullptr}, *q;
+  const int names[4] = {VS, VS1, VS2, VS3};
+  for (int k = 0; k < nsteps; k++) TRY(level_vec(c, 0, P16, names[k], &sv[k], nrhs));
+  TRY(level_vec(c, 0, P16, VQ, &q, nrhs));
+  const double vb = (double)L.g.V * 36 * 4;  // FP16 links
+  c->st_fine++;
+  int slot = prof_begin(c, K_DSLASH_RES, vb + (double)L.g.V * 12 * (8 + 8 + 4) * nrhs);
+  int rc = wilson_soa_h16(L.g, L.U[P16], P32, L.m, e, sv[0], nrhs, r, rn2, 4, nullptr, nullptr, 0, c->st);
+  prof_end(c, slot);
+  TRY(rc);
+  dim3 g = grid_for<double2>(L.n, nrhs);
+  for (int k = 0; k < nsteps; k++) {
+    c->st_fine++;
+    slot = prof_begin(c, K_DSLASH_CYCLE, vb + (double)L.g.V * 12 * (4 + 4) * nrhs);
+    rc = wilson_soa_h16(L.g, L.U[P16], P16, L.m, sv[k], q, nrhs, nullptr, nullptr, 0, c->dred,
+                        c->mr_red + (size_t)k * 64 * 4, 4, c->st);
+    prof_end(c, slot);
+    TRY(rc);
+    if (k + 1 < nsteps) {
+      hipLaunchKernelGGL(k_mr_next<__half2>, g, dim3(256), 0, c->st, c->mr_red, k, (const __half2 *)sv[k],
+                         (const __half2 *)q, (__half2 *)sv[k + 1], L.n);
+      WMG_HIP(hipGetLastError());
+    }
+  }
+  MrVecs mv{{sv[0], sv[1], sv[2], sv[3]}};
+  hipLaunchKernelGGL((k_mr_accum<float2, __half2>), g, dim3(256), 0, c->st, c->mr_red, nsteps, mv, (float2 *)e, L.n);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
 // nsteps minimal-residual steps on A e = r from e (post-smoother, Sec. 3).
 // On the fine level the residual and the two step reductions are fused into
 // the operator's kernel.
@@ -556,7 +594,14 @@ static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int n
   void *rc, *ec;
   TRY(level_vec(c, l + 1, prec, VR, &rc, nrhs));
   TRY(level_vec(c, l + 1, prec, VE, &ec, nrhs));
+  // FP32 cycle on the fine level: FP16 smoother storage on the normalised
+  // problem r/|r| (e comes out scaled by 1/|r|, which the flexible outer
+  // solver absorbs)
+  const bool h16 = l == 0 && prec == P32 && c->lv[0].fine && c->p.post_smooth >= 1 && c->p.post_smooth <= 4 &&
+                   nrhs <= 64;
+  if (h16) TRY(norm2(c->red, P32, r, c->lv[0].n, nrhs, c->cyc_nrm, 4, c->st));
   TRY(transfer_restrict(c, l, prec, r, rc, nrhs));
+  if (h16) TRY(scale_inv_sqrt(P32, rc, c->cyc_nrm, 4, C.n, nrhs, c->st));
   if (l + 1 == c->nl_cur - 1) {
     TRY(cgnr(c, l + 1, prec, rc, ec, nrhs));
   } else {
@@ -572,6 +617,7 @@ static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int n
     }
   }
   TRY(transfer_prolong(c, l, prec, ec, e, nrhs));
+  if (h16) return mr_smooth_h16(c, r, c->cyc_nrm, e, c->p.post_smooth, nrhs);
   TRY(mr_smooth(c, l, prec, r, e, c->p.post_smooth, nrhs));
   return 0;
 }
@@ -822,7 +868,7 @@ static void free_ctx(wmg_ctx *c) {
     void *ps[] = {L.Y64, L.Y32, L.Ym, L.vecs, L.P64, L.P32, L.P16, L.Ps};
     for (void *p : ps)
       if (p) (void)hipFree(p);
-    for (int a = 0; a < 2; a++)
+    for (int a = 0; a < 3; a++)
       for (int k = 0; k < NVW; k++)
         if (L.w[a][k]) (void)hipFree(L.w[a][k]);
   }
@@ -962,7 +1008,8 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
   c->cg = c->dsc + 4 * 64;
   c->gcr = c->cg + 8 * 64;
   c->mask = c->gcr + GS * 64;
-  c->mr_red = c->mask + 64;  // [4 steps][64 rhs][4]
+  c->mr_red = c->mask + 64;          // [4 steps][64 rhs][4]
+  c->cyc_nrm = c->mr_red + 4 * 64 * 4;  // [64 rhs][4]
   CK(dalloc((void **)&c->flag, sizeof(int)));
   CK(hipHostMalloc((void **)&c->hbuf, sizeof(double) * 4096) == hipSuccess ? 0 : set_error(WMG_ENOMEM, "hipHostMalloc"));
   {

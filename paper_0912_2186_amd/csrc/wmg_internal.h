@@ -59,6 +59,13 @@ __device__ __forceinline__ void stc(double2 *p, cx<double> v) { *p = make_double
 __device__ __forceinline__ void stc(float2 *p, cx<float> v) { *p = make_float2(v.re, v.im); }
 __device__ __forceinline__ void stc(double2 *p, cx<float> v) { *p = make_double2(v.re, v.im); }
 __device__ __forceinline__ void stc(float2 *p, cx<double> v) { *p = make_float2((float)v.re, (float)v.im); }
+__device__ __forceinline__ void stc(__half2 *p, cx<float> v) { *p = __floats2half2_rn(v.re, v.im); }
+// value as it reads back after a store to S (rounding of FP16 storage)
+__device__ __forceinline__ cx<float> as_stored(const __half2 *, cx<float> v) {
+  float2 r = __half22float2(__floats2half2_rn(v.re, v.im));
+  return {r.x, r.y};
+}
+template <class S, class R> __device__ __forceinline__ cx<R> as_stored(const S *, cx<R> v) { return v; }
 
 template <class S> struct store_traits;
 template <> struct store_traits<double2> { using real = double; };
@@ -116,6 +123,14 @@ int wilson_soa(const Geom &g, int lprec, const void *U, int sprec, double m, con
 // red_out[rhs * red_stride + 0..2] (red: scratch of nrhs * wilson_red_blocks * 3)
 int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
                      const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st);
+// Smoother variant with FP16 links and FP16 output storage: in is FP32
+// (iprec P32) or FP16 (P16); out (FP16) = [b/|b| -] D in, where bsub (FP32,
+// only with iprec P32) is scaled per rhs by 1/sqrt(bnrm2[rhs * bstride])
+// (0 where that norm is 0); red as in wilson_soa_fused, computed from the
+// stored (rounded) output.
+int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
+                   const void *bsub, const double *bnrm2, int bstride, double *red, double *red_out, int red_stride,
+                   hipStream_t st);
 long wilson_red_blocks(const Geom &g);
 int links_to_soa(const Geom &g, const double *Ucanon, int lprec, void *Usoa, hipStream_t st);
 int spinor_to_soa(const Geom &g, const double *canon, double2 *soa, int nrhs, hipStream_t st);
