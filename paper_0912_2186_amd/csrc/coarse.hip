@@ -133,6 +133,8 @@ __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__r
   for (int d = 0; d < 9; d++) {
     cx<double> w[12];
     for (int c = 0; c < 12; c++) w[c] = czero<double>();
+    // only sites on the block face crossed by direction d contribute to d > 0
+    bool nz = act && d == 0;
     if (act) {
       if (d == 0) {
         cx<double> v[12];
@@ -144,6 +146,7 @@ __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__r
           bool cross = sg > 0 ? (x[mu] % g.b[mu] == g.b[mu] - 1) : (x[mu] % g.b[mu] == 0);
           int cls = cross ? (sg > 0 ? 1 + mu : 5 + mu) : 0;
           if (cls != d) continue;
+          nz = true;
           int y[4] = {x[0], x[1], x[2], x[3]};
           y[mu] = (y[mu] + sg + g.L[mu]) % g.L[mu];
           cx<double> v[12];
@@ -159,7 +162,7 @@ __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__r
       for (int j = 0; j < 16; j++) {
         acc[j] = czero<double>();
         int row = r0 + j;
-        if (act && row < n) {
+        if (nz && row < n) {
           int chir = row / nv, be = row % nv;
           for (int c = chir * 6; c < chir * 6 + 6; c++)
             acc[j] = cfmac(ldc(P + ((size_t)be * g.Vc + xh) * E + (size_t)c * g.bs + k), w[c], acc[j]);

@@ -1,0 +1,182 @@
+"""GPU checks at the workloads' full sizes, in the launch configurations the
+benchmark times: the oracle computes the sampled outputs (one FP64 operator
+application per checked right-hand side) or the properties that hold at any
+size (FP64 true residual, mass independence of the MG iteration count).
+
+Workloads (inputs recipe in the benchmark): 32^3x64 with 28 right-hand sides
+(12 point sources + 16 Z4 vectors) in mixed precision; 24^3x48 three-level
+W-cycle in mixed precision; 16^3x32 FP64 mass scan against BiCGStab; an
+uneven batch of 16 instances (8^4, 12^4, 16^4, 16^3x32, four each)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0912_2186_amd import inputs
+from helpers import relerr, vol
+
+pytestmark = pytest.mark.gpu
+
+L4 = (32, 32, 32, 64)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def empty(shape):
+    import torch
+
+    return torch.zeros(shape, dtype=torch.complex128, device="cuda")
+
+
+def relres(L, U, m, b, x):
+    return np.linalg.norm(b - oracle.wilson(L, U, m, x)) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def links32():
+    say("generating 32^3x64 links")
+    return inputs.gauge_field(L4, 0.6, 401)
+
+
+def test_fullsize_dslash_all_precisions(wmg, links32):
+    """32^3x64: the canonical FP64 operator and the internal FP32 and
+    FP16-link operators against the oracle's D on the whole lattice."""
+    say("full-size dslash", L4)
+    U = links32
+    m = -0.32
+    b = inputs.gaussian_rhs(L4, 410)
+    ref = oracle.wilson(L4, U, m, b[0])
+    out = empty((vol(L4), 12))
+    wmg.wilson_apply(L4, dev(U), m, dev(b[0]), out)
+    e64 = relerr(host(out), ref)
+    p = wmg.default_params(setup_iters=0, nrhs_max=2, seed=3)
+    mg = wmg.MG(L4, dev(U), m, 2, (4, 4, 4, 4), p)
+    o2 = empty((2, vol(L4), 12))
+    b2 = np.concatenate([b, inputs.z4_noise(L4, 411, 1)])
+    ref2 = oracle.wilson(L4, U, m, b2[1])
+    res = {}
+    for prec in (0, 1, 2):
+        mg.mg_apply_fine(prec, dev(b2), o2, 2)
+        oh = host(o2)
+        res[prec] = max(relerr(oh[0], ref), relerr(oh[1], ref2))
+    mg.close()
+    say("  fp64 canonical", e64, "internal", res)
+    assert e64 < 1e-13
+    assert res[0] < 1e-13 and res[1] < 1e-6 and res[2] < 2e-3
+
+
+def test_fullsize_headline_solve(wmg, links32):
+    """32^3x64, 28 right-hand sides in one mixed-precision solve, N_nu = 24,
+    10 setup iterations: converged, and the oracle's FP64 residual of a
+    sample of point-source and Z4 solutions is below 1e-10."""
+    say("headline solve", L4)
+    U = links32
+    m = -0.32
+    b = np.concatenate([inputs.point_sources(L4)[:12], inputs.z4_noise(L4, 410, 16)])
+    nrhs = b.shape[0]
+    p = wmg.default_params(setup_iters=10, seed=450, nrhs_max=nrhs, precision=wmg.WMG_MIXED, coarse_tol=1e-5)
+    mg = wmg.MG(L4, dev(U), m, 24, (4, 4, 4, 4), p)
+    bd = dev(b)
+    x = empty((nrhs, vol(L4), 12))
+    st = mg.mg_solve(bd, x, 1e-10)
+    its = mg.mg_last_iters(nrhs)
+    say("  ", st, its)
+    assert st["converged"] and st["true_relres"] <= 1e-10
+    mg.close()
+    del bd
+    xh = host(x)
+    for r in (0, 7, 12, 27):
+        rr = relres(L4, U, m, b[r], xh[r])
+        say("  rhs", r, "oracle relres", rr)
+        assert rr <= 1e-10 * 1.0001
+
+
+def test_config3_three_level_mixed(wmg):
+    """24^3x48, three-level W-cycle (4^4 then 2^4 aggregates, N_nu = 24 / 32),
+    mixed precision, eps 0.6, m = -0.3: converged to the oracle's 1e-10."""
+    L = (24, 24, 24, 48)
+    say("three-level mixed", L)
+    U = inputs.gauge_field(L, 0.6, 301)
+    m = -0.3
+    b = inputs.gaussian_rhs(L, 310, 2)
+    p = wmg.default_params(levels=3, block=((4, 4, 4, 4), (2, 2, 2, 2)), nvec=(24, 32), setup_iters=10, seed=350,
+                           precision=wmg.WMG_MIXED, nrhs_max=2, coarse_tol=1e-5)
+    mg = wmg.MG(L, dev(U), m, 24, (4, 4, 4, 4), p)
+    x = empty((2, vol(L), 12))
+    st = mg.mg_solve(dev(b), x, 1e-10)
+    say("  ", st, mg.mg_last_iters(2), mg.level_info(1), mg.level_info(2))
+    assert st["converged"]
+    mg.close()
+    xh = host(x)
+    for r in range(2):
+        rr = relres(L, U, m, b[r], xh[r])
+        say("  rhs", r, "oracle relres", rr)
+        assert rr <= 1e-10 * 1.0001
+
+
+def test_config2_mass_scan_against_bicgstab(wmg):
+    """16^3x32, eps 0.5, FP64: one setup at m = -0.35, exact coarse shift to
+    m in {0, -0.2, -0.3, -0.35}.  The MG outer iteration count stays within
+    1.5x over the scan (the paper's Table 1 criterion) and grows less than
+    BiCGStab's; every solution meets the oracle's 1e-10."""
+    L = (16, 16, 16, 32)
+    say("mass scan", L)
+    U = inputs.gauge_field(L, 0.5, 201)
+    b = inputs.gaussian_rhs(L, 210)
+    p = wmg.default_params(setup_iters=10, seed=250, precision=wmg.WMG_FP64, coarse_tol=1e-8)
+    mg = wmg.MG(L, dev(U), -0.35, 24, (4, 4, 4, 4), p)
+    mg_its, bi_its = [], []
+    for m in (0.0, -0.2, -0.3, -0.35):
+        mg.mg_set_mass(m)
+        x = empty((1, vol(L), 12))
+        st = mg.mg_solve(dev(b), x, 1e-10)
+        rr = relres(L, U, m, b[0], host(x)[0])
+        xb = empty((vol(L), 12))
+        sb = wmg.bicgstab_solve(L, dev(U), m, dev(b[0]), xb, 1e-10, maxiter=20000)
+        say("  m", m, "MG", st["outer_iters"], "relres", rr, "BiCGStab", sb["outer_iters"], sb["converged"])
+        assert st["converged"] and rr <= 1e-10 * 1.0001
+        mg_its.append(st["outer_iters"])
+        bi_its.append(sb["outer_iters"])
+    mg.close()
+    g_mg = max(mg_its) / min(mg_its)
+    g_bi = max(bi_its) / min(bi_its)
+    say("  growth MG", g_mg, "BiCGStab", g_bi)
+    assert g_mg <= 1.5
+    assert g_bi > g_mg
+
+
+def test_config5_uneven_batch_of_16(wmg):
+    """16 instances, four each of 8^4, 12^4, 16^4 and 16^3x32, with
+    eps_k = 0.3 + 0.1k, m_k = -0.1 - 0.2k/3, seeds 1000 + 10*size + k, set up
+    and solved together (N_nu = 24): every solution meets the oracle's 1e-10."""
+    sizes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32)]
+    shapes, Us, ms, bs = [], [], [], []
+    for si, L in enumerate(sizes):
+        for k in range(4):
+            shapes.append(L)
+            Us.append(inputs.gauge_field(L, 0.3 + 0.1 * k, 1000 + 10 * si + k))
+            ms.append(-0.1 - 0.2 * k / 3)
+            bs.append(inputs.gaussian_rhs(L, 2000 + 10 * si + k))
+    say("uneven batch of", len(shapes))
+    p = wmg.default_params(setup_iters=10, seed=1077)
+    batch = wmg.MGBatch(shapes, [dev(U) for U in Us], ms, 24, (4, 4, 4, 4), p)
+    xs = [empty((1, vol(L), 12)) for L in shapes]
+    sts = batch.mg_solve_batch([dev(b) for b in bs], xs, 1e-10)
+    for i, L in enumerate(shapes):
+        rr = relres(L, Us[i], ms[i], bs[i][0], host(xs[i])[0])
+        say("  instance", i, L, "m", round(ms[i], 4), sts[i]["outer_iters"], rr)
+        assert sts[i]["converged"] and rr <= 1e-10 * 1.0001
