@@ -35,6 +35,11 @@ WORKLOADS = {
                               setup_iters=10, seed_cfg=2),
     "8^4-1rhs-fp64": dict(L=(8, 8, 8, 8), eps=0.3, m=-0.1, nv=8, npoint=0, nz4=0, ngauss=1, mixed=False,
                           setup_iters=5, seed_cfg=1),
+    # mass scan towards the critical mass of eps = 0.6 fields (m_crit = -0.865,
+    # smallest real part of the spectrum of D(0) on a 16^4 field of this
+    # kind): one setup at the lightest mass, exact coarse shifts to the others
+    "48^3x96-critical-scan": dict(L=(48, 48, 48, 96), eps=0.6, m_crit=-0.865, scan=(0.2, 0.1, 0.05, 0.02), nv=24,
+                                  npoint=0, nz4=0, ngauss=1, mixed=True, setup_iters=10, seed_cfg=5),
 }
 DEFAULT = "32^3x64-28rhs-mixed"
 
@@ -122,6 +127,66 @@ def cpu_baseline(w):
     }
 
 
+def critical_scan(args, w):
+    """Mixed-precision solves of one Gaussian rhs at m = m_crit + dm for each
+    dm of the scan, after one setup at the lightest mass: outer iterations
+    and seconds per solve (the paper's Table 1 criterion is the growth of the
+    iteration count as m - m_crit shrinks)."""
+    import torch
+
+    from paper_0912_2186_amd import inputs, wmg
+
+    L = w["L"]
+    t0 = time.time()
+    U = inputs.gauge_field(L, w["eps"], w["seed_cfg"] * 100 + 1)
+    b = inputs.gaussian_rhs(L, w["seed_cfg"] * 100 + 10)
+    log("inputs %.1fs" % (time.time() - t0))
+    Ud = torch.from_numpy(U).cuda()
+    del U
+    bd = torch.from_numpy(b).cuda()
+    masses = [w["m_crit"] + dm for dm in w["scan"]]
+    kw = {}
+    if args.levels == 3:
+        kw = dict(levels=3, block=((4, 4, 4, 4), (2, 2, 2, 2)), nvec=(w["nv"], 32))
+    p = wmg.default_params(setup_iters=w["setup_iters"], seed=w["seed_cfg"] * 100 + 50, nrhs_max=1,
+                           precision=wmg.WMG_MIXED, coarse_tol=1e-5, **kw)
+    os.environ.setdefault("WMG_VERBOSE", "1")  # the setup reports each null vector
+    torch.cuda.synchronize()
+    t0 = time.time()
+    mg = wmg.MG(L, Ud, min(masses), w["nv"], (4, 4, 4, 4), p)
+    setup_s = time.time() - t0
+    log("setup at m = %.4f: %.1fs" % (min(masses), setup_s))
+    rows = []
+    for m in masses:
+        mg.mg_set_mass(m)
+        x = torch.zeros_like(bd)
+        mg.mg_solve(bd, x, 1e-10)  # warm-up (work vectors)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        st = mg.mg_solve(bd, x, 1e-10)
+        el = time.time() - t0
+        rows.append({"mass": round(m, 4), "m_minus_mcrit": round(m - w["m_crit"], 4), "outer_iters": st["outer_iters"],
+                     "coarse_iters": st["coarse_iters"], "s_per_rhs": round(el, 4), "true_relres": st["true_relres"],
+                     "converged": st["converged"]})
+        log("m %.4f: %s (%.3fs)" % (m, st, el))
+    dsl = {}
+    for prec, name, lb, sb in [(0, "fp64", 16, 16), (1, "fp32", 8, 8), (2, "fp16links_fp32spinor", 4, 8)]:
+        ms = mg.mg_time_dslash(prec, 1, 10)
+        V = L[0] * L[1] * L[2] * L[3]
+        dsl[name] = {"ms": round(ms, 4), "GB/s": round(V * (36 * lb + 24 * sb) / (ms * 1e-3) / 1e9, 1)}
+    mg.close()
+    its = [r["outer_iters"] for r in rows]
+    print(json.dumps({
+        "metric": "MG-GCR outer iterations vs m - m_crit (mass scan), s/RHS", "value": rows[-1]["s_per_rhs"],
+        "unit": "s/RHS", "n_gpus": 1, "higher_is_better": False, "dtype": "f32 cycle, f64 outer",
+        "data": "synthetic: seeded SU(3) links exp(i eps H), Gaussian rhs",
+        "config": {"workload": args.workload, "lattice": list(L), "eps": w["eps"], "m_crit": w["m_crit"],
+                   "Nv": w["nv"], "block": [4, 4, 4, 4], "levels": args.levels, "tol": 1e-10,
+                   "setup_mass": round(min(masses), 4),
+                   "setup_s": round(setup_s, 2)},
+        "scan": rows, "iteration_growth": round(max(its) / min(its), 3), "dslash_nrhs1": dsl}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +197,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-RHS comparison solve")
     ap.add_argument("--delta", type=float, default=None, help="reliable-update threshold (default: library's)")
     ap.add_argument("--coarse-tol", type=float, default=None, help="coarsest CGNR tolerance (mixed default 1e-5)")
+    ap.add_argument("--levels", type=int, choices=[2, 3], default=2,
+                    help="multigrid levels of the critical-mass scan (3: 4^4 then 2^4 aggregates, N_nu 24 / 32)")
     ap.add_argument("--only", choices=["dslash", "copy"], default=None,
                     help="counter runs: only the fine-operator kernels (FP64, FP32, FP16-link) on the workload "
                          "lattice, or only a 1 GiB device copy (bytes reference for the HBM counters)")
@@ -149,6 +216,8 @@ def main():
     w = WORKLOADS[args.workload]
     L = w["L"]
     V = L[0] * L[1] * L[2] * L[3]
+    if "scan" in w:
+        return critical_scan(args, w)
     if args.only == "copy":
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

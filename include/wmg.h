@@ -108,7 +108,9 @@ int wilson_apply(const wmg_geom *g, const double *U, double m, const double *in,
  * orthonormal prolongator P (sigma_3 P = P gamma_5) and the Galerkin coarse
  * operator P^dag D P, recursively for `levels` levels, at mass m.
  * block[4] must divide the lattice; 1 <= Nv <= 6*|block|.  p may be NULL
- * (defaults).  On success *out receives a new context. */
+ * (defaults).  On success *out receives a new context.  With the environment
+ * variable WMG_VERBOSE set (not "0") the setup prints one line per finished
+ * null vector to stderr. */
 int mg_setup(const wmg_geom *g, const double *U, double m, int Nv, const int block[4], const wmg_params *p,
              wmg_ctx **out);
 

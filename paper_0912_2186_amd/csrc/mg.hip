@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -249,6 +250,7 @@ struct wmg_ctx {
   double *red_out = nullptr;
   double *mr_red = nullptr;  // fused MR step reductions, [step][rhs][4]
   double *cyc_nrm = nullptr;  // |r|^2 of the cycle input per rhs, [rhs][4]
+  bool verbose = false;       // WMG_VERBOSE set: one stderr line per setup vector
   double *cg = nullptr;
   double *gcr = nullptr;
   double *mask = nullptr;
@@ -852,6 +854,10 @@ static int setup_level(wmg_ctx *c, int l) {
     TRY(norm2(c->red, P64, B->x64, n, 1, c->red_out, 4, c->st));
     TRY(scale_inv_sqrt(P64, B->x64, c->red_out, 4, n, 1, c->st));
     TRY(copy(P64, F.vecs + (size_t)k * n, P64, B->x64, n, 1, c->st));
+    if (c->verbose) {
+      TRY(sync(c));
+      std::fprintf(stderr, "wmg setup: level %d vector %d/%d done\n", l, k + 1, nv);
+    }
   }
   TRY(build_level(c, l, nv));
   c->nl_cur = c->nl;
@@ -1004,6 +1010,10 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
   CK(hipStreamCreate(&c->st) == hipSuccess ? 0 : set_error(WMG_EHIP, "hipStreamCreate"));
   CK(red_init(c->red, p.nrhs_max));
   CK(dalloc((void **)&c->dsc, sizeof(double) * ((size_t)(4 + 8 + GS + 1) * 64 + 4096)));
+  {
+    const char *v = std::getenv("WMG_VERBOSE");
+    c->verbose = v && *v && *v != '0';
+  }
   c->red_out = c->dsc;
   c->cg = c->dsc + 4 * 64;
   c->gcr = c->cg + 8 * 64;
