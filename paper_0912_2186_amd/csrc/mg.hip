@@ -679,6 +679,21 @@ static int gcr_buffers(wmg_ctx *c, int l, int prec, int nrhs, GcrBuf **out) {
 // the triangular system A z_k = gamma_k w_k + sum_j beta_jk w_j, and the
 // residual is recomputed in FP64 (the reliable update).
 // precond: 0 = smoother only (first setup vector), 1 = multigrid cycle.
+// r = b - A x in FP64 and |r|^2 per rhs into c->red_out[rhs*4 + *off]; on
+// the fine level one fused operator launch (residual and norm in its
+// epilogue), elsewhere operator, subtraction and norm.
+static int residual64(wmg_ctx *c, int l, GcrBuf &B, int nrhs, int *off) {
+  Level &L = c->lv[l];
+  if (L.fine) {
+    *off = 2;
+    return fine_apply_fused(c, P64, B.x64, B.r64, nrhs, B.b64, true);
+  }
+  *off = 0;
+  TRY(apply_op(c, l, P64, B.x64, B.t64, nrhs, false));
+  TRY(csub(P64, B.b64, B.t64, B.r64, L.n, nrhs, c->st));
+  return norm2(c->red, P64, B.r64, L.n, nrhs, c->red_out, 4, c->st);
+}
+
 static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int maxiter, int precond, double delta,
                      bool x0_nonzero, std::vector<int> &iters, double *relres_out) {
   Level &L = c->lv[l];
@@ -694,18 +709,18 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
   WMG_HIP(hipMemcpyAsync(c->hbuf, c->red_out, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, st));
   TRY(sync(c));
   for (int r = 0; r < nrhs; r++) bn[r] = sqrt(c->hbuf[4 * r]);
+  int roff = 0;
   if (x0_nonzero) {
-    TRY(apply_op(c, l, P64, B.x64, B.t64, nrhs, false));
-    TRY(csub(P64, B.b64, B.t64, B.r64, n, nrhs, st));
+    TRY(residual64(c, l, B, nrhs, &roff));
   } else {
     TRY(copy(P64, B.r64, P64, B.b64, n, nrhs, st));
+    TRY(norm2(c->red, P64, B.r64, n, nrhs, c->red_out, 4, st));
   }
-  TRY(norm2(c->red, P64, B.r64, n, nrhs, c->red_out, 4, st));
   WMG_HIP(hipMemcpyAsync(c->hbuf, c->red_out, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, st));
   TRY(sync(c));
   bool any = false;
   for (int r = 0; r < nrhs; r++) {
-    rn[r] = sqrt(c->hbuf[4 * r]);
+    rn[r] = sqrt(c->hbuf[4 * r + roff]);
     active[r] = !(rn[r] <= tol * bn[r]);
     if (!std::isfinite(rn[r])) return set_error(WMG_EBREAKDOWN, "non-finite initial residual");
     any |= active[r];
@@ -765,15 +780,13 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
     hipLaunchKernelGGL(k_gcr_trisolve2, dim3(1), dim3(64), 0, st, c->gcr, k, nrhs);
     TRY(multi_caxpy(P64, B.x64, ip, (const void *const *)B.zdev, k, c->gcr + G_C, GS, 1.0, 1, n, nrhs, st));
     // reliable update: true residual in FP64
-    TRY(apply_op(c, l, P64, B.x64, B.t64, nrhs, false));
-    TRY(csub(P64, B.b64, B.t64, B.r64, n, nrhs, st));
+    TRY(residual64(c, l, B, nrhs, &roff));
     c->st_rel++;
-    TRY(norm2(c->red, P64, B.r64, n, nrhs, c->red_out, 4, st));
     WMG_HIP(hipMemcpyAsync(c->hbuf, c->red_out, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, st));
     TRY(sync(c));
     any = false;
     for (int r = 0; r < nrhs; r++) {
-      rn[r] = sqrt(c->hbuf[4 * r]);
+      rn[r] = sqrt(c->hbuf[4 * r + roff]);
       if (!std::isfinite(rn[r])) return set_error(WMG_EBREAKDOWN, "non-finite true residual (rhs %d)", r);
       if (active[r] && rn[r] <= tol * bn[r]) active[r] = 0;
       any |= (bool)active[r];

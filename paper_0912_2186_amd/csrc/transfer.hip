@@ -476,7 +476,7 @@ static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, 
       hipLaunchKernelGGL((k_restrict<FINE, N, TP, TV>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps,  \
                          (const TV *)in, (TV *)out, nrhs);                                                 \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_prolong<FINE, N, sizeof(TV) == 16 ? 4 : 16, TP, TV>), dim3((unsigned)xcd_grid(bg.Vc)), \
+      hipLaunchKernelGGL((k_prolong<FINE, N, sizeof(TV) == 16 ? 4 : 32, TP, TV>), dim3((unsigned)xcd_grid(bg.Vc)), \
                          dim3(TB), 0, st, bg, nv, (const TP *)P, Ps, (const TV *)in, (TV *)out, nrhs);       \
     WMG_HIP(hipGetLastError());                                                                            \
     return 0;                                                                                              \
