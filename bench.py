@@ -91,7 +91,7 @@ def make_rhs(inputs, L, w):
 
 def cpu_baseline(w):
     """The FP64 oracle, as it stands, on a bounded sample of the same
-    workload: setup + one-RHS MG-GCR solves on an 8^3 x 16 sub-volume with
+    workload: setup + one-RHS MG-GCR solves on a 12^3 x 16 sub-volume with
     the same parameters; its solve time is scaled to the full volume (the
     iteration count is nearly volume independent, the cost per iteration
     linear in the volume)."""
@@ -100,7 +100,7 @@ def cpu_baseline(w):
     import oracle
     from paper_0912_2186_amd import inputs
 
-    Ls = (8, 8, 8, 16)
+    Ls = (12, 12, 12, 16)
     Vs = Ls[0] * Ls[1] * Ls[2] * Ls[3]
     V = w["L"][0] * w["L"][1] * w["L"][2] * w["L"][3]
     U = inputs.gauge_field(Ls, w["eps"], w["seed_cfg"] * 100 + 1)
@@ -110,20 +110,20 @@ def cpu_baseline(w):
     t0 = time.time()
     mg.setup()
     ts = time.time() - t0
-    nsample = 4
+    nsample = 8
     bs = inputs.gaussian_rhs(Ls, 7, nsample)
     t0 = time.time()
     for k in range(nsample):
         x, st = mg.solve(bs[k], 1e-10)
     t = (time.time() - t0) / nsample
     return {
-        "value": t * V / Vs,
+        "value": t * V / Vs,  # Vs does not divide V: the ratio is fractional
         "unit": "s/RHS",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": "FP64 oracle MG-GCR (same N_nu, blocks, eps, m, tol 1e-10) on an 8^3x16 sub-volume, "
+        "sample": "FP64 oracle MG-GCR (same N_nu, blocks, eps, m, tol 1e-10) on a 12^3x16 sub-volume, "
                   "%d Gaussian RHS solved one by one: %.2f s/RHS (%d outer iterations; setup %.1f s not counted), "
-                  "scaled by the volume ratio %d" % (nsample, t, st["outer_iters"], ts, V // Vs),
+                  "scaled by the volume ratio %.2f" % (nsample, t, st["outer_iters"], ts, V / Vs),
     }
 
 
