@@ -53,6 +53,8 @@ extern "C" {
 #define WMG_WCYCLE 1
 
 #define WMG_X0_GIVEN 1 /* flags: x holds the initial guess on entry to mg_solve */
+#define WMG_COARSE_FP32 2 /* flags: mixed precision keeps FP32 coarse links in the cycle
+                             (default: FP16 with one FP32 scale per site and direction) */
 
 typedef struct wmg_ctx wmg_ctx;
 
@@ -79,7 +81,7 @@ typedef struct {
   double reliable_delta;  /* mixed: restart in FP64 when |r_inner| < delta * |r_last_update| */
   int maxiter;            /* outer GCR iteration cap */
   unsigned long long seed;/* Philox key of the setup's random start vectors */
-  int flags;              /* WMG_X0_GIVEN */
+  int flags;              /* WMG_X0_GIVEN | WMG_COARSE_FP32 */
 } wmg_params;
 
 typedef struct {

@@ -475,6 +475,51 @@ int coarse_to_mfma(long Vc, int n, const double2 *Y64, float *Ym, hipStream_t st
 
 size_t coarse_mfma_floats(long Vc, int n) { return (size_t)Vc * 9 * ((n + 15) / 16) * mfma_km(n) * 64; }
 
+size_t coarse_mfma_halfs(long Vc, int n) { return coarse_mfma_floats(Vc, n); }
+
+// FP16 copy of the swizzled links: one workgroup per (site, direction)
+// block; its scale is the largest |re| or |im| of the block (1 for a zero
+// block), entries are stored as RNE(y / scale)
+__global__ void __launch_bounds__(TB) k_Y_to_mfma16(int n, int MT, int KM, const double2 *__restrict__ Y,
+                                                   __half *__restrict__ Yh, float *__restrict__ Ysc) {
+  const size_t sd = blockIdx.x;  // site*9 + d
+  const double2 *blk = Y + sd * (size_t)n * n;
+  double mx = 0;
+  for (int i = threadIdx.x; i < n * n; i += TB) mx = fmax(mx, fmax(fabs(blk[i].x), fabs(blk[i].y)));
+  __shared__ double sh[TB / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  double scale = sh[0];
+  for (int w = 1; w < TB / 64; w++) scale = fmax(scale, sh[w]);
+  if (!(scale > 0)) scale = 1.0;
+  const double inv = 1.0 / scale;
+  if (threadIdx.x == 0) Ysc[sd] = (float)scale;
+  const size_t per = (size_t)MT * KM * 64;
+  for (size_t rem = threadIdx.x; rem < per; rem += TB) {
+    int mt = (int)(rem / ((size_t)KM * 64));
+    int q = (int)(rem % ((size_t)KM * 64));
+    int e = q % 4, lane = (q / 4) % 64, kq = q / 256;
+    int ks = kq * 4 + e;
+    int row = mt * 16 + lane % 16, kk = ks * 4 + lane / 16;
+    float v = 0.f;
+    if (row < n && kk < 2 * n) {
+      int col = kk < n ? kk : kk - n;
+      double2 y = blk[(size_t)col * n + row];  // internal [site][d][col][row]
+      v = (float)((kk < n ? y.x : y.y) * inv);
+    }
+    Yh[sd * per + rem] = __float2half_rn(v);
+  }
+}
+
+int coarse_to_mfma16(long Vc, int n, const double2 *Y64, __half *Yh, float *Ysc, hipStream_t st) {
+  int MT = (n + 15) / 16, KM = mfma_km(n);
+  hipLaunchKernelGGL(k_Y_to_mfma16, dim3((unsigned)(Vc * 9)), dim3(TB), 0, st, n, MT, KM, Y64, Yh, Ysc);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
 // LDS row stride of the transposed B tile: a multiple of 32 plus 4, so the
 // 16 columns x 4 k-rows read by one MFMA B fragment spread over all banks
 __host__ __device__ __forceinline__ int mfma_ldk(int n) { return (2 * n + 31) / 32 * 32 + 4; }
@@ -485,10 +530,11 @@ __host__ __device__ __forceinline__ int mfma_ldk(int n) { return (2 * n + 31) / 
 // of direction d run, the link fragments of direction d+1 (registers) and
 // its neighbour vectors (registers, written to LDS after the next barrier)
 // are already in flight, so no direction waits for a cold load.
-template <int NT, int KM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_coarse_apply_mfma(const float *__restrict__ Ym, const float2 *__restrict__ in,
-                                                          float2 *__restrict__ out, int L0, int L1, int L2, int L3,
-                                                          long Vc, int n, int nrhs, int dagger) {
+template <int NT, int KM, bool AH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_coarse_apply_mfma(const float *__restrict__ Ym, const __half *__restrict__ Yh, const float *__restrict__ Ysc,
+                    const float2 *__restrict__ in, float2 *__restrict__ out, int L0, int L1, int L2, int L3, long Vc,
+                    int n, int nrhs, int dagger) {
   extern __shared__ float Bt[];  // B transposed: [NT*16 columns][LDK], column j, k-row kk at j*LDK + kk
   const int LDK = mfma_ldk(n);
   const int MT = (n + 15) / 16;
@@ -546,14 +592,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   };
   const int mts = mt < MT ? mt : 0;
   auto a_load = [&](float *a, int d) {
-    const float4 *Ad = (const float4 *)(Ym + (((size_t)xh * 9 + d) * MT + mts) * KM * 64) + lane;
+    if constexpr (AH) {
+      // four k-steps as four halves (8 bytes) per lane, scaled back
+      const float sc = Ysc[(size_t)xh * 9 + d];
+      const uint2 *Ad = (const uint2 *)(Yh + (((size_t)xh * 9 + d) * MT + mts) * KM * 64) + lane;
 #pragma unroll
-    for (int kq = 0; kq < KM / 4; kq++) {
-      float4 v = Ad[kq * 64];
-      a[4 * kq] = v.x;
-      a[4 * kq + 1] = v.y;
-      a[4 * kq + 2] = v.z;
-      a[4 * kq + 3] = v.w;
+      for (int kq = 0; kq < KM / 4; kq++) {
+        uint2 v = Ad[kq * 64];
+        float2 f01 = __half22float2(*(const __half2 *)&v.x), f23 = __half22float2(*(const __half2 *)&v.y);
+        a[4 * kq] = f01.x * sc;
+        a[4 * kq + 1] = f01.y * sc;
+        a[4 * kq + 2] = f23.x * sc;
+        a[4 * kq + 3] = f23.y * sc;
+      }
+    } else {
+      const float4 *Ad = (const float4 *)(Ym + (((size_t)xh * 9 + d) * MT + mts) * KM * 64) + lane;
+#pragma unroll
+      for (int kq = 0; kq < KM / 4; kq++) {
+        float4 v = Ad[kq * 64];
+        a[4 * kq] = v.x;
+        a[4 * kq + 1] = v.y;
+        a[4 * kq + 2] = v.z;
+        a[4 * kq + 3] = v.w;
+      }
     }
   };
   floatx4 acc[NT];
@@ -601,8 +662,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     }
 }
 
-int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, float2 *out, int dagger, int nrhs,
-                      hipStream_t st) {
+static int coarse_apply_mfma_any(const Geom &gc, int n, const float *Ym, const __half *Yh, const float *Ysc,
+                                 const float2 *in, float2 *out, int dagger, int nrhs, hipStream_t st) {
   if (n > 64 || (n & 1)) return set_error(-1, "coarse_apply_mfma: n=%d (even, <= 64)", n);
   int MT = (n + 15) / 16;
   int rmax = nrhs < 32 ? nrhs : 32;
@@ -613,8 +674,12 @@ int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, 
   const int KM = mfma_km(n);  // 8, 16, 24 or 32
 #define NT_CASE(N, K)                                                                                           \
   if (NT == N && KM == K) {                                                                                    \
-    hipLaunchKernelGGL((k_coarse_apply_mfma<N, K>), grid, blk, lds, st, Ym, in, out, gc.L[0], gc.L[1], gc.L[2], \
-                       gc.L[3], gc.V, n, nrhs, dagger);                                                       \
+    if (Yh)                                                                                                    \
+      hipLaunchKernelGGL((k_coarse_apply_mfma<N, K, true>), grid, blk, lds, st, Ym, Yh, Ysc, in, out, gc.L[0],  \
+                         gc.L[1], gc.L[2], gc.L[3], gc.V, n, nrhs, dagger);                                   \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_coarse_apply_mfma<N, K, false>), grid, blk, lds, st, Ym, Yh, Ysc, in, out, gc.L[0], \
+                         gc.L[1], gc.L[2], gc.L[3], gc.V, n, nrhs, dagger);                                   \
   } else
 #define NT_ALL(N) NT_CASE(N, 8) NT_CASE(N, 16) NT_CASE(N, 24) NT_CASE(N, 32)
   NT_ALL(1) NT_ALL(2) NT_ALL(3) NT_ALL(4)
@@ -623,6 +688,17 @@ int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, 
 #undef NT_CASE
   WMG_HIP(hipGetLastError());
   return 0;
+}
+
+int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, float2 *out, int dagger, int nrhs,
+                      hipStream_t st) {
+  return coarse_apply_mfma_any(gc, n, Ym, nullptr, nullptr, in, out, dagger, nrhs, st);
+}
+
+int coarse_apply_mfma16(const Geom &gc, int n, const __half *Yh, const float *Ysc, const float2 *in, float2 *out,
+                        int dagger, int nrhs, hipStream_t st) {
+  if (!Yh || !Ysc) return set_error(-1, "coarse_apply_mfma16: null links");
+  return coarse_apply_mfma_any(gc, n, nullptr, Yh, Ysc, in, out, dagger, nrhs, st);
 }
 
 }  // namespace wmg

@@ -215,6 +215,8 @@ struct Level {
   double2 *Y64 = nullptr;
   float2 *Y32 = nullptr;  // FP32 copy for the vector-FMA stencil (n > 64)
   float *Ym = nullptr;    // FP32 copy swizzled for the MFMA stencil (n <= 64)
+  __half *Ymh = nullptr;  // ... or its FP16 copy with one scale per (site, direction)
+  float *Ymsc = nullptr;
   int dof_max = 0;
   // transfer to level+1
   int b[4] = {1, 1, 1, 1};
@@ -372,11 +374,15 @@ static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int 
     return rc;
   }
   int n = L.dof;
-  double yb = prec == P64 ? 16 : 8;
+  // algorithmic bytes: links once (FP64 / FP32 complex, or FP16 + scales)
+  // and the in and out vectors of every rhs
+  double yb = prec == P64 ? 16 : (prec == P32 && L.Ymh ? 4 : 8), vb = prec == P64 ? 16 : 8;
   int slot = prof_begin(c, prec == P64 ? K_COARSE64 : K_COARSE32,
-                        (double)L.g.V * (9.0 * n * n * yb + 2.0 * n * yb * nrhs));
+                        (double)L.g.V * (9.0 * n * n * yb + 2.0 * n * vb * nrhs));
   int rc;
-  if (prec == P32 && L.Ym)
+  if (prec == P32 && L.Ymh)
+    rc = coarse_apply_mfma16(L.g, n, L.Ymh, L.Ymsc, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st);
+  else if (prec == P32 && L.Ym)
     rc = coarse_apply_mfma(L.g, n, L.Ym, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st);
   else
     rc = coarse_apply(L.g, n, prec, prec == P64 ? (const void *)L.Y64 : (const void *)L.Y32, prec, in, out, dagger,
@@ -833,7 +839,13 @@ static int make_low_precision(wmg_ctx *c) {
   }
   for (int l = 1; l < c->nl; l++) {
     Level &C = c->lv[l];
-    if (C.dof_max <= 64) {
+    if (C.dof_max <= 64 && !(c->p.flags & WMG_COARSE_FP32)) {
+      if (!C.Ymh) {
+        TRY(dalloc((void **)&C.Ymh, sizeof(__half) * coarse_mfma_halfs(C.g.V, C.dof_max)));
+        TRY(dalloc((void **)&C.Ymsc, sizeof(float) * 9 * (size_t)C.g.V));
+      }
+      TRY(coarse_to_mfma16(C.g.V, C.dof, C.Y64, C.Ymh, C.Ymsc, c->st));
+    } else if (C.dof_max <= 64) {
       if (!C.Ym) TRY(dalloc((void **)&C.Ym, sizeof(float) * coarse_mfma_floats(C.g.V, C.dof_max)));
       TRY(coarse_to_mfma(C.g.V, C.dof, C.Y64, C.Ym, c->st));
     } else {
@@ -884,7 +896,7 @@ static void free_ctx(wmg_ctx *c) {
     Level &L = c->lv[l];
     for (int i = 0; i < 3; i++)
       if (L.U[i]) (void)hipFree(L.U[i]);
-    void *ps[] = {L.Y64, L.Y32, L.Ym, L.vecs, L.P64, L.P32, L.P16, L.Ps};
+    void *ps[] = {L.Y64, L.Y32, L.Ym, L.Ymh, L.Ymsc, L.vecs, L.P64, L.P32, L.P16, L.Ps};
     for (void *p : ps)
       if (p) (void)hipFree(p);
     for (int a = 0; a < 3; a++)

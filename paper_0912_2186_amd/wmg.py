@@ -32,6 +32,7 @@ WMG_MIXED = 1
 WMG_VCYCLE = 0
 WMG_WCYCLE = 1
 WMG_X0_GIVEN = 1
+WMG_COARSE_FP32 = 2
 
 
 class WmgError(RuntimeError):

@@ -117,17 +117,21 @@ def test_transfer_and_galerkin_from_given_vectors(wmg, L, block):
         assert relerr(host(o), oracle.coarse_apply(Lc, n, Y_ref, c_ref, dagger=dag)) < 1e-13
 
 
+@pytest.mark.parametrize("fp32_links", [False, True])
 @pytest.mark.parametrize("nv,nrhs", [(5, 1), (8, 7), (20, 28), (24, 28), (24, 40), (32, 3)])
-def test_mfma_coarse_apply_multi_rhs(wmg, nv, nrhs):
-    """FP32 matrix-core coarse stencil (and its sigma_3 adjoint) for many
-    right-hand sides against the oracle's FP64 stencil."""
+def test_mfma_coarse_apply_multi_rhs(wmg, nv, nrhs, fp32_links):
+    """Matrix-core coarse stencil (and its sigma_3 adjoint) for many
+    right-hand sides against the oracle's FP64 stencil: FP32 links (FP32
+    rounding) and the default FP16 links with one scale per site and
+    direction (a few 2^-11 relative)."""
     L = (8, 8, 8, 16) if nv <= 8 else (8, 8, 8, 8)
     block = (4, 4, 4, 4) if nv <= 8 else (2, 2, 4, 4)
     say("mfma coarse", nv, nrhs, L, block)
     V = vol(L)
     m = -0.1
     U = inputs.gauge_field(L, 0.5, 307)
-    p = wmg.default_params(setup_iters=0, seed=2, nrhs_max=nrhs, precision=wmg.WMG_MIXED)
+    p = wmg.default_params(setup_iters=0, seed=2, nrhs_max=nrhs, precision=wmg.WMG_MIXED,
+                           flags=wmg.WMG_COARSE_FP32 if fp32_links else 0)
     mg = wmg.MG(L, dev(U), m, nv, block, p)
     vecs = rand_vecs(nv, V, 12, 81)
     mg.mg_set_null_vectors(0, dev(vecs))
@@ -143,7 +147,7 @@ def test_mfma_coarse_apply_multi_rhs(wmg, nv, nrhs):
         ref = np.stack([oracle.coarse_apply(Lc, n, Y, v[r], dagger=dag) for r in range(nrhs)])
         e = relerr(host(o), ref)
         say("  dagger", dag, "relerr", e)
-        assert e < 2e-6
+        assert e < (2e-6 if fp32_links else 1.5e-3)
 
 
 @pytest.mark.parametrize("L,block,nv,nrhs", [((8, 8, 8, 16), (4, 4, 4, 4), 24, 28), ((8, 8, 8, 8), (4, 4, 4, 4), 6, 1),
