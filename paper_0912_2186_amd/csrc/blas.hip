@@ -14,7 +14,7 @@
 namespace wmg {
 
 static constexpr int RB = 256;      // reduction workgroup size
-static constexpr int RMAXBLK = 512; // partial slots per rhs
+static constexpr int RMAXBLK = 1024; // partial slots per rhs
 static constexpr int RSLOT = 32;    // doubles per partial slot
 
 int red_init(Reducer &r, int nrhs_max) {
@@ -29,8 +29,10 @@ void red_free(Reducer &r) {
   r.partial = nullptr;
 }
 
-static int red_blocks(long n) {
-  long b = (n + RB * 4 - 1) / (RB * 4);
+// workgroups per rhs of a reduction over np packs (two packs per thread at
+// least, at most RMAXBLK)
+static int red_blocks(long np) {
+  long b = (np + RB * 2 - 1) / (RB * 2);
   if (b < 1) b = 1;
   if (b > RMAXBLK) b = RMAXBLK;
   return (int)b;
@@ -111,35 +113,54 @@ static int red_final(Reducer &R, int nblk, int nc, int nrhs, double *out, int ou
 template <int MODE, class S>
 __global__ void __launch_bounds__(RB) k_reduce(const S *__restrict__ x, const S *__restrict__ y, long n,
                                               double *partial) {
+  using R = typename store_traits<S>::real;
   constexpr int NC = MODE == 0 ? 2 : (MODE == 1 ? 1 : 3);
+  constexpr int PK = pack_len<S>();
   int rhs = blockIdx.y;
   const S *xr = x + (size_t)rhs * n;
   const S *yr = y ? y + (size_t)rhs * n : nullptr;
   double v[NC];
 #pragma unroll
   for (int c = 0; c < NC; c++) v[c] = 0;
-  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) {
-    auto a = ldc(xr + i);
-    double ar = a.re, ai = a.im;
-    if (MODE == 1) {
-      v[0] += ar * ar + ai * ai;
-    } else {
-      auto b = ldc(yr + i);
-      double br = b.re, bi = b.im;
-      v[0] += ar * br + ai * bi;
-      v[1] += ar * bi - ai * br;
-      if (MODE == 2) v[2] += ar * ar + ai * ai;
+  const long np = n / PK;
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < np; i += (long)gridDim.x * RB) {
+    cx<R> a[PK], b[PK];
+    ldp<PK>(xr + i * PK, a);
+    if (MODE != 1) ldp<PK>(yr + i * PK, b);
+#pragma unroll
+    for (int e = 0; e < PK; e++) {
+      double ar = a[e].re, ai = a[e].im;
+      if constexpr (MODE == 1) {
+        v[0] += ar * ar + ai * ai;
+      } else {
+        double br = b[e].re, bi = b[e].im;
+        v[0] += ar * br + ai * bi;
+        v[1] += ar * bi - ai * br;
+        if constexpr (MODE == 2) v[2] += ar * ar + ai * ai;
+      }
     }
   }
   wg_sum<NC>(v);
   wg_store<NC>(v, partial, rhs);
 }
 
+// per-rhs vector length must hold whole packs
+template <class S> static int check_packs(long n, const char *who) {
+  if (n % pack_len<S>()) return set_error(-1, "%s: length %ld not a multiple of %d", who, n, pack_len<S>());
+  return 0;
+}
+#define TRY_PK(prec, n, who)                                                     \
+  do {                                                                           \
+    int e_ = (prec) == P64 ? check_packs<double2>((n), (who)) : check_packs<float2>((n), (who)); \
+    if (e_) return e_;                                                           \
+  } while (0)
+
 template <int MODE>
 static int launch_reduce(Reducer &R, int prec, const void *x, const void *y, long n, int nrhs, double *out,
                          int out_stride, hipStream_t st) {
-  dim3 grid(red_blocks(n), nrhs);
   if (nrhs > R.nrhs_max) return set_error(-1, "reduction nrhs %d > %d", nrhs, R.nrhs_max);
+  TRY_PK(prec, n, "reduction");
+  dim3 grid(red_blocks(n / (prec == P64 ? 1 : 2)), nrhs);
   if (prec == P64)
     hipLaunchKernelGGL((k_reduce<MODE, double2>), grid, dim3(RB), 0, st, (const double2 *)x, (const double2 *)y, n,
                        R.partial);
@@ -184,40 +205,61 @@ __device__ __forceinline__ void wg_store_n(double v[NMAX], int nv, double *parti
   }
 }
 
-template <class S>
+// KT >= k bounds the register arrays (k <= KT, the basis size rounded up
+// to 1, 2, 4, 8 or 16)
+template <class S, int KT>
 __global__ void __launch_bounds__(RB) k_multi_dot(const S *const *__restrict__ xs, int k, const S *__restrict__ y,
                                                  long n, double *partial) {
+  using R = typename store_traits<S>::real;
+  constexpr int PK = pack_len<S>();
   int rhs = blockIdx.y;
-  double v[32];
+  double v[2 * KT];
 #pragma unroll
-  for (int c = 0; c < 32; c++) v[c] = 0;
-  const S *yr = y + (size_t)rhs * n;
-  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) {
-    auto b = ldc(yr + i);
-    double br = b.re, bi = b.im;
+  for (int c = 0; c < 2 * KT; c++) v[c] = 0;
+  const size_t off = (size_t)rhs * n;
+  const long np = n / PK;
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < np; i += (long)gridDim.x * RB) {
+    cx<R> b[PK];
+    ldp<PK>(y + off + i * PK, b);
 #pragma unroll
-    for (int j = 0; j < 16; j++) {
+    for (int j = 0; j < KT; j++) {
       if (j < k) {
-        auto a = ldc(xs[j] + (size_t)rhs * n + i);
-        v[2 * j] += a.re * br + a.im * bi;
-        v[2 * j + 1] += a.re * bi - a.im * br;
+        cx<R> a[PK];
+        ldp<PK>(xs[j] + off + i * PK, a);
+#pragma unroll
+        for (int e = 0; e < PK; e++) {
+          double ar = a[e].re, ai = a[e].im, br = b[e].re, bi = b[e].im;
+          v[2 * j] += ar * br + ai * bi;
+          v[2 * j + 1] += ar * bi - ai * br;
+        }
       }
     }
   }
-  wg_store_n<32>(v, 2 * k, partial, rhs);
+  wg_store_n<2 * KT>(v, 2 * k, partial, rhs);
 }
+
+static int kt_of(int k) { return k <= 1 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : (k <= 8 ? 8 : 16))); }
+#define KT_SWITCH(k, LAUNCH)          \
+  switch (kt_of(k)) {                 \
+    case 1: { constexpr int KT = 1; LAUNCH; } break;  \
+    case 2: { constexpr int KT = 2; LAUNCH; } break;  \
+    case 4: { constexpr int KT = 4; LAUNCH; } break;  \
+    case 8: { constexpr int KT = 8; LAUNCH; } break;  \
+    default: { constexpr int KT = 16; LAUNCH; } break; \
+  }
 
 int multi_dot(Reducer &R, int prec, const void *const *xs_dev, int k, const void *y, long n, int nrhs, double *out,
               int out_stride, hipStream_t st) {
   if (k < 1 || k > 16) return set_error(-1, "multi_dot k=%d", k);
   if (nrhs > R.nrhs_max) return set_error(-1, "multi_dot nrhs");
-  dim3 grid(red_blocks(n), nrhs);
+  TRY_PK(prec, n, "multi_dot");
+  dim3 grid(red_blocks(n / (prec == P64 ? 1 : 2)), nrhs);
   if (prec == P64)
-    hipLaunchKernelGGL((k_multi_dot<double2>), grid, dim3(RB), 0, st, (const double2 *const *)xs_dev, k,
-                       (const double2 *)y, n, R.partial);
+    KT_SWITCH(k, hipLaunchKernelGGL((k_multi_dot<double2, KT>), grid, dim3(RB), 0, st,
+                                    (const double2 *const *)xs_dev, k, (const double2 *)y, n, R.partial))
   else
-    hipLaunchKernelGGL((k_multi_dot<float2>), grid, dim3(RB), 0, st, (const float2 *const *)xs_dev, k,
-                       (const float2 *)y, n, R.partial);
+    KT_SWITCH(k, hipLaunchKernelGGL((k_multi_dot<float2, KT>), grid, dim3(RB), 0, st, (const float2 *const *)xs_dev,
+                                    k, (const float2 *)y, n, R.partial))
   WMG_HIP(hipGetLastError());
   return red_final(R, (int)grid.x, 2 * k, nrhs, out, out_stride, st);
 }
@@ -228,16 +270,17 @@ int multi_dot(Reducer &R, int prec, const void *const *xs_dev, int k, const void
 // b_j recorded in beta[j][k] (PASS 1: =, PASS 2: +=).  PASS 1 then reduces
 // the new projections <w_j, w> (2k values, the dots of the second pass);
 // PASS 2 reduces <w, r> and |w|^2.  One read of every w_j, w (and r).
-template <class S, int PASS>
+template <class S, int PASS, int KT>
 __global__ void __launch_bounds__(RB) k_gcr_proj(const S *const *__restrict__ W, int k, S *__restrict__ w,
                                                 const S *__restrict__ r, const double *__restrict__ d, int dstride,
                                                 const double *__restrict__ wn2, int wstride, double *__restrict__ beta,
                                                 int bstride, int kcol, long n, double *partial) {
   using R = typename store_traits<S>::real;
+  constexpr int PK = pack_len<S>();
   int rhs = blockIdx.y;
-  cx<R> b[16];
+  cx<R> b[KT];
 #pragma unroll
-  for (int j = 0; j < 16; j++) {
+  for (int j = 0; j < KT; j++) {
     double q = j < k ? wn2[(size_t)rhs * wstride + j] : 0.0;
     double br = (j < k && q > 0) ? d[(size_t)rhs * dstride + 2 * j] / q : 0.0;
     double bi = (j < k && q > 0) ? d[(size_t)rhs * dstride + 2 * j + 1] / q : 0.0;
@@ -248,42 +291,50 @@ __global__ void __launch_bounds__(RB) k_gcr_proj(const S *const *__restrict__ W,
       else { bb[0] += br; bb[1] += bi; }
     }
   }
-  constexpr int NV = PASS == 1 ? 32 : 3;
+  constexpr int NV = PASS == 1 ? 2 * KT : 3;
   double v[NV];
 #pragma unroll
   for (int c = 0; c < NV; c++) v[c] = 0;
   size_t off = (size_t)rhs * n;
-  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) {
-    cx<R> wj[16];
-    cx<R> x = ldc(w + off + i);
+  const long np = n / PK;
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < np; i += (long)gridDim.x * RB) {
+    cx<R> wj[KT][PK];
+    cx<R> x[PK];
+    ldp<PK>(w + off + i * PK, x);
 #pragma unroll
-    for (int j = 0; j < 16; j++)
+    for (int j = 0; j < KT; j++)
       if (j < k) {
-        auto t = ldc(W[j] + off + i);
-        wj[j] = {(R)t.re, (R)t.im};
-        x = x - b[j] * wj[j];
-      }
-    stc(w + off + i, x);
-    if (PASS == 1) {
+        ldp<PK>(W[j] + off + i * PK, wj[j]);
 #pragma unroll
-      for (int j = 0; j < 16; j++)
-        if (j < k) {
-          v[2 * j] += (double)wj[j].re * x.re + (double)wj[j].im * x.im;
-          v[2 * j + 1] += (double)wj[j].re * x.im - (double)wj[j].im * x.re;
-        }
+        for (int e = 0; e < PK; e++) x[e] = x[e] - b[j] * wj[j][e];
+      }
+    stp<PK>(w + off + i * PK, x);
+    if constexpr (PASS == 1) {
+#pragma unroll
+      for (int j = 0; j < KT; j++)
+        if (j < k)
+#pragma unroll
+          for (int e = 0; e < PK; e++) {
+            v[2 * j] += (double)wj[j][e].re * x[e].re + (double)wj[j][e].im * x[e].im;
+            v[2 * j + 1] += (double)wj[j][e].re * x[e].im - (double)wj[j][e].im * x[e].re;
+          }
     } else {
-      auto rr = ldc(r + off + i);
-      v[0] += (double)x.re * rr.re + (double)x.im * rr.im;
-      v[1] += (double)x.re * rr.im - (double)x.im * rr.re;
-      v[2] += (double)x.re * x.re + (double)x.im * x.im;
+      cx<R> rr[PK];
+      ldp<PK>(r + off + i * PK, rr);
+#pragma unroll
+      for (int e = 0; e < PK; e++) {
+        v[0] += (double)x[e].re * rr[e].re + (double)x[e].im * rr[e].im;
+        v[1] += (double)x[e].re * rr[e].im - (double)x[e].im * rr[e].re;
+        v[2] += (double)x[e].re * x[e].re + (double)x[e].im * x[e].im;
+      }
     }
   }
-  if (PASS == 2) {
+  if constexpr (PASS == 2) {
     double t3[3] = {v[0], v[1], v[2]};
     wg_sum<3>(t3);
     wg_store<3>(t3, partial, rhs);
   } else {
-    wg_store_n<32>(v, 2 * k, partial, rhs);
+    wg_store_n<NV>(v, 2 * k, partial, rhs);
   }
 }
 
@@ -291,12 +342,13 @@ int gcr_project(Reducer &R, int prec, int pass, const void *const *W, int k, voi
                 int dstride, const double *wn2, int wstride, double *beta, int bstride, int kcol, long n, int nrhs,
                 double *out, int out_stride, hipStream_t st) {
   if (k < 1 || k > 16 || nrhs > R.nrhs_max) return set_error(-1, "gcr_project k=%d", k);
-  dim3 grid(red_blocks(n), nrhs);
-#define GP(S, P)                                                                                                \
-  hipLaunchKernelGGL((k_gcr_proj<S, P>), grid, dim3(RB), 0, st, (const S *const *)W, k, (S *)w, (const S *)r, d,  \
-                     dstride, wn2, wstride, beta, bstride, kcol, n, R.partial)
-  if (prec == P64) { if (pass == 1) GP(double2, 1); else GP(double2, 2); }
-  else { if (pass == 1) GP(float2, 1); else GP(float2, 2); }
+  TRY_PK(prec, n, "gcr_project");
+  dim3 grid(red_blocks(n / (prec == P64 ? 1 : 2)), nrhs);
+#define GP(S, P)                                                                                                  \
+  KT_SWITCH(k, hipLaunchKernelGGL((k_gcr_proj<S, P, KT>), grid, dim3(RB), 0, st, (const S *const *)W, k, (S *)w,   \
+                                  (const S *)r, d, dstride, wn2, wstride, beta, bstride, kcol, n, R.partial))
+  if (prec == P64) { if (pass == 1) { GP(double2, 1); } else { GP(double2, 2); } }
+  else { if (pass == 1) { GP(float2, 1); } else { GP(float2, 2); } }
 #undef GP
   WMG_HIP(hipGetLastError());
   return red_final(R, (int)grid.x, pass == 1 ? 2 * k : 3, nrhs, out, out_stride, st);
@@ -307,14 +359,22 @@ template <class S>
 __global__ void __launch_bounds__(RB) k_caxpy_norm(const double *__restrict__ a, int astride, const S *__restrict__ x,
                                                   S *__restrict__ y, long n, double *partial) {
   using R = typename store_traits<S>::real;
+  constexpr int PK = pack_len<S>();
   int rhs = blockIdx.y;
   cx<R> c = {(R)(-a[(size_t)rhs * astride]), (R)(-a[(size_t)rhs * astride + 1])};
   size_t off = (size_t)rhs * n;
   double v[1] = {0};
-  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) {
-    auto yv = cfma(c, ldc(x + off + i), ldc(y + off + i));
-    stc(y + off + i, yv);
-    v[0] += (double)yv.re * yv.re + (double)yv.im * yv.im;
+  const long np = n / PK;
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < np; i += (long)gridDim.x * RB) {
+    cx<R> xv[PK], yv[PK];
+    ldp<PK>(x + off + i * PK, xv);
+    ldp<PK>(y + off + i * PK, yv);
+#pragma unroll
+    for (int e = 0; e < PK; e++) {
+      yv[e] = cfma(c, xv[e], yv[e]);
+      v[0] += (double)yv[e].re * yv[e].re + (double)yv[e].im * yv[e].im;
+    }
+    stp<PK>(y + off + i * PK, yv);
   }
   wg_sum<1>(v);
   wg_store<1>(v, partial, rhs);
@@ -322,7 +382,8 @@ __global__ void __launch_bounds__(RB) k_caxpy_norm(const double *__restrict__ a,
 
 int caxpy_norm(Reducer &R, int prec, const double *a, int astride, const void *x, void *y, long n, int nrhs,
                double *out, int out_stride, hipStream_t st) {
-  dim3 grid(red_blocks(n), nrhs);
+  TRY_PK(prec, n, "caxpy_norm");
+  dim3 grid(red_blocks(n / (prec == P64 ? 1 : 2)), nrhs);
   if (prec == P64)
     hipLaunchKernelGGL((k_caxpy_norm<double2>), grid, dim3(RB), 0, st, a, astride, (const double2 *)x, (double2 *)y, n,
                        R.partial);
@@ -341,17 +402,27 @@ static dim3 ew_grid(long n, int nrhs) {
   return dim3((unsigned)b, nrhs);
 }
 
+template <class A, class B> __host__ __device__ constexpr int pack_len2() {
+  return pack_len<A>() > pack_len<B>() ? pack_len<A>() : pack_len<B>();
+}
+
 template <class SD, class SS>
 __global__ void k_copy(SD *__restrict__ d, const SS *__restrict__ s, long n) {
+  using R = typename store_traits<SS>::real;
+  constexpr int PK = pack_len2<SD, SS>();
   size_t off = (size_t)blockIdx.y * n;
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-    auto v = ldc(s + off + i);
-    stc(d + off + i, v);
+  const long np = n / PK;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
+    cx<R> v[PK];
+    ldp<PK>(s + off + i * PK, v);
+    stp<PK>(d + off + i * PK, v);
   }
 }
 
 int copy(int pdst, void *dst, int psrc, const void *src, long n, int nrhs, hipStream_t st) {
-  dim3 g = ew_grid(n, nrhs);
+  const int pk = (pdst == P64 && psrc == P64) ? 1 : 2;
+  TRY_PK(pk == 1 ? P64 : P32, n, "copy");
+  dim3 g = ew_grid(n / pk, nrhs);
   if (pdst == P64 && psrc == P64)
     hipLaunchKernelGGL((k_copy<double2, double2>), g, dim3(256), 0, st, (double2 *)dst, (const double2 *)src, n);
   else if (pdst == P32 && psrc == P64)
@@ -366,12 +437,18 @@ int copy(int pdst, void *dst, int psrc, const void *src, long n, int nrhs, hipSt
 
 template <class S> __global__ void k_zero(S *__restrict__ x, long n) {
   using R = typename store_traits<S>::real;
+  constexpr int PK = pack_len<S>();
   size_t off = (size_t)blockIdx.y * n;
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) stc(x + off + i, czero<R>());
+  cx<R> z[PK];
+#pragma unroll
+  for (int e = 0; e < PK; e++) z[e] = czero<R>();
+  const long np = n / PK;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < np; i += (long)gridDim.x * 256) stp<PK>(x + off + i * PK, z);
 }
 
 int zero(int prec, void *x, long n, int nrhs, hipStream_t st) {
-  dim3 g = ew_grid(n, nrhs);
+  TRY_PK(prec, n, "zero");
+  dim3 g = ew_grid(n / (prec == P64 ? 1 : 2), nrhs);
   if (prec == P64) hipLaunchKernelGGL((k_zero<double2>), g, dim3(256), 0, st, (double2 *)x, n);
   else hipLaunchKernelGGL((k_zero<float2>), g, dim3(256), 0, st, (float2 *)x, n);
   WMG_HIP(hipGetLastError());
@@ -431,26 +508,36 @@ int cxpay_dev(int prec, const void *x, const double *a, int astride, double sgn,
 }
 
 // y (+)= sum_j c_j x_j
-template <class SY, class SX>
+template <class SY, class SX, int KT>
 __global__ void k_multi_caxpy(SY *__restrict__ y, const SX *const *__restrict__ xs, int k, const double *__restrict__ c,
                               int cstride, double sgn, int accumulate, long n) {
   using R = typename store_traits<SY>::real;
+  constexpr int PK = pack_len2<SY, SX>();
   int rhs = blockIdx.y;
   size_t off = (size_t)rhs * n;
-  cx<R> cc[16];
+  cx<R> cc[KT];
 #pragma unroll
-  for (int j = 0; j < 16; j++)
+  for (int j = 0; j < KT; j++)
     cc[j] = j < k ? cx<R>{(R)(sgn * c[(size_t)rhs * cstride + 2 * j]), (R)(sgn * c[(size_t)rhs * cstride + 2 * j + 1])}
                   : czero<R>();
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-    cx<R> acc = accumulate ? ldc(y + off + i) : czero<R>();
+  const long np = n / PK;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
+    cx<R> acc[PK];
+    if (accumulate) {
+      ldp<PK>(y + off + i * PK, acc);
+    } else {
 #pragma unroll
-    for (int j = 0; j < 16; j++)
+      for (int e = 0; e < PK; e++) acc[e] = czero<R>();
+    }
+#pragma unroll
+    for (int j = 0; j < KT; j++)
       if (j < k) {
-        auto xv = ldc(xs[j] + off + i);
-        acc = cfma(cc[j], cx<R>{(R)xv.re, (R)xv.im}, acc);
+        cx<R> xv[PK];
+        ldp<PK>(xs[j] + off + i * PK, xv);
+#pragma unroll
+        for (int e = 0; e < PK; e++) acc[e] = cfma(cc[j], xv[e], acc[e]);
       }
-    stc(y + off + i, acc);
+    stp<PK>(y + off + i * PK, acc);
   }
 }
 
@@ -458,16 +545,18 @@ int multi_caxpy(int py, void *y, int px, const void *const *xs_dev, int k, const
                 int accumulate, long n, int nrhs, hipStream_t st) {
   if (k < 0 || k > 16) return set_error(-1, "multi_caxpy k=%d", k);
   if (k == 0 && accumulate) return 0;
-  dim3 g = ew_grid(n, nrhs);
+  const int pk = (py == P64 && px == P64) ? 1 : 2;
+  TRY_PK(pk == 1 ? P64 : P32, n, "multi_caxpy");
+  dim3 g = ew_grid(n / pk, nrhs);
   if (py == P64 && px == P64)
-    hipLaunchKernelGGL((k_multi_caxpy<double2, double2>), g, dim3(256), 0, st, (double2 *)y,
-                       (const double2 *const *)xs_dev, k, c, cstride, sgn, accumulate, n);
+    KT_SWITCH(k, hipLaunchKernelGGL((k_multi_caxpy<double2, double2, KT>), g, dim3(256), 0, st, (double2 *)y,
+                                    (const double2 *const *)xs_dev, k, c, cstride, sgn, accumulate, n))
   else if (py == P64 && px == P32)
-    hipLaunchKernelGGL((k_multi_caxpy<double2, float2>), g, dim3(256), 0, st, (double2 *)y,
-                       (const float2 *const *)xs_dev, k, c, cstride, sgn, accumulate, n);
+    KT_SWITCH(k, hipLaunchKernelGGL((k_multi_caxpy<double2, float2, KT>), g, dim3(256), 0, st, (double2 *)y,
+                                    (const float2 *const *)xs_dev, k, c, cstride, sgn, accumulate, n))
   else if (py == P32 && px == P32)
-    hipLaunchKernelGGL((k_multi_caxpy<float2, float2>), g, dim3(256), 0, st, (float2 *)y,
-                       (const float2 *const *)xs_dev, k, c, cstride, sgn, accumulate, n);
+    KT_SWITCH(k, hipLaunchKernelGGL((k_multi_caxpy<float2, float2, KT>), g, dim3(256), 0, st, (float2 *)y,
+                                    (const float2 *const *)xs_dev, k, c, cstride, sgn, accumulate, n))
   else
     return set_error(-1, "multi_caxpy precision pair %d %d", py, px);
   WMG_HIP(hipGetLastError());

@@ -166,15 +166,25 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
                                                    TO *__restrict__ out, int L0, int L1, int L2, int L3, long V,
                                                    float diagf, double diagd, int nrhs, SweepMap sm, long Vs,
                                                    const TS *__restrict__ bsub, const double *__restrict__ bnrm2,
-                                                   int bstride, double *__restrict__ red) {
+                                                   int bstride, double *__restrict__ red, int inner) {
   using R = typename store_traits<TS>::real;
   const R diag = sizeof(R) == 8 ? (R)diagd : (R)diagf;
   // one sweep over the lattice per tile of RT right-hand sides (grid.y)
   const int L[4] = {L0, L1, L2, L3};
   int x[4];
   long s = 0;
-  const bool valid = sweep_site(sm, L, blockIdx.x, threadIdx.x, x, s);
+  // site-tile workgroup index tb and first rhs r0: grid (tiles, rhs tiles),
+  // or with `inner` one dimension in which each XCD (blockIdx % 8) takes the
+  // rhs tiles of its site tiles consecutively
+  long tb = blockIdx.x;
   int r0 = blockIdx.y * RT;
+  if (inner) {
+    const int nrt = (nrhs + RT - 1) / RT;
+    const long q = (long)blockIdx.x / NXCD;
+    tb = (q / nrt) * NXCD + blockIdx.x % NXCD;
+    r0 = (int)(q % nrt) * RT;
+  }
+  const bool valid = sweep_site(sm, L, tb, threadIdx.x, x, s);
   // the tile's own spinors, [t][c][thread] (sized for the right-hand sides
   // this launch has, at most RT)
   extern __shared__ unsigned char dsm[];
@@ -188,7 +198,7 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
   }
   __syncthreads();
   // tile-local slot of a neighbour site, -1 when it lies in another tile
-  const long gtile = (blockIdx.x % NXCD) * sm.per_xcd + blockIdx.x / NXCD;
+  const long gtile = (tb % NXCD) * sm.per_xcd + tb / NXCD;
   const long ttile = gtile % sm.td, slab = gtile / sm.td;
   const int iy = (int)(slab % sm.ny), iz = (int)(slab / sm.ny);
   auto local_of = [&](const int y[4]) -> int {
@@ -309,7 +319,7 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
     if (threadIdx.x < RT * 3) {
       int t = threadIdx.x / 3, q = threadIdx.x % 3;
       if (r0 + t < nrhs)
-        red[((size_t)(r0 + t) * gridDim.x + blockIdx.x) * 3 + q] = sh[t][q][0] + sh[t][q][1] + sh[t][q][2] + sh[t][q][3];
+        red[((size_t)(r0 + t) * sm.nblocks + tb) * 3 + q] = sh[t][q][0] + sh[t][q][1] + sh[t][q][2] + sh[t][q][3];
     }
   }
 }
@@ -342,20 +352,27 @@ static void launch_soa(const Geom &g, const void *U, double m, const void *in, v
                        double *red, double *red_out, int red_stride, hipStream_t st, const double *bnrm2 = nullptr,
                        int bstride = 0) {
   constexpr int RT = sizeof(TS) == 16 ? 1 : 2;
+  const int nrt = (nrhs + RT - 1) / RT;
+  // FP64 and FP32 links (288-576 B per site) would be re-read from HBM by
+  // every rhs tile's sweep: the rhs tiles of one site tile then run back to
+  // back on one XCD and share the links in its L2 (FP64, 28 rhs: 14.6 ->
+  // 10.4 ms on 32^3x64).  FP16 links are cheap to re-read, and one sweep per
+  // rhs tile keeps the spinor halo in L2.
+  const int inner = sizeof(TL) >= 8 && nrt > 1;
   // bytes a site brings into L2 during one sweep: its links and RT spinors
   SweepMap sm = make_sweep(g.L, 36 * (int)sizeof(TL) + 24 * (int)sizeof(TS) / 2 * RT);
-  dim3 grid((unsigned)sm.nblocks, (nrhs + RT - 1) / RT);
+  dim3 grid = inner ? dim3((unsigned)(sm.nblocks * nrt)) : dim3((unsigned)sm.nblocks, nrt);
   const size_t lds = (size_t)(nrhs < RT ? nrhs : RT) * 12 * 256 * sizeof(TS);
   if (red) {
     hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
                        (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                       (const TS *)bsub, bnrm2, bstride, red);
+                       (const TS *)bsub, bnrm2, bstride, red, inner);
     hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
                        red_stride);
   } else {
     hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
                        (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                       (const TS *)bsub, bnrm2, bstride, (double *)nullptr);
+                       (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner);
   }
 }
 

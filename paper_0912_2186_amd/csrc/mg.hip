@@ -67,11 +67,19 @@ template <class S>
 __global__ void k_mr_next(const double *__restrict__ red, int k, const S *__restrict__ s, const S *__restrict__ q,
                           S *__restrict__ snext, long n) {
   using R = typename store_traits<S>::real;
+  constexpr int PK = pack_len<S>();
   int rhs = blockIdx.y;
-  cx<R> a = mr_alpha<R>(red, k, rhs);
+  cx<R> a = neg(mr_alpha<R>(red, k, rhs));
   size_t off = (size_t)rhs * n;
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
-    stc(snext + off + i, cfma(neg(a), ldc(q + off + i), ldc(s + off + i)));
+  const long np = n / PK;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
+    cx<R> qv[PK], sv[PK];
+    ldp<PK>(q + off + i * PK, qv);
+    ldp<PK>(s + off + i * PK, sv);
+#pragma unroll
+    for (int e = 0; e < PK; e++) sv[e] = cfma(a, qv[e], sv[e]);
+    stp<PK>(snext + off + i * PK, sv);
+  }
 }
 struct MrVecs {
   const void *s[4];
@@ -79,17 +87,25 @@ struct MrVecs {
 template <class S, class SS = S>
 __global__ void k_mr_accum(const double *__restrict__ red, int nsteps, MrVecs v, S *__restrict__ e, long n) {
   using R = typename store_traits<S>::real;
+  constexpr int PK = pack_len<S>() > pack_len<SS>() ? pack_len<S>() : pack_len<SS>();
   int rhs = blockIdx.y;
   cx<R> a[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) a[k] = k < nsteps ? mr_alpha<R>(red, k, rhs) : czero<R>();
   size_t off = (size_t)rhs * n;
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-    cx<R> acc = ldc(e + off + i);
+  const long np = n / PK;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
+    cx<R> acc[PK];
+    ldp<PK>(e + off + i * PK, acc);
 #pragma unroll
     for (int k = 0; k < 4; k++)
-      if (k < nsteps) acc = cfma(a[k], ldc((const SS *)v.s[k] + off + i), acc);
-    stc(e + off + i, acc);
+      if (k < nsteps) {
+        cx<R> sv[PK];
+        ldp<PK>((const SS *)v.s[k] + off + i * PK, sv);
+#pragma unroll
+        for (int q = 0; q < PK; q++) acc[q] = cfma(a[k], sv[q], acc[q]);
+      }
+    stp<PK>(e + off + i * PK, acc);
   }
 }
 
@@ -445,6 +461,7 @@ static int mr_smooth_h16(wmg_ctx *c, const void *r, const double *rn2, void *e, 
   Level &L = c->lv[0];
   void *sv[4] = {nullptr, nullptr, nullptr, nullptr}, *q;
   const int names[4] = {VS, VS1, VS2, VS3};
+  if (L.n % 4) return set_error(-1, "mr_smooth_h16: length %ld not a multiple of 4", L.n);
   for (int k = 0; k < nsteps; k++) TRY(level_vec(c, 0, P16, names[k], &sv[k], nrhs));
   TRY(level_vec(c, 0, P16, VQ, &q, nrhs));
   const double vb = (double)L.g.V * 36 * 4;  // FP16 links

@@ -365,13 +365,22 @@ __global__ void __launch_bounds__(TB) k_prolong(BlockGeom bg, int nv, const TP *
       cx<R> acc[RC];
 #pragma unroll
       for (int r = 0; r < RC; r++) acc[r] = czero<R>();
-      for (int a = 0; a < nv; a++) {
-        auto pv0 = ldc(P + ((size_t)a * bg.Vc + xh) * E + e);
-        float sc = pscale<TP>::get(Pscale, (size_t)a * bg.Vc * bg.bs + si);
-        cx<R> pv = {(R)(sc * pv0.re), (R)(sc * pv0.im)};
+      // P entries (and scales) of 8 null vectors in flight at once
+      for (int a0 = 0; a0 < nv; a0 += 8) {
+        cx<R> pv[8];
 #pragma unroll
-        for (int r = 0; r < RC; r++)
-          if (r < rc) acc[r] = cfma(pv, cs[r * n + off + a], acc[r]);
+        for (int u = 0; u < 8; u++) {
+          const int a = a0 + u < nv ? a0 + u : nv - 1;
+          auto pv0 = ldc(P + ((size_t)a * bg.Vc + xh) * E + e);
+          float sc = pscale<TP>::get(Pscale, (size_t)a * bg.Vc * bg.bs + si);
+          pv[u] = {(R)(sc * pv0.re), (R)(sc * pv0.im)};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+          if (a0 + u < nv)
+#pragma unroll
+            for (int r = 0; r < RC; r++)
+              if (r < rc) acc[r] = cfma(pv[u], cs[r * n + off + a0 + u], acc[r]);
       }
       long s = block_site(bg, xh, k);
 #pragma unroll

@@ -72,6 +72,31 @@ template <> struct store_traits<double2> { using real = double; };
 template <> struct store_traits<float2> { using real = float; };
 template <> struct store_traits<__half2> { using real = float; };
 
+// ---------------------------------------------------------------- packs
+// Vector kernels move PK consecutive complex elements per lane and access so
+// that every load and store is 16 bytes wide (one FP64, two FP32 or four
+// FP16 complex numbers; a wider pack of a mixed-precision kernel is two
+// accesses).  Vectors are hipMalloc'd and their per-rhs length is a multiple
+// of PK, so every pack is aligned.
+template <class S> __host__ __device__ constexpr int pack_len() { return 16 / (int)sizeof(S); }
+template <class S, int PK> struct alignas(sizeof(S) * PK >= 16 ? 16 : sizeof(S) * PK) Pack {
+  S v[PK];
+};
+template <int PK, class S, class R> __device__ __forceinline__ void ldp(const S *p, cx<R> o[PK]) {
+  const Pack<S, PK> t = *reinterpret_cast<const Pack<S, PK> *>(p);
+#pragma unroll
+  for (int k = 0; k < PK; k++) {
+    auto c = ldc(&t.v[k]);
+    o[k] = {(R)c.re, (R)c.im};
+  }
+}
+template <int PK, class S, class R> __device__ __forceinline__ void stp(S *p, const cx<R> v[PK]) {
+  Pack<S, PK> t;
+#pragma unroll
+  for (int k = 0; k < PK; k++) stc(&t.v[k], v[k]);
+  *reinterpret_cast<Pack<S, PK> *>(p) = t;
+}
+
 // ---------------------------------------------------------------- geometry
 struct Geom {
   int L[4];

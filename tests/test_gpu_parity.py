@@ -150,6 +150,46 @@ def test_mfma_coarse_apply_multi_rhs(wmg, nv, nrhs, fp32_links):
         assert e < (2e-6 if fp32_links else 1.5e-3)
 
 
+def test_mfma16_coarse_apply_dynamic_range(wmg):
+    """FP16-link matrix-core stencil on vectors whose sites span 12 decades
+    (each site and rhs scaled by 10^u, u uniform in [-8, 4]), one zero rhs
+    and one of size 1e-30: per rhs, the result matches the oracle applying
+    the same stored FP16 links to FP32 precision."""
+    L, block, nv, nrhs = (8, 8, 8, 8), (4, 4, 4, 4), 24, 6
+    say("mfma16 dynamic range", L, nv, nrhs)
+    U = inputs.gauge_field(L, 0.5, 309)
+    p = wmg.default_params(setup_iters=0, seed=2, nrhs_max=nrhs, precision=wmg.WMG_MIXED)
+    mg = wmg.MG(L, dev(U), -0.1, nv, block, p)
+    vecs = rand_vecs(nv, vol(L), 12, 84)
+    mg.mg_set_null_vectors(0, dev(vecs))
+    P = oracle.block_orthonormalize(L, 12, block, vecs)
+    Y = oracle.coarse_build_wilson(L, U, -0.1, block, P)
+    Lc = oracle.coarse_dims(L, block)
+    Vc, n = vol(Lc), 2 * nv
+    s = np.maximum(np.abs(Y.real).max(axis=(2, 3)), np.abs(Y.imag).max(axis=(2, 3)))
+    s = np.where(s > 0, s, 1.0)[:, :, None, None]
+    q = lambda a: np.float16(np.float32(a / s)).astype(np.float64) * s
+    Yq = q(Y.real) + 1j * q(Y.imag)
+    rng = np.random.default_rng(85)
+    v = rand_vecs(nrhs, Vc, n, 86) * 10.0 ** rng.uniform(-8, 4, size=(nrhs, Vc, 1))
+    v[1] = 0
+    v[2] *= 1e-30 / np.abs(v[2]).max()
+    # FP32 inputs: compare with the oracle on the FP32-rounded vectors
+    v = v.astype(np.complex64).astype(np.complex128)
+    for dag in (False, True):
+        o = empty((nrhs, Vc, n))
+        mg.mg_coarse_apply_f32(1, dev(v), o, dagger=dag, nrhs=nrhs)
+        oh = host(o)
+        for r in range(nrhs):
+            ref = oracle.coarse_apply(Lc, n, Yq, v[r], dagger=dag)
+            if r == 1:
+                assert np.all(oh[r] == 0)
+                continue
+            e = relerr(oh[r], ref)
+            say("  dagger", dag, "rhs", r, "relerr", e)
+            assert e < 5e-6
+
+
 @pytest.mark.parametrize("L,block,nv,nrhs", [((8, 8, 8, 16), (4, 4, 4, 4), 24, 28), ((8, 8, 8, 8), (4, 4, 4, 4), 6, 1),
                                              ((8, 8, 8, 8), (4, 4, 4, 4), 8, 37), ((8, 4, 4, 8), (2, 2, 2, 4), 5, 3)])
 def test_low_precision_transfers_multi_rhs(wmg, L, block, nv, nrhs):
