@@ -553,7 +553,7 @@ k_coarse_apply_mfma(const float *__restrict__ Ym, const __half *__restrict__ Yh,
     y[mu] = d < 5 ? (x[mu] + 1) % L[mu] : (x[mu] - 1 + L[mu]) % L[mu];
     return site_index(L, y);
   };
-  const int h = n / 2, NC = NT * 16, KS = n / 2;
+  const int h = n / 2, NC = NT * 16;
   // padding columns 2R..NC-1 and padding k-rows 2n..4KM-1 stay zero for
   // every direction (4KM <= LDK - 4)
   for (int idx = threadIdx.x; idx < (NC - 2 * R) * LDK; idx += blockDim.x) Bt[2 * R * LDK + idx] = 0.f;
@@ -662,6 +662,137 @@ k_coarse_apply_mfma(const float *__restrict__ Ym, const __half *__restrict__ Yh,
     }
 }
 
+// Variant for n = N in {32, 40, 48, 64} that stages each neighbour value
+// once: with B = [Br; Bi] (2n x R, no duplication) the real and imaginary
+// parts of C are two GEMMs over the same B,
+//   Cr = [Yr | -Yi] B,   Ci = [Yi | Yr] B,
+// and both A operands are the stored fragments [Yr | Yi] of the wave's
+// registers: for k-step ks (4 k each, Q = N/4 k-steps per half) the first
+// is S(ks) or -S(ks), the second S(ks + Q) or S(ks - Q).  Half the LDS
+// writes and reads of the duplicated form, the same MFMA count, and C
+// comes out as (re, im) pairs per lane.
+template <int NTR, int N, bool AH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_coarse_apply_mfma2(const float *__restrict__ Ym, const __half *__restrict__ Yh, const float *__restrict__ Ysc,
+                     const float2 *__restrict__ in, float2 *__restrict__ out, int L0, int L1, int L2, int L3, long Vc,
+                     int nrhs, int dagger) {
+  constexpr int KM = (N / 2 + 7) / 8 * 8;  // k-steps of the stored fragments
+  constexpr int KS = N / 2, Q = N / 4;     // k-steps used; per half
+  constexpr int MT = (N + 15) / 16;
+  extern __shared__ float Bt[];  // [NTR*16 columns][LDK], column r, k-row kk at r*LDK + kk
+  const int LDK = mfma_ldk(N);
+  long xh = blockIdx.x;
+  int r0 = blockIdx.y * 32;
+  int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
+  int mt = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int L[4] = {L0, L1, L2, L3};
+  int x[4];
+  site_coords(L, xh, x);
+  auto nbr = [&](int d) -> long {
+    if (d == 0) return xh;
+    int mu = (d - 1) & 3;
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    y[mu] = d < 5 ? (x[mu] + 1) % L[mu] : (x[mu] - 1 + L[mu]) % L[mu];
+    return site_index(L, y);
+  };
+  constexpr int h = N / 2;
+  // padding columns R..16 NTR - 1 stay zero for every direction
+  for (int idx = threadIdx.x; idx < (NTR * 16 - R) * LDK; idx += blockDim.x) Bt[R * LDK + idx] = 0.f;
+  constexpr int tpr = 64 * MT / N;  // >= 4 row groups: 8 rounds cover R <= 32
+  const int col = threadIdx.x % N, rg = threadIdx.x / N;
+  const bool stager = rg < tpr;
+  const bool neg = dagger && col >= h;
+  float2 stg[8];
+  auto stage_load = [&](int d) {
+    const float2 *src = in + ((size_t)(r0 + rg) * Vc + nbr(d)) * N + col;
+    const size_t step = (size_t)tpr * Vc * N;
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (stager && rg + q * tpr < R) stg[q] = src[q * step];
+  };
+  auto stage_store = [&]() {
+    float *dst = Bt + rg * LDK + col;
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (stager && rg + q * tpr < R) {
+        float2 v = stg[q];
+        if (neg) { v.x = -v.x; v.y = -v.y; }
+        dst[q * tpr * LDK] = v.x;
+        dst[q * tpr * LDK + N] = v.y;
+      }
+  };
+  const int mts = mt < MT ? mt : 0;
+  auto a_load = [&](float *a, int d) {
+    if constexpr (AH) {
+      const float sc = Ysc[(size_t)xh * 9 + d];
+      const uint2 *Ad = (const uint2 *)(Yh + (((size_t)xh * 9 + d) * MT + mts) * KM * 64) + lane;
+#pragma unroll
+      for (int kq = 0; kq < KS / 4; kq++) {
+        uint2 v = Ad[kq * 64];
+        float2 f01 = __half22float2(*(const __half2 *)&v.x), f23 = __half22float2(*(const __half2 *)&v.y);
+        a[4 * kq] = f01.x * sc;
+        a[4 * kq + 1] = f01.y * sc;
+        a[4 * kq + 2] = f23.x * sc;
+        a[4 * kq + 3] = f23.y * sc;
+      }
+    } else {
+      const float4 *Ad = (const float4 *)(Ym + (((size_t)xh * 9 + d) * MT + mts) * KM * 64) + lane;
+#pragma unroll
+      for (int kq = 0; kq < KS / 4; kq++) {
+        float4 v = Ad[kq * 64];
+        a[4 * kq] = v.x;
+        a[4 * kq + 1] = v.y;
+        a[4 * kq + 2] = v.z;
+        a[4 * kq + 3] = v.w;
+      }
+    }
+  };
+  floatx4 cr[NTR], ci[NTR];
+#pragma unroll
+  for (int t = 0; t < NTR; t++) cr[t] = ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float a_cur[KS], a_nxt[KS];
+  stage_load(0);
+  a_load(a_cur, 0);
+  const int krow = lane >> 4, jc = lane & 15;
+  for (int d = 0; d < 9; d++) {
+    __syncthreads();  // every wave is done reading B of direction d-1
+    stage_store();
+    __syncthreads();
+    if (d + 1 < 9) {
+      stage_load(d + 1);
+      a_load(a_nxt, d + 1);
+    }
+    if (mt < MT) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ks++) {
+        const float a1 = ks < Q ? a_cur[ks] : -a_cur[ks];
+        const float a2 = ks < Q ? a_cur[ks + Q] : a_cur[ks - Q];
+        const float *bcol = Bt + jc * LDK + ks * 4 + krow;
+#pragma unroll
+        for (int t = 0; t < NTR; t++) {
+          const float b = bcol[t * 16 * LDK];
+          cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, cr[t], 0, 0, 0);
+          ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b, ci[t], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) a_cur[ks] = a_nxt[ks];
+  }
+  if (mt >= MT) return;
+#pragma unroll
+  for (int t = 0; t < NTR; t++)
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const int row = mt * 16 + 4 * (lane >> 4) + v, r = t * 16 + (lane & 15);
+      if (row < N && r < R) {
+        float2 val = make_float2(cr[t][v], ci[t][v]);
+        if (dagger && row >= h) { val.x = -val.x; val.y = -val.y; }
+        out[((size_t)(r0 + r) * Vc + xh) * N + row] = val;
+      }
+    }
+}
+
 static int coarse_apply_mfma_any(const Geom &gc, int n, const float *Ym, const __half *Yh, const float *Ysc,
                                  const float2 *in, float2 *out, int dagger, int nrhs, hipStream_t st) {
   if (n > 64 || (n & 1)) return set_error(-1, "coarse_apply_mfma: n=%d (even, <= 64)", n);
@@ -670,6 +801,24 @@ static int coarse_apply_mfma_any(const Geom &gc, int n, const float *Ym, const _
   int NT = (2 * rmax + 15) / 16;
   dim3 grid((unsigned)gc.V, (nrhs + 31) / 32);
   dim3 blk(64 * MT);
+  if (n == 32 || n == 40 || n == 48 || n == 64) {
+    const int NTR = (rmax + 15) / 16;
+    size_t lds2 = sizeof(float) * NTR * 16 * mfma_ldk(n);
+#define N2_CASE(T, NN)                                                                                         \
+  if (NTR == T && n == NN) {                                                                                  \
+    if (Yh)                                                                                                   \
+      hipLaunchKernelGGL((k_coarse_apply_mfma2<T, NN, true>), grid, blk, lds2, st, Ym, Yh, Ysc, in, out,       \
+                         gc.L[0], gc.L[1], gc.L[2], gc.L[3], gc.V, nrhs, dagger);                             \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_coarse_apply_mfma2<T, NN, false>), grid, blk, lds2, st, Ym, Yh, Ysc, in, out,      \
+                         gc.L[0], gc.L[1], gc.L[2], gc.L[3], gc.V, nrhs, dagger);                             \
+    WMG_HIP(hipGetLastError());                                                                               \
+    return 0;                                                                                                 \
+  }
+    N2_CASE(1, 32) N2_CASE(1, 40) N2_CASE(1, 48) N2_CASE(1, 64)
+    N2_CASE(2, 32) N2_CASE(2, 40) N2_CASE(2, 48) N2_CASE(2, 64)
+#undef N2_CASE
+  }
   size_t lds = sizeof(float) * NT * 16 * mfma_ldk(n);
   const int KM = mfma_km(n);  // 8, 16, 24 or 32
 #define NT_CASE(N, K)                                                                                           \
