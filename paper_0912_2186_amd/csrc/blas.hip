@@ -267,14 +267,16 @@ int multi_dot(Reducer &R, int prec, const void *const *xs_dev, int k, const void
 // ---------------------------------------------------------------- GCR fusions
 // Projection step of classical Gram-Schmidt against unnormalised basis
 // vectors w_j (|w_j|^2 kept in wn2): b_j = d_j / |w_j|^2, w <- w - sum b_j w_j,
-// b_j recorded in beta[j][k] (PASS 1: =, PASS 2: +=).  PASS 1 then reduces
-// the new projections <w_j, w> (2k values, the dots of the second pass);
+// b_j recorded in beta[j][k] (set_beta: =, else +=).  PASS 1 then reduces
+// the new projections <w_j, w> (2k values, the dots of a second pass);
 // PASS 2 reduces <w, r> and |w|^2.  One read of every w_j, w (and r).
+// gcr_project's pass: 1 and 2 for the two passes of CGS2, 3 for a single
+// pass (PASS 2 reductions, beta set).
 template <class S, int PASS, int KT>
 __global__ void __launch_bounds__(RB) k_gcr_proj(const S *const *__restrict__ W, int k, S *__restrict__ w,
                                                 const S *__restrict__ r, const double *__restrict__ d, int dstride,
                                                 const double *__restrict__ wn2, int wstride, double *__restrict__ beta,
-                                                int bstride, int kcol, long n, double *partial) {
+                                                int bstride, int kcol, long n, double *partial, int set_beta) {
   using R = typename store_traits<S>::real;
   constexpr int PK = pack_len<S>();
   int rhs = blockIdx.y;
@@ -287,7 +289,7 @@ __global__ void __launch_bounds__(RB) k_gcr_proj(const S *const *__restrict__ W,
     b[j] = {(R)br, (R)bi};
     if (blockIdx.x == 0 && threadIdx.x == 0 && j < k) {
       double *bb = beta + (size_t)rhs * bstride + (j * 16 + kcol) * 2;
-      if (PASS == 1) { bb[0] = br; bb[1] = bi; }
+      if (set_beta) { bb[0] = br; bb[1] = bi; }
       else { bb[0] += br; bb[1] += bi; }
     }
   }
@@ -346,7 +348,8 @@ int gcr_project(Reducer &R, int prec, int pass, const void *const *W, int k, voi
   dim3 grid(red_blocks(n / (prec == P64 ? 1 : 2)), nrhs);
 #define GP(S, P)                                                                                                  \
   KT_SWITCH(k, hipLaunchKernelGGL((k_gcr_proj<S, P, KT>), grid, dim3(RB), 0, st, (const S *const *)W, k, (S *)w,   \
-                                  (const S *)r, d, dstride, wn2, wstride, beta, bstride, kcol, n, R.partial))
+                                  (const S *)r, d, dstride, wn2, wstride, beta, bstride, kcol, n, R.partial,      \
+                                  pass != 2))
   if (prec == P64) { if (pass == 1) { GP(double2, 1); } else { GP(double2, 2); } }
   else { if (pass == 1) { GP(float2, 1); } else { GP(float2, 2); } }
 #undef GP
