@@ -394,12 +394,15 @@ __global__ void __launch_bounds__(TB) k_prolong(BlockGeom bg, int nv, const TP *
 // Fine-level restriction of many right-hand sides on the matrix cores.  Per
 // aggregate xh and chirality chi the complex product
 //   O[alpha][r] = sum_e conj(P[alpha][e]) v[r][e]      (e: elements of chi)
-// is the real GEMM [Or | Oi] = [Pr | Pi] . [[vr, vi], [vi, -vr]] (M = Nv,
-// N = 2R, K = 2 x elements), streamed in chunks of CH elements: the chunk of
-// P (FP16 with its per-site scale, expanded to FP32) and of all R vectors is
-// staged in LDS, so P and the vectors are each read once.  Both LDS tiles are
-// kept k-contiguous with a row stride of 2*CH+4 floats, which spreads the 16
-// rows x 4 k of an MFMA fragment over all banks.
+// is two real GEMMs over the same B = [vr; vi] (K = 2 x elements, N = R):
+//   Or = [Pr | Pi] B,   Oi = [-Pi | Pr] B,
+// the second A operand read from the same LDS tile of P at the other half
+// with a sign.  Streamed in chunks of RCH elements: the chunk of P (FP16
+// with its per-site scale, expanded to FP32) and of all R vectors is staged
+// in LDS, so P and the vectors are each read once.  Both LDS tiles are kept
+// k-contiguous with a row stride of 2*RCH+4 floats, which spreads the 16
+// rows x 4 k of an MFMA fragment over all banks.  Fine sites of the block
+// come from a per-workgroup offset table (no index arithmetic per element).
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 static constexpr int RCH = 64;            // elements per chunk
 static constexpr int RLD = 2 * RCH + 4;   // LDS row stride
@@ -408,66 +411,60 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, cons
                                                      const float *__restrict__ Pscale, const float2 *__restrict__ fine,
                                                      float2 *__restrict__ coarse, int nrhs) {
   __shared__ float As[32 * RLD];
-  __shared__ float Bt[64 * RLD];
+  __shared__ float Bt[32 * RLD];
+  __shared__ int soff[256];  // fine-site offset of block element k from the block's first site
   long xh = xcd_tile(blockIdx.x, gridDim.x);
   if (xh >= bg.Vc) return;
+  const long origin = block_site(bg, xh, 0);
+  for (int k = threadIdx.x; k < bg.bs; k += TB) soff[k] = (int)(block_site(bg, xh, k) - origin);
   const int r0 = blockIdx.y * 32;
   const int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
   const int E = bg.bs * 12, H = bg.bs * 6;
-  const int MTr = (nv + 15) / 16, NTr = (2 * R + 15) / 16, ntile = MTr * NTr;
+  const int MTr = (nv + 15) / 16, NTr = (R + 15) / 16;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // zero the padding rows once (rows nv..31 of A, columns 2R..63 of B)
+  // zero the padding rows once (rows nv..31 of A, columns R..31 of B)
   for (int i = threadIdx.x; i < (32 - nv) * RLD; i += TB) As[nv * RLD + i] = 0.f;
-  for (int i = threadIdx.x; i < (64 - 2 * R) * RLD; i += TB) Bt[2 * R * RLD + i] = 0.f;
+  for (int i = threadIdx.x; i < (32 - R) * RLD; i += TB) Bt[R * RLD + i] = 0.f;
+  const int mt = w / 2, nt = w % 2;  // wave w: row tile w/2, rhs tile w%2
+  const bool mine = mt < MTr && nt < NTr;
   for (int chi = 0; chi < 2; chi++) {
-    floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+    floatx4 accr = floatx4{0.f, 0.f, 0.f, 0.f}, acci = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int e0 = 0; e0 < H; e0 += RCH) {
+      // the chunk lies inside one spin-colour component c0 (bs % RCH == 0)
+      const int g0 = chi * H + e0, c0 = g0 / bg.bs, k0 = g0 % bg.bs;
       __syncthreads();
       for (int i = threadIdx.x; i < nv * RCH; i += TB) {
         int a = i / RCH, e = i % RCH;
-        int ee = chi * H + e0 + e;
-        float2 pv = __half22float2(P[((size_t)a * bg.Vc + xh) * E + ee]);
-        float sc = Pscale[((size_t)a * bg.Vc + xh) * bg.bs + ee % bg.bs];
+        float2 pv = __half22float2(P[((size_t)a * bg.Vc + xh) * E + g0 + e]);
+        float sc = Pscale[((size_t)a * bg.Vc + xh) * bg.bs + k0 + e];
         As[a * RLD + e] = sc * pv.x;
         As[a * RLD + RCH + e] = sc * pv.y;
       }
       for (int i = threadIdx.x; i < R * RCH; i += TB) {
         int r = i / RCH, e = i % RCH;
-        int ee = chi * H + e0 + e;
-        int c = ee / bg.bs, k = ee % bg.bs;
-        long st = block_site(bg, xh, k);
-        float2 v = fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + st];
+        float2 v = fine[((size_t)(r0 + r) * 12 + c0) * bg.Vs + origin + soff[k0 + e]];
         Bt[r * RLD + e] = v.x;
-        Bt[(R + r) * RLD + e] = v.y;
         Bt[r * RLD + RCH + e] = v.y;
-        Bt[(R + r) * RLD + RCH + e] = -v.x;
       }
       __syncthreads();
+      if (mine) {
+        const float *ar = As + (mt * 16 + (lane & 15)) * RLD + (lane >> 4);
+        const float *br = Bt + (nt * 16 + (lane & 15)) * RLD + (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < 2; i++) {
-        int tt = w + 4 * i;
-        if (tt < ntile) {
-          int mt = tt / NTr, nt = tt % NTr;
-          const float *ar = As + (mt * 16 + (lane & 15)) * RLD + (lane >> 4);
-          const float *br = Bt + (nt * 16 + (lane & 15)) * RLD + (lane >> 4);
-          for (int ks = 0; ks < 2 * RCH / 4; ks++)
-            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ks * 4], br[ks * 4], acc[i], 0, 0, 0);
+        for (int ks = 0; ks < 2 * RCH / 4; ks++) {
+          const float b = br[ks * 4];
+          const float a2 = ks < RCH / 4 ? -ar[(ks + RCH / 4) * 4] : ar[(ks - RCH / 4) * 4];
+          accr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ks * 4], b, accr, 0, 0, 0);
+          acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b, acci, 0, 0, 0);
         }
       }
     }
-    float *of = (float *)coarse;
-#pragma unroll
-    for (int i = 0; i < 2; i++) {
-      int tt = w + 4 * i;
-      if (tt >= ntile) continue;
-      int mt = tt / NTr, nt = tt % NTr;
+    if (mine) {
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        int a = mt * 16 + 4 * (lane >> 4) + v, j = nt * 16 + (lane & 15);
-        if (a < nv && j < 2 * R) {
-          int r = j < R ? j : j - R;
-          of[2 * (((size_t)(r0 + r) * bg.Vc + xh) * (2 * nv) + chi * nv + a) + (j < R ? 0 : 1)] = acc[i][v];
-        }
+        int a = mt * 16 + 4 * (lane >> 4) + v, r = nt * 16 + (lane & 15);
+        if (a < nv && r < R)
+          coarse[((size_t)(r0 + r) * bg.Vc + xh) * (2 * nv) + chi * nv + a] = make_float2(accr[v], acci[v]);
       }
     }
   }
@@ -499,7 +496,7 @@ static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int
                     const float *Ps, int vprec, const void *in, void *out, int fine_soa, int nrhs, hipStream_t st) {
   BlockGeom bg = make_bg(g, dof, b);
   if (nv > 64) return set_error(-1, "transfer: nv=%d > 64", nv);
-  if (dir == 0 && fine_soa && pprec == P16 && vprec == P32 && nv <= 32 && (bg.bs * 6) % RCH == 0) {
+  if (dir == 0 && fine_soa && pprec == P16 && vprec == P32 && nv <= 32 && bg.bs % RCH == 0 && bg.bs <= 256) {
     dim3 grid((unsigned)xcd_grid(bg.Vc), (nrhs + 31) / 32);
     hipLaunchKernelGGL(k_restrict_mfma, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps, (const float2 *)in,
                        (float2 *)out, nrhs);
