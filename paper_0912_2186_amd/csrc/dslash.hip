@@ -166,7 +166,8 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
                                                    TO *__restrict__ out, int L0, int L1, int L2, int L3, long V,
                                                    float diagf, double diagd, int nrhs, SweepMap sm, long Vs,
                                                    const TS *__restrict__ bsub, const double *__restrict__ bnrm2,
-                                                   int bstride, double *__restrict__ red, int inner) {
+                                                   int bstride, double *__restrict__ red, int inner,
+                                                   float2 *__restrict__ out32) {
   using R = typename store_traits<TS>::real;
   const R diag = sizeof(R) == 8 ? (R)diagd : (R)diagf;
   // one sweep over the lattice per tile of RT right-hand sides (grid.y)
@@ -294,6 +295,7 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
         o = cx<R>{bs * (R)bv.re - o.re, bs * (R)bv.im - o.im};
       }
       stc(out + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
+      if (out32) stc(out32 + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
       if (RED) o = as_stored(out, o);
       if (RED) {
         rs[t][0] += (double)o.re * p[c].re + (double)o.im * p[c].im;
@@ -350,7 +352,7 @@ __global__ void __launch_bounds__(256) k_dslash_red_finalize(const double *__res
 template <class TL, class TS, class TO = TS>
 static void launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, const void *bsub,
                        double *red, double *red_out, int red_stride, hipStream_t st, const double *bnrm2 = nullptr,
-                       int bstride = 0) {
+                       int bstride = 0, void *out32 = nullptr) {
   constexpr int RT = sizeof(TS) == 16 ? 1 : 2;
   const int nrt = (nrhs + RT - 1) / RT;
   // FP64 and FP32 links (288-576 B per site) would be re-read from HBM by
@@ -366,13 +368,13 @@ static void launch_soa(const Geom &g, const void *U, double m, const void *in, v
   if (red) {
     hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
                        (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                       (const TS *)bsub, bnrm2, bstride, red, inner);
+                       (const TS *)bsub, bnrm2, bstride, red, inner, (float2 *)out32);
     hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
                        red_stride);
   } else {
     hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
                        (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                       (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner);
+                       (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner, (float2 *)out32);
   }
 }
 
@@ -388,9 +390,10 @@ long wilson_red_blocks(const Geom &g) {
 }
 
 int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
-                     const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st) {
+                     const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st, void *out32) {
+  if (out32 && sprec != P64) return set_error(-1, "wilson_soa: FP32 copy of the output only for FP64 spinors");
   if (sprec == P64 && lprec == P64)
-    launch_soa<double2, double2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st);
+    launch_soa<double2, double2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st, nullptr, 0, out32);
   else if (sprec == P32 && lprec == P32)
     launch_soa<float2, float2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st);
   else if (sprec == P32 && lprec == P16)

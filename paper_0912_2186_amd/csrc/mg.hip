@@ -437,7 +437,7 @@ static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, voi
 // fine operator with the smoother's fusions: out = [bsub -] D in, and with
 // reduce also <out, in>, |out|^2 -> red_out (cycle links)
 static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int nrhs, const void *bsub, bool reduce,
-                            double *red_dst = nullptr) {
+                            double *red_dst = nullptr, void *out32 = nullptr) {
   Level &L = c->lv[0];
   int lp = prec == P64 ? P64 : P16;
   c->st_fine++;
@@ -446,7 +446,7 @@ static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int
   int slot = prof_begin(c, prec == P64 ? K_DSLASH_64 : (bsub ? K_DSLASH_RES : K_DSLASH_CYCLE),
                         (double)L.g.V * (36 * lb + (bsub ? 36.0 : 24.0) * sb * nrhs));
   int rc = wilson_soa_fused(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, bsub, reduce ? c->dred : nullptr,
-                            red_dst ? red_dst : c->red_out, 4, c->st);
+                            red_dst ? red_dst : c->red_out, 4, c->st, out32);
   prof_end(c, slot);
   return rc;
 }
@@ -705,11 +705,16 @@ static int gcr_buffers(wmg_ctx *c, int l, int prec, int nrhs, GcrBuf **out) {
 // r = b - A x in FP64 and |r|^2 per rhs into c->red_out[rhs*4 + *off]; on
 // the fine level one fused operator launch (residual and norm in its
 // epilogue), elsewhere operator, subtraction and norm.
-static int residual64(wmg_ctx *c, int l, GcrBuf &B, int nrhs, int *off) {
+// r = b - A x in FP64 and |r|^2 (at red_out[4 rhs + *off]); on the fine level
+// of a mixed solve the same kernel also writes the FP32 copy of r into B.rin
+// (*rin_done = true)
+static int residual64(wmg_ctx *c, int l, GcrBuf &B, int nrhs, int *off, bool *rin_done) {
   Level &L = c->lv[l];
+  *rin_done = false;
   if (L.fine) {
     *off = 2;
-    return fine_apply_fused(c, P64, B.x64, B.r64, nrhs, B.b64, true);
+    *rin_done = B.prec == P32;
+    return fine_apply_fused(c, P64, B.x64, B.r64, nrhs, B.b64, true, nullptr, B.prec == P32 ? B.rin : nullptr);
   }
   *off = 0;
   TRY(apply_op(c, l, P64, B.x64, B.t64, nrhs, false));
@@ -733,8 +738,9 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
   TRY(sync(c));
   for (int r = 0; r < nrhs; r++) bn[r] = sqrt(c->hbuf[4 * r]);
   int roff = 0;
+  bool rin_done = false;  // B.rin already holds the FP32 copy of r
   if (x0_nonzero) {
-    TRY(residual64(c, l, B, nrhs, &roff));
+    TRY(residual64(c, l, B, nrhs, &roff, &rin_done));
   } else {
     TRY(copy(P64, B.r64, P64, B.b64, n, nrhs, st));
     TRY(norm2(c->red, P64, B.r64, n, nrhs, c->red_out, 4, st));
@@ -755,7 +761,7 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
       rn_last[r] = rn[r];
       frozen[r] = !active[r];
     }
-    if (ip != P64) TRY(copy(ip, B.rin, P64, B.r64, n, nrhs, st));
+    if (ip != P64 && !rin_done) TRY(copy(ip, B.rin, P64, B.r64, n, nrhs, st));
     int k = 0;
     while (k < K && total < maxiter) {
       // per-rhs participation mask of this step
@@ -812,7 +818,7 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
     hipLaunchKernelGGL(k_gcr_trisolve2, dim3(1), dim3(64), 0, st, c->gcr, k, nrhs);
     TRY(multi_caxpy(P64, B.x64, ip, (const void *const *)B.zdev, k, c->gcr + G_C, GS, 1.0, 1, n, nrhs, st));
     // reliable update: true residual in FP64
-    TRY(residual64(c, l, B, nrhs, &roff));
+    TRY(residual64(c, l, B, nrhs, &roff, &rin_done));
     c->st_rel++;
     WMG_HIP(hipMemcpyAsync(c->hbuf, c->red_out, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, st));
     TRY(sync(c));

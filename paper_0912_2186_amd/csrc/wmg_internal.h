@@ -145,9 +145,11 @@ int wilson_canonical(const Geom &g, const double *U, double m, const double *in,
 int wilson_soa(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
                hipStream_t st);
 // out = [bsub -] D in; with red != nullptr also <out, in>, |out|^2 per rhs ->
-// red_out[rhs * red_stride + 0..2] (red: scratch of nrhs * wilson_red_blocks * 3)
+// red_out[rhs * red_stride + 0..2] (red: scratch of nrhs * wilson_red_blocks * 3);
+// with out32 != nullptr (FP64 spinors only) out is also written as FP32 there
 int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
-                     const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st);
+                     const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st,
+                     void *out32 = nullptr);
 // Smoother variant with FP16 links and FP16 output storage: in is FP32
 // (iprec P32) or FP16 (P16); out (FP16) = [b/|b| -] D in, where bsub (FP32,
 // only with iprec P32) is scaled per rhs by 1/sqrt(bnrm2[rhs * bstride])
