@@ -109,6 +109,22 @@ static int red_final(Reducer &R, int nblk, int nc, int nrhs, double *out, int ou
   return 0;
 }
 
+__global__ void __launch_bounds__(RB) k_sum_partials(const double *__restrict__ part, long nblk,
+                                                    double *__restrict__ out, int out_stride) {
+  const int rhs = blockIdx.x;
+  const double *p = part + (size_t)rhs * nblk;
+  double v[1] = {0};
+  for (long b = threadIdx.x; b < nblk; b += RB) v[0] += p[b];
+  wg_sum<1>(v);
+  if (threadIdx.x == 0) out[(size_t)rhs * out_stride] = v[0];
+}
+
+int sum_partials(const double *part, long nblk, int nrhs, double *out, int out_stride, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(RB), 0, st, part, nblk, out, out_stride);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
 // MODE 0: <x,y> (2), 1: |x|^2 (1), 2: <x,y>,|x|^2 (3)
 template <int MODE, class S>
 __global__ void __launch_bounds__(RB) k_reduce(const S *__restrict__ x, const S *__restrict__ y, long n,

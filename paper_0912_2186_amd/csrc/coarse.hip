@@ -675,7 +675,7 @@ template <int NTR, int N, bool AH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_coarse_apply_mfma2(const float *__restrict__ Ym, const __half *__restrict__ Yh, const float *__restrict__ Ysc,
                      const float2 *__restrict__ in, float2 *__restrict__ out, int L0, int L1, int L2, int L3, long Vc,
-                     int nrhs, int dagger) {
+                     int nrhs, int dagger, double *__restrict__ npart) {
   constexpr int KM = (N / 2 + 7) / 8 * 8;  // k-steps of the stored fragments
   constexpr int KS = N / 2, Q = N / 4;     // k-steps used; per half
   constexpr int MT = (N + 15) / 16;
@@ -779,7 +779,7 @@ k_coarse_apply_mfma2(const float *__restrict__ Ym, const __half *__restrict__ Yh
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) a_cur[ks] = a_nxt[ks];
   }
-  if (mt >= MT) return;
+  // the block has exactly MT waves: every wave reaches the barrier below
 #pragma unroll
   for (int t = 0; t < NTR; t++)
 #pragma unroll
@@ -791,10 +791,35 @@ k_coarse_apply_mfma2(const float *__restrict__ Ym, const __half *__restrict__ Yh
         out[((size_t)(r0 + r) * Vc + xh) * N + row] = val;
       }
     }
+  if (npart) {
+    // |out|^2 of this site per rhs: the wave's rows, then the MT waves in order
+    __shared__ double nsh[MT][NTR * 16];
+#pragma unroll
+    for (int t = 0; t < NTR; t++) {
+      double q = 0;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int row = mt * 16 + 4 * (lane >> 4) + v;
+        if (row < N) q += (double)cr[t][v] * cr[t][v] + (double)ci[t][v] * ci[t][v];
+      }
+      q += __shfl_xor(q, 16, 64);
+      q += __shfl_xor(q, 32, 64);
+      if (lane < 16) nsh[mt][t * 16 + lane] = q;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+      double q = 0;
+#pragma unroll
+      for (int m = 0; m < MT; m++) q += nsh[m][threadIdx.x];
+      npart[(size_t)(r0 + threadIdx.x) * Vc + xh] = q;
+    }
+  }
 }
 
 static int coarse_apply_mfma_any(const Geom &gc, int n, const float *Ym, const __half *Yh, const float *Ysc,
-                                 const float2 *in, float2 *out, int dagger, int nrhs, hipStream_t st) {
+                                 const float2 *in, float2 *out, int dagger, int nrhs, hipStream_t st,
+                                 double *npart = nullptr, bool *fused = nullptr) {
+  if (fused) *fused = false;
   if (n > 64 || (n & 1)) return set_error(-1, "coarse_apply_mfma: n=%d (even, <= 64)", n);
   int MT = (n + 15) / 16;
   int rmax = nrhs < 32 ? nrhs : 32;
@@ -808,11 +833,12 @@ static int coarse_apply_mfma_any(const Geom &gc, int n, const float *Ym, const _
   if (NTR == T && n == NN) {                                                                                  \
     if (Yh)                                                                                                   \
       hipLaunchKernelGGL((k_coarse_apply_mfma2<T, NN, true>), grid, blk, lds2, st, Ym, Yh, Ysc, in, out,       \
-                         gc.L[0], gc.L[1], gc.L[2], gc.L[3], gc.V, nrhs, dagger);                             \
+                         gc.L[0], gc.L[1], gc.L[2], gc.L[3], gc.V, nrhs, dagger, npart);                      \
     else                                                                                                      \
       hipLaunchKernelGGL((k_coarse_apply_mfma2<T, NN, false>), grid, blk, lds2, st, Ym, Yh, Ysc, in, out,      \
-                         gc.L[0], gc.L[1], gc.L[2], gc.L[3], gc.V, nrhs, dagger);                             \
+                         gc.L[0], gc.L[1], gc.L[2], gc.L[3], gc.V, nrhs, dagger, npart);                      \
     WMG_HIP(hipGetLastError());                                                                               \
+    if (fused) *fused = npart != nullptr;                                                                     \
     return 0;                                                                                                 \
   }
     N2_CASE(1, 32) N2_CASE(1, 40) N2_CASE(1, 48) N2_CASE(1, 64)
@@ -845,9 +871,9 @@ int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, 
 }
 
 int coarse_apply_mfma16(const Geom &gc, int n, const __half *Yh, const float *Ysc, const float2 *in, float2 *out,
-                        int dagger, int nrhs, hipStream_t st) {
+                        int dagger, int nrhs, hipStream_t st, double *npart, bool *fused) {
   if (!Yh || !Ysc) return set_error(-1, "coarse_apply_mfma16: null links");
-  return coarse_apply_mfma_any(gc, n, nullptr, Yh, Ysc, in, out, dagger, nrhs, st);
+  return coarse_apply_mfma_any(gc, n, nullptr, Yh, Ysc, in, out, dagger, nrhs, st, npart, fused);
 }
 
 }  // namespace wmg

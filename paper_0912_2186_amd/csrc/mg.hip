@@ -110,21 +110,35 @@ __global__ void k_mr_accum(const double *__restrict__ red, int nsteps, MrVecs v,
 }
 
 // CG: alpha = act ? ss/uu : 0; x += alpha p; r -= alpha u
+// and the workgroup's part of |r|^2 (after the update) into
+// part[rhs * gridDim.x + blockIdx.x]
 template <class S>
-__global__ void k_cg_step1(const double *__restrict__ cg, int ssoff, S *__restrict__ x, S *__restrict__ r,
-                           const S *__restrict__ p, const S *__restrict__ u, long n, int nrhs) {
+__global__ void __launch_bounds__(256) k_cg_step1(const double *__restrict__ cg, int ssoff, S *__restrict__ x,
+                                                 S *__restrict__ r, const S *__restrict__ p, const S *__restrict__ u,
+                                                 long n, int nrhs, double *__restrict__ part) {
   using R = typename store_traits<S>::real;
   int rhs = blockIdx.y;
   const double *c = cg + rhs * 8;
   double uu = c[0], ss = c[ssoff], act = c[5];
   R a = (act > 0 && uu > 0) ? (R)(ss / uu) : R(0);
   size_t off = (size_t)rhs * n;
-  if (a == R(0)) return;
+  double q = 0;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-    auto pv = ldc(p + off + i), uv = ldc(u + off + i);
-    stc(x + off + i, ldc(x + off + i) + a * pv);
-    stc(r + off + i, ldc(r + off + i) - a * uv);
+    auto rv = ldc(r + off + i);
+    if (a != R(0)) {
+      auto pv = ldc(p + off + i), uv = ldc(u + off + i);
+      stc(x + off + i, ldc(x + off + i) + a * pv);
+      rv = rv - a * uv;
+      stc(r + off + i, rv);
+    }
+    q += (double)rv.re * rv.re + (double)rv.im * rv.im;
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) q += __shfl_down(q, o, 64);
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)rhs * gridDim.x + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // CG: p = s + beta p, beta = ss_new/ss_old, only while active
@@ -273,6 +287,8 @@ struct wmg_ctx {
   double *gcr = nullptr;
   double *mask = nullptr;
   double *dred = nullptr;  // per-workgroup partials of the fused Dslash reductions
+  double *cpart = nullptr;  // per-(rhs, site or workgroup) partials of fused coarse norms
+  size_t cpart_cap = 0;
   int *flag = nullptr;
   double *hbuf = nullptr;  // pinned host mirror
   GcrBuf gb[2][2];         // [level 0 / level 1][FP64 / FP32 inner precision]
@@ -374,7 +390,22 @@ static int level_vec(wmg_ctx *c, int l, int prec, int name, void **out, int nrhs
 // ------------------------------------------------------------ operators
 // op(level, prec, in, out, nrhs, lowlinks): fine Wilson (links P64 / P32 /
 // P16 when lowlinks) or coarse stencil.
-static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int nrhs, bool lowlinks, int dagger = 0) {
+static int cpart_get(wmg_ctx *c, size_t n, double **p) {
+  if (c->cpart_cap < n) {
+    if (c->cpart) (void)hipFree(c->cpart);
+    c->cpart = nullptr;
+    c->cpart_cap = 0;
+    TRY(dalloc((void **)&c->cpart, sizeof(double) * n));
+    c->cpart_cap = n;
+  }
+  *p = c->cpart;
+  return 0;
+}
+
+// With nrm_out, |out|^2 per rhs -> nrm_out[rhs * nrm_stride] as well (fused
+// into the multi-RHS coarse stencil where it supports it).
+static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int nrhs, bool lowlinks, int dagger = 0,
+                    double *nrm_out = nullptr, int nrm_stride = 0) {
   Level &L = c->lv[l];
   if (L.fine) {
     int lp = prec == P64 ? P64 : (lowlinks ? P16 : P32);
@@ -387,7 +418,8 @@ static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int 
     int slot = prof_begin(c, kind, (double)L.g.V * (36 * lb + 24.0 * sb * nrhs));
     int rc = wilson_soa(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, c->st);
     prof_end(c, slot);
-    return rc;
+    TRY(rc);
+    return nrm_out ? norm2(c->red, prec, out, L.n, nrhs, nrm_out, nrm_stride, c->st) : 0;
   }
   int n = L.dof;
   // algorithmic bytes: links once (FP64 / FP32 complex, or FP16 + scales)
@@ -396,15 +428,22 @@ static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int 
   int slot = prof_begin(c, prec == P64 ? K_COARSE64 : K_COARSE32,
                         (double)L.g.V * (9.0 * n * n * yb + 2.0 * n * vb * nrhs));
   int rc;
+  bool fused = false;
+  double *npart = nullptr;
+  if (nrm_out && prec == P32 && L.Ymh) TRY(cpart_get(c, (size_t)nrhs * L.g.V, &npart));
   if (prec == P32 && L.Ymh)
-    rc = coarse_apply_mfma16(L.g, n, L.Ymh, L.Ymsc, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st);
+    rc = coarse_apply_mfma16(L.g, n, L.Ymh, L.Ymsc, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st, npart,
+                             &fused);
   else if (prec == P32 && L.Ym)
     rc = coarse_apply_mfma(L.g, n, L.Ym, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st);
   else
     rc = coarse_apply(L.g, n, prec, prec == P64 ? (const void *)L.Y64 : (const void *)L.Y32, prec, in, out, dagger,
                       nrhs, c->st);
   prof_end(c, slot);
-  return rc;
+  TRY(rc);
+  if (!nrm_out) return 0;
+  if (fused) return sum_partials(npart, L.g.V, nrhs, nrm_out, nrm_stride, c->st);
+  return norm2(c->red, prec, out, L.n, nrhs, nrm_out, nrm_stride, c->st);
 }
 
 // algorithmic bytes of one transfer: P once (plus FP16 scales) and the fine
@@ -567,23 +606,24 @@ static int cgnr(wmg_ctx *c, int l, int prec, const void *b, void *x, int nrhs) {
   // cg[rhs*8 + 4] = |b|^2
   TRY(norm2(c->red, prec, b, L.n, nrhs, c->cg + 4, 8, c->st));
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64), 0, c->st, c->cg, nrhs, tol * tol, (const double *)nullptr);
-  TRY(apply_op(c, l, prec, r, s, nrhs, false, 1));
+  TRY(apply_op(c, l, prec, r, s, nrhs, false, 1, c->cg + 1, 8));
   TRY(copy(prec, p, prec, s, L.n, nrhs, c->st));
-  TRY(norm2(c->red, prec, s, L.n, nrhs, c->cg + 1, 8, c->st));
   int cur = 1;
   const int check = 4;
   int it = 0;
   dim3 g = grid_for<double2>(L.n, nrhs);
+  double *spart;
+  TRY(cpart_get(c, (size_t)nrhs * (g.x > L.g.V ? g.x : L.g.V), &spart));
   for (; it < c->p.coarse_maxiter; it++) {
-    TRY(apply_op(c, l, prec, p, u, nrhs, false));
-    TRY(norm2(c->red, prec, u, L.n, nrhs, c->cg + 0, 8, c->st));
+    // u = A p, |u|^2; x += alpha p, r -= alpha u, |r|^2
+    TRY(apply_op(c, l, prec, p, u, nrhs, false, 0, c->cg + 0, 8));
     if (prec == P64)
       hipLaunchKernelGGL(k_cg_step1<double2>, g, dim3(256), 0, c->st, c->cg, cur, (double2 *)x, (double2 *)r,
-                         (const double2 *)p, (const double2 *)u, L.n, nrhs);
+                         (const double2 *)p, (const double2 *)u, L.n, nrhs, spart);
     else
       hipLaunchKernelGGL(k_cg_step1<float2>, g, dim3(256), 0, c->st, c->cg, cur, (float2 *)x, (float2 *)r,
-                         (const float2 *)p, (const float2 *)u, L.n, nrhs);
-    TRY(norm2(c->red, prec, r, L.n, nrhs, c->cg + 3, 8, c->st));
+                         (const float2 *)p, (const float2 *)u, L.n, nrhs, spart);
+    TRY(sum_partials(spart, g.x, nrhs, c->cg + 3, 8, c->st));
     hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, c->st, c->cg, nrhs, c->flag);
     if ((it + 1) % check == 0 || it + 1 == c->p.coarse_maxiter) {
       int done = 0;
@@ -591,9 +631,8 @@ static int cgnr(wmg_ctx *c, int l, int prec, const void *b, void *x, int nrhs) {
       TRY(sync(c));
       if (done) { it++; break; }
     }
-    TRY(apply_op(c, l, prec, r, s, nrhs, false, 1));
     int nxt = 3 - cur;
-    TRY(norm2(c->red, prec, s, L.n, nrhs, c->cg + nxt, 8, c->st));
+    TRY(apply_op(c, l, prec, r, s, nrhs, false, 1, c->cg + nxt, 8));
     if (prec == P64)
       hipLaunchKernelGGL(k_cg_step2<double2>, g, dim3(256), 0, c->st, c->cg, nxt, cur, (const double2 *)s,
                          (double2 *)p, L.n);
@@ -950,6 +989,7 @@ static void free_ctx(wmg_ctx *c) {
   red_free(c->red);
   if (c->dsc) (void)hipFree(c->dsc);
   if (c->dred) (void)hipFree(c->dred);
+  if (c->cpart) (void)hipFree(c->cpart);
   if (c->flag) (void)hipFree(c->flag);
   if (c->hbuf) (void)hipHostFree(c->hbuf);
   if (c->st) (void)hipStreamDestroy(c->st);

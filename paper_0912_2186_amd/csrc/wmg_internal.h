@@ -174,6 +174,8 @@ void red_free(Reducer &r);
 // out[rhs*stride + 0..1] = <x,y> (re, im)
 int dot(Reducer &R, int prec, const void *x, const void *y, long n, int nrhs, double *out, int out_stride, hipStream_t st);
 int norm2(Reducer &R, int prec, const void *x, long n, int nrhs, double *out, int out_stride, hipStream_t st);
+// out[rhs * out_stride] = sum_b part[rhs * nblk + b], fixed order (one workgroup per rhs)
+int sum_partials(const double *part, long nblk, int nrhs, double *out, int out_stride, hipStream_t st);
 // out[rhs*stride+0..1] = <x,y>, out[rhs*stride+2] = |x|^2
 int dot_norm(Reducer &R, int prec, const void *x, const void *y, long n, int nrhs, double *out, int out_stride,
              hipStream_t st);
@@ -240,7 +242,10 @@ int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, 
 // (site, direction) block (its largest |entry|); FP32 arithmetic
 int coarse_to_mfma16(long Vc, int n, const double2 *Y64, __half *Yh, float *Ysc, hipStream_t st);
 size_t coarse_mfma_halfs(long Vc, int n);
+// With npart != nullptr the kernels that support it (n = 32, 40, 48, 64) also
+// write |out|^2 of every (rhs, site) to npart[rhs * Vc + site] and set
+// *fused (sum them with sum_partials); otherwise *fused = false.
 int coarse_apply_mfma16(const Geom &gc, int n, const __half *Yh, const float *Ysc, const float2 *in, float2 *out,
-                        int dagger, int nrhs, hipStream_t st);
+                        int dagger, int nrhs, hipStream_t st, double *npart = nullptr, bool *fused = nullptr);
 
 }  // namespace wmg
