@@ -477,74 +477,97 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, cons
 // as two real GEMMs with the right-hand sides as rows (M = R), the elements
 // as columns and K = 2 Nv:
 //   Fr = [Cr | Ci] [Pr; -Pi],   Fi = [Cr | Ci] [Pi; Pr].
-// The coarse values [Cr | Ci] of the block (both chiralities) are staged in
-// LDS once; each lane loads the P entries of its element column straight
-// from HBM (one FP16 complex per alpha, with its per-site scale) and forms
-// both B operands from them.  A lane's results are (re, im) pairs of 16
-// consecutive elements, i.e. x-runs of the block, per rhs.
-template <int NV>
+// The coarse values [Cr | Ci] of the aggregate are staged in LDS one
+// chirality at a time; each lane loads the P entries of its element column
+// straight from HBM (one FP16 complex per alpha, with its per-site scale)
+// and forms both B operands from them.  A lane's results are (re, im) pairs
+// of 16 consecutive elements, i.e. x-runs of 4 sites, per rhs.  A workgroup
+// takes G aggregates adjacent in x, one wave each, which walk their element
+// tiles in step: with 4-site x-runs and G = 4, the four partial writes to
+// each 128-byte line of the output come from one workgroup at about the
+// same time and merge in L2 before the line is written back.
+template <int NV, int G>
 __global__ void __launch_bounds__(TB) k_prolong_mfma(BlockGeom bg, const __half2 *__restrict__ P,
                                                     const float *__restrict__ Pscale, const float2 *__restrict__ coarse,
                                                     float2 *__restrict__ fine, int nrhs) {
   constexpr int Q = NV / 4;        // k-steps per half of K = 2 NV
   constexpr int LDA = 2 * NV + 4;  // LDS row stride of [Cr | Ci]
-  __shared__ float Ac[2][32 * LDA];
+  constexpr int NW = TB / 64;      // waves
+  __shared__ float Ac[G == 4 ? NW : 1][32 * LDA];  // per aggregate: [Cr | Ci] of one chirality
   __shared__ int soff[256];
-  long xh = xcd_tile(blockIdx.x, gridDim.x);
-  if (xh >= bg.Vc) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, krow = lane >> 4;
+  // G = 4: wave w takes aggregate 4 g + w (x-adjacent); G = 1: one aggregate
+  // per workgroup, its element tiles spread over the waves
+  const long grp = xcd_tile(blockIdx.x, gridDim.x);
+  const long xh = G == 4 ? grp * 4 + w : grp;
+  const long ngrp = G == 4 ? bg.Vc / 4 : bg.Vc;
+  if (grp >= ngrp) return;
+  for (int k = threadIdx.x; k < bg.bs; k += TB) soff[k] = (int)(block_site(bg, 0, k) - block_site(bg, 0, 0));
   const long origin = block_site(bg, xh, 0);
-  for (int k = threadIdx.x; k < bg.bs; k += TB) soff[k] = (int)(block_site(bg, xh, k) - origin);
   const int r0 = blockIdx.y * 32;
   const int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
   const int NTr = (R + 15) / 16;
-  for (int i = threadIdx.x; i < 2 * 32 * NV; i += TB) {
-    const int chi = i / (32 * NV), r = (i / NV) % 32, a = i % NV;
-    float2 v = make_float2(0.f, 0.f);
-    if (r < R) v = coarse[((size_t)(r0 + r) * bg.Vc + xh) * (2 * NV) + chi * NV + a];
-    Ac[chi][r * LDA + a] = v.x;
-    Ac[chi][r * LDA + NV + a] = v.y;
-  }
-  __syncthreads();
   const int E = bg.bs * 12, H = bg.bs * 6, nt_el = H / 16;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, krow = lane >> 4;
-  for (int t = w; t < 2 * nt_el; t += TB / 64) {
-    const int chi = t / nt_el, e0 = chi * H + (t % nt_el) * 16;
-    const int c = e0 / bg.bs, k0 = e0 % bg.bs;  // 16 elements inside one component (bs % 16 == 0)
-    // P entries alpha = 4 ks + krow of element e0 + col
-    float pr[Q], pi[Q];
-#pragma unroll
-    for (int ks = 0; ks < Q; ks++) {
-      const int a = 4 * ks + krow;
-      const size_t pa = (size_t)a * bg.Vc + xh;
-      const float2 pv = __half22float2(P[pa * E + e0 + col]);
-      const float sc = Pscale[pa * bg.bs + k0 + col];
-      pr[ks] = sc * pv.x;
-      pi[ks] = sc * pv.y;
-    }
-    floatx4 fr[2], fi[2];
-#pragma unroll
-    for (int m = 0; m < 2; m++) fr[m] = fi[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int m = 0; m < 2; m++) {
-      if (m >= NTr) break;
-      const float *ar = Ac[chi] + (m * 16 + col) * LDA + krow;
-#pragma unroll
-      for (int ks = 0; ks < 2 * Q; ks++) {
-        const float a = ar[4 * ks];
-        const float b1 = ks < Q ? pr[ks] : -pi[ks - Q];
-        const float b2 = ks < Q ? pi[ks] : pr[ks - Q];
-        fr[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, fr[m], 0, 0, 0);
-        fi[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b2, fi[m], 0, 0, 0);
+  float *A = Ac[G == 4 ? w : 0];
+  for (int chi = 0; chi < 2; chi++) {
+    __syncthreads();  // previous chirality's tiles done
+    if (G == 4) {
+      for (int i = lane; i < 32 * NV; i += 64) {
+        const int r = i / NV, a = i % NV;
+        float2 v = make_float2(0.f, 0.f);
+        if (r < R) v = coarse[((size_t)(r0 + r) * bg.Vc + xh) * (2 * NV) + chi * NV + a];
+        A[r * LDA + a] = v.x;
+        A[r * LDA + NV + a] = v.y;
+      }
+    } else {
+      for (int i = threadIdx.x; i < 32 * NV; i += TB) {
+        const int r = i / NV, a = i % NV;
+        float2 v = make_float2(0.f, 0.f);
+        if (r < R) v = coarse[((size_t)(r0 + r) * bg.Vc + xh) * (2 * NV) + chi * NV + a];
+        A[r * LDA + a] = v.x;
+        A[r * LDA + NV + a] = v.y;
       }
     }
-    const long site = origin + soff[k0 + col];
+    __syncthreads();
+    for (int t = G == 4 ? 0 : w; t < nt_el; t += G == 4 ? 1 : NW) {
+      const int e0 = chi * H + t * 16;
+      const int c = e0 / bg.bs, k0 = e0 % bg.bs;  // 16 elements inside one component (bs % 16 == 0)
+      // P entries alpha = 4 ks + krow of element e0 + col
+      float pr[Q], pi[Q];
 #pragma unroll
-    for (int m = 0; m < 2; m++) {
-      if (m >= NTr) break;
+      for (int ks = 0; ks < Q; ks++) {
+        const int a = 4 * ks + krow;
+        const size_t pa = (size_t)a * bg.Vc + xh;
+        const float2 pv = __half22float2(P[pa * E + e0 + col]);
+        const float sc = Pscale[pa * bg.bs + k0 + col];
+        pr[ks] = sc * pv.x;
+        pi[ks] = sc * pv.y;
+      }
+      floatx4 fr[2], fi[2];
 #pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int r = m * 16 + 4 * krow + v;
-        if (r < R) fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + site] = make_float2(fr[m][v], fi[m][v]);
+      for (int m = 0; m < 2; m++) fr[m] = fi[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int m = 0; m < 2; m++) {
+        if (m >= NTr) break;
+        const float *ar = A + (m * 16 + col) * LDA + krow;
+#pragma unroll
+        for (int ks = 0; ks < 2 * Q; ks++) {
+          const float a = ar[4 * ks];
+          const float b1 = ks < Q ? pr[ks] : -pi[ks - Q];
+          const float b2 = ks < Q ? pi[ks] : pr[ks - Q];
+          fr[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, fr[m], 0, 0, 0);
+          fi[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b2, fi[m], 0, 0, 0);
+        }
+      }
+      const long site = origin + soff[k0 + col];
+#pragma unroll
+      for (int m = 0; m < 2; m++) {
+        if (m >= NTr) break;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int r = m * 16 + 4 * krow + v;
+          if (r < R) fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + site] = make_float2(fr[m][v], fi[m][v]);
+        }
       }
     }
   }
@@ -585,11 +608,18 @@ static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int
   }
   if (dir == 1 && fine_soa && pprec == P16 && vprec == P32 && nv % 4 == 0 && nv <= 32 && bg.bs % 16 == 0 &&
       bg.bs <= 256) {
-    dim3 grid((unsigned)xcd_grid(bg.Vc), (nrhs + 31) / 32);
+    // four x-adjacent aggregates per workgroup when their 4-site x-runs
+    // tile 128-byte lines
+    const bool g4 = bg.b[0] == 4 && bg.Lc[0] % 4 == 0;
+    dim3 grid((unsigned)xcd_grid(g4 ? bg.Vc / 4 : bg.Vc), (nrhs + 31) / 32);
 #define PM_CASE(N)                                                                                           \
   if (nv == N) {                                                                                            \
-    hipLaunchKernelGGL(k_prolong_mfma<N>, grid, dim3(TB), 0, st, bg, (const __half2 *)P, Ps,               \
-                       (const float2 *)in, (float2 *)out, nrhs);                                            \
+    if (g4)                                                                                                 \
+      hipLaunchKernelGGL((k_prolong_mfma<N, 4>), grid, dim3(TB), 0, st, bg, (const __half2 *)P, Ps,         \
+                         (const float2 *)in, (float2 *)out, nrhs);                                          \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_prolong_mfma<N, 1>), grid, dim3(TB), 0, st, bg, (const __half2 *)P, Ps,         \
+                         (const float2 *)in, (float2 *)out, nrhs);                                          \
     WMG_HIP(hipGetLastError());                                                                             \
     return 0;                                                                                               \
   }
