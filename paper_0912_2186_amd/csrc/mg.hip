@@ -653,7 +653,8 @@ static int cgnr(wmg_ctx *c, int l, int prec, const void *b, void *x, int nrhs) {
 // ------------------------------------------------------------ cycle
 // e = M_l r: restrict, coarse correction (CGNR at the coarsest level, else
 // one or two recursive cycles), prolong, post-smooth (no pre-smoothing).
-static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int nrhs) {
+// rn2: |r|^2 per rhs (device, stride 4) when the caller already has it
+static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int nrhs, const double *rn2 = nullptr) {
   Level &C = c->lv[l + 1];
   void *rc, *ec;
   TRY(level_vec(c, l + 1, prec, VR, &rc, nrhs));
@@ -663,7 +664,13 @@ static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int n
   // solver absorbs)
   const bool h16 = l == 0 && prec == P32 && c->lv[0].fine && c->p.post_smooth >= 1 && c->p.post_smooth <= 4 &&
                    nrhs <= 64;
-  if (h16) TRY(norm2(c->red, P32, r, c->lv[0].n, nrhs, c->cyc_nrm, 4, c->st));
+  if (h16) {
+    if (rn2)
+      WMG_HIP(hipMemcpyAsync(c->cyc_nrm, rn2, sizeof(double) * (4 * (size_t)(nrhs - 1) + 1), hipMemcpyDeviceToDevice,
+                             c->st));
+    else
+      TRY(norm2(c->red, P32, r, c->lv[0].n, nrhs, c->cyc_nrm, 4, c->st));
+  }
   TRY(transfer_restrict(c, l, prec, r, rc, nrhs));
   if (h16) TRY(scale_inv_sqrt(P32, rc, c->cyc_nrm, 4, C.n, nrhs, c->st));
   if (l + 1 == c->nl_cur - 1) {
@@ -809,7 +816,9 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
       WMG_HIP(hipMemcpyAsync(c->mask, hm, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
       void *z = B.z[k], *w = B.wv[k];
       if (precond == 1) {
-        TRY(mg_cycle_l(c, l, ip, B.rin, z, nrhs));
+        // |r_in|^2 is at hand: from the last reliable update (k = 0) or
+        // from the previous step's r_in update
+        TRY(mg_cycle_l(c, l, ip, B.rin, z, nrhs, c->red_out + (k == 0 ? roff : 0)));
       } else {
         TRY(zero(ip, z, n, nrhs, st));
         TRY(mr_smooth(c, l, ip, B.rin, z, c->p.post_smooth, nrhs));
