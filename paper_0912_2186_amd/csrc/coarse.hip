@@ -866,8 +866,8 @@ static int coarse_apply_mfma_any(const Geom &gc, int n, const float *Ym, const _
 }
 
 int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, float2 *out, int dagger, int nrhs,
-                      hipStream_t st) {
-  return coarse_apply_mfma_any(gc, n, Ym, nullptr, nullptr, in, out, dagger, nrhs, st);
+                      hipStream_t st, double *npart, bool *fused) {
+  return coarse_apply_mfma_any(gc, n, Ym, nullptr, nullptr, in, out, dagger, nrhs, st, npart, fused);
 }
 
 int coarse_apply_mfma16(const Geom &gc, int n, const __half *Yh, const float *Ysc, const float2 *in, float2 *out,

@@ -430,12 +430,12 @@ static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int 
   int rc;
   bool fused = false;
   double *npart = nullptr;
-  if (nrm_out && prec == P32 && L.Ymh) TRY(cpart_get(c, (size_t)nrhs * L.g.V, &npart));
+  if (nrm_out && prec == P32 && (L.Ymh || L.Ym)) TRY(cpart_get(c, (size_t)nrhs * L.g.V, &npart));
   if (prec == P32 && L.Ymh)
     rc = coarse_apply_mfma16(L.g, n, L.Ymh, L.Ymsc, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st, npart,
                              &fused);
   else if (prec == P32 && L.Ym)
-    rc = coarse_apply_mfma(L.g, n, L.Ym, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st);
+    rc = coarse_apply_mfma(L.g, n, L.Ym, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st, npart, &fused);
   else
     rc = coarse_apply(L.g, n, prec, prec == P64 ? (const void *)L.Y64 : (const void *)L.Y32, prec, in, out, dagger,
                       nrhs, c->st);

@@ -237,14 +237,15 @@ int coarse_transpose(long nblk, int n, const double2 *a, double2 *b, hipStream_t
 int coarse_to_mfma(long Vc, int n, const double2 *Y64, float *Ym, hipStream_t st);
 size_t coarse_mfma_floats(long Vc, int n);
 int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, float2 *out, int dagger, int nrhs,
-                      hipStream_t st);
+                      hipStream_t st, double *npart = nullptr, bool *fused = nullptr);
 // the same stencil with the swizzled links stored in FP16, one FP32 scale per
 // (site, direction) block (its largest |entry|); FP32 arithmetic
 int coarse_to_mfma16(long Vc, int n, const double2 *Y64, __half *Yh, float *Ysc, hipStream_t st);
 size_t coarse_mfma_halfs(long Vc, int n);
 // With npart != nullptr the kernels that support it (n = 32, 40, 48, 64) also
 // write |out|^2 of every (rhs, site) to npart[rhs * Vc + site] and set
-// *fused (sum them with sum_partials); otherwise *fused = false.
+// *fused (sum them with sum_partials); otherwise *fused = false.  The same
+// holds for coarse_apply_mfma above.
 int coarse_apply_mfma16(const Geom &gc, int n, const __half *Yh, const float *Ysc, const float2 *in, float2 *out,
                         int dagger, int nrhs, hipStream_t st, double *npart = nullptr, bool *fused = nullptr);
 

@@ -329,18 +329,22 @@ def test_fp64_solve_given_vectors_iteration_parity(wmg):
     assert relerr(xg, xo) < 1e-7
 
 
-def test_mixed_precision_multi_rhs_solve(wmg):
+@pytest.mark.parametrize("nv,fp32_coarse", [(8, False), (24, False), (24, True)])
+def test_mixed_precision_multi_rhs_solve(wmg, nv, fp32_coarse):
     """FP64 outer GCR with reliable updates around the FP32 cycle on FP16
     links and null vectors: every rhs reaches 1e-10 in FP64 (oracle's D),
-    and the batched solve matches single-rhs solves."""
+    and the batched solve matches single-rhs solves.  Nv = 24 runs the
+    coarse stencil whose epilogue also forms the CGNR norms, with FP16 and
+    with FP32 coarse links."""
     L = (8, 8, 8, 16)
     V = vol(L)
-    say("mixed multi-rhs", L)
+    say("mixed multi-rhs", L, nv, "fp32 coarse links" if fp32_coarse else "")
     U = inputs.gauge_field(L, 0.5, 305)
     m = -0.2
     nrhs = 3
-    p = wmg.default_params(setup_iters=6, seed=9, precision=wmg.WMG_MIXED, nrhs_max=nrhs, coarse_tol=1e-5)
-    mg = wmg.MG(L, dev(U), m, 8, (4, 4, 4, 4), p)
+    p = wmg.default_params(setup_iters=6, seed=9, precision=wmg.WMG_MIXED, nrhs_max=nrhs, coarse_tol=1e-5,
+                           flags=wmg.WMG_COARSE_FP32 if fp32_coarse else 0)
+    mg = wmg.MG(L, dev(U), m, nv, (4, 4, 4, 4), p)
     b = np.concatenate([inputs.point_sources(L)[:1], inputs.z4_noise(L, 51, 1), inputs.gaussian_rhs(L, 52)])
     x = empty((nrhs, V, 12))
     st = mg.mg_solve(dev(b), x, 1e-10)
