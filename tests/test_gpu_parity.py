@@ -362,6 +362,36 @@ def test_mixed_precision_multi_rhs_solve(wmg, nv, fp32_coarse):
         assert relerr(host(x1)[0], xh[r]) < 1e-8
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_initial_guess(wmg, mixed):
+    """WMG_X0_GIVEN: a solve to 1e-4, continued from its result to 1e-10,
+    meets the oracle's 1e-10 with fewer outer iterations than a solve from
+    zero; the first residual of a continued solve is the FP64 b - D x."""
+    L = (8, 8, 8, 16)
+    V = vol(L)
+    say("initial guess", L, "mixed" if mixed else "fp64")
+    U = inputs.gauge_field(L, 0.5, 306)
+    m = -0.2
+    nrhs = 2
+    p = wmg.default_params(setup_iters=6, seed=11, nrhs_max=nrhs, precision=wmg.WMG_MIXED if mixed else wmg.WMG_FP64,
+                           coarse_tol=1e-5 if mixed else 1e-8, flags=wmg.WMG_X0_GIVEN)
+    mg = wmg.MG(L, dev(U), m, 8, (4, 4, 4, 4), p)
+    b = inputs.gaussian_rhs(L, 61, nrhs)
+    bd = dev(b)
+    x = empty((nrhs, V, 12))
+    st1 = mg.mg_solve(bd, x, 1e-4)
+    st2 = mg.mg_solve(bd, x, 1e-10)
+    x0 = empty((nrhs, V, 12))
+    st0 = mg.mg_solve(bd, x0, 1e-10)
+    say("  loose", st1["outer_iters"], "continued", st2["outer_iters"], "from zero", st0["outer_iters"])
+    assert st1["converged"] and st2["converged"] and st0["converged"]
+    assert st2["outer_iters"] < st0["outer_iters"]
+    xh = host(x)
+    for r in range(nrhs):
+        res = np.linalg.norm(b[r] - oracle.wilson(L, U, m, xh[r])) / np.linalg.norm(b[r])
+        assert res <= 1e-10 * 1.0001, (r, res)
+
+
 def test_three_level_w_cycle_mixed(wmg):
     L = (8, 8, 8, 16)
     V = vol(L)
