@@ -392,6 +392,30 @@ def test_initial_guess(wmg, mixed):
         assert res <= 1e-10 * 1.0001, (r, res)
 
 
+def test_mixed_solve_two_rhs_tiles(wmg):
+    """40 right-hand sides in one mixed solve (two tiles of at most 32 in the
+    coarse stencil, restriction and prolongation; Nv = 24): every rhs
+    converged, the oracle's FP64 residual of a sample below 1e-10."""
+    L = (8, 8, 8, 16)
+    V = vol(L)
+    nrhs = 40
+    say("mixed solve, two rhs tiles", L, nrhs)
+    U = inputs.gauge_field(L, 0.5, 307)
+    m = -0.2
+    p = wmg.default_params(setup_iters=6, seed=13, precision=wmg.WMG_MIXED, nrhs_max=nrhs, coarse_tol=1e-5)
+    mg = wmg.MG(L, dev(U), m, 24, (4, 4, 4, 4), p)
+    b = np.concatenate([inputs.point_sources(L), inputs.gaussian_rhs(L, 71, nrhs - 12)])
+    x = empty((nrhs, V, 12))
+    st = mg.mg_solve(dev(b), x, 1e-10)
+    its = mg.mg_last_iters(nrhs)
+    say("  ", st, its)
+    assert st["converged"] and st["true_relres"] <= 1e-10
+    xh = host(x)
+    for r in (0, 11, 31, 32, 39):
+        res = np.linalg.norm(b[r] - oracle.wilson(L, U, m, xh[r])) / np.linalg.norm(b[r])
+        assert res <= 1e-10 * 1.0001, (r, res)
+
+
 def test_three_level_w_cycle_mixed(wmg):
     L = (8, 8, 8, 16)
     V = vol(L)
