@@ -204,7 +204,7 @@ def main():
                          "lattice, or only a 1 GiB device copy (bytes reference for the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (lattice domain decomposition is designed, not built).",
               file=sys.stderr)
         sys.exit(2)
 
