@@ -26,8 +26,11 @@
  *
  * Parity pins: every function here is checked by tests against closed forms,
  * invariants, brute-force dense linear algebra or library routines (see the
- * oracle tests).  Setup null-vector quality is "parity unpinned": it is a
- * random, iterative heuristic; only its invariants are checked.
+ * oracle tests): the cycle against the dense coarse-grid correction and its
+ * smoothed and three-level (V, W) forms, the adaptive setup against the
+ * near-null space of a dense singular value decomposition.  The setup's
+ * vectors themselves are random and iterative: no two correct setups agree
+ * vector by vector, so only these properties are pinned.
  */
 #include <complex.h>
 #include <math.h>
@@ -546,6 +549,8 @@ typedef struct {
     orc_op op;
     cplx *Ybuf;  /* owned coarse links */
     cplx *P;     /* [nv][nsite][dof] prolongator to the next level */
+    cplx *vecs;  /* [nv][nsite][dof] adapted null vectors before block
+                    orthonormalisation (kept after the setup for inspection) */
     int nv;
     int b[4];
     long n;      /* nsite * dof */
@@ -768,6 +773,7 @@ orc_mg *orc_mg_create(const int L[4], const double *U, double m, const orc_mg_pa
         memcpy(A->b, p->block[l], sizeof(int) * 4);
         A->nv = p->nv[l];
         A->P = valloc((long)A->nv * A->n);
+        A->vecs = valloc((long)A->nv * A->n);
         lvl_set_op(g, l);
         C->Ybuf = valloc(C->op.nsite * 9L * C->op.dof * C->op.dof);
         C->op.Y = C->Ybuf;
@@ -778,7 +784,7 @@ orc_mg *orc_mg_create(const int L[4], const double *U, double m, const orc_mg_pa
 void orc_mg_free(orc_mg *g)
 {
     if (!g) return;
-    for (int l = 0; l < 3; l++) { free(g->lv[l].P); free(g->lv[l].Ybuf); }
+    for (int l = 0; l < 3; l++) { free(g->lv[l].P); free(g->lv[l].vecs); free(g->lv[l].Ybuf); }
     free(g->U);
     free(g);
 }
@@ -812,6 +818,7 @@ static int setup_level(orc_mg *g, int l, orc_stats *st)
     F->nv = nv;
     if (!rc) rc = build_level(g, l, vecs, nv);
     g->nl = save_nl;
+    memcpy(F->vecs, vecs, sizeof(cplx) * (size_t)nv * n);
     free(vecs);
     free(zero);
     (void)st;
@@ -830,7 +837,15 @@ int orc_mg_setup(orc_mg *g)
 /* install given null vectors at level l (and rebuild P_l and level l+1) */
 int orc_mg_set_null_vectors(orc_mg *g, int l, const double *vecs)
 {
+    memcpy(g->lv[l].vecs, vecs, sizeof(cplx) * (size_t)g->lv[l].nv * g->lv[l].n);
     return build_level(g, l, (const cplx *)vecs, g->lv[l].nv);
+}
+
+/* the null vectors of level l as the setup left them (normalised, before
+ * the chirality split and block orthonormalisation) */
+void orc_mg_get_null_vectors(orc_mg *g, int l, double *out)
+{
+    memcpy(out, g->lv[l].vecs, sizeof(cplx) * (size_t)g->lv[l].nv * g->lv[l].n);
 }
 
 /* exact coarse mass shift: D_hat(m) = D_hat(m0) + (m - m0) 1, since
