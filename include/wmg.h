@@ -143,8 +143,14 @@ int bicgstab_solve(const wmg_geom *g, const double *U, double m, const double *b
                    wmg_stats *st);
 
 /* ---- uneven batch (Sec. 4: one API over several lattices) ------------ */
-/* n independent instances with their own lattice, links and mass, the same
- * Nv/block/params; solved back to back on the context's stream. */
+/* n (1..256) independent instances with their own lattice, links and mass,
+ * the same Nv/block/params.  Each instance gets its own context (own HIP
+ * stream and buffers); mg_setup_batch and mg_solve_batch drive the
+ * instances from one host thread each, so their kernels run concurrently on
+ * the device.  mg_solve_batch takes one rhs per instance (b[i], x[i] device
+ * pointers of instance i's size) and fills st[i] (st may be NULL); it
+ * returns the first negative error of any instance, else WMG_ENOTCONV if
+ * any instance did not converge, else 0. */
 int mg_setup_batch(int n, const wmg_geom *g, const double *const *U, const double *m, int Nv, const int block[4],
                    const wmg_params *p, wmg_ctx **out);
 int mg_solve_batch(wmg_ctx *ctx, const double *const *b, double *const *x, double tol, wmg_stats *st);

@@ -125,6 +125,11 @@ def num_threads() -> int:
     return int(_lib.orc_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops from now on (timing only)."""
+    _lib.orc_set_num_threads(ctypes.c_int(int(n)))
+
+
 def gamma(mu: int) -> np.ndarray:
     out = np.zeros((4, 4), np.complex128)
     _lib.orc_gamma(ctypes.c_int(mu), _p(out))

@@ -955,6 +955,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* thread count of the following parallel regions (timing of the oracle) */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* standalone CGNR on a coarse stencil (for the oracle's own pins) */
 long orc_cgnr_coarse(const int L[4], int dof, const double *Y, const double *b, double *x, double tol, int maxiter)
 {

@@ -13,6 +13,8 @@
 //
 // Internal link layout (for coalesced apply): [Vc][9][col][row], i.e. the
 // element (row, col) of block d of site xh sits at ((xh*9+d)*n + col)*n + row.
+#include <mutex>
+
 #include "wmg_internal.h"
 
 namespace wmg {
@@ -251,10 +253,11 @@ __global__ void __launch_bounds__(TB) k_build_coarse(CGeom g, const double2 *__r
   }
 }
 
-static bool gamma_uploaded = false;
-static int upload_gamma() {
-  if (gamma_uploaded) return 0;
-  // chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = [[0,1],[1,0]]
+// The gamma table is uploaded once per process (std::call_once: concurrent
+// setups of a batch may reach this together).
+static std::once_flag gamma_once;
+static int gamma_status = 0;
+static int upload_gamma_once() {  // chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = [[0,1],[1,0]]
   double2 G[4][4][4];
   for (int mu = 0; mu < 4; mu++)
     for (int i = 0; i < 4; i++)
@@ -274,8 +277,11 @@ static int upload_gamma() {
     G[3][2 + i][i] = make_double2(1, 0);
   }
   WMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gamma), G, sizeof(G)));
-  gamma_uploaded = true;
   return 0;
+}
+static int upload_gamma() {
+  std::call_once(gamma_once, [] { gamma_status = upload_gamma_once(); });
+  return gamma_status;
 }
 
 int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf, const int b[4],
