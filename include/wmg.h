@@ -142,6 +142,25 @@ const char *wmg_strerror(int code);
 int bicgstab_solve(const wmg_geom *g, const double *U, double m, const double *b, double *x, double tol, int maxiter,
                    wmg_stats *st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * BiCGStab solve as bicgstab_solve, with every work buffer (SoA links, eight
+ * fine vectors, device scalars, reduction partials) placed in one fixed
+ * device array of WMG_NOALLOC_SCRATCH_BYTES inside the library, one copy per
+ * GPU, held until the process ends.  Needs about 2112 * (V + 384) + 262656
+ * bytes, so lattices up to about 15,400 sites fit (8^4, 8^3 x 16, 12^3 x 8);
+ * larger ones return WMG_EINVAL with the sizes in the message.  It calls no
+ * hipMalloc, hipFree or host-pinning routine.  Work runs on hip_stream (NULL
+ * = the default stream), which the call synchronises at every scalar
+ * read-back and before it returns.  All calls on one GPU share that GPU's
+ * array: calls that overlap in time on the same GPU (from several host
+ * threads, or on several streams) race and give wrong results.  The array
+ * keeps the previous call's contents; the call clears what it needs with a
+ * fill kernel first. */
+#define WMG_NOALLOC_SCRATCH_BYTES (32u << 20)
+int bicgstab_solve_noalloc(const wmg_geom *g, const double *U, double m, const double *b, double *x, double tol,
+                           int maxiter, wmg_stats *st, void *hip_stream);
+
 /* ---- uneven batch (Sec. 4: one API over several lattices) ------------ */
 /* n (1..256) independent instances with their own lattice, links and mass,
  * the same Nv/block/params.  Each instance gets its own context (own HIP

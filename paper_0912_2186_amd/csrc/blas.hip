@@ -20,13 +20,23 @@ static constexpr int RSLOT = 32;    // doubles per partial slot
 int red_init(Reducer &r, int nrhs_max) {
   r.maxblk = RMAXBLK;
   r.nrhs_max = nrhs_max;
-  WMG_HIP(hipMalloc(&r.partial, sizeof(double) * RSLOT * RMAXBLK * (size_t)nrhs_max));
+  r.owned = true;
+  WMG_HIP(hipMalloc(&r.partial, red_bytes(nrhs_max)));
   return 0;
 }
 
 void red_free(Reducer &r) {
-  if (r.partial) (void)hipFree(r.partial);
+  if (r.partial && r.owned) (void)hipFree(r.partial);
   r.partial = nullptr;
+}
+
+size_t red_bytes(int nrhs_max) { return sizeof(double) * RSLOT * RMAXBLK * (size_t)nrhs_max; }
+
+void red_attach(Reducer &r, int nrhs_max, double *partial) {
+  r.maxblk = RMAXBLK;
+  r.nrhs_max = nrhs_max;
+  r.partial = partial;
+  r.owned = false;
 }
 
 // workgroups per rhs of a reduction over np packs (two packs per thread at

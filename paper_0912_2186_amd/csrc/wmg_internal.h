@@ -168,9 +168,14 @@ struct Reducer {
   double *partial;  // [nrhs][maxblk][32] per-workgroup partial sums
   int maxblk;
   int nrhs_max;
+  bool owned;       // partial was allocated by red_init (freed by red_free)
 };
 int red_init(Reducer &r, int nrhs_max);
 void red_free(Reducer &r);
+// bytes of partials for nrhs_max right-hand sides; red_attach uses memory the
+// caller owns (red_free then leaves it alone)
+size_t red_bytes(int nrhs_max);
+void red_attach(Reducer &r, int nrhs_max, double *partial);
 // out[rhs*stride + 0..1] = <x,y> (re, im)
 int dot(Reducer &R, int prec, const void *x, const void *y, long n, int nrhs, double *out, int out_stride, hipStream_t st);
 int norm2(Reducer &R, int prec, const void *x, long n, int nrhs, double *out, int out_stride, hipStream_t st);

@@ -96,6 +96,7 @@ _sig = {
     "mg_set_precision": (_i, [_vp, _i]),
     "mg_destroy": (_i, [_vp]),
     "bicgstab_solve": (_i, [_P(Geom), _vp, _d, _vp, _vp, _d, _i, _P(Stats)]),
+    "bicgstab_solve_noalloc": (_i, [_P(Geom), _vp, _d, _vp, _vp, _d, _i, _P(Stats), _vp]),
     "mg_setup_batch": (_i, [_i, _P(Geom), _P(_vp), _P(_d), _i, _P(ctypes.c_int * 4), _P(Params), _P(_vp)]),
     "mg_solve_batch": (_i, [_vp, _P(_vp), _P(_vp), _d, _P(Stats)]),
     "mg_level_info": (_i, [_vp, _i, _P(ctypes.c_int * 4), _P(_i), _P(_i)]),
@@ -178,6 +179,16 @@ def bicgstab_solve(L, U, m, b, x, tol, maxiter=100000):
     st = Stats()
     rc = _lib.bicgstab_solve(ctypes.byref(_geom(L)), _ptr(U), float(m), _ptr(b), _ptr(x), float(tol), int(maxiter),
                              ctypes.byref(st))
+    _check(rc, allow_notconv=True)
+    return st.as_dict()
+
+
+def bicgstab_solve_noalloc(L, U, m, b, x, tol, maxiter=100000, stream=None):
+    """The allocation-free variant (work buffers in the library's fixed
+    device array); runs on `stream` (default: torch's current stream)."""
+    st = Stats()
+    rc = _lib.bicgstab_solve_noalloc(ctypes.byref(_geom(L)), _ptr(U), float(m), _ptr(b), _ptr(x), float(tol),
+                                     int(maxiter), ctypes.byref(st), _stream_ptr(stream))
     _check(rc, allow_notconv=True)
     return st.as_dict()
 

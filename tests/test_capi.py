@@ -90,3 +90,19 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_noalloc_rejects_sizes_beyond_its_array(lib):
+    # host-side size check of the allocation-free entry point: returns
+    # EINVAL before any device work (fake non-null pointers are never touched)
+    f = lib.bicgstab_solve_noalloc
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.POINTER(Geom), ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    g = Geom()
+    g.L[:] = [16, 16, 16, 8]
+    assert f(ctypes.byref(g), 8, -0.1, 16, 32, 1e-10, 100, None, None) == -1
+    lib.wmg_strerror.restype = ctypes.c_char_p
+    assert b"fixed maximum" in lib.wmg_strerror(-1)
+    g.L[:] = [8, 8, 8, 8]
+    assert f(ctypes.byref(g), None, -0.1, 16, 32, 1e-10, 100, None, None) == -1
