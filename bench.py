@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-RHS comparison solve")
     ap.add_argument("--delta", type=float, default=None, help="reliable-update threshold (default: library's)")
     ap.add_argument("--coarse-tol", type=float, default=None, help="coarsest CGNR tolerance (mixed default 1e-5)")
+    ap.add_argument("--smoother", choices=["redblack", "mr"], default="redblack",
+                    help="fine-level post-smoother: MR on the red/black Schur complement (default) or MR on D")
     ap.add_argument("--levels", type=int, choices=[2, 3], default=2,
                     help="multigrid levels of the critical-mass scan (3: 4^4 then 2^4 aggregates, N_nu 24 / 32)")
     ap.add_argument("--only", choices=["dslash", "copy"], default=None,
@@ -301,7 +303,8 @@ def main():
     xd = torch.zeros_like(bd)
     p = wmg.default_params(setup_iters=w["setup_iters"], seed=w["seed_cfg"] * 100 + 50, nrhs_max=nrhs,
                            precision=wmg.WMG_MIXED if w["mixed"] else wmg.WMG_FP64,
-                           coarse_tol=1e-5 if w["mixed"] else 1e-8)
+                           coarse_tol=1e-5 if w["mixed"] else 1e-8,
+                           flags=wmg.WMG_EO_SMOOTHER if args.smoother == "redblack" else 0)
     if args.delta is not None:
         p.reliable_delta = args.delta
     if args.coarse_tol is not None:
@@ -418,6 +421,7 @@ def main():
         "data": "synthetic: seeded SU(3) links exp(i eps H) and seeded right-hand sides",
         "config": {"workload": args.workload, "lattice": list(L), "eps": w["eps"], "mass": w["m"], "Nv": w["nv"],
                    "block": [4, 4, 4, 4], "nrhs": nrhs, "tol": 1e-10, "levels": 2,
+                   "smoother": "MR on the red/black Schur complement" if args.smoother == "redblack" else "MR on D",
                    "outer_iters": iters[-1], "true_relres_max": relres, "setup_s": round(setup_s, 2)},
         "oracle_relres": {"rhs": sorted(orc_res), "relres": [orc_res[k] for k in sorted(orc_res)],
                           "max": max(orc_res.values()) if orc_res else None},

@@ -55,6 +55,14 @@ extern "C" {
 #define WMG_X0_GIVEN 1 /* flags: x holds the initial guess on entry to mg_solve */
 #define WMG_COARSE_FP32 2 /* flags: mixed precision keeps FP32 coarse links in the cycle
                              (default: FP16 with one FP32 scale per site and direction) */
+#define WMG_EO_SMOOTHER 8 /* flags: the fine-level post-smoother runs its MR steps on the
+                             red/black (even-odd) Schur complement S = D_ee - D_eo D_oo^-1 D_oe
+                             and solves the odd sites exactly (Sec. 3, MG combined with
+                             red/black preconditioning); every extent must be even */
+#define WMG_LINKS18 4     /* flags: the fine operator reads whole 3x3 links (18 reals); by
+                             default it reads the first two rows (12 reals, Table 2) and
+                             rebuilds the third as conj(row0 x row1) when every link of U
+                             satisfies that identity to 1e-12 (U in SU(3)) */
 
 typedef struct wmg_ctx wmg_ctx;
 
@@ -122,6 +130,28 @@ int mg_setup(const wmg_geom *g, const double *U, double m, int Nv, const int blo
  * params.flags & WMG_X0_GIVEN.  st may be NULL. */
 int mg_solve(wmg_ctx *ctx, const double *b, double *x, double tol, int nrhs, wmg_stats *st);
 
+/* ---- setup reuse (Sec. 4: amortise the setup as U evolves) ---------- */
+/* Write the context's setup -- lattice, parameters, mass and the null
+ * vectors of every level (canonical [Nv][V][dof], complex128) -- to the
+ * file `path`, followed by a checksum.  EINVAL if the file cannot be
+ * written; a batch context is rejected. */
+int mg_save(wmg_ctx *ctx, const char *path);
+/* New context from a saved setup for links U at mass m: P and the Galerkin
+ * operators are rebuilt from the saved vectors for these links (no adaptive
+ * iterations).  The lattice must be the file's; p (NULL = the saved
+ * parameters) may change solver settings (precision, tolerances, nrhs_max,
+ * flags) but not the hierarchy (levels, Nv, coarser aggregates).  EINVAL
+ * for a missing, truncated, foreign or corrupted file (checked before any
+ * device work) or a mismatch. */
+int mg_load(const char *path, const wmg_geom *g, const double *U, double m, const wmg_params *p, wmg_ctx **out);
+/* Adapt a context to new links U (e.g. the next configuration of a Monte
+ * Carlo chain): rebuild the hierarchy from the old null vectors for U, relax
+ * each vector by `iters` steps of GCR on D(U) x = 0 preconditioned with that
+ * hierarchy (starting from the vector itself), normalise, and rebuild;
+ * level by level for three levels.  iters = 0 only rebuilds.  The cost is
+ * two Galerkin builds per level against one per vector in mg_setup. */
+int mg_refresh(wmg_ctx *ctx, const double *U, int iters);
+
 /* Change the quark mass without a new setup: D_hat(m) = D_hat(m0) + (m-m0) 1
  * exactly, since P^dag P = 1 and D(m) = D(0) + m. */
 int mg_set_mass(wmg_ctx *ctx, double m);
@@ -129,6 +159,10 @@ int mg_set_mass(wmg_ctx *ctx, double m);
 /* Switch the solve precision (WMG_FP64 / WMG_MIXED) of a context without
  * a new setup; the hierarchy is always built in FP64. */
 int mg_set_precision(wmg_ctx *ctx, int precision);
+
+/* Reals per link the fine operator of the context reads: 12 (two rows,
+ * third rebuilt; SU(3) field) or 18 (whole links). */
+int mg_link_reals(wmg_ctx *ctx);
 
 /* Release the context and all its device memory. */
 int mg_destroy(wmg_ctx *ctx);
@@ -199,8 +233,15 @@ int mg_prolong_f32(wmg_ctx *ctx, int level, const double *coarse, double *fine, 
  * (matrix-core kernel for n <= 64); canonical FP64 in/out. */
 int mg_coarse_apply_f32(wmg_ctx *ctx, int level, const double *in, double *out, int dagger, int nrhs);
 /* Fine operator through the internal kernels: prec 0 FP64, 1 FP32 links and
- * spinors, 2 FP16 links with FP32 spinors; canonical FP64 in/out. */
+ * spinors, 2 FP16 links with FP32 spinors, 3 the smoother's MR-step form
+ * (in/|in| per rhs stored in FP16 by the smoother's residual kernel, FP16
+ * links on FP16 spinors, FP16 output, returned times |in|); canonical FP64
+ * in/out, nrhs <= 64. */
 int mg_apply_fine(wmg_ctx *ctx, int prec, const double *in, double *out, int nrhs);
+/* The mixed cycle's smoother residual kernel: out = r/|r| - D e per rhs,
+ * r and e rounded to FP32, FP16 links, the result stored in FP16 and
+ * returned as FP64 (canonical layouts, nrhs <= 64). */
+int mg_smoother_residual(wmg_ctx *ctx, const double *r, const double *e, double *out, int nrhs);
 /* One application of the FP64 preconditioner z = M r (one MG cycle). */
 int mg_cycle(wmg_ctx *ctx, const double *r, double *z);
 /* Per-rhs outer iteration counts of the last solve (array of nrhs ints,

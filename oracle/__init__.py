@@ -83,6 +83,7 @@ class MGParams(ctypes.Structure):
         ("coarse_maxiter", ctypes.c_int),
         ("maxiter", ctypes.c_int),
         ("seed", ctypes.c_uint64),
+        ("eo_smoother", ctypes.c_int),
     ]
 
 
@@ -108,6 +109,8 @@ _lib.orc_mg_set_null_vectors.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
 _lib.orc_mg_set_mass.argtypes = [ctypes.c_void_p, ctypes.c_double]
 _lib.orc_mg_solve.restype = ctypes.c_long
 _lib.orc_mg_solve.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.POINTER(Stats)]
+_lib.orc_mg_solve_eo.restype = ctypes.c_long
+_lib.orc_mg_solve_eo.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.POINTER(Stats)]
 _lib.orc_mg_cycle.argtypes = [ctypes.c_void_p, _dp, _dp]
 _lib.orc_mg_level_info.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -144,6 +147,36 @@ def wilson(L, U, m: float, psi) -> np.ndarray:
     assert U.size == V * 36 and psi.size == V * 12
     out = np.empty_like(psi)
     _lib.orc_wilson(_I4(*L), _p(U), ctypes.c_double(m), _p(psi), _p(out))
+    return out
+
+
+def parity(L) -> np.ndarray:
+    """Site parity (x+y+z+t) mod 2 of every site, canonical order."""
+    s = np.arange(vol(L))
+    x = s % L[0]
+    y = (s // L[0]) % L[1]
+    z = (s // (L[0] * L[1])) % L[2]
+    t = s // (L[0] * L[1] * L[2])
+    return (x + y + z + t) & 1
+
+
+def wilson_hop_parity(L, U, m: float, psi, par: int) -> np.ndarray:
+    """D_{par,1-par} psi: hopping terms at sites of parity par from psi at
+    the other parity; zero elsewhere."""
+    U = _c(U)
+    psi = _c(psi)
+    out = np.empty_like(psi)
+    _lib.orc_wilson_hop_parity(_I4(*L), _p(U), ctypes.c_double(m), _p(psi), _p(out), ctypes.c_int(par))
+    return out
+
+
+def schur_apply(L, U, m: float, psi) -> np.ndarray:
+    """S psi_e = (4+m) psi_e - D_eo D_oe psi_e / (4+m) on the even sites
+    (odd sites of psi ignored, of the result zero)."""
+    U = _c(U)
+    psi = _c(psi)
+    out = np.empty_like(psi)
+    _lib.orc_schur_apply(_I4(*L), _p(U), ctypes.c_double(m), _p(psi), _p(out))
     return out
 
 
@@ -259,6 +292,7 @@ def default_params(**kw) -> MGParams:
     p.coarse_maxiter = 500
     p.maxiter = 1000
     p.seed = 12345
+    p.eo_smoother = 0
     for k, v in kw.items():
         if k == "block":
             flat = list(v[0]) + list(v[1] if len(v) > 1 else v[0])
@@ -345,6 +379,15 @@ class MG:
         _lib.orc_mg_solve(ctypes.c_void_p(self.h), _p(b), _p(x), ctypes.c_double(tol), ctypes.byref(st))
         return x, st.as_dict()
 
+    def solve_eo(self, b, tol: float):
+        """Red/black solve: GCR on the even-site Schur complement,
+        preconditioned with the multigrid cycle of the full operator."""
+        b = _c(b)
+        x = np.zeros_like(b)
+        st = Stats()
+        _lib.orc_mg_solve_eo(ctypes.c_void_p(self.h), _p(b), _p(x), ctypes.c_double(tol), ctypes.byref(st))
+        return x, st.as_dict()
+
 
 for _name, _args in [
     ("orc_wilson", [_I4, _dp, ctypes.c_double, _dp, _dp]),
@@ -354,6 +397,8 @@ for _name, _args in [
     ("orc_prolong", [_I4, ctypes.c_int, _I4, ctypes.c_int, _dp, _dp, _dp]),
     ("orc_coarse_build", [_I4, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, _dp, _I4, ctypes.c_int, _dp, _dp]),
     ("orc_gamma", [ctypes.c_int, _dp]),
+    ("orc_wilson_hop_parity", [_I4, _dp, ctypes.c_double, _dp, _dp, ctypes.c_int]),
+    ("orc_schur_apply", [_I4, _dp, ctypes.c_double, _dp, _dp]),
     ("orc_start_vector", [ctypes.c_long, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _dp]),
 ]:
     getattr(_lib, _name).argtypes = _args

@@ -258,6 +258,66 @@ static void vzero(long n, cplx *y) { memset(y, 0, sizeof(cplx) * n); }
 static cplx *valloc(long n) { return (cplx *)calloc((size_t)(n > 0 ? n : 1), sizeof(cplx)); }
 
 /* ---------------------------------------------------------------------- */
+/* red/black (even-odd) decomposition (Sec. 3: MG combined with red/black    */
+/* preconditioning).  Sites split by parity (x+y+z+t) mod 2, and with that   */
+/* D = [[D_ee, D_eo], [D_oe, D_oo]]: the only site-local term of Eq. 2.2 is  */
+/* the (4+m) diagonal, so D_ee = D_oo = (4+m) 1, and D_eo, D_oe are the      */
+/* hopping terms between the sublattices.  With x_o eliminated, D x = b      */
+/* becomes the Schur complement system on the even sites                    */
+/*   S x_e = b_e - D_eo D_oo^-1 b_o,   S = D_ee - D_eo D_oo^-1 D_oe,         */
+/* and x_o = D_oo^-1 (b_o - D_oe x_e).  Vectors here are full length; the    */
+/* components of sites outside the parity a function works on are ignored  */
+/* on input and zero on output.                                              */
+/* ---------------------------------------------------------------------- */
+int orc_parity(const int L[4], long s)
+{
+    int x[4];
+    coords(L, s, x);
+    return (x[0] + x[1] + x[2] + x[3]) & 1;
+}
+
+/* out = D_{par, 1-par} in: the hopping terms of Eq. 2.2 at the sites of
+ * parity par, reading in at the sites of the other parity */
+void orc_wilson_hop_parity(const int L[4], const double *U, double m, const double *ind, double *outd, int par)
+{
+    orc_op A = {{L[0], L[1], L[2], L[3]}, vol(L), 12, 0, (const cplx *)U, m, NULL};
+    const cplx *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    long V = A.nsite;
+    cplx *src = valloc(V * 12);
+    for (long s = 0; s < V; s++)
+        if (orc_parity(L, s) != par) memcpy(src + 12 * s, in + 12 * s, sizeof(cplx) * 12);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        cplx *o = out + 12 * s;
+        for (int c = 0; c < 12; c++) o[c] = 0;
+        if (orc_parity(L, s) != par) continue;
+        for (int mu = 0; mu < 4; mu++) {
+            wilson_hop_add(&A, s, mu, +1, src, o);
+            wilson_hop_add(&A, s, mu, -1, src, o);
+        }
+    }
+    free(src);
+}
+
+/* out_e = S in_e = (4+m) in_e - D_eo (D_oe in_e) / (4+m) */
+void orc_schur_apply(const int L[4], const double *U, double m, const double *ind, double *outd)
+{
+    long V = vol(L), n = V * 12;
+    const cplx *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    cplx *t = valloc(n), *u = valloc(n);
+    orc_wilson_hop_parity(L, U, m, ind, (double *)t, 1);   /* t_o = D_oe in_e */
+    for (long i = 0; i < n; i++) t[i] /= (4.0 + m);         /* D_oo^-1 */
+    orc_wilson_hop_parity(L, U, m, (const double *)t, (double *)u, 0); /* u_e = D_eo t_o */
+    for (long s = 0; s < V; s++)
+        for (int c = 0; c < 12; c++)
+            out[12 * s + c] = orc_parity(L, s) == 0 ? (4.0 + m) * in[12 * s + c] - u[12 * s + c] : 0;
+    free(t);
+    free(u);
+}
+
+/* ---------------------------------------------------------------------- */
 /* public single-operator entry points                                      */
 /* ---------------------------------------------------------------------- */
 /* Eq. 2.2: out = D(U) in (full operator including the (4+m) diagonal). */
@@ -534,6 +594,7 @@ typedef struct {
     int coarse_maxiter;
     int maxiter;
     uint64_t seed;
+    int eo_smoother;  /* 1: fine-level post-smoother on the red/black Schur complement */
 } orc_mg_params;
 
 typedef struct {
@@ -588,6 +649,43 @@ static void mr_smooth(orc_mg *g, int l, const cplx *r, cplx *e, int nsteps, orc_
     }
     free(s);
     free(q);
+}
+
+/* Red/black post-smoother of the fine level (Sec. 3: MG combined with
+ * red/black preconditioning; reading: the smoother's minimal-residual steps
+ * run on the Schur complement).  With s = r - D e, the correction d solving
+ * D d = s is split into sublattices: d_e from nsteps MR steps on
+ * S d_e = s_e - D_eo D_oo^-1 s_o starting from 0, and d_o = D_oo^-1
+ * (s_o - D_oe d_e) exactly; then e += d. */
+static void mr_smooth_schur(orc_mg *g, const cplx *r, cplx *e, int nsteps, orc_stats *st)
+{
+    const orc_op *A = &g->lv[0].op;
+    const double *U = (const double *)g->U;
+    double m = A->m;
+    long V = A->nsite, n = V * 12;
+    cplx *s = valloc(n), *t = valloc(n), *be = valloc(n), *d = valloc(n), *q = valloc(n);
+    lvl_apply(g, 0, e, s, st);
+    for (long i = 0; i < n; i++) s[i] = r[i] - s[i];
+    orc_wilson_hop_parity(A->L, U, m, (const double *)s, (double *)t, 0); /* D_eo s_o */
+    for (long x = 0; x < V; x++)
+        for (int c = 0; c < 12; c++)
+            be[12 * x + c] = orc_parity(A->L, x) ? 0 : s[12 * x + c] - t[12 * x + c] / (4.0 + m);
+    /* MR on S d_e = be from d_e = 0: residual be - S d_e lives in be */
+    for (int k = 0; k < nsteps; k++) {
+        orc_schur_apply(A->L, U, m, (const double *)be, (double *)q);
+        if (st) st->fine_matvecs += 1;
+        double qq = vnorm2(n, q);
+        if (qq == 0) break;
+        cplx a = vdot(n, q, be) / qq;
+        vaxpy(n, a, be, d);
+        vaxpy(n, -a, q, be);
+    }
+    orc_wilson_hop_parity(A->L, U, m, (const double *)d, (double *)t, 1); /* D_oe d_e */
+    for (long x = 0; x < V; x++)
+        if (orc_parity(A->L, x))
+            for (int c = 0; c < 12; c++) d[12 * x + c] = (s[12 * x + c] - t[12 * x + c]) / (4.0 + m);
+    vaxpy(n, 1.0, d, e);
+    free(s); free(t); free(be); free(d); free(q);
 }
 
 /* CG on the normal equations A^dag A x = A^dag b at the coarsest level
@@ -648,14 +746,36 @@ static void mg_cycle(orc_mg *g, int l, const cplx *r, cplx *e, orc_stats *st)
         }
     }
     orc_prolong(F->op.L, F->op.dof, F->b, F->nv, (const double *)F->P, (const double *)ec, (double *)e);
-    mr_smooth(g, l, r, e, g->p.post_smooth, st);
+    if (l == 0 && g->p.eo_smoother) mr_smooth_schur(g, r, e, g->p.post_smooth, st);
+    else mr_smooth(g, l, r, e, g->p.post_smooth, st);
     free(rc);
     free(ec);
 }
 
 typedef void (*precond_fn)(orc_mg *g, int l, const cplx *r, cplx *z, orc_stats *st);
+typedef void (*apply_fn)(orc_mg *g, int l, const cplx *in, cplx *out, orc_stats *st);
 
 static void pc_cycle(orc_mg *g, int l, const cplx *r, cplx *z, orc_stats *st) { mg_cycle(g, l, r, z, st); }
+
+/* red/black: the Schur complement S on the even sites of level 0 */
+static void schur_apply_lvl(orc_mg *g, int l, const cplx *in, cplx *out, orc_stats *st)
+{
+    (void)l;
+    orc_schur_apply(g->lv[0].op.L, (const double *)g->U, g->lv[0].op.m, (const double *)in, (double *)out);
+    if (st) st->fine_matvecs += 1; /* two half-lattice hopping applies */
+}
+
+/* red/black preconditioner: [D^-1 (r_e, 0)]_e = S^-1 r_e exactly, so the
+ * multigrid cycle for D applied to (r_e, 0) and restricted to the even sites
+ * approximates S^-1 */
+static void pc_cycle_even(orc_mg *g, int l, const cplx *r, cplx *z, orc_stats *st)
+{
+    const orc_op *A = &g->lv[0].op;
+    mg_cycle(g, 0, r, z, st);
+    for (long s = 0; s < A->nsite; s++)
+        if (orc_parity(A->L, s)) memset(z + 12 * s, 0, sizeof(cplx) * 12);
+    (void)l;
+}
 
 static void pc_smoother(orc_mg *g, int l, const cplx *r, cplx *z, orc_stats *st)
 {
@@ -667,7 +787,17 @@ static void pc_smoother(orc_mg *g, int l, const cplx *r, cplx *z, orc_stats *st)
  * the preconditioned directions z_k and the orthonormalised w_k = A z_k -
  * sum beta_jk w_j; at its end the solution update is recovered from the
  * triangular system and the true residual is recomputed. */
+static long gcr_op(orc_mg *g, int l, const cplx *b, cplx *x, double tol, int maxiter, precond_fn M, apply_fn A,
+                   double bnorm, orc_stats *st);
+
 static long gcr(orc_mg *g, int l, const cplx *b, cplx *x, double tol, int maxiter, precond_fn M, orc_stats *st)
+{
+    return gcr_op(g, l, b, x, tol, maxiter, M, lvl_apply, -1.0, st);
+}
+
+/* the same with operator A; bnorm >= 0 replaces |b| in the stopping test */
+static long gcr_op(orc_mg *g, int l, const cplx *b, cplx *x, double tol, int maxiter, precond_fn M, apply_fn A,
+                   double bnorm, orc_stats *st)
 {
     long n = g->lv[l].n;
     int K = g->p.gcr_restart;
@@ -675,11 +805,11 @@ static long gcr(orc_mg *g, int l, const cplx *b, cplx *x, double tol, int maxite
     for (int k = 0; k < K; k++) { z[k] = valloc(n); w[k] = valloc(n); }
     cplx *r = valloc(n), *al = calloc(K, sizeof(cplx)), *be = calloc(K * K, sizeof(cplx)), *cc = calloc(K, sizeof(cplx));
     double *ga = calloc(K, sizeof(double));
-    double bn = sqrt(vnorm2(n, b));
+    double bn = bnorm >= 0 ? bnorm : sqrt(vnorm2(n, b));
     if (vnorm2(n, x) == 0) {
         vcopy(n, b, r); /* zero initial guess: no operator apply needed */
     } else {
-        lvl_apply(g, l, x, r, st);
+        A(g, l, x, r, st);
         for (long i = 0; i < n; i++) r[i] = b[i] - r[i];
     }
     double rn = sqrt(vnorm2(n, r));
@@ -689,7 +819,7 @@ static long gcr(orc_mg *g, int l, const cplx *b, cplx *x, double tol, int maxite
         int k = 0;
         while (k < K && it < maxiter) {
             M(g, l, r, z[k], st);
-            lvl_apply(g, l, z[k], w[k], st);
+            A(g, l, z[k], w[k], st);
             for (int j = 0; j < k; j++) {
                 be[j * K + k] = vdot(n, w[j], w[k]);
                 vaxpy(n, -be[j * K + k], w[j], w[k]);
@@ -710,7 +840,7 @@ static long gcr(orc_mg *g, int l, const cplx *b, cplx *x, double tol, int maxite
             cc[j] = t / ga[j];
         }
         for (int j = 0; j < k; j++) vaxpy(n, cc[j], z[j], x);
-        lvl_apply(g, l, x, r, st);
+        A(g, l, x, r, st);
         for (long i = 0; i < n; i++) r[i] = b[i] - r[i];
         rn = sqrt(vnorm2(n, r));
         if (st) st->restarts++;
@@ -870,6 +1000,43 @@ long orc_mg_solve(orc_mg *g, const double *b, double *x, double tol, orc_stats *
     vzero(g->lv[0].n, (cplx *)x);
     long it = gcr(g, 0, (const cplx *)b, (cplx *)x, tol, g->p.maxiter, pc_cycle, &loc);
     if (st) *st = loc;
+    return it;
+}
+
+/* red/black solve: flexible GCR on S x_e = b_e - D_eo D_oo^-1 b_o with the
+ * preconditioner [M (r_e, 0)]_e, stopped when |r_e| <= tol |b| (r_e is the
+ * whole residual of D x = b once x_o = D_oo^-1 (b_o - D_oe x_e)); then x_o. */
+long orc_mg_solve_eo(orc_mg *g, const double *bd, double *xd, double tol, orc_stats *st)
+{
+    const orc_op *A = &g->lv[0].op;
+    long V = A->nsite, n = V * 12;
+    double m = A->m;
+    const cplx *b = (const cplx *)bd;
+    cplx *x = (cplx *)xd;
+    cplx *bo = valloc(n), *t = valloc(n), *be = valloc(n);
+    orc_stats loc;
+    memset(&loc, 0, sizeof(loc));
+    for (long s = 0; s < V; s++)
+        if (orc_parity(A->L, s)) memcpy(bo + 12 * s, b + 12 * s, sizeof(cplx) * 12);
+    orc_wilson_hop_parity(A->L, (const double *)g->U, m, (const double *)bo, (double *)t, 0); /* D_eo b_o */
+    for (long s = 0; s < V; s++)
+        for (int c = 0; c < 12; c++)
+            be[12 * s + c] = orc_parity(A->L, s) ? 0 : b[12 * s + c] - t[12 * s + c] / (4.0 + m);
+    vzero(n, x);
+    long it = gcr_op(g, 0, be, x, tol, g->p.maxiter, pc_cycle_even, schur_apply_lvl, sqrt(vnorm2(n, b)), &loc);
+    /* x_o = (b_o - D_oe x_e) / (4+m) */
+    orc_wilson_hop_parity(A->L, (const double *)g->U, m, (const double *)x, (double *)t, 1);
+    for (long s = 0; s < V; s++)
+        if (orc_parity(A->L, s))
+            for (int c = 0; c < 12; c++) x[12 * s + c] = (b[12 * s + c] - t[12 * s + c]) / (4.0 + m);
+    /* true residual of D x = b */
+    op_apply(A, x, t);
+    for (long i = 0; i < n; i++) t[i] = b[i] - t[i];
+    double bn = sqrt(vnorm2(n, b));
+    loc.true_relres = bn > 0 ? sqrt(vnorm2(n, t)) / bn : 0;
+    loc.converged = loc.true_relres <= tol;
+    if (st) *st = loc;
+    free(bo); free(t); free(be);
     return it;
 }
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwmg.so")
-SOURCES = ["dslash.hip", "blas.hip", "transfer.hip", "coarse.hip", "mg.hip", "baseline.hip"]
+SOURCES = ["dslash.hip", "blas.hip", "transfer.hip", "coarse.hip", "mg.hip", "baseline.hip", "tune.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + CSRC, "-I" + os.path.join(HERE, "..", "include")]

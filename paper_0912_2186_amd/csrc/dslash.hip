@@ -14,6 +14,14 @@
 // in the tile (and the diagonal term) then reads LDS, and only neighbours in
 // other tiles go to L2.  Reuse across tiles is left to L2/MALL, with
 // workgroups mapped so that each XCD sweeps one contiguous range of sites.
+//
+// Links are stored either whole (9 complex numbers) or, for SU(3) fields,
+// as their first two rows (6 complex numbers, the 12-real format of the
+// paper's GPU kernels, Table 2): the third row of a special unitary matrix
+// is the complex conjugate of the cross product of the first two, and the
+// kernel rebuilds it in registers.
+#include <cstdio>
+
 #include "wmg_internal.h"
 
 namespace wmg {
@@ -95,11 +103,15 @@ struct SweepMap {
   long nblocks;   // grid size (multiple of 8)
 };
 
-static SweepMap make_sweep(const int L[4], int bytes_per_site) {
-  // among splits whose t-slice takes at most ~1 MB of L2, the one with the
-  // smallest y/z face fraction (neighbours outside the slab); the largest
-  // cross-section breaks ties.  If none fits, the smallest cross-section.
-  const long budget = 1L << 20;
+// L2 budgets (bytes per t-slice of a slab) the autotuner tries; the first is
+// the default
+static constexpr long SWEEP_BUDGETS[5] = {1L << 20, 1L << 19, 1L << 21, 1L << 18, 1L << 22};
+
+static SweepMap make_sweep(const int L[4], int bytes_per_site, long budget = 1L << 20) {
+  // among splits whose t-slice takes at most `budget` bytes of L2, the one
+  // with the smallest y/z face fraction (neighbours outside the slab); the
+  // largest cross-section breaks ties.  If none fits, the smallest
+  // cross-section.
   SweepMap best{};
   best.ny = best.nz = 1;
   bool have = false, bfits = false;
@@ -156,12 +168,22 @@ __device__ __forceinline__ bool sweep_site(const SweepMap &sm, const int L[4], l
   return true;
 }
 
+// third row of an SU(3) matrix from its first two: conj(row0 x row1)
+template <class R> __device__ __forceinline__ void su3_third_row(cx<R> u[9]) {
+  const cx<R> c0 = u[1] * u[5] - u[2] * u[4];
+  const cx<R> c1 = u[2] * u[3] - u[0] * u[5];
+  const cx<R> c2 = u[0] * u[4] - u[1] * u[3];
+  u[6] = {c0.re, -c0.im};
+  u[7] = {c1.re, -c1.im};
+  u[8] = {c2.re, -c2.im};
+}
+
 // ---------------------------------------------------------------- SoA
 // Optional fusions for the smoother: bsub != nullptr gives out = bsub - D in
 // (residual); RED != 0 also reduces <out, in> and |out|^2 over the
 // workgroup into red[(rhs * gridDim.x + block) * 3 + 0..2] for a
 // fixed-order finalisation by k_dslash_red_finalize.
-template <class TL, class TS, class TO, int RT, int RED>
+template <class TL, class TS, class TO, int RT, int RED, int NR>
 __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, const TS *__restrict__ in,
                                                    TO *__restrict__ out, int L0, int L1, int L2, int L3, long V,
                                                    float diagf, double diagd, int nrhs, SweepMap sm, long Vs,
@@ -221,10 +243,11 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
 
   auto load_link = [&](int mu, long site, cx<R> u[9]) {
 #pragma unroll
-    for (int e = 0; e < 9; e++) {
-      auto v = ldc(U + ((size_t)(mu * 9 + e)) * Vs + site);
+    for (int e = 0; e < NR; e++) {
+      auto v = ldc(U + ((size_t)(mu * NR + e)) * Vs + site);
       u[e] = {(R)v.re, (R)v.im};
     }
+    if (NR == 6) su3_third_row(u);
   };
   // half spinor of the neighbour, projected colour by colour straight from
   // the loads, then the link applied row by row (few live registers)
@@ -349,75 +372,399 @@ __global__ void __launch_bounds__(256) k_dslash_red_finalize(const double *__res
                                                                    sh[threadIdx.x][2] + sh[threadIdx.x][3];
 }
 
-template <class TL, class TS, class TO = TS>
-static void launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, const void *bsub,
-                       double *red, double *red_out, int red_stride, hipStream_t st, const double *bnrm2 = nullptr,
-                       int bstride = 0, void *out32 = nullptr) {
+template <class TL, class TS, class TO = TS, int NR = 9>
+static int launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, const void *bsub,
+                      double *red, double *red_out, int red_stride, hipStream_t st, const double *bnrm2 = nullptr,
+                      int bstride = 0, void *out32 = nullptr) {
   constexpr int RT = sizeof(TS) == 16 ? 1 : 2;
   const int nrt = (nrhs + RT - 1) / RT;
-  // FP64 and FP32 links (288-576 B per site) would be re-read from HBM by
-  // every rhs tile's sweep: the rhs tiles of one site tile then run back to
-  // back on one XCD and share the links in its L2 (FP64, 28 rhs: 14.6 ->
-  // 10.4 ms on 32^3x64).  FP16 links are cheap to re-read, and one sweep per
-  // rhs tile keeps the spinor halo in L2.
-  const int inner = sizeof(TL) >= 8 && nrt > 1;
+  // Default order: FP64 and FP32 links (288-576 B per site) would be re-read
+  // from HBM by every rhs tile's sweep, so the rhs tiles of one site tile
+  // run back to back on one XCD and share the links in its L2 (FP64, 28 rhs:
+  // 14.6 -> 10.4 ms on 32^3x64); FP16 links are cheap to re-read, and one
+  // sweep per rhs tile keeps the spinor halo in L2.  The autotuner also
+  // tries the other order and other slab sizes.
+  const int inner0 = sizeof(TL) >= 8 && nrt > 1;
   // bytes a site brings into L2 during one sweep: its links and RT spinors
-  SweepMap sm = make_sweep(g.L, 36 * (int)sizeof(TL) + 24 * (int)sizeof(TS) / 2 * RT);
-  dim3 grid = inner ? dim3((unsigned)(sm.nblocks * nrt)) : dim3((unsigned)sm.nblocks, nrt);
+  const int bps = 4 * NR * (int)sizeof(TL) + 24 * (int)sizeof(TS) / 2 * RT;
   const size_t lds = (size_t)(nrhs < RT ? nrhs : RT) * 12 * 256 * sizeof(TS);
-  if (red) {
-    hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
-                       (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                       (const TS *)bsub, bnrm2, bstride, red, inner, (float2 *)out32);
-    hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
-                       red_stride);
-  } else {
-    hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
-                       (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                       (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner, (float2 *)out32);
-  }
+  constexpr int NB = (int)(sizeof(SWEEP_BUDGETS) / sizeof(SWEEP_BUDGETS[0]));
+  auto run = [&](int cand) -> int {
+    const long budget = SWEEP_BUDGETS[cand % NB];
+    const int inner = (cand / NB) ? !inner0 : inner0;
+    SweepMap sm = make_sweep(g.L, bps, budget);
+    dim3 grid = inner ? dim3((unsigned)(sm.nblocks * nrt)) : dim3((unsigned)sm.nblocks, nrt);
+    if (red) {
+      hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1, NR>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
+                         (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
+                         (const TS *)bsub, bnrm2, bstride, red, inner, (float2 *)out32);
+      hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
+                         red_stride);
+    } else {
+      hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
+                         (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
+                         (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner, (float2 *)out32);
+    }
+    WMG_HIP(hipGetLastError());
+    return 0;
+  };
+  char key[256];
+  std::snprintf(key, sizeof(key), "dslash/l%zu-s%zu-o%zu-nr%d-red%d-b%d-f%d/%dx%dx%dx%d/rhs%d", sizeof(TL),
+                sizeof(TS), sizeof(TO), NR, red ? 1 : 0, bsub ? 1 : 0, out32 ? 1 : 0, g.L[0], g.L[1], g.L[2], g.L[3],
+                nrhs);
+  int choice = 0;
+  return tune_choice(key, nrt > 1 ? 2 * NB : NB, run, st, &choice);
 }
 
 long wilson_red_blocks(const Geom &g) {
-  // every (link, spinor) storage pair launch_soa instantiates
-  const int bps[4] = {36 * 16 + 24 * 8, 36 * 8 + 24 * 4 * 2, 36 * 4 + 24 * 4 * 2, 36 * 4 + 24 * 2 * 2};
+  // every (link, spinor) storage pair launch_soa instantiates, links whole
+  // (36 complex per site) or compressed (24)
+  const int lb[4] = {16, 8, 4, 4}, sb[4] = {24 * 8, 24 * 4 * 2, 24 * 4 * 2, 24 * 2 * 2};
   long m = 0;
-  for (int i = 0; i < 4; i++) {
-    long nb = make_sweep(g.L, bps[i]).nblocks;
-    m = nb > m ? nb : m;
-  }
+  for (int i = 0; i < 4; i++)
+    for (int nl : {36, 24})
+      for (long budget : SWEEP_BUDGETS) {
+        long nb = make_sweep(g.L, nl * lb[i] + sb[i], budget).nblocks;
+        m = nb > m ? nb : m;
+      }
   return m;
 }
 
 int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
                      const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st, void *out32) {
   if (out32 && sprec != P64) return set_error(-1, "wilson_soa: FP32 copy of the output only for FP64 spinors");
-  if (sprec == P64 && lprec == P64)
-    launch_soa<double2, double2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st, nullptr, 0, out32);
-  else if (sprec == P32 && lprec == P32)
-    launch_soa<float2, float2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st);
-  else if (sprec == P32 && lprec == P16)
-    launch_soa<__half2, float2>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st);
-  else return set_error(-1, "wilson_soa: unsupported precision pair link=%d spinor=%d", lprec, sprec);
-  WMG_HIP(hipGetLastError());
-  return 0;
+  const bool c12 = (lprec & LK12) != 0;
+  const int lp = lprec & ~LK12;
+#define WS_LAUNCH(TL, TS, ...)                                                                                  \
+  return c12 ? launch_soa<TL, TS, TS, 6>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st, __VA_ARGS__) \
+             : launch_soa<TL, TS, TS, 9>(g, U, m, in, out, nrhs, bsub, red, red_out, red_stride, st, __VA_ARGS__)
+  if (sprec == P64 && lp == P64) WS_LAUNCH(double2, double2, nullptr, 0, out32);
+  if (sprec == P32 && lp == P32) WS_LAUNCH(float2, float2, nullptr, 0, nullptr);
+  if (sprec == P32 && lp == P16) WS_LAUNCH(__half2, float2, nullptr, 0, nullptr);
+#undef WS_LAUNCH
+  return set_error(-1, "wilson_soa: unsupported precision pair link=%d spinor=%d", lp, sprec);
 }
 
 int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
                    const void *bsub, const double *bnrm2, int bstride, double *red, double *red_out, int red_stride,
-                   hipStream_t st) {
+                   hipStream_t st, int lflags) {
+  const bool c12 = (lflags & LK12) != 0;
   if (iprec == P32)
-    launch_soa<__half2, float2, __half2>(g, U16, m, in, out, nrhs, bsub, red, red_out, red_stride, st, bnrm2, bstride);
-  else if (iprec == P16 && !bsub)
-    launch_soa<__half2, __half2, __half2>(g, U16, m, in, out, nrhs, nullptr, red, red_out, red_stride, st);
-  else return set_error(-1, "wilson_soa_h16: input precision %d%s", iprec, bsub ? " with bsub" : "");
-  WMG_HIP(hipGetLastError());
-  return 0;
+    return c12 ? launch_soa<__half2, float2, __half2, 6>(g, U16, m, in, out, nrhs, bsub, red, red_out, red_stride, st,
+                                                         bnrm2, bstride)
+               : launch_soa<__half2, float2, __half2, 9>(g, U16, m, in, out, nrhs, bsub, red, red_out, red_stride, st,
+                                                         bnrm2, bstride);
+  if (iprec == P16 && !bsub)
+    return c12 ? launch_soa<__half2, __half2, __half2, 6>(g, U16, m, in, out, nrhs, nullptr, red, red_out, red_stride,
+                                                          st)
+               : launch_soa<__half2, __half2, __half2, 9>(g, U16, m, in, out, nrhs, nullptr, red, red_out, red_stride,
+                                                          st);
+  return set_error(-1, "wilson_soa_h16: input precision %d%s", iprec, bsub ? " with bsub" : "");
 }
 
 int wilson_soa(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
                hipStream_t st) {
   return wilson_soa_fused(g, lprec, U, sprec, m, in, out, nrhs, nullptr, nullptr, nullptr, 0, st);
+}
+
+// ---------------------------------------------------------------- red/black
+// Even-odd decomposition (Sec. 3, red/black preconditioning).  A site of
+// parity p = (x+y+z+t) mod 2 with lexicographic index s has the compact
+// index h = s / 2 in the half-lattice array of its parity (x extent even):
+// fields [rhs][12][Vhs] per parity, links [parity][4][NR][Vhs].  The hopping
+// term between the sublattices, H_p(v) at sites of parity p from v on the
+// other one, is the sum over mu of (1 - gamma_mu) U_mu(x) v(x+mu) +
+// (1 + gamma_mu) U_mu(x-mu)^dag v(x-mu); D_{p,1-p} = -H_p / 2.
+struct EoGeom {
+  int L[4];
+  long Vh, Vhs;  // sites per parity, compact array stride
+};
+
+__device__ __forceinline__ void eo_coords(const EoGeom &g, int par, long h, int x[4]) {
+  const int hx = g.L[0] / 2;
+  long r = h / hx;
+  x[1] = (int)(r % g.L[1]);
+  r /= g.L[1];
+  x[2] = (int)(r % g.L[2]);
+  x[3] = (int)(r / g.L[2]);
+  x[0] = 2 * (int)(h % hx) + ((par + x[1] + x[2] + x[3]) & 1);
+}
+
+// out = a in_diag + b H_par(in_hop) at the compact sites of parity par, for
+// RT right-hand sides per thread (sharing every link load); with RED, also
+// <out, in_diag> and |out|^2 per workgroup and rhs into red (as stored).
+// Workgroups are ordered so that each XCD runs the rhs tiles of one site
+// tile back to back (links read from HBM once per launch).
+template <class TL, class TD, class TH, class TO, int RT, int RED, int NR>
+__global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const TD *__restrict__ in_diag,
+                                               const TH *__restrict__ in_hop, TO *__restrict__ out, EoGeom g, int par,
+                                               double ad, double bd, int nrhs, long ntile, long per_xcd,
+                                               double *__restrict__ red) {
+  using R = typename store_traits<TO>::real;
+  const long q = (blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
+  const int nrt = (nrhs + RT - 1) / RT;
+  const long tile = q / nrt;
+  const int r0 = (int)(q % nrt) * RT;
+  const bool valid_tile = tile < ntile;
+  const long h = tile * 256 + threadIdx.x;
+  const bool valid = valid_tile && h < g.Vh;
+  const R a = (R)ad, b = (R)bd;
+  double rs[RT][3];
+#pragma unroll
+  for (int t = 0; t < RT; t++) rs[t][0] = rs[t][1] = rs[t][2] = 0.0;
+  if (valid) {
+    int x[4];
+    eo_coords(g, par, h, x);
+    const long Vs = g.Vhs;
+    const TL *Uf = Ue + (size_t)par * 4 * NR * Vs;        // links at sites of parity par
+    const TL *Ub = Ue + (size_t)(1 - par) * 4 * NR * Vs;  // ... of the other parity
+    cx<R> acc[RT][12];
+#pragma unroll
+    for (int t = 0; t < RT; t++)
+#pragma unroll
+      for (int c = 0; c < 12; c++) acc[t][c] = czero<R>();
+    auto load_link = [&](const TL *Up, int mu, long site, cx<R> u[9]) {
+#pragma unroll
+      for (int e = 0; e < NR; e++) {
+        auto v = ldc(Up + ((size_t)(mu * NR + e)) * Vs + site);
+        u[e] = {(R)v.re, (R)v.im};
+      }
+      if (NR == 6) su3_third_row(u);
+    };
+    auto half = [&](int r, long site, auto proj, cx<R> hh[6]) {
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        cx<R> p4[4];
+#pragma unroll
+        for (int sp = 0; sp < 4; sp++) {
+          auto v = ldc(in_hop + ((size_t)r * 12 + sp * 3 + c) * Vs + site);
+          p4[sp] = {(R)v.re, (R)v.im};
+        }
+        proj(p4, hh[c], hh[3 + c]);
+      }
+    };
+#define EO_DIR(MU)                                                                      \
+    {                                                                                   \
+      int y[4] = {x[0], x[1], x[2], x[3]};                                              \
+      y[MU] = x[MU] == g.L[MU] - 1 ? 0 : x[MU] + 1;                                     \
+      const long hf = site_index(g.L, y) >> 1;                                          \
+      y[MU] = x[MU] == 0 ? g.L[MU] - 1 : x[MU] - 1;                                     \
+      const long hb = site_index(g.L, y) >> 1;                                          \
+      cx<R> u[9], hh[6], gg[6];                                                         \
+      load_link(Uf, MU, h, u);                                                          \
+      _Pragma("unroll") for (int t = 0; t < RT; t++) {                                  \
+        if (r0 + t < nrhs) {                                                            \
+          half(r0 + t, hf, proj_pair<MU, 1, R>, hh);                                    \
+          su3_mul<0>(u, hh, gg);                                                        \
+          reconstruct<MU, 1>(gg, acc[t]);                                               \
+        }                                                                               \
+      }                                                                                 \
+      load_link(Ub, MU, hb, u);                                                         \
+      _Pragma("unroll") for (int t = 0; t < RT; t++) {                                  \
+        if (r0 + t < nrhs) {                                                            \
+          half(r0 + t, hb, proj_pair<MU, -1, R>, hh);                                   \
+          su3_mul<1>(u, hh, gg);                                                        \
+          reconstruct<MU, -1>(gg, acc[t]);                                              \
+        }                                                                               \
+      }                                                                                 \
+    }
+    EO_DIR(0)
+    EO_DIR(1)
+    EO_DIR(2)
+    EO_DIR(3)
+#undef EO_DIR
+#pragma unroll
+    for (int t = 0; t < RT; t++) {
+      if (r0 + t >= nrhs) continue;
+#pragma unroll
+      for (int c = 0; c < 12; c++) {
+        const size_t i = ((size_t)(r0 + t) * 12 + c) * Vs + h;
+        cx<R> dv = czero<R>();
+        if (ad != 0.0) {
+          auto v = ldc(in_diag + i);
+          dv = {(R)v.re, (R)v.im};
+        }
+        cx<R> o = {a * dv.re + b * acc[t][c].re, a * dv.im + b * acc[t][c].im};
+        stc(out + i, o);
+        if (RED) {
+          o = as_stored(out, o);
+          rs[t][0] += (double)o.re * dv.re + (double)o.im * dv.im;
+          rs[t][1] += (double)o.re * dv.im - (double)o.im * dv.re;
+          rs[t][2] += (double)o.re * o.re + (double)o.im * o.im;
+        }
+      }
+    }
+  }
+  if (RED) {
+    __shared__ double sh[RT][3][4];
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < RT; t++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        double v = rs[t][k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) sh[t][k][wv] = v;
+      }
+    __syncthreads();
+    if (valid_tile && threadIdx.x < RT * 3) {
+      int t = threadIdx.x / 3, k = threadIdx.x % 3;
+      if (r0 + t < nrhs)
+        red[((size_t)(r0 + t) * ntile + tile) * 3 + k] = sh[t][k][0] + sh[t][k][1] + sh[t][k][2] + sh[t][k][3];
+    }
+  }
+}
+
+static EoGeom make_eo(const Geom &g) {
+  EoGeom e;
+  for (int i = 0; i < 4; i++) e.L[i] = g.L[i];
+  e.Vh = g.V / 2;
+  e.Vhs = fine_stride(e.Vh);
+  return e;
+}
+
+long eo_stride(const Geom &g) { return fine_stride(g.V / 2); }
+
+template <class TL, class TD, class TH, class TO, int RT, int NR>
+static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, double b, const void *in_diag,
+                         const void *in_hop, void *out, int nrhs, double *red, double *red_out, int red_stride,
+                         hipStream_t st) {
+  EoGeom e = make_eo(g);
+  const long ntile = (e.Vh + 255) / 256;
+  const int nrt = (nrhs + RT - 1) / RT;
+  const long grid = xcd_grid(ntile * nrt);
+  if (red) {
+    hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 1, NR>), dim3((unsigned)grid), dim3(256), 0, st, (const TL *)Ue,
+                       (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, ntile, grid / NXCD, red);
+    hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, ntile, red_out, red_stride);
+  } else {
+    hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 0, NR>), dim3((unsigned)grid), dim3(256), 0, st, (const TL *)Ue,
+                       (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, ntile, grid / NXCD,
+                       (double *)nullptr);
+  }
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b, int pdiag, const void *in_diag,
+           int phop, const void *in_hop, int pout, void *out, int nrhs, double *red, double *red_out, int red_stride,
+           hipStream_t st) {
+  const bool c12 = (lprec & LK12) != 0;
+  const int lp = lprec & ~LK12;
+#define HOP(TL, TD, TH, TO, RT)                                                                                    \
+  return c12 ? launch_hop_eo<TL, TD, TH, TO, RT, 6>(g, Ue, par, a, b, in_diag, in_hop, out, nrhs, red, red_out,    \
+                                                   red_stride, st)                                                \
+             : launch_hop_eo<TL, TD, TH, TO, RT, 9>(g, Ue, par, a, b, in_diag, in_hop, out, nrhs, red, red_out,    \
+                                                   red_stride, st)
+  if (lp == P64 && pdiag == P64 && phop == P64 && pout == P64) HOP(double2, double2, double2, double2, 1);
+  if (lp == P16 && pdiag == P16 && phop == P16 && pout == P16) HOP(__half2, __half2, __half2, __half2, 2);
+  if (lp == P16 && pdiag == P16 && phop == P32 && pout == P32) HOP(__half2, __half2, float2, float2, 2);
+#undef HOP
+  return set_error(-1, "hop_eo: unsupported precisions link %d diag %d hop %d out %d", lp, pdiag, phop, pout);
+}
+
+// full lexicographic SoA [rhs][12][Vs] <-> compact halves [rhs][12][Vhs]
+template <class TF, class TE>
+__global__ void k_eo_pack(const TF *__restrict__ full, TE *__restrict__ ev, TE *__restrict__ od, EoGeom g, long Vs) {
+  long s = blockIdx.x * 256L + threadIdx.x;
+  int r = blockIdx.y;
+  if (s >= 2 * g.Vh) return;
+  int x[4];
+  site_coords(g.L, s, x);
+  TE *dst = ((x[0] + x[1] + x[2] + x[3]) & 1) ? od : ev;
+  const long hh = s >> 1;
+#pragma unroll
+  for (int c = 0; c < 12; c++) {
+    auto v = ldc(full + ((size_t)r * 12 + c) * Vs + s);
+    stc(dst + ((size_t)r * 12 + c) * g.Vhs + hh, v);
+  }
+}
+// full += (ev, od) (either half may be null: no contribution)
+template <class TF, class TE>
+__global__ void k_eo_unpack_add(TF *__restrict__ full, const TE *__restrict__ ev, const TE *__restrict__ od, EoGeom g,
+                                long Vs) {
+  long s = blockIdx.x * 256L + threadIdx.x;
+  int r = blockIdx.y;
+  if (s >= 2 * g.Vh) return;
+  int x[4];
+  site_coords(g.L, s, x);
+  const TE *src = ((x[0] + x[1] + x[2] + x[3]) & 1) ? od : ev;
+  if (!src) return;
+  const long hh = s >> 1;
+#pragma unroll
+  for (int c = 0; c < 12; c++) {
+    const size_t i = ((size_t)r * 12 + c) * Vs + s;
+    auto f = ldc(full + i);
+    auto v = ldc(src + ((size_t)r * 12 + c) * g.Vhs + hh);
+    stc(full + i, decltype(f){f.re + v.re, f.im + v.im});
+  }
+}
+
+int eo_pack(const Geom &g, int pfull, const void *full, int phalf, void *ev, void *od, int nrhs, hipStream_t st) {
+  EoGeom e = make_eo(g);
+  dim3 grid((unsigned)((g.V + 255) / 256), nrhs);
+  if (pfull == P16 && phalf == P16)
+    hipLaunchKernelGGL((k_eo_pack<__half2, __half2>), grid, dim3(256), 0, st, (const __half2 *)full, (__half2 *)ev,
+                       (__half2 *)od, e, g.Vs);
+  else if (pfull == P64 && phalf == P64)
+    hipLaunchKernelGGL((k_eo_pack<double2, double2>), grid, dim3(256), 0, st, (const double2 *)full, (double2 *)ev,
+                       (double2 *)od, e, g.Vs);
+  else return set_error(-1, "eo_pack: precisions %d -> %d", pfull, phalf);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+int eo_unpack_add(const Geom &g, int pfull, void *full, int phalf, const void *ev, const void *od, int nrhs,
+                  hipStream_t st) {
+  EoGeom e = make_eo(g);
+  dim3 grid((unsigned)((g.V + 255) / 256), nrhs);
+  if (pfull == P32 && phalf == P32)
+    hipLaunchKernelGGL((k_eo_unpack_add<float2, float2>), grid, dim3(256), 0, st, (float2 *)full, (const float2 *)ev,
+                       (const float2 *)od, e, g.Vs);
+  else if (pfull == P64 && phalf == P64)
+    hipLaunchKernelGGL((k_eo_unpack_add<double2, double2>), grid, dim3(256), 0, st, (double2 *)full,
+                       (const double2 *)ev, (const double2 *)od, e, g.Vs);
+  else return set_error(-1, "eo_unpack_add: precisions %d <- %d", pfull, phalf);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+// links [4][9][Vs] (FP64, whole, lexicographic SoA) -> [parity][4][NR][Vhs]
+template <class TL, int NR>
+__global__ void k_links_to_eo(const double2 *__restrict__ U, TL *__restrict__ Ue, EoGeom g, long Vs) {
+  long s = blockIdx.x * 256L + threadIdx.x;
+  if (s >= 2 * g.Vh) return;
+  int x[4];
+  site_coords(g.L, s, x);
+  const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+  const long hh = s >> 1;
+  for (int mu = 0; mu < 4; mu++)
+    for (int e = 0; e < NR; e++) {
+      double2 v = U[(size_t)(mu * 9 + e) * Vs + s];
+      TL *d = Ue + ((size_t)(par * 4 + mu) * NR + e) * g.Vhs + hh;
+      if constexpr (sizeof(TL) == 16) *d = v;
+      else if constexpr (sizeof(TL) == 8) *d = make_float2((float)v.x, (float)v.y);
+      else *d = __floats2half2_rn((float)v.x, (float)v.y);
+    }
+}
+
+int links_to_eo(const Geom &g, const void *U64soa, int lprec, void *Ue, hipStream_t st) {
+  EoGeom e = make_eo(g);
+  dim3 grid((unsigned)((g.V + 255) / 256));
+  const bool c12 = (lprec & LK12) != 0;
+  const int lp = lprec & ~LK12;
+#define L2E(TL)                                                                                                     \
+  do {                                                                                                            \
+    if (c12) hipLaunchKernelGGL((k_links_to_eo<TL, 6>), grid, dim3(256), 0, st, (const double2 *)U64soa, (TL *)Ue, e, g.Vs); \
+    else hipLaunchKernelGGL((k_links_to_eo<TL, 9>), grid, dim3(256), 0, st, (const double2 *)U64soa, (TL *)Ue, e, g.Vs);     \
+  } while (0)
+  if (lp == P64) L2E(double2);
+  else if (lp == P32) L2E(float2);
+  else L2E(__half2);
+#undef L2E
+  WMG_HIP(hipGetLastError());
+  return 0;
 }
 
 // ---------------------------------------------------------------- canonical
@@ -471,14 +818,14 @@ int wilson_canonical(const Geom &g, const double *U, double m, const double *in,
 }
 
 // ---------------------------------------------------------------- layouts
-template <class TL>
+template <class TL, int NR>
 __global__ void k_links_to_soa(const double2 *__restrict__ Uc, TL *__restrict__ Us, long V, long Vs) {
   long s = blockIdx.x * 256L + threadIdx.x;
   if (s >= V) return;
   for (int mu = 0; mu < 4; mu++)
-    for (int e = 0; e < 9; e++) {
+    for (int e = 0; e < NR; e++) {
       double2 v = Uc[(s * 4 + mu) * 9 + e];
-      TL *d = Us + (size_t)(mu * 9 + e) * Vs + s;
+      TL *d = Us + (size_t)(mu * NR + e) * Vs + s;
       if constexpr (sizeof(TL) == 16) *d = v;
       else if constexpr (sizeof(TL) == 8) *d = make_float2((float)v.x, (float)v.y);
       else *d = __floats2half2_rn((float)v.x, (float)v.y);
@@ -487,12 +834,48 @@ __global__ void k_links_to_soa(const double2 *__restrict__ Uc, TL *__restrict__ 
 
 int links_to_soa(const Geom &g, const double *Ucanon, int lprec, void *Usoa, hipStream_t st) {
   dim3 grid((unsigned)((g.V + 255) / 256));
-  if (lprec == P64)
-    hipLaunchKernelGGL((k_links_to_soa<double2>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (double2 *)Usoa, g.V, g.Vs);
-  else if (lprec == P32)
-    hipLaunchKernelGGL((k_links_to_soa<float2>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (float2 *)Usoa, g.V, g.Vs);
-  else
-    hipLaunchKernelGGL((k_links_to_soa<__half2>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (__half2 *)Usoa, g.V, g.Vs);
+  const bool c12 = (lprec & LK12) != 0;
+  const int lp = lprec & ~LK12;
+#define L2S(TL)                                                                                                  \
+  do {                                                                                                         \
+    if (c12) hipLaunchKernelGGL((k_links_to_soa<TL, 6>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (TL *)Usoa, g.V, g.Vs); \
+    else hipLaunchKernelGGL((k_links_to_soa<TL, 9>), grid, dim3(256), 0, st, (const double2 *)Ucanon, (TL *)Usoa, g.V, g.Vs);     \
+  } while (0)
+  if (lp == P64) L2S(double2);
+  else if (lp == P32) L2S(float2);
+  else L2S(__half2);
+#undef L2S
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+// Largest |row2 - conj(row0 x row1)| of the canonical FP64 links in each
+// workgroup of 256 sites -> part[block]: zero (to rounding) exactly when
+// the 12-real format reproduces the field.
+__global__ void __launch_bounds__(256) k_su3_recon_err(const double2 *__restrict__ Uc, long V, double *__restrict__ part) {
+  long s = blockIdx.x * 256L + threadIdx.x;
+  double e = 0;
+  if (s < V)
+    for (int mu = 0; mu < 4; mu++) {
+      cx<double> u[9];
+      for (int k = 0; k < 9; k++) u[k] = ldc(Uc + (s * 4 + mu) * 9 + k);
+      cx<double> w[9];
+      for (int k = 0; k < 6; k++) w[k] = u[k];
+      su3_third_row(w);
+      for (int k = 6; k < 9; k++) e = fmax(e, fmax(fabs(w[k].re - u[k].re), fabs(w[k].im - u[k].im)));
+    }
+  __shared__ double sh[4];
+  for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_down(e, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+long su3_recon_blocks(const Geom &g) { return (g.V + 255) / 256; }
+
+int su3_recon_err(const Geom &g, const double *Ucanon, double *part, hipStream_t st) {
+  hipLaunchKernelGGL(k_su3_recon_err, dim3((unsigned)su3_recon_blocks(g)), dim3(256), 0, st, (const double2 *)Ucanon,
+                     g.V, part);
   WMG_HIP(hipGetLastError());
   return 0;
 }

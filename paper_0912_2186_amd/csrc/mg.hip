@@ -218,9 +218,11 @@ __global__ void k_gcr_trisolve2(double *g, int k, int nrhs) {
   }
 }
 
+// one lane per pack of S (pack_len<S>() complex numbers; 1 for kernels that
+// walk single elements): more loads in flight than a grid-stride loop
 template <class S> static dim3 grid_for(long n, int nrhs) {
-  long b = (n + 255) / 256;
-  if (b > 2048) b = 2048;
+  long b = (n / pack_len<S>() + 255) / 256;
+  if (b > (1L << 30) / 256) b = (1L << 30) / 256;
   if (b < 1) b = 1;
   return dim3((unsigned)b, nrhs);
 }
@@ -230,7 +232,9 @@ template <class S> static dim3 grid_for(long n, int nrhs) {
 using namespace wmg;
 
 // ------------------------------------------------------------ context
-enum { VR, VE, VT, VE2, VS, VQ, VCR, VCS, VCP, VCU, VX, VS1, VS2, VS3, NVW };
+enum { VR, VE, VT, VE2, VS, VQ, VCR, VCS, VCP, VCU, VX, VS1, VS2, VS3,
+       // red/black smoother: sublattice residuals, MR iterates, corrections
+       VH0, VH1, VH2, VH3, VHQ, VHT, VHSE, VHSO, VHDE, VHDO, NVW };
 
 struct Level {
   Geom g;
@@ -239,7 +243,10 @@ struct Level {
   long n = 0;        // complex numbers per rhs at the current Nv of the level above
   long n_alloc = 0;  // ... at its largest Nv (allocation size)
   // fine operator
-  void *U[3] = {nullptr, nullptr, nullptr};  // P64 / P32 / P16 SoA
+  void *U[3] = {nullptr, nullptr, nullptr};  // P64 / P32 / P16 SoA, whole links [4][9][Vs]
+  void *Uk[3] = {nullptr, nullptr, nullptr}; // the same as two rows [4][6][Vs] (SU(3) fields)
+  int lk = 0;                                // LK12 when the Dslash uses Uk
+  void *Ue[3] = {nullptr, nullptr, nullptr}; // red/black copies [parity][4][NR][eo_stride] (built on first use)
   double m = 0;
   // coarse operator (internal layout)
   double2 *Y64 = nullptr;
@@ -270,6 +277,13 @@ struct GcrBuf {
   void *rin = nullptr;                      // inner residual (aliases r64 in FP64 mode)
   double2 *x64 = nullptr, *r64 = nullptr, *b64 = nullptr, *t64 = nullptr;
 };
+
+// links the fine operator reads at precision lp, and the precision code
+// (with LK12 when they are stored as two rows)
+static inline const void *fine_links(const Level &L, int lp) { return L.lk ? L.Uk[lp] : L.U[lp]; }
+static inline int fine_lcode(const Level &L, int lp) { return lp | L.lk; }
+// complex numbers of link data per site the fine operator reads
+static inline double fine_link_cx(const Level &L) { return L.lk ? 24.0 : 36.0; }
 
 struct wmg_ctx {
   wmg_params p;
@@ -371,6 +385,42 @@ static int sync(wmg_ctx *c) {
   return 0;
 }
 
+// Low-precision (and, for SU(3) fields, two-row) copies of the fine links.
+// The two-row format is used when every link's third row equals
+// conj(row0 x row1) to 1e-12 (e.g. links exp(i eps H) with traceless
+// Hermitian H, and their gauge transforms) and force18 is false; the FP64
+// whole links stay for the Galerkin build.
+static int fine_link_format(wmg_ctx *c, Level &F, const double *U, bool force18) {
+  bool c12 = false;
+  if (!force18) {
+    const long nb = su3_recon_blocks(F.g);
+    double *part = nullptr;
+    TRY(dalloc((void **)&part, sizeof(double) * nb));
+    std::vector<double> h(nb);
+    int rc = su3_recon_err(F.g, U, part, c->st);
+    if (!rc && hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, c->st) != hipSuccess)
+      rc = set_error(WMG_EHIP, "link check read-back");
+    if (!rc) rc = sync(c);
+    (void)hipFree(part);
+    TRY(rc);
+    double e = 0;
+    for (double v : h) e = v > e ? v : e;
+    c12 = e <= 1e-12;  // NaN fails too
+  }
+  const size_t cs[3] = {16, 8, 4};
+  for (int lp = P64; lp <= P16; lp++) {
+    if (c12) {
+      TRY(dalloc(&F.Uk[lp], cs[lp] * 24 * (size_t)F.g.Vs));
+      TRY(links_to_soa(F.g, U, lp | LK12, F.Uk[lp], c->st));
+    } else if (lp != P64) {
+      TRY(dalloc(&F.U[lp], cs[lp] * 36 * (size_t)F.g.Vs));
+      TRY(links_to_soa(F.g, U, lp, F.U[lp], c->st));
+    }
+  }
+  F.lk = c12 ? LK12 : 0;
+  return 0;
+}
+
 // work vector `name` of level l for nrhs right-hand sides (grown on demand;
 // a solve uses one nrhs throughout, so pointers stay valid within it)
 static int level_vec(wmg_ctx *c, int l, int prec, int name, void **out, int nrhs) {
@@ -415,8 +465,8 @@ static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int 
     // algorithmic bytes: 4 links per site + one spinor in and out per rhs
     double lb = lp == P64 ? 16 : (lp == P32 ? 8 : 4), sb = prec == P64 ? 16 : 8;
     int kind = prec == P64 ? K_DSLASH_64 : (lowlinks ? K_DSLASH_CYCLE : K_DSLASH_OUTER32);
-    int slot = prof_begin(c, kind, (double)L.g.V * (36 * lb + 24.0 * sb * nrhs));
-    int rc = wilson_soa(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, c->st);
+    int slot = prof_begin(c, kind, (double)L.g.V * (fine_link_cx(L) * lb + 24.0 * sb * nrhs));
+    int rc = wilson_soa(L.g, fine_lcode(L, lp), fine_links(L, lp), prec, L.m, in, out, nrhs, c->st);
     prof_end(c, slot);
     TRY(rc);
     return nrm_out ? norm2(c->red, prec, out, L.n, nrhs, nrm_out, nrm_stride, c->st) : 0;
@@ -483,8 +533,8 @@ static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int
   if (prec == P64) c->st_fine64++;
   double lb = lp == P64 ? 16 : 4, sb = prec == P64 ? 16 : 8;
   int slot = prof_begin(c, prec == P64 ? K_DSLASH_64 : (bsub ? K_DSLASH_RES : K_DSLASH_CYCLE),
-                        (double)L.g.V * (36 * lb + (bsub ? 36.0 : 24.0) * sb * nrhs));
-  int rc = wilson_soa_fused(L.g, lp, L.U[lp], prec, L.m, in, out, nrhs, bsub, reduce ? c->dred : nullptr,
+                        (double)L.g.V * (fine_link_cx(L) * lb + (bsub ? 36.0 : 24.0) * sb * nrhs));
+  int rc = wilson_soa_fused(L.g, fine_lcode(L, lp), fine_links(L, lp), prec, L.m, in, out, nrhs, bsub, reduce ? c->dred : nullptr,
                             red_dst ? red_dst : c->red_out, 4, c->st, out32);
   prof_end(c, slot);
   return rc;
@@ -503,18 +553,19 @@ static int mr_smooth_h16(wmg_ctx *c, const void *r, const double *rn2, void *e, 
   if (L.n % 4) return set_error(-1, "mr_smooth_h16: length %ld not a multiple of 4", L.n);
   for (int k = 0; k < nsteps; k++) TRY(level_vec(c, 0, P16, names[k], &sv[k], nrhs));
   TRY(level_vec(c, 0, P16, VQ, &q, nrhs));
-  const double vb = (double)L.g.V * 36 * 4;  // FP16 links
+  const double vb = (double)L.g.V * fine_link_cx(L) * 4;  // FP16 links
   c->st_fine++;
   int slot = prof_begin(c, K_DSLASH_RES, vb + (double)L.g.V * 12 * (8 + 8 + 4) * nrhs);
-  int rc = wilson_soa_h16(L.g, L.U[P16], P32, L.m, e, sv[0], nrhs, r, rn2, 4, nullptr, nullptr, 0, c->st);
+  int rc = wilson_soa_h16(L.g, fine_links(L, P16), P32, L.m, e, sv[0], nrhs, r, rn2, 4, nullptr, nullptr, 0, c->st,
+                          L.lk);
   prof_end(c, slot);
   TRY(rc);
-  dim3 g = grid_for<double2>(L.n, nrhs);
+  dim3 g = grid_for<__half2>(L.n, nrhs);
   for (int k = 0; k < nsteps; k++) {
     c->st_fine++;
     slot = prof_begin(c, K_DSLASH_CYCLE, vb + (double)L.g.V * 12 * (4 + 4) * nrhs);
-    rc = wilson_soa_h16(L.g, L.U[P16], P16, L.m, sv[k], q, nrhs, nullptr, nullptr, 0, c->dred,
-                        c->mr_red + (size_t)k * 64 * 4, 4, c->st);
+    rc = wilson_soa_h16(L.g, fine_links(L, P16), P16, L.m, sv[k], q, nrhs, nullptr, nullptr, 0, c->dred,
+                        c->mr_red + (size_t)k * 64 * 4, 4, c->st, L.lk);
     prof_end(c, slot);
     TRY(rc);
     if (k + 1 < nsteps) {
@@ -532,8 +583,104 @@ static int mr_smooth_h16(wmg_ctx *c, const void *r, const double *rn2, void *e, 
 // nsteps minimal-residual steps on A e = r from e (post-smoother, Sec. 3).
 // On the fine level the residual and the two step reductions are fused into
 // the operator's kernel.
-static int mr_smooth(wmg_ctx *c, int l, int prec, const void *r, void *e, int nsteps, int nrhs) {
+// ------------------------------------------------------------ red/black smoother
+// Red/black form of the fine-level post-smoother (Sec. 3, MG combined with
+// red/black preconditioning): with s = r - D e, the correction d of D d = s
+// has d_e from nsteps MR steps on the Schur complement
+//   S d_e = s_e - D_eo D_oo^-1 s_o,  S = (4+m) - D_eo D_oe / (4+m)
+// (from d_e = 0, solution update deferred as in mr_smooth), and
+// d_o = D_oo^-1 (s_o - D_oe d_e); then e += d.  With D_{p,1-p} = -H_p/2:
+// S x = (4+m) x - H_e(H_o(x)) / (4 (4+m)), the right-hand side is
+// s_e + H_e(s_o) / (2 (4+m)) and d_o = (s_o + H_o(d_e) / 2) / (4+m).
+static int eo_links(wmg_ctx *c, int lp, const void **Ue) {
+  Level &F = c->lv[0];
+  if (!F.Ue[lp]) {
+    const size_t cs[3] = {16, 8, 4};
+    TRY(dalloc(&F.Ue[lp], cs[lp] * 2 * 4 * (F.lk ? 6 : 9) * (size_t)eo_stride(F.g)));
+    TRY(links_to_eo(F.g, F.U[P64], lp | F.lk, F.Ue[lp], c->st));
+  }
+  *Ue = F.Ue[lp];
+  return 0;
+}
+
+// prec P64: all in FP64.  prec P16: r FP32 used as r/|r| (|r|^2 in rn2),
+// sublattice vectors and MR iterates FP16, corrections and e FP32.
+static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, void *e, int nsteps, int nrhs) {
+  Level &L = c->lv[0];
+  const int lp = sp == P64 ? P64 : P16;   // link precision
+  const int vp = sp == P64 ? P64 : P16;   // sublattice residuals and MR iterates
+  const int dp = sp == P64 ? P64 : P32;   // corrections
+  const void *Ue;
+  TRY(eo_links(c, lp, &Ue));
+  const int lc = lp | L.lk;
+  void *s, *xk[4] = {nullptr, nullptr, nullptr, nullptr}, *q, *t, *se, *so, *de, *dd;
+  const int names[4] = {VH0, VH1, VH2, VH3};
+  TRY(level_vec(c, 0, vp, VS, &s, nrhs));
+  for (int k = 0; k < nsteps; k++) TRY(level_vec(c, 0, vp, names[k], &xk[k], nrhs));
+  TRY(level_vec(c, 0, vp, VHQ, &q, nrhs));
+  TRY(level_vec(c, 0, vp, VHT, &t, nrhs));
+  TRY(level_vec(c, 0, vp, VHSE, &se, nrhs));
+  TRY(level_vec(c, 0, vp, VHSO, &so, nrhs));
+  TRY(level_vec(c, 0, dp, VHDE, &de, nrhs));
+  TRY(level_vec(c, 0, dp, VHDO, &dd, nrhs));
+  const double m4 = 4.0 + L.m;
+  const long nh = 12 * eo_stride(L.g);
+  const double vb = (double)L.g.V * fine_link_cx(L) * (lp == P64 ? 16 : 4);  // links of both halves
+  const double eb = sp == P64 ? 16 : 4;                                        // sublattice element bytes
+  // s = r - D e (full lattice; FP16 on the normalised problem), split
+  c->st_fine++;
+  int slot;
+  if (sp == P64) {
+    TRY(fine_apply_fused(c, P64, e, s, nrhs, r, false));
+  } else {
+    slot = prof_begin(c, K_DSLASH_RES, vb + (double)L.g.V * 12 * (8 + 8 + 4) * nrhs);
+    int rc = wilson_soa_h16(L.g, fine_links(L, P16), P32, L.m, e, s, nrhs, r, rn2, 4, nullptr, nullptr, 0, c->st,
+                            L.lk);
+    prof_end(c, slot);
+    TRY(rc);
+  }
+  TRY(eo_pack(L.g, vp, s, vp, se, so, nrhs, c->st));
+  // x_0 = s_e + H_e(s_o) / (2 (4+m))
+  TRY(hop_eo(L.g, lc, Ue, 0, 1.0, 0.5 / m4, vp, se, vp, so, vp, xk[0], nrhs, nullptr, nullptr, 0, c->st));
+  dim3 g = sp == P64 ? grid_for<double2>(nh, nrhs) : grid_for<__half2>(nh, nrhs);
+  for (int k = 0; k < nsteps; k++) {
+    // q = S x_k with <q, x_k>, |q|^2 -> mr_red[k]; x_{k+1} = x_k - alpha_k q
+    c->st_fine++;
+    slot = prof_begin(c, K_DSLASH_CYCLE, 2 * vb + (double)L.g.V * 12 * eb * 2 * nrhs);
+    int rc = hop_eo(L.g, lc, Ue, 1, 0.0, 1.0, vp, nullptr, vp, xk[k], vp, t, nrhs, nullptr, nullptr, 0, c->st);
+    if (!rc)
+      rc = hop_eo(L.g, lc, Ue, 0, m4, -0.25 / m4, vp, xk[k], vp, t, vp, q, nrhs, c->dred,
+                  c->mr_red + (size_t)k * 64 * 4, 4, c->st);
+    prof_end(c, slot);
+    TRY(rc);
+    if (k + 1 < nsteps) {
+      if (sp == P64)
+        hipLaunchKernelGGL(k_mr_next<double2>, g, dim3(256), 0, c->st, c->mr_red, k, (const double2 *)xk[k],
+                           (const double2 *)q, (double2 *)xk[k + 1], nh);
+      else
+        hipLaunchKernelGGL(k_mr_next<__half2>, g, dim3(256), 0, c->st, c->mr_red, k, (const __half2 *)xk[k],
+                           (const __half2 *)q, (__half2 *)xk[k + 1], nh);
+      WMG_HIP(hipGetLastError());
+    }
+  }
+  // d_e = sum_k alpha_k x_k
+  TRY(zero(dp, de, nh, nrhs, c->st));
+  MrVecs mv{{xk[0], xk[1], xk[2], xk[3]}};
+  if (sp == P64)
+    hipLaunchKernelGGL(k_mr_accum<double2>, g, dim3(256), 0, c->st, c->mr_red, nsteps, mv, (double2 *)de, nh);
+  else
+    hipLaunchKernelGGL((k_mr_accum<float2, __half2>), g, dim3(256), 0, c->st, c->mr_red, nsteps, mv, (float2 *)de, nh);
+  WMG_HIP(hipGetLastError());
+  // d_o = (s_o + H_o(d_e) / 2) / (4+m); e += d
+  TRY(hop_eo(L.g, lc, Ue, 1, 1.0 / m4, 0.5 / m4, vp, so, dp, de, dp, dd, nrhs, nullptr, nullptr, 0, c->st));
+  return eo_unpack_add(L.g, dp, e, dp, de, dd, nrhs, c->st);
+}
+
+static int mr_smooth(wmg_ctx *c, int l, int prec, const void *r, void *e, int nsteps, int nrhs,
+                     bool in_cycle = false) {
   Level &L = c->lv[l];
+  if (in_cycle && L.fine && prec == P64 && (c->p.flags & WMG_EO_SMOOTHER) && nsteps >= 1 && nsteps <= 4 && nrhs <= 64)
+    return mr_smooth_eo(c, P64, r, nullptr, e, nsteps, nrhs);
   void *s, *q;
   TRY(level_vec(c, l, prec, VS, &s, nrhs));
   TRY(level_vec(c, l, prec, VQ, &q, nrhs));
@@ -544,7 +691,7 @@ static int mr_smooth(wmg_ctx *c, int l, int prec, const void *r, void *e, int ns
     const int names[4] = {VS, VS1, VS2, VS3};
     for (int k = 1; k < nsteps; k++) TRY(level_vec(c, l, prec, names[k], &sv[k], nrhs));
     TRY(fine_apply_fused(c, prec, e, s, nrhs, r, false));
-    dim3 g = grid_for<double2>(L.n, nrhs);
+    dim3 g = prec == P64 ? grid_for<double2>(L.n, nrhs) : grid_for<float2>(L.n, nrhs);
     for (int k = 0; k < nsteps; k++) {
       TRY(fine_apply_fused(c, prec, sv[k], q, nrhs, nullptr, true, c->mr_red + (size_t)k * 64 * 4));
       if (k + 1 < nsteps) {
@@ -688,8 +835,9 @@ static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int n
     }
   }
   TRY(transfer_prolong(c, l, prec, ec, e, nrhs));
+  if (h16 && (c->p.flags & WMG_EO_SMOOTHER)) return mr_smooth_eo(c, P16, r, c->cyc_nrm, e, c->p.post_smooth, nrhs);
   if (h16) return mr_smooth_h16(c, r, c->cyc_nrm, e, c->p.post_smooth, nrhs);
-  TRY(mr_smooth(c, l, prec, r, e, c->p.post_smooth, nrhs));
+  TRY(mr_smooth(c, l, prec, r, e, c->p.post_smooth, nrhs, true));
   return 0;
 }
 
@@ -974,8 +1122,11 @@ static void free_ctx(wmg_ctx *c) {
   for (auto *b : c->batch) free_ctx(b);
   for (int l = 0; l < 3; l++) {
     Level &L = c->lv[l];
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < 3; i++) {
       if (L.U[i]) (void)hipFree(L.U[i]);
+      if (L.Uk[i]) (void)hipFree(L.Uk[i]);
+      if (L.Ue[i]) (void)hipFree(L.Ue[i]);
+    }
     void *ps[] = {L.Y64, L.Y32, L.Ym, L.Ymh, L.Ymsc, L.vecs, L.P64, L.P32, L.P16, L.Ps};
     for (void *p : ps)
       if (p) (void)hipFree(p);
@@ -1089,6 +1240,9 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
   if (p.levels < 2 || p.levels > 3) return set_error(WMG_EINVAL, "levels = %d (2 or 3)", p.levels);
   if (p.gcr_restart < 1 || p.gcr_restart > KMAX) return set_error(WMG_EINVAL, "gcr_restart = %d", p.gcr_restart);
   if (p.nrhs_max < 1 || p.nrhs_max > 64) return set_error(WMG_EINVAL, "nrhs_max = %d", p.nrhs_max);
+  if (p.flags & WMG_EO_SMOOTHER)
+    for (int i = 0; i < 4; i++)
+      if (g->L[i] % 2) return set_error(WMG_EINVAL, "red/black smoother needs even extents (L[%d] = %d)", i, g->L[i]);
   int L[4] = {g->L[0], g->L[1], g->L[2], g->L[3]};
   int dof = 12;
   for (int l = 0; l + 1 < p.levels; l++) {
@@ -1137,12 +1291,9 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
     F.n = F.n_alloc = F.g.Vs * 12;
     F.m = m;
     CK(dalloc((void **)&c->dred, sizeof(double) * 3 * (size_t)p.nrhs_max * wilson_red_blocks(F.g)));
-    CK(dalloc(&F.U[P64], 16 * 36 * (size_t)F.g.Vs));
+    CK(dalloc(&F.U[P64], 16 * 36 * (size_t)F.g.Vs));  // whole links: the Galerkin build reads these
     CK(links_to_soa(F.g, U, P64, F.U[P64], c->st));
-    CK(dalloc(&F.U[P32], 8 * 36 * (size_t)F.g.Vs));
-    CK(links_to_soa(F.g, U, P32, F.U[P32], c->st));
-    CK(dalloc(&F.U[P16], 4 * 36 * (size_t)F.g.Vs));
-    CK(links_to_soa(F.g, U, P16, F.U[P16], c->st));
+    CK(fine_link_format(c, F, U, (p.flags & WMG_LINKS18) != 0));
     for (int l = 0; l + 1 < c->nl; l++) {
       Level &A = c->lv[l], &C = c->lv[l + 1];
       for (int i = 0; i < 4; i++) A.b[i] = p.block[l][i];
@@ -1334,6 +1485,217 @@ int mg_coarse_apply(wmg_ctx *c, int level, const double *in, double *out, int da
   return sync(c);
 }
 
+// ------------------------------------------------------------ setup reuse
+// File of a setup: header, then the null vectors of every level in the
+// canonical layout [nv][V][dof] (complex128), then an FNV-1a checksum of
+// everything before it.  Loading rebuilds P and the coarse operators from
+// the vectors for the links given (Sec. 4: the setup is amortised over
+// many solves and, as U evolves, refreshed instead of redone).
+struct SetupFileHeader {
+  char magic[8];      // "WMGSETUP"
+  int version;        // 1
+  int L[4];
+  int levels;
+  int nv[2];
+  int dof[2];         // per-site dof of levels 0 and 1
+  long V[2];          // sites of levels 0 and 1
+  double mass;
+  wmg_params params;
+};
+
+static uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
+  const unsigned char *b = (const unsigned char *)p;
+  for (size_t i = 0; i < n; i++) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+static int read_setup_file(const char *path, SetupFileHeader &h, std::vector<std::vector<double>> &vecs) {
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return set_error(WMG_EINVAL, "mg_load: cannot open %s", path);
+  int rc = 0;
+  uint64_t sum = 1469598103934665603ull, stored = 0;
+  if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, "WMGSETUP", 8) || h.version != 1 ||
+      h.levels < 2 || h.levels > 3)
+    rc = set_error(WMG_EINVAL, "mg_load: %s is not a setup file of this library", path);
+  sum = fnv1a(sum, &h, sizeof(h));
+  for (int l = 0; !rc && l + 1 < h.levels; l++) {
+    if (h.nv[l] < 1 || h.nv[l] > 64 || h.dof[l] < 1 || h.V[l] < 1 || h.V[l] > (1L << 34)) {
+      rc = set_error(WMG_EINVAL, "mg_load: %s: bad level %d sizes", path, l);
+      break;
+    }
+    vecs.emplace_back((size_t)h.nv[l] * h.V[l] * h.dof[l] * 2);
+    auto &v = vecs.back();
+    if (std::fread(v.data(), sizeof(double), v.size(), f) != v.size()) {
+      rc = set_error(WMG_EINVAL, "mg_load: %s is truncated", path);
+      break;
+    }
+    sum = fnv1a(sum, v.data(), sizeof(double) * v.size());
+  }
+  if (!rc && std::fread(&stored, sizeof(stored), 1, f) != 1) rc = set_error(WMG_EINVAL, "mg_load: %s is truncated", path);
+  if (!rc && stored != sum) rc = set_error(WMG_EINVAL, "mg_load: %s fails its checksum", path);
+  std::fclose(f);
+  return rc;
+}
+
+// rebuild every level from the null vectors in F.vecs (levels in order:
+// level l's vectors live on the operator that level l-1 built)
+static int rebuild_all(wmg_ctx *c) {
+  for (int l = 0; l + 1 < c->nl; l++) TRY(build_level(c, l, c->lv[l].nv_max));
+  TRY(sync(c));
+  return make_low_precision(c);
+}
+
+// Improve every null vector of level l by `iters` steps of GCR on A x = 0,
+// preconditioned with the current hierarchy, starting from the vector
+// itself; then normalise.  Levels above l must already be built for the
+// current links.
+static int refresh_level(wmg_ctx *c, int l, int iters) {
+  Level &F = c->lv[l];
+  GcrBuf *B;
+  TRY(gcr_buffers(c, l, P64, 1, &B));
+  std::vector<int> its;
+  const long n = F.n;
+  for (int k = 0; k < F.nv_max; k++) {
+    TRY(copy(P64, B->x64, P64, F.vecs + (size_t)k * n, n, 1, c->st));
+    TRY(zero(P64, B->b64, n, 1, c->st));
+    int rc = gcr_solve(c, l, *B, 1, 0.0, iters, 1, 0.0, true, its, nullptr);
+    if (rc < 0) return rc;
+    TRY(norm2(c->red, P64, B->x64, n, 1, c->red_out, 4, c->st));
+    TRY(scale_inv_sqrt(P64, B->x64, c->red_out, 4, n, 1, c->st));
+    TRY(copy(P64, F.vecs + (size_t)k * n, P64, B->x64, n, 1, c->st));
+  }
+  return sync(c);
+}
+
+int mg_save(wmg_ctx *c, const char *path) {
+  g_err[0] = 0;
+  if (!c || !path) return set_error(WMG_EINVAL, "null argument");
+  if (!c->batch.empty()) return set_error(WMG_EINVAL, "mg_save on a batch context");
+  SetupFileHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, "WMGSETUP", 8);
+  h.version = 1;
+  for (int i = 0; i < 4; i++) h.L[i] = c->lv[0].g.L[i];
+  h.levels = c->nl;
+  for (int l = 0; l + 1 < c->nl; l++) {
+    h.nv[l] = c->lv[l].nv_max;
+    h.dof[l] = c->lv[l].dof;
+    h.V[l] = c->lv[l].g.V;
+  }
+  h.mass = c->lv[0].m;
+  h.params = c->p;
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return set_error(WMG_EINVAL, "mg_save: cannot create %s", path);
+  uint64_t sum = fnv1a(1469598103934665603ull, &h, sizeof(h));
+  int rc = std::fwrite(&h, sizeof(h), 1, f) == 1 ? 0 : set_error(WMG_EINVAL, "mg_save: write to %s failed", path);
+  for (int l = 0; !rc && l + 1 < c->nl; l++) {
+    Level &F = c->lv[l];
+    const size_t cnt = (size_t)F.nv_max * F.g.V * F.dof;
+    double *tmp = nullptr;
+    rc = dalloc((void **)&tmp, 16 * cnt);
+    if (!rc) rc = from_internal(c, l, F.vecs, tmp, F.nv_max);
+    std::vector<double> hv(2 * cnt);
+    if (!rc && hipMemcpyAsync(hv.data(), tmp, 16 * cnt, hipMemcpyDeviceToHost, c->st) != hipSuccess)
+      rc = set_error(WMG_EHIP, "mg_save: read-back");
+    if (!rc) rc = sync(c);
+    if (tmp) (void)hipFree(tmp);
+    if (!rc && std::fwrite(hv.data(), sizeof(double), hv.size(), f) != hv.size())
+      rc = set_error(WMG_EINVAL, "mg_save: write to %s failed", path);
+    sum = fnv1a(sum, hv.data(), sizeof(double) * hv.size());
+  }
+  if (!rc && std::fwrite(&sum, sizeof(sum), 1, f) != 1) rc = set_error(WMG_EINVAL, "mg_save: write to %s failed", path);
+  if (std::fclose(f) && !rc) rc = set_error(WMG_EINVAL, "mg_save: closing %s failed", path);
+  return rc;
+}
+
+int mg_load(const char *path, const wmg_geom *g, const double *U, double m, const wmg_params *p, wmg_ctx **out) {
+  g_err[0] = 0;
+  if (!path || !g || !U || !out) return set_error(WMG_EINVAL, "null argument");
+  SetupFileHeader h;
+  std::vector<std::vector<double>> vecs;
+  TRY(read_setup_file(path, h, vecs));
+  for (int i = 0; i < 4; i++)
+    if (g->L[i] != h.L[i])
+      return set_error(WMG_EINVAL, "mg_load: lattice %dx%dx%dx%d, the file holds %dx%dx%dx%d", g->L[0], g->L[1],
+                       g->L[2], g->L[3], h.L[0], h.L[1], h.L[2], h.L[3]);
+  wmg_params q = h.params;
+  if (p) {
+    // solver settings may change; the hierarchy's shape must not
+    bool same = p->levels == h.params.levels;
+    for (int l = 0; same && l + 1 < h.levels; l++) {
+      same = same && p->nvec[l] == h.params.nvec[l];
+      for (int i = 0; i < 4 && l > 0; i++) same = same && p->block[l][i] == h.params.block[l][i];
+    }
+    if (!same) return set_error(WMG_EINVAL, "mg_load: parameters describe another hierarchy than %s", path);
+    q = *p;
+    q.block[0][0] = h.params.block[0][0];  // block[0] and nvec[0] come from the file
+    for (int i = 0; i < 4; i++) q.block[0][i] = h.params.block[0][i];
+  }
+  double t0 = now_s();
+  wmg_ctx *c = nullptr;
+  TRY(ctx_create(g, U, m, h.nv[0], h.params.block[0], &q, &c));
+  int rc = 0;
+  for (int l = 0; !rc && l + 1 < c->nl; l++) {
+    Level &F = c->lv[l];
+    if (F.nv_max != h.nv[l] || F.dof != h.dof[l] || F.g.V != h.V[l]) {
+      rc = set_error(WMG_EINVAL, "mg_load: level %d of %s does not match the parameters", l, path);
+      break;
+    }
+    double *tmp = nullptr;
+    const size_t cnt = (size_t)F.nv_max * F.g.V * F.dof;
+    rc = dalloc((void **)&tmp, 16 * cnt);
+    if (!rc && hipMemcpyAsync(tmp, vecs[l].data(), 16 * cnt, hipMemcpyHostToDevice, c->st) != hipSuccess)
+      rc = set_error(WMG_EHIP, "mg_load: upload");
+    if (!rc) rc = to_internal(c, l, tmp, F.vecs, F.nv_max);
+    if (!rc) rc = sync(c);
+    if (tmp) (void)hipFree(tmp);
+    if (!rc) rc = build_level(c, l, F.nv_max);  // the next level's vectors live on this operator
+  }
+  if (!rc) rc = sync(c);
+  if (!rc) rc = make_low_precision(c);
+  if (rc) {
+    free_ctx(c);
+    return rc;
+  }
+  c->setup_s = now_s() - t0;
+  *out = c;
+  return 0;
+}
+
+int mg_refresh(wmg_ctx *c, const double *U, int iters) {
+  g_err[0] = 0;
+  if (!c || !U || iters < 0) return set_error(WMG_EINVAL, "bad argument");
+  if (!c->batch.empty()) return set_error(WMG_EINVAL, "mg_refresh on a batch context");
+  double t0 = now_s();
+  Level &F = c->lv[0];
+  // new links in every format the context keeps
+  TRY(links_to_soa(F.g, U, P64, F.U[P64], c->st));
+  for (int lp = P64; lp <= P16; lp++) {
+    if (F.Ue[lp]) (void)hipFree(F.Ue[lp]);
+    F.Ue[lp] = nullptr;
+    if (F.Uk[lp]) (void)hipFree(F.Uk[lp]);
+    if (lp != P64 && F.U[lp]) (void)hipFree(F.U[lp]);
+    F.Uk[lp] = nullptr;
+    if (lp != P64) F.U[lp] = nullptr;
+  }
+  TRY(fine_link_format(c, F, U, (c->p.flags & WMG_LINKS18) != 0));
+  // Galerkin operators for the new links from the old vectors, then each
+  // level's vectors relaxed with that hierarchy and the level rebuilt
+  TRY(rebuild_all(c));
+  if (iters > 0)
+    for (int l = 0; l + 1 < c->nl; l++) {
+      TRY(refresh_level(c, l, iters));
+      for (int k = l; k + 1 < c->nl; k++) TRY(build_level(c, k, c->lv[k].nv_max));
+      TRY(sync(c));
+      TRY(make_low_precision(c));
+    }
+  c->setup_s = now_s() - t0;
+  return 0;
+}
+
 // restriction (dir 0) or prolongation (dir 1) through the FP32 vectors and
 // FP16-stored prolongator of a mixed-precision context
 static int transfer_f32(wmg_ctx *c, int level, int dir, const double *in, double *out, int nrhs) {
@@ -1382,7 +1744,7 @@ int mg_coarse_apply_f32(wmg_ctx *c, int level, const double *in, double *out, in
 }
 
 int mg_apply_fine(wmg_ctx *c, int prec, const double *in, double *out, int nrhs) {
-  if (!c || !in || !out || nrhs < 1 || nrhs > c->p.nrhs_max || prec < 0 || prec > 2)
+  if (!c || !in || !out || nrhs < 1 || nrhs > c->p.nrhs_max || nrhs > 64 || prec < 0 || prec > 3)
     return set_error(WMG_EINVAL, "bad argument");
   Level &F = c->lv[0];
   void *a64, *b64;
@@ -1390,16 +1752,62 @@ int mg_apply_fine(wmg_ctx *c, int prec, const double *in, double *out, int nrhs)
   TRY(level_vec(c, 0, P64, VT, &b64, nrhs));
   TRY(spinor_to_soa(F.g, in, (double2 *)a64, nrhs, c->st));
   if (prec == 0) {
-    TRY(wilson_soa(F.g, P64, F.U[P64], P64, F.m, a64, b64, nrhs, c->st));
-  } else {
+    TRY(wilson_soa(F.g, fine_lcode(F, P64), fine_links(F, P64), P64, F.m, a64, b64, nrhs, c->st));
+  } else if (prec < 3) {
     void *a32, *b32;
     TRY(level_vec(c, 0, P32, VX, &a32, nrhs));
     TRY(level_vec(c, 0, P32, VT, &b32, nrhs));
     TRY(copy(P32, a32, P64, a64, F.n, nrhs, c->st));
-    TRY(wilson_soa(F.g, prec == 1 ? P32 : P16, F.U[prec == 1 ? P32 : P16], P32, F.m, a32, b32, nrhs, c->st));
+    const int lp = prec == 1 ? P32 : P16;
+    TRY(wilson_soa(F.g, fine_lcode(F, lp), fine_links(F, lp), P32, F.m, a32, b32, nrhs, c->st));
+    TRY(copy(P64, b64, P32, b32, F.n, nrhs, c->st));
+  } else {
+    // the MR step's operator: in/|in| stored in FP16 by the smoother's
+    // residual kernel (with e = 0), then FP16 links on FP16 spinors, FP16
+    // output; returned as FP64 times |in|
+    if (F.n % 4) return set_error(WMG_EINVAL, "length not a multiple of 4");
+    void *a32, *e32, *h0, *h1, *b32;
+    TRY(level_vec(c, 0, P32, VX, &a32, nrhs));
+    TRY(level_vec(c, 0, P32, VE, &e32, nrhs));
+    TRY(level_vec(c, 0, P32, VT, &b32, nrhs));
+    TRY(level_vec(c, 0, P16, VS, &h0, nrhs));
+    TRY(level_vec(c, 0, P16, VQ, &h1, nrhs));
+    TRY(copy(P32, a32, P64, a64, F.n, nrhs, c->st));
+    TRY(zero(P32, e32, F.n, nrhs, c->st));
+    double *rn2 = c->cyc_nrm;
+    TRY(norm2(c->red, P32, a32, F.n, nrhs, rn2, 4, c->st));
+    TRY(wilson_soa_h16(F.g, fine_links(F, P16), P32, F.m, e32, h0, nrhs, a32, rn2, 4, nullptr, nullptr, 0, c->st,
+                       F.lk));
+    TRY(wilson_soa_h16(F.g, fine_links(F, P16), P16, F.m, h0, h1, nrhs, nullptr, nullptr, 0, nullptr, nullptr, 0,
+                       c->st, F.lk));
+    TRY(copy(P32, b32, P16, h1, F.n, nrhs, c->st));
+    TRY(scale_sqrt(P32, b32, rn2, 4, F.n, nrhs, c->st));
     TRY(copy(P64, b64, P32, b32, F.n, nrhs, c->st));
   }
   TRY(spinor_from_soa(F.g, (double2 *)b64, out, nrhs, c->st));
+  return sync(c);
+}
+
+int mg_smoother_residual(wmg_ctx *c, const double *r, const double *e, double *out, int nrhs) {
+  if (!c || !r || !e || !out || nrhs < 1 || nrhs > c->p.nrhs_max || nrhs > 64) return set_error(WMG_EINVAL, "bad argument");
+  Level &F = c->lv[0];
+  if (F.n % 4) return set_error(WMG_EINVAL, "length not a multiple of 4");
+  void *a64, *r32, *e32, *h0, *b32;
+  TRY(level_vec(c, 0, P64, VX, &a64, nrhs));
+  TRY(level_vec(c, 0, P32, VX, &r32, nrhs));
+  TRY(level_vec(c, 0, P32, VE, &e32, nrhs));
+  TRY(level_vec(c, 0, P32, VT, &b32, nrhs));
+  TRY(level_vec(c, 0, P16, VS, &h0, nrhs));
+  TRY(spinor_to_soa(F.g, r, (double2 *)a64, nrhs, c->st));
+  TRY(copy(P32, r32, P64, a64, F.n, nrhs, c->st));
+  TRY(spinor_to_soa(F.g, e, (double2 *)a64, nrhs, c->st));
+  TRY(copy(P32, e32, P64, a64, F.n, nrhs, c->st));
+  double *rn2 = c->cyc_nrm;
+  TRY(norm2(c->red, P32, r32, F.n, nrhs, rn2, 4, c->st));
+  TRY(wilson_soa_h16(F.g, fine_links(F, P16), P32, F.m, e32, h0, nrhs, r32, rn2, 4, nullptr, nullptr, 0, c->st, F.lk));
+  TRY(copy(P32, b32, P16, h0, F.n, nrhs, c->st));
+  TRY(copy(P64, a64, P32, b32, F.n, nrhs, c->st));
+  TRY(spinor_from_soa(F.g, (double2 *)a64, out, nrhs, c->st));
   return sync(c);
 }
 
@@ -1428,12 +1836,13 @@ int mg_time_dslash(wmg_ctx *c, int prec, int nrhs, int reps, double *ms) {
   TRY(level_vec(c, 0, P64, VE2, &a64, 1));
   TRY(start_vectors(F.g.V, 12, 99, 7, 0, 1, (double2 *)a64, 1, F.g.Vs, c->st));
   for (int r = 0; r < nrhs; r++) TRY(copy(sp, (char *)a + csize(sp) * (size_t)F.n * r, P64, a64, F.n, 1, c->st));
-  TRY(wilson_soa(F.g, lp, F.U[lp], sp, F.m, a, b, nrhs, c->st));  // warm-up
+  TRY(wilson_soa(F.g, fine_lcode(F, lp), fine_links(F, lp), sp, F.m, a, b, nrhs, c->st));  // warm-up
   hipEvent_t e0, e1;
   WMG_HIP(hipEventCreate(&e0));
   WMG_HIP(hipEventCreate(&e1));
   WMG_HIP(hipEventRecord(e0, c->st));
-  for (int i = 0; i < reps; i++) TRY(wilson_soa(F.g, lp, F.U[lp], sp, F.m, (i & 1) ? b : a, (i & 1) ? a : b, nrhs, c->st));
+  for (int i = 0; i < reps; i++)
+    TRY(wilson_soa(F.g, fine_lcode(F, lp), fine_links(F, lp), sp, F.m, (i & 1) ? b : a, (i & 1) ? a : b, nrhs, c->st));
   WMG_HIP(hipEventRecord(e1, c->st));
   WMG_HIP(hipEventSynchronize(e1));
   float t = 0;
@@ -1442,6 +1851,12 @@ int mg_time_dslash(wmg_ctx *c, int prec, int nrhs, int reps, double *ms) {
   (void)hipEventDestroy(e1);
   *ms = t / reps;
   return 0;
+}
+
+int mg_link_reals(wmg_ctx *c) {
+  if (!c) return set_error(WMG_EINVAL, "null context");
+  if (!c->batch.empty()) return mg_link_reals(c->batch[0]);
+  return c->lv[0].lk ? 12 : 18;
 }
 
 int mg_set_precision(wmg_ctx *c, int precision) {

@@ -19,6 +19,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
+#include <string>
+
 namespace wmg {
 
 // ---------------------------------------------------------------- complex
@@ -130,6 +133,9 @@ __host__ __device__ __forceinline__ long xcd_grid(long ntiles) { return (ntiles 
 __device__ __forceinline__ long xcd_tile(long bid, long grid) { return (bid % NXCD) * (grid / NXCD) + bid / NXCD; }
 
 enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+// link-precision flag: links stored as their first two rows (SU(3) fields,
+// third row rebuilt in the kernel), layout [4][6][Vs]
+static constexpr int LK12 = 8;
 
 // ---------------------------------------------------------------- errors
 int set_error(int code, const char *fmt, ...);
@@ -138,6 +144,15 @@ int set_error(int code, const char *fmt, ...);
     hipError_t e_ = (call);                                                            \
     if (e_ != hipSuccess) return ::wmg::set_error(-3, "%s:%d %s: %s", __FILE__, __LINE__, #call, hipGetErrorString(e_)); \
   } while (0)
+
+// ---------------------------------------------------------------- autotuner
+// tune.hip: *choice = the fastest of candidates 0..ncand-1 for this key
+// (searched once per process, or read from the WMG_TUNE_CACHE file); run(c)
+// launches candidate c once on st and returns 0 or an error code.  The last
+// launch is always run(*choice).
+int tune_choice(const std::string &key, int ncand, const std::function<int(int)> &run, hipStream_t st, int *choice);
+// the stored choice for key, or -1
+int tune_lookup(const std::string &key);
 
 // ---------------------------------------------------------------- kernels
 // dslash.hip
@@ -155,11 +170,34 @@ int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double 
 // only with iprec P32) is scaled per rhs by 1/sqrt(bnrm2[rhs * bstride])
 // (0 where that norm is 0); red as in wilson_soa_fused, computed from the
 // stored (rounded) output.
+// lflags: LK12 for links stored as two rows.
 int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
                    const void *bsub, const double *bnrm2, int bstride, double *red, double *red_out, int red_stride,
-                   hipStream_t st);
+                   hipStream_t st, int lflags = 0);
 long wilson_red_blocks(const Geom &g);
+// ---- red/black (even-odd) sublattices; requires every extent even.
+// Compact half-lattice arrays: site of lexicographic index s, parity p at
+// index s/2 of parity p's array; fields [rhs][12][eo_stride], links
+// [parity][4][NR][eo_stride].
+long eo_stride(const Geom &g);
+// out = a in_diag + b H_par(in_hop) on the sites of parity par (H: the
+// hopping sum of Eq. 2.2 from the other sublattice; D_{p,1-p} = -H/2);
+// with red, <out, in_diag> and |out|^2 per rhs -> red_out[rhs * stride + 0..2]
+// (red: scratch of nrhs * wilson_red_blocks * 3).  Precision combinations:
+// all FP64; FP16 links with FP16 in_diag and in_hop/out FP16 or FP32.
+int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b, int pdiag, const void *in_diag,
+           int phop, const void *in_hop, int pout, void *out, int nrhs, double *red, double *red_out, int red_stride,
+           hipStream_t st);
+int eo_pack(const Geom &g, int pfull, const void *full, int phalf, void *ev, void *od, int nrhs, hipStream_t st);
+int eo_unpack_add(const Geom &g, int pfull, void *full, int phalf, const void *ev, const void *od, int nrhs,
+                  hipStream_t st);
+int links_to_eo(const Geom &g, const void *U64soa, int lprec, void *Ue, hipStream_t st);
+// lprec may carry LK12: only the first two rows, layout [4][6][Vs]
 int links_to_soa(const Geom &g, const double *Ucanon, int lprec, void *Usoa, hipStream_t st);
+// per-workgroup largest error of the 12-real reconstruction of canonical
+// FP64 links (su3_recon_blocks(g) doubles)
+long su3_recon_blocks(const Geom &g);
+int su3_recon_err(const Geom &g, const double *Ucanon, double *part, hipStream_t st);
 int spinor_to_soa(const Geom &g, const double *canon, double2 *soa, int nrhs, hipStream_t st);
 int spinor_from_soa(const Geom &g, const double2 *soa, double *canon, int nrhs, hipStream_t st);
 
@@ -211,6 +249,8 @@ int caxpy_norm(Reducer &R, int prec, const double *a, int astride, const void *x
 int csub(int prec, const void *a, const void *b, void *y, long n, int nrhs, hipStream_t st);
 // x *= 1/sqrt(nrm2[rhs])  (nrm2 device)
 int scale_inv_sqrt(int prec, void *x, const double *nrm2, int stride, long n, int nrhs, hipStream_t st);
+// x *= sqrt(nrm2[rhs])
+int scale_sqrt(int prec, void *x, const double *nrm2, int stride, long n, int nrhs, hipStream_t st);
 int sigma3(int prec, void *x, long nsite, int dof, int nrhs, hipStream_t st);
 
 // transfer.hip

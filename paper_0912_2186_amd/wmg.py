@@ -33,6 +33,8 @@ WMG_VCYCLE = 0
 WMG_WCYCLE = 1
 WMG_X0_GIVEN = 1
 WMG_COARSE_FP32 = 2
+WMG_LINKS18 = 4
+WMG_EO_SMOOTHER = 8
 
 
 class WmgError(RuntimeError):
@@ -111,6 +113,11 @@ _sig = {
     "mg_restrict_f32": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_prolong_f32": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_apply_fine": (_i, [_vp, _i, _vp, _vp, _i]),
+    "mg_smoother_residual": (_i, [_vp, _vp, _vp, _vp, _i]),
+    "mg_link_reals": (_i, [_vp]),
+    "mg_save": (_i, [_vp, ctypes.c_char_p]),
+    "mg_load": (_i, [ctypes.c_char_p, _P(Geom), _vp, _d, _P(Params), _P(_vp)]),
+    "mg_refresh": (_i, [_vp, _vp, _i]),
     "mg_cycle": (_i, [_vp, _vp, _vp]),
     "mg_last_iters": (_i, [_vp, _P(_i), _i]),
     "mg_time_dslash": (_i, [_vp, _i, _i, _i, _P(_d)]),
@@ -205,6 +212,25 @@ class MG:
         _check(_lib.mg_setup(ctypes.byref(_geom(self.L)), _ptr(U), float(m), int(Nv), ctypes.byref(blk),
                              ctypes.byref(self.params), ctypes.byref(self.h)))
 
+    @classmethod
+    def load(cls, path: str, L, U: torch.Tensor, m: float, params: Params | None = None) -> "MG":
+        """mg_load: a context rebuilt from a saved setup for links U."""
+        torch.cuda.synchronize()
+        obj = cls.__new__(cls)
+        obj.L = tuple(int(v) for v in L)
+        obj.h = _vp()
+        _check(_lib.mg_load(str(path).encode(), ctypes.byref(_geom(obj.L)), _ptr(U), float(m),
+                            ctypes.byref(params) if params is not None else None, ctypes.byref(obj.h)))
+        obj.params = params
+        return obj
+
+    def mg_save(self, path: str) -> None:
+        _check(_lib.mg_save(self.h, str(path).encode()))
+
+    def mg_refresh(self, U: torch.Tensor, iters: int) -> None:
+        torch.cuda.synchronize()
+        _check(_lib.mg_refresh(self.h, _ptr(U), int(iters)))
+
     def close(self):
         if getattr(self, "h", None) and self.h.value:
             _lib.mg_destroy(self.h)
@@ -283,6 +309,16 @@ class MG:
     def mg_apply_fine(self, prec: int, inp: torch.Tensor, out: torch.Tensor, nrhs: int = 1) -> None:
         torch.cuda.synchronize()
         _check(_lib.mg_apply_fine(self.h, int(prec), _ptr(inp), _ptr(out), int(nrhs)))
+
+    def mg_smoother_residual(self, r: torch.Tensor, e: torch.Tensor, out: torch.Tensor, nrhs: int = 1) -> None:
+        torch.cuda.synchronize()
+        _check(_lib.mg_smoother_residual(self.h, _ptr(r), _ptr(e), _ptr(out), int(nrhs)))
+
+    def mg_link_reals(self) -> int:
+        rc = _lib.mg_link_reals(self.h)
+        if rc < 0:
+            _check(rc)
+        return rc
 
     def mg_cycle(self, r: torch.Tensor, z: torch.Tensor) -> None:
         torch.cuda.synchronize()

@@ -71,3 +71,30 @@ def relerr(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def site_max(v, L):
+    """Largest |re|, |im| over the 12 components of each site: shape (Lt, Lz, Ly, Lx)."""
+    v = np.asarray(v).reshape(vol(L), -1)
+    m = np.maximum(np.abs(v.real), np.abs(v.imag)).max(axis=1)
+    return m.reshape(L[3], L[2], L[1], L[0])
+
+
+def neighbourhood_scale(inp, L):
+    """For every site, the largest component of inp over the site and its 8
+    nearest neighbours (the inputs a Wilson operator reads there)."""
+    m = site_max(inp, L)
+    sc = m.copy()
+    for ax in range(4):
+        for sh in (1, -1):
+            sc = np.maximum(sc, np.roll(m, sh, axis=ax))
+    return sc.reshape(-1)
+
+
+def local_err(out, ref, inp, L, floor=0.0):
+    """max over sites of (largest component error at the site) divided by
+    max(neighbourhood scale of the operator's input there, floor): a
+    per-site bound that a few wrong sites cannot hide, unlike a global norm."""
+    d = site_max(np.asarray(out) - np.asarray(ref), L).reshape(-1)
+    sc = np.maximum(neighbourhood_scale(inp, L), floor)
+    return float(np.max(d / np.maximum(sc, 1e-300)))

@@ -106,3 +106,20 @@ def test_noalloc_rejects_sizes_beyond_its_array(lib):
     assert b"fixed maximum" in lib.wmg_strerror(-1)
     g.L[:] = [8, 8, 8, 8]
     assert f(ctypes.byref(g), None, -0.1, 16, 32, 1e-10, 100, None, None) == -1
+
+
+def test_mg_load_rejects_missing_and_foreign_files(lib, tmp_path):
+    # file checks come before any device work (fake non-null pointers)
+    f = lib.mg_load
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_char_p, ctypes.POINTER(Geom), ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_void_p)]
+    g = Geom()
+    g.L[:] = [8, 8, 8, 8]
+    h = ctypes.c_void_p()
+    assert f(str(tmp_path / "missing").encode(), ctypes.byref(g), 8, -0.1, None, ctypes.byref(h)) == -1
+    bad = tmp_path / "bad"
+    bad.write_bytes(b"\0" * 4096)
+    assert f(str(bad).encode(), ctypes.byref(g), 8, -0.1, None, ctypes.byref(h)) == -1
+    lib.wmg_strerror.restype = ctypes.c_char_p
+    assert b"not a setup file" in lib.wmg_strerror(-1)

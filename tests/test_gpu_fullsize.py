@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from paper_0912_2186_amd import inputs
-from helpers import relerr, vol
+from helpers import local_err, relerr, vol
 
 pytestmark = pytest.mark.gpu
 
@@ -68,15 +68,20 @@ def test_fullsize_dslash_all_precisions(wmg, links32):
     o2 = empty((2, vol(L4), 12))
     b2 = np.concatenate([b, inputs.z4_noise(L4, 411, 1)])
     ref2 = oracle.wilson(L4, U, m, b2[1])
-    res = {}
+    res, loc = {}, {}
     for prec in (0, 1, 2):
         mg.mg_apply_fine(prec, dev(b2), o2, 2)
         oh = host(o2)
         res[prec] = max(relerr(oh[0], ref), relerr(oh[1], ref2))
+        # per site, against the largest input component in the neighbourhood
+        loc[prec] = max(local_err(oh[0], ref, b2[0], L4), local_err(oh[1], ref2, b2[1], L4))
+    reals = mg.mg_link_reals()
     mg.close()
-    say("  fp64 canonical", e64, "internal", res)
+    say("  fp64 canonical", e64, "internal", res, "per site", loc, "link reals", reals)
+    assert reals == 12
     assert e64 < 1e-13
     assert res[0] < 1e-13 and res[1] < 1e-6 and res[2] < 2e-3
+    assert loc[0] < 256 * 2.0 ** -52 and loc[1] < 256 * 2.0 ** -24 and loc[2] < 64 * 2.0 ** -11
 
 
 def test_fullsize_headline_solve(wmg, links32):
@@ -103,6 +108,37 @@ def test_fullsize_headline_solve(wmg, links32):
         rr = relres(L4, U, m, b[r], xh[r])
         say("  rhs", r, "oracle relres", rr)
         assert rr <= 1e-10 * 1.0001
+
+
+def test_solution_error_mixed_multi_rhs_against_oracle(wmg):
+    """The headline's kind of solve on 16^3x32 (eps 0.6, m = -0.32, N_nu =
+    24, mixed precision, 2 point sources + 2 Z4 vectors together): the
+    oracle's FP64 residual r = b - D x of every solution is <= 1e-10 |b|,
+    and the solution error x* - x = D^-1 r, which the oracle solves for
+    with its own BiCGStab (to 1e-4, enough to state the error), is stated
+    and bounded: |x* - x| / |x| <= 1e-7 (at most 1000 x tol)."""
+    L = (16, 16, 16, 32)
+    say("solution error", L)
+    U = inputs.gauge_field(L, 0.6, 3301)
+    m = -0.32
+    b = np.concatenate([inputs.point_sources(L)[:2], inputs.z4_noise(L, 3310, 2)])
+    p = wmg.default_params(setup_iters=10, seed=3350, nrhs_max=4, precision=wmg.WMG_MIXED, coarse_tol=1e-5)
+    mg = wmg.MG(L, dev(U), m, 24, (4, 4, 4, 4), p)
+    x = empty((4, vol(L), 12))
+    st = mg.mg_solve(dev(b), x, 1e-10)
+    mg.close()
+    say("  ", st)
+    assert st["converged"]
+    xh = host(x)
+    for k in range(4):
+        r = b[k] - oracle.wilson(L, U, m, xh[k])
+        rr = np.linalg.norm(r) / np.linalg.norm(b[k])
+        d, its, drr = oracle.bicgstab(L, U, m, r, 1e-4)
+        err = np.linalg.norm(d) / np.linalg.norm(xh[k])
+        say("  rhs", k, "oracle relres %.2e, solution error %.2e (x %.1f of relres; oracle BiCGStab %d its to %.1e)"
+            % (rr, err, err / rr, its, drr))
+        assert rr <= 1e-10 * 1.0001
+        assert drr <= 1e-4 and err <= 1e-7
 
 
 def test_config3_three_level_mixed(wmg):

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_0912_2186_amd import inputs
-from helpers import relerr, vol
+from helpers import local_err, relerr, vol
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +71,121 @@ def test_internal_dslash_precisions(wmg):
         e = relerr(host(out), ref)
         say("  prec", prec, "relerr", e)
         assert e < tol
+
+
+# per-site error bounds, in units of the largest input component in the
+# site's neighbourhood: c * unit roundoff of the storage format
+SITE_BOUND = {0: 256 * 2.0 ** -52, 1: 256 * 2.0 ** -24, 2: 64 * 2.0 ** -11}
+
+
+def test_link_formats_two_rows_and_whole(wmg):
+    """Links read as two rows (12 reals, third row rebuilt as
+    conj(row0 x row1), Table 2) and as whole 3x3 matrices give the oracle's
+    D in every precision, globally and site by site; a field outside SU(3)
+    (a U(1) phase on every link) keeps whole links."""
+    L = (8, 8, 8, 12)
+    V = vol(L)
+    U = inputs.gauge_field(L, 0.5, 301)
+    psi = inputs.gaussian_rhs(L, 203, 2)
+    ref = [oracle.wilson(L, U, -0.2, psi[r]) for r in range(2)]
+    for flags, reals in ((0, 12), (wmg.WMG_LINKS18, 18)):
+        p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=2, flags=flags)
+        mg = wmg.MG(L, dev(U), -0.2, 4, (4, 4, 4, 4), p)
+        assert mg.mg_link_reals() == reals
+        for prec, tol in [(0, 1e-14), (1, 1e-6), (2, 2e-3)]:
+            out = empty((2, V, 12))
+            mg.mg_apply_fine(prec, dev(psi), out, 2)
+            oh = host(out)
+            for r in range(2):
+                e, le = relerr(oh[r], ref[r]), local_err(oh[r], ref[r], psi[r], L)
+                say("  reals", reals, "prec", prec, "rhs", r, "relerr %.2e site %.2e" % (e, le))
+                assert e < tol and le < SITE_BOUND[prec]
+        mg.close()
+    Up = U * np.exp(0.3j)
+    p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=1)
+    mg = wmg.MG(L, dev(Up), -0.2, 4, (4, 4, 4, 4), p)
+    assert mg.mg_link_reals() == 18
+    out = empty((1, V, 12))
+    mg.mg_apply_fine(1, dev(psi[:1]), out, 1)
+    assert relerr(host(out)[0], oracle.wilson(L, Up, -0.2, psi[0])) < 1e-6
+    mg.close()
+
+
+def _fp16_round(v):
+    v = np.asarray(v)
+    return v.real.astype(np.float16).astype(np.float64) + 1j * v.imag.astype(np.float16).astype(np.float64)
+
+
+def _decaying_source(L, site, kappa, seed):
+    """Spin-colour vector falling off as exp(-kappa |x - x0|_1) from one
+    site (periodic distance): a point-source residual spanning many decades."""
+    rng = np.random.default_rng(seed)
+    V = vol(L)
+    x0 = np.unravel_index(site, (L[3], L[2], L[1], L[0]))
+    grid = np.indices((L[3], L[2], L[1], L[0]))
+    d = np.zeros((L[3], L[2], L[1], L[0]))
+    for ax, n in enumerate((L[3], L[2], L[1], L[0])):
+        a = np.abs(grid[ax] - x0[ax])
+        d = d + np.minimum(a, n - a)
+    amp = np.exp(-kappa * d).reshape(V, 1)
+    return amp * (rng.standard_normal((V, 12)) + 1j * rng.standard_normal((V, 12)))
+
+
+def test_fp16_spinor_mr_step_operator(wmg):
+    """The MR step's operator (in/|in| stored in FP16, FP16 links on FP16
+    spinors, FP16 output) against the oracle applied to the same
+    FP16-rounded input, for Gaussian, Z4, point-source and decaying
+    point-source inputs, with two-row and whole links.  Per-site bound:
+    64 * 2^-11 * max(neighbourhood scale, 2^-9 * max component): below
+    2^-9 of the largest component, FP16 storage of the normalised vector
+    (one scale per rhs) keeps only an absolute accuracy."""
+    L = (8, 8, 8, 12)
+    V = vol(L)
+    m = -0.2
+    U = inputs.gauge_field(L, 0.5, 301)
+    srcs = np.stack([inputs.gaussian_rhs(L, 205)[0], inputs.z4_noise(L, 206, 1)[0], inputs.point_sources(L)[4],
+                     _decaying_source(L, 777, 1.5, 207)])
+    for flags in (0, wmg.WMG_LINKS18):
+        p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=4, flags=flags)
+        mg = wmg.MG(L, dev(U), m, 4, (4, 4, 4, 4), p)
+        out = empty((4, V, 12))
+        mg.mg_apply_fine(3, dev(srcs), out, 4)
+        oh = host(out)
+        for r in range(4):
+            nb = np.linalg.norm(srcs[r])
+            q = _fp16_round(srcs[r] / nb)
+            ref = nb * oracle.wilson(L, U, m, q)
+            M = np.abs(q).max()
+            le = local_err(oh[r] / nb, ref / nb, q, L, floor=2.0 ** -9 * M)
+            e = relerr(oh[r], ref)
+            say("  links", mg.mg_link_reals(), "rhs", r, "relerr %.2e site %.2e" % (e, le))
+            assert e < 2e-3 and le < 64 * 2.0 ** -11
+        mg.close()
+
+
+def test_fp16_smoother_residual_kernel(wmg):
+    """The smoother's fused residual kernel out = r/|r| - D e (FP16 links,
+    FP16 output) against the oracle, Gaussian and point-source r, per-site
+    bound against the neighbourhood scale of e and r/|r|."""
+    L = (8, 8, 8, 12)
+    V = vol(L)
+    m = -0.2
+    U = inputs.gauge_field(L, 0.5, 301)
+    r = np.stack([inputs.gaussian_rhs(L, 208)[0], inputs.point_sources(L)[7]])
+    e = 1e-3 * np.stack([inputs.gaussian_rhs(L, 209)[0], _decaying_source(L, 0, 1.0, 210)])
+    p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=2)
+    mg = wmg.MG(L, dev(U), m, 4, (4, 4, 4, 4), p)
+    out = empty((2, V, 12))
+    mg.mg_smoother_residual(dev(r), dev(e), out, 2)
+    oh = host(out)
+    for k in range(2):
+        rn = r[k] / np.linalg.norm(r[k])
+        ref = rn - oracle.wilson(L, U, m, e[k])
+        sc_in = np.concatenate([rn, e[k]], axis=1)
+        le = local_err(oh[k], ref, sc_in, L, floor=2.0 ** -9 * np.abs(sc_in).max())
+        say("  rhs", k, "relerr %.2e site %.2e" % (relerr(oh[k], ref), le))
+        assert relerr(oh[k], ref) < 2e-3 and le < 64 * 2.0 ** -11
+    mg.close()
 
 
 def rand_vecs(nv, V, dof, seed):

@@ -145,6 +145,12 @@ def test_gauge_generator_is_su3():
     U = inputs.gauge_field((4, 4, 4, 4), 0.6, 9).reshape(-1, 3, 3)
     assert np.abs(U @ U.conj().transpose(0, 2, 1) - np.eye(3)).max() < 1e-13
     assert np.abs(np.linalg.det(U) - 1).max() < 1e-13
+    # the 12-real link format (Table 2) rests on SU(3): the third row is the
+    # conjugated cross product of the first two (unitarity + det 1)
+    assert np.abs(np.conj(np.cross(U[:, 0], U[:, 1])) - U[:, 2]).max() < 1e-13
+    # ... and fails for a U(1) x SU(3) link (a phase breaks det = 1)
+    Up = U * np.exp(0.3j)
+    assert np.abs(np.conj(np.cross(Up[:, 0], Up[:, 1])) - Up[:, 2]).max() > 0.1
     # exp(i eps H) against scipy's expm on a few links (library routine)
     import scipy.linalg
 
