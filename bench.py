@@ -202,7 +202,8 @@ def critical_scan(args, w):
     if args.levels == 3:
         kw = dict(levels=3, block=((4, 4, 4, 4), (2, 2, 2, 2)), nvec=(w["nv"], 32))
     p = wmg.default_params(setup_iters=w["setup_iters"], seed=w["seed_cfg"] * 100 + 50, nrhs_max=1,
-                           precision=wmg.WMG_MIXED, coarse_tol=1e-5, **kw)
+                           precision=wmg.WMG_MIXED, coarse_tol=1e-5,
+                           flags=wmg.WMG_EO_SMOOTHER if args.smoother == "redblack" else 0, **kw)
     os.environ.setdefault("WMG_VERBOSE", "1")  # the setup reports each null vector
     torch.cuda.synchronize()
     t0 = time.time()
@@ -222,11 +223,12 @@ def critical_scan(args, w):
                      "coarse_iters": st["coarse_iters"], "s_per_rhs": round(el, 4), "true_relres": st["true_relres"],
                      "converged": st["converged"]})
         log("m %.4f: %s (%.3fs)" % (m, st, el))
-    dsl = {}
+    lcx = 24 if mg.mg_link_reals() == 12 else 36
+    dsl = {"link_reals": mg.mg_link_reals()}
     for prec, name, lb, sb in [(0, "fp64", 16, 16), (1, "fp32", 8, 8), (2, "fp16links_fp32spinor", 4, 8)]:
         ms = mg.mg_time_dslash(prec, 1, 10)
         V = L[0] * L[1] * L[2] * L[3]
-        dsl[name] = {"ms": round(ms, 4), "GB/s": round(V * (36 * lb + 24 * sb) / (ms * 1e-3) / 1e9, 1)}
+        dsl[name] = {"ms": round(ms, 4), "GB/s": round(V * (lcx * lb + 24 * sb) / (ms * 1e-3) / 1e9, 1)}
     mg.close()
     its = [r["outer_iters"] for r in rows]
     print(json.dumps({
@@ -286,11 +288,12 @@ def main():
         Ud = torch.from_numpy(U).cuda()
         p = wmg.default_params(setup_iters=0, nrhs_max=1)
         mg = wmg.MG(L, Ud, w["m"], 4, (4, 4, 4, 4), p)
-        res = {}
+        lcx = 24 if mg.mg_link_reals() == 12 else 36
+        res = {"link_reals": mg.mg_link_reals()}
         for prec, name, lb, sb in [(0, "fp64", 16, 16), (1, "fp32", 8, 8), (2, "fp16links_fp32spinor", 4, 8)]:
             ms = mg.mg_time_dslash(prec, 1, 10)
-            res[name] = {"ms": round(ms, 4), "alg_bytes": V * (36 * lb + 24 * sb),
-                         "GB/s": round(V * (36 * lb + 24 * sb) / (ms * 1e-3) / 1e9, 1)}
+            res[name] = {"ms": round(ms, 4), "alg_bytes": V * (lcx * lb + 24 * sb),
+                         "GB/s": round(V * (lcx * lb + 24 * sb) / (ms * 1e-3) / 1e9, 1)}
         print(json.dumps({"workload": args.workload, "dslash": res, "launches_each": 11}))
         return
     t0 = time.time()
@@ -379,12 +382,18 @@ def main():
     log("oracle residuals %.1fs: %s" % (time.time() - t0, orc_res))
     del xh
     # Dslash bandwidth on internal layouts (algorithmic bytes, HIP events)
-    dsl = {}
+    # algorithmic bytes of the operator as stored: 4 links per site in the
+    # context's format (12 reals for SU(3) fields: 24 complex per site, else
+    # 36) and one spinor in and out per rhs
+    link_reals = mg.mg_link_reals()
+    lcx = 24 if link_reals == 12 else 36
+    dsl = {"link_reals": link_reals}
     for prec, name, lb, sb in [(0, "fp64", 16, 16), (1, "fp32", 8, 8), (2, "fp16links_fp32spinor", 4, 8)]:
         for nr in sorted({1, nrhs}):
             ms = mg.mg_time_dslash(prec, nr, 10)
-            by = V * (36 * lb + 24 * sb * nr)
-            dsl["%s_nrhs%d" % (name, nr)] = {"ms": round(ms, 4), "GB/s": round(by / (ms * 1e-3) / 1e9, 1)}
+            by = V * (lcx * lb + 24 * sb * nr)
+            dsl["%s_nrhs%d" % (name, nr)] = {"ms": round(ms, 4), "GB/s": round(by / (ms * 1e-3) / 1e9, 1),
+                                             "frac_of_8TBs": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
     fp64 = None
     if not args.no_fp64 and w["mixed"]:
         mg.mg_set_precision(wmg.WMG_FP64)

@@ -16,7 +16,9 @@
  *   site      s = x + L0*(y + L1*(z + L2*t))
  *   U         [V][4][3][3]   U[s][mu][a][b]: link s -> s+mu, row a, column b
  *   spinor    [nrhs][V][12]  component spin*3 + colour
- *   coarse    [nrhs][Vc][n]  n = 2*Nv, dof ordered (chirality, vector)
+ *   coarse    [nrhs][Vc][n]  n = 2*Nv, dof ordered (chirality, vector); with
+ *                            WMG_SPIN_SPLIT n = 4*Nv on the first coarse level,
+ *                            ordered (spin, vector)
  *   links     [Vc][9][n][n]  block d = 0 local, 1+mu forward, 5+mu backward
  *   vectors   [Nv][V][dof]   null vectors / prolongator columns (dof = 12 on
  *                            the fine lattice, n of the finer level otherwise)
@@ -59,6 +61,13 @@ extern "C" {
                              red/black (even-odd) Schur complement S = D_ee - D_eo D_oo^-1 D_oe
                              and solves the odd sites exactly (Sec. 3, MG combined with
                              red/black preconditioning); every extent must be even */
+#define WMG_GRAPHS 16     /* flags: the coarsest CGNR runs its iterations as captured HIP
+                             graphs of 4 iterations (same launches, same results; captured
+                             at the second solve of a buffer set, not while profiling) */
+#define WMG_SPIN_SPLIT 32 /* flags: the fine level's blocking splits each null vector into its
+                             four Dirac spins instead of its two chiralities (Sec. 3, exposing
+                             the full spin structure on the coarse blocks): 4 Nv coarse dof per
+                             block, ordered (spin, vector); coarser levels split by chirality */
 #define WMG_LINKS18 4     /* flags: the fine operator reads whole 3x3 links (18 reals); by
                              default it reads the first two rows (12 reals, Table 2) and
                              rebuilds the third as conj(row0 x row1) when every link of U

@@ -84,6 +84,7 @@ class MGParams(ctypes.Structure):
         ("maxiter", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("eo_smoother", ctypes.c_int),
+        ("spin_parts", ctypes.c_int),
     ]
 
 
@@ -121,6 +122,7 @@ _lib.orc_bicgstab.restype = ctypes.c_long
 _lib.orc_bicgstab.argtypes = [_I4, _dp, ctypes.c_double, _dp, _dp, ctypes.c_double, ctypes.c_int,
                               ctypes.POINTER(ctypes.c_double)]
 _lib.orc_block_orthonormalize.restype = ctypes.c_int
+_lib.orc_block_orthonormalize_ns.restype = ctypes.c_int
 _lib.orc_num_threads.restype = ctypes.c_int
 
 
@@ -188,6 +190,49 @@ def coarse_apply(Lc, dof: int, Y, v, dagger: bool = False) -> np.ndarray:
     out = np.empty_like(v)
     _lib.orc_coarse_apply(_I4(*Lc), ctypes.c_int(dof), _p(Y), _p(v), _p(out), ctypes.c_int(int(dagger)))
     return out
+
+
+def block_orthonormalize_ns(L, dof: int, block, vecs, ns: int) -> np.ndarray:
+    """Eq. 2.7 with the per-site components split into ns parts (2:
+    chirality, 4: Dirac spin)."""
+    vecs = _c(vecs)
+    P = np.empty_like(vecs)
+    rc = _lib.orc_block_orthonormalize_ns(_I4(*L), ctypes.c_int(dof), _I4(*block), ctypes.c_int(vecs.shape[0]),
+                                          ctypes.c_int(ns), _p(vecs), _p(P))
+    if rc != 0:
+        raise RuntimeError("block Gram-Schmidt breakdown")
+    return P
+
+
+def restrict_ns(L, dof: int, block, P, fine, ns: int) -> np.ndarray:
+    P = _c(P)
+    fine = _c(fine)
+    Lc = coarse_dims(L, block)
+    out = np.empty((vol(Lc), ns * P.shape[0]), np.complex128)
+    _lib.orc_restrict_ns(_I4(*L), ctypes.c_int(dof), _I4(*block), ctypes.c_int(P.shape[0]), ctypes.c_int(ns), _p(P),
+                         _p(fine), _p(out))
+    return out
+
+
+def prolong_ns(L, dof: int, block, P, coarse, ns: int) -> np.ndarray:
+    P = _c(P)
+    coarse = _c(coarse)
+    out = np.empty((vol(L), dof), np.complex128)
+    _lib.orc_prolong_ns(_I4(*L), ctypes.c_int(dof), _I4(*block), ctypes.c_int(P.shape[0]), ctypes.c_int(ns), _p(P),
+                        _p(coarse), _p(out))
+    return out
+
+
+def coarse_build_wilson_ns(L, U, m: float, block, P, ns: int) -> np.ndarray:
+    """Galerkin P^dag D P of the Wilson operator with ns parts per site."""
+    U = _c(U)
+    P = _c(P)
+    Lc = coarse_dims(L, block)
+    n = ns * P.shape[0]
+    Y = np.empty((vol(Lc), 9, n, n), np.complex128)
+    _lib.orc_coarse_build_ns(_I4(*L), ctypes.c_int(0), ctypes.c_int(12), _p(U), ctypes.c_double(m), ctypes.cast(None, _dp),
+                             _I4(*block), ctypes.c_int(P.shape[0]), ctypes.c_int(ns), _p(P), _p(Y))
+    return Y
 
 
 def block_orthonormalize(L, dof: int, block, vecs) -> np.ndarray:
@@ -293,6 +338,7 @@ def default_params(**kw) -> MGParams:
     p.maxiter = 1000
     p.seed = 12345
     p.eo_smoother = 0
+    p.spin_parts = 2
     for k, v in kw.items():
         if k == "block":
             flat = list(v[0]) + list(v[1] if len(v) > 1 else v[0])
@@ -398,6 +444,11 @@ for _name, _args in [
     ("orc_coarse_build", [_I4, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, _dp, _I4, ctypes.c_int, _dp, _dp]),
     ("orc_gamma", [ctypes.c_int, _dp]),
     ("orc_wilson_hop_parity", [_I4, _dp, ctypes.c_double, _dp, _dp, ctypes.c_int]),
+    ("orc_block_orthonormalize_ns", [_I4, ctypes.c_int, _I4, ctypes.c_int, ctypes.c_int, _dp, _dp]),
+    ("orc_restrict_ns", [_I4, ctypes.c_int, _I4, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
+    ("orc_prolong_ns", [_I4, ctypes.c_int, _I4, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
+    ("orc_coarse_build_ns", [_I4, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, _dp, _I4, ctypes.c_int,
+                             ctypes.c_int, _dp, _dp]),
     ("orc_schur_apply", [_I4, _dp, ctypes.c_double, _dp, _dp]),
     ("orc_start_vector", [ctypes.c_long, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _dp]),
 ]:

@@ -371,26 +371,30 @@ static void block_sites(const int L[4], const int b[4], long xh, long *sites)
                 }
 }
 
-/* Eq. 2.7: for every block xh and chirality chi, replace the restrictions
- * theta_xh(x) Pi_chi psi^(alpha) (alpha = 0..nv-1, in order) by an
- * orthonormal basis of their span: modified Gram-Schmidt run twice, unit
- * norms, diag(R) > 0.  Returns 0, or -4 on rank breakdown. */
-int orc_block_orthonormalize(const int L[4], int dof, const int b[4], int nv, const double *vecs_in,
-                             double *P_out)
+/* Eq. 2.7: for every block xh and part chi of the per-site components,
+ * replace the restrictions theta_xh(x) Pi_chi psi^(alpha) (alpha = 0..nv-1,
+ * in order) by an orthonormal basis of their span: modified Gram-Schmidt
+ * run twice, unit norms, diag(R) > 0.  The components split into ns equal
+ * parts: ns = 2 the chiralities of Sec. 3 (spins 0,1 / 2,3 on the fine
+ * lattice), ns = 4 the four Dirac spins (the full spin structure the
+ * paper's Sec. 3 exposes on the coarse blocks as a variant).  Returns 0, or
+ * -4 on rank breakdown. */
+int orc_block_orthonormalize_ns(const int L[4], int dof, const int b[4], int nv, int ns, const double *vecs_in,
+                                double *P_out)
 {
     long V = vol(L);
     int Lc[4];
     coarse_dims(L, b, Lc);
     long Vc = vol(Lc), bs = (long)b[0] * b[1] * b[2] * b[3];
-    int h = dof / 2;
+    int h = dof / ns;
     const cplx *vin = (const cplx *)vecs_in;
     cplx *P = (cplx *)P_out;
     if (P != vin) memcpy(P, vin, sizeof(cplx) * (size_t)nv * V * dof);
     int fail = 0;
 #pragma omp parallel for schedule(dynamic) reduction(| : fail)
-    for (long q = 0; q < 2 * Vc; q++) {
-        long xh = q / 2;
-        int chi = (int)(q % 2);
+    for (long q = 0; q < ns * Vc; q++) {
+        long xh = q / ns;
+        int chi = (int)(q % ns);
         long *sites = malloc(sizeof(long) * bs);
         block_sites(L, b, xh, sites);
         long n = bs * h;
@@ -425,39 +429,51 @@ int orc_block_orthonormalize(const int L[4], int dof, const int b[4], int nv, co
     return fail ? -4 : 0;
 }
 
-/* r_hat = P^dag r  (coarse dof index chi*nv + alpha) */
-void orc_restrict(const int L[4], int dof, const int b[4], int nv, const double *Pd, const double *fine,
-                  double *coarse)
+int orc_block_orthonormalize(const int L[4], int dof, const int b[4], int nv, const double *vecs_in,
+                             double *P_out)
+{
+    return orc_block_orthonormalize_ns(L, dof, b, nv, 2, vecs_in, P_out);
+}
+
+/* r_hat = P^dag r  (coarse dof index chi*nv + alpha, chi one of ns parts) */
+void orc_restrict_ns(const int L[4], int dof, const int b[4], int nv, int ns, const double *Pd, const double *fine,
+                     double *coarse)
 {
     long V = vol(L);
     int Lc[4];
     coarse_dims(L, b, Lc);
     long Vc = vol(Lc), bs = (long)b[0] * b[1] * b[2] * b[3];
-    int h = dof / 2;
+    int h = dof / ns, nc = ns * nv;
     const cplx *P = (const cplx *)Pd, *f = (const cplx *)fine;
     cplx *c = (cplx *)coarse;
 #pragma omp parallel for schedule(static)
     for (long xh = 0; xh < Vc; xh++) {
         long *sites = malloc(sizeof(long) * bs);
         block_sites(L, b, xh, sites);
-        for (int chi = 0; chi < 2; chi++)
+        for (int chi = 0; chi < ns; chi++)
             for (int a = 0; a < nv; a++) {
                 cplx acc = 0;
                 for (long k = 0; k < bs; k++)
                     for (int cc = chi * h; cc < (chi + 1) * h; cc++)
                         acc += conj(P[((size_t)a * V + sites[k]) * dof + cc]) * f[(size_t)sites[k] * dof + cc];
-                c[xh * 2 * nv + chi * nv + a] = acc;
+                c[xh * nc + chi * nv + a] = acc;
             }
         free(sites);
     }
 }
 
+void orc_restrict(const int L[4], int dof, const int b[4], int nv, const double *Pd, const double *fine,
+                  double *coarse)
+{
+    orc_restrict_ns(L, dof, b, nv, 2, Pd, fine, coarse);
+}
+
 /* e = P e_hat   (Eq. 2.3) */
-void orc_prolong(const int L[4], int dof, const int b[4], int nv, const double *Pd, const double *coarse,
-                 double *fine)
+void orc_prolong_ns(const int L[4], int dof, const int b[4], int nv, int ns, const double *Pd, const double *coarse,
+                    double *fine)
 {
     long V = vol(L);
-    int h = dof / 2;
+    int h = dof / ns, nc = ns * nv;
     const cplx *P = (const cplx *)Pd, *c = (const cplx *)coarse;
     cplx *f = (cplx *)fine;
 #pragma omp parallel for schedule(static)
@@ -466,10 +482,16 @@ void orc_prolong(const int L[4], int dof, const int b[4], int nv, const double *
         for (int cc = 0; cc < dof; cc++) {
             int chi = cc / h;
             cplx acc = 0;
-            for (int a = 0; a < nv; a++) acc += P[((size_t)a * V + s) * dof + cc] * c[xh * 2 * nv + chi * nv + a];
+            for (int a = 0; a < nv; a++) acc += P[((size_t)a * V + s) * dof + cc] * c[xh * nc + chi * nv + a];
             f[(size_t)s * dof + cc] = acc;
         }
     }
+}
+
+void orc_prolong(const int L[4], int dof, const int b[4], int nv, const double *Pd, const double *coarse,
+                 double *fine)
+{
+    orc_prolong_ns(L, dof, b, nv, 2, Pd, coarse, fine);
 }
 
 /* Galerkin coarse operator D_hat = P^dag D P (Sec. 2), stored as a 9-point
@@ -481,11 +503,11 @@ void orc_prolong(const int L[4], int dof, const int b[4], int nv, const double *
  * X (class 0) and Y_{+-mu}.  Keeping classes apart by hop direction keeps
  * the forward and backward links apart even where the coarse extent is 1 or
  * 2 and both neighbours are the same coarse site. */
-static void coarse_build(const orc_op *A, const int b[4], int nv, const cplx *P, cplx *Y)
+static void coarse_build(const orc_op *A, const int b[4], int nv, int ns, const cplx *P, cplx *Y)
 {
     const int *L = A->L;
     long V = A->nsite;
-    int dof = A->dof, h = dof / 2, nd = 2 * nv;
+    int dof = A->dof, h = dof / ns, nd = ns * nv;
     int Lc[4];
     coarse_dims(L, b, Lc);
     long Vc = vol(Lc), bs = (long)b[0] * b[1] * b[2] * b[3];
@@ -533,13 +555,20 @@ static void coarse_build(const orc_op *A, const int b[4], int nv, const cplx *P,
     free(v);
 }
 
-/* public wrapper: level operator given by (kind, U, m) or (kind, Y) */
-void orc_coarse_build(const int L[4], int kind, int dof, const double *U, double m, const double *Yf,
-                      const int b[4], int nv, const double *P, double *Yc)
+/* public wrapper: level operator given by (kind, U, m) or (kind, Y); ns
+ * parts per site (2 chiralities, or 4 spins on the fine level) */
+void orc_coarse_build_ns(const int L[4], int kind, int dof, const double *U, double m, const double *Yf,
+                         const int b[4], int nv, int ns, const double *P, double *Yc)
 {
     orc_op A = {{L[0], L[1], L[2], L[3]}, vol(L), kind == 0 ? 12 : dof, kind, (const cplx *)U, m,
                 (const cplx *)Yf};
-    coarse_build(&A, b, nv, (const cplx *)P, (cplx *)Yc);
+    coarse_build(&A, b, nv, ns, (const cplx *)P, (cplx *)Yc);
+}
+
+void orc_coarse_build(const int L[4], int kind, int dof, const double *U, double m, const double *Yf,
+                      const int b[4], int nv, const double *P, double *Yc)
+{
+    orc_coarse_build_ns(L, kind, dof, U, m, Yf, b, nv, 2, P, Yc);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -595,6 +624,7 @@ typedef struct {
     int maxiter;
     uint64_t seed;
     int eo_smoother;  /* 1: fine-level post-smoother on the red/black Schur complement */
+    int spin_parts;   /* parts per fine site in the blocking of level 0: 2 (chirality) or 4 (spin) */
 } orc_mg_params;
 
 typedef struct {
@@ -624,6 +654,10 @@ typedef struct {
     cplx *U;
     double m;
 } orc_mg;
+
+/* parts per site of the blocking of level l: chirality (2), or the four
+ * spins on the fine level when spin_parts = 4 */
+static int lvl_parts(const orc_mg *g, int l) { return l == 0 && g->p.spin_parts == 4 ? 4 : 2; }
 
 static void lvl_apply(orc_mg *g, int l, const cplx *in, cplx *out, orc_stats *st)
 {
@@ -729,7 +763,8 @@ static void mg_cycle(orc_mg *g, int l, const cplx *r, cplx *e, orc_stats *st)
 {
     orc_lvl *F = &g->lv[l], *C = &g->lv[l + 1];
     cplx *rc = valloc(C->n), *ec = valloc(C->n);
-    orc_restrict(F->op.L, F->op.dof, F->b, F->nv, (const double *)F->P, (const double *)r, (double *)rc);
+    orc_restrict_ns(F->op.L, F->op.dof, F->b, F->nv, lvl_parts(g, l), (const double *)F->P, (const double *)r,
+                    (double *)rc);
     if (l + 1 == g->nl - 1) {
         long it = cgnr(&C->op, rc, ec, g->p.coarse_tol, g->p.coarse_maxiter);
         if (st) st->coarse_iters += it;
@@ -745,7 +780,8 @@ static void mg_cycle(orc_mg *g, int l, const cplx *r, cplx *e, orc_stats *st)
             free(e2);
         }
     }
-    orc_prolong(F->op.L, F->op.dof, F->b, F->nv, (const double *)F->P, (const double *)ec, (double *)e);
+    orc_prolong_ns(F->op.L, F->op.dof, F->b, F->nv, lvl_parts(g, l), (const double *)F->P, (const double *)ec,
+                   (double *)e);
     if (l == 0 && g->p.eo_smoother) mr_smooth_schur(g, r, e, g->p.post_smooth, st);
     else mr_smooth(g, l, r, e, g->p.post_smooth, st);
     free(rc);
@@ -861,7 +897,7 @@ static void lvl_set_op(orc_mg *g, int l)
     orc_lvl *F = &g->lv[l], *C = &g->lv[l + 1];
     coarse_dims(F->op.L, F->b, C->op.L);
     C->op.nsite = vol(C->op.L);
-    C->op.dof = 2 * F->nv;
+    C->op.dof = lvl_parts(g, l) * F->nv;
     C->op.kind = 1;
     C->n = C->op.nsite * C->op.dof;
 }
@@ -874,8 +910,9 @@ static int build_level(orc_mg *g, int l, const cplx *vecs, int k)
     int nv_full = F->nv;
     F->nv = k;
     lvl_set_op(g, l);
-    int rc = orc_block_orthonormalize(F->op.L, F->op.dof, F->b, k, (const double *)vecs, (double *)F->P);
-    coarse_build(&F->op, F->b, k, F->P, C->Ybuf);
+    int rc = orc_block_orthonormalize_ns(F->op.L, F->op.dof, F->b, k, lvl_parts(g, l), (const double *)vecs,
+                                         (double *)F->P);
+    coarse_build(&F->op, F->b, k, lvl_parts(g, l), F->P, C->Ybuf);
     C->op.Y = C->Ybuf;
     if (k != nv_full) { /* trial scheme: remember the size used */ }
     return rc;

@@ -26,6 +26,7 @@ struct CGeom {
   long V, Vc;
   long Vs;  // fine-lattice site stride of the links
   int bs, dof, nv;
+  int ns;   // parts of the fine site's 12 components: 2 chiralities or 4 spins
 };
 
 __device__ __forceinline__ long cg_block_site(const CGeom &g, long xh, int k, int x[4]) {
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__r
                                                     const double2 *__restrict__ P, double2 *__restrict__ Yc) {
   long xh = blockIdx.x;
   int col = blockIdx.y;
-  int nv = g.nv, n = 2 * nv;
+  int nv = g.nv, n = g.ns * nv, hc = 12 / g.ns;
   int chic = col / nv, al = col % nv;
   __shared__ double sh[4 * 2 * 16];
   __shared__ double red[2 * 16];
@@ -123,13 +124,13 @@ __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__r
   long s = 0;
   if (act) s = cg_block_site(g, xh, k, x);
   const long E = (long)g.bs * 12;
-  // v(site) = chirality chic part of P[al] at that site
+  // v(site) = part chic (chirality or spin) of P[al] at that site
   auto loadv = [&](const int y[4], cx<double> v[12]) {
     long yh;
     int ky;
     cg_locate(g, y, yh, ky);
     for (int c = 0; c < 12; c++) {
-      v[c] = (c / 6 == chic) ? ldc(P + ((size_t)al * g.Vc + yh) * E + (size_t)c * g.bs + ky) : czero<double>();
+      v[c] = (c / hc == chic) ? ldc(P + ((size_t)al * g.Vc + yh) * E + (size_t)c * g.bs + ky) : czero<double>();
     }
   };
   for (int d = 0; d < 9; d++) {
@@ -166,7 +167,7 @@ __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__r
         int row = r0 + j;
         if (nz && row < n) {
           int chir = row / nv, be = row % nv;
-          for (int c = chir * 6; c < chir * 6 + 6; c++)
+          for (int c = chir * hc; c < chir * hc + hc; c++)
             acc[j] = cfmac(ldc(P + ((size_t)be * g.Vc + xh) * E + (size_t)c * g.bs + k), w[c], acc[j]);
         }
       }
@@ -285,7 +286,7 @@ static int upload_gamma() {
 }
 
 int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf, const int b[4],
-                 int nv, const double2 *P, double2 *Yc, double2 * /*work*/, hipStream_t st) {
+                 int nv, const double2 *P, double2 *Yc, double2 * /*work*/, hipStream_t st, int ns) {
   CGeom g;
   for (int i = 0; i < 4; i++) {
     g.L[i] = gf.L[i];
@@ -298,7 +299,9 @@ int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, dou
   g.bs = b[0] * b[1] * b[2] * b[3];
   g.dof = fine_kind == 0 ? 12 : dof;
   g.nv = nv;
-  dim3 grid((unsigned)g.Vc, 2 * nv);
+  g.ns = fine_kind == 0 ? ns : 2;
+  if (g.ns != 2 && g.ns != 4) return set_error(-1, "coarse_build: %d parts", g.ns);
+  dim3 grid((unsigned)g.Vc, g.ns * nv);
   if (fine_kind == 0) {
     if (g.bs > TB) return set_error(-1, "coarse_build: aggregate of %d sites > %d", g.bs, TB);
     int rc = upload_gamma();
@@ -529,6 +532,10 @@ int coarse_to_mfma16(long Vc, int n, const double2 *Y64, __half *Yh, float *Ysc,
 // LDS row stride of the transposed B tile: a multiple of 32 plus 4, so the
 // 16 columns x 4 k-rows read by one MFMA B fragment spread over all banks
 __host__ __device__ __forceinline__ int mfma_ldk(int n) { return (2 * n + 31) / 32 * 32 + 4; }
+// ... of the k-step-contiguous tile of k_coarse_apply_mfma2 (n a multiple of
+// 8): 2n + 4 floats, four times an odd number modulo 64, so the 16 columns
+// of a 16-lane group of 16-byte reads start in distinct bank quadruples
+__host__ __device__ __forceinline__ int mfma2_ldk(int n) { return 2 * n + 4; }
 
 // One workgroup per (coarse site, tile of up to 32 right-hand sides); wave mt
 // owns rows 16mt..16mt+15 of the n x n blocks and all NT column tiles.  The
@@ -685,8 +692,8 @@ k_coarse_apply_mfma2(const float *__restrict__ Ym, const __half *__restrict__ Yh
   constexpr int KM = (N / 2 + 7) / 8 * 8;  // k-steps of the stored fragments
   constexpr int KS = N / 2, Q = N / 4;     // k-steps used; per half
   constexpr int MT = (N + 15) / 16;
-  extern __shared__ float Bt[];  // [NTR*16 columns][LDK], column r, k-row kk at r*LDK + kk
-  const int LDK = mfma_ldk(N);
+  extern __shared__ float Bt[];  // [NTR*16 columns][LDK]; see stage_store for the k order
+  const int LDK = mfma2_ldk(N);
   long xh = blockIdx.x;
   int r0 = blockIdx.y * 32;
   int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
@@ -716,15 +723,17 @@ k_coarse_apply_mfma2(const float *__restrict__ Ym, const __half *__restrict__ Yh
     for (int q = 0; q < 8; q++)
       if (stager && rg + q * tpr < R) stg[q] = src[q * step];
   };
+  // B row k of column r lives at r*LDK + (k % 4)*KS + k/4: the KS k-steps a
+  // lane multiplies (k = 4 ks + krow) are contiguous, four per 16-byte read
   auto stage_store = [&]() {
-    float *dst = Bt + rg * LDK + col;
+    float *dst = Bt + rg * LDK + (col % 4) * KS + col / 4;
 #pragma unroll
     for (int q = 0; q < 8; q++)
       if (stager && rg + q * tpr < R) {
         float2 v = stg[q];
         if (neg) { v.x = -v.x; v.y = -v.y; }
-        dst[q * tpr * LDK] = v.x;
-        dst[q * tpr * LDK + N] = v.y;
+        dst[q * tpr * LDK] = v.x;           // k = col
+        dst[q * tpr * LDK + N / 4] = v.y;   // k = N + col (N % 4 == 0)
       }
   };
   const int mts = mt < MT ? mt : 0;
@@ -769,16 +778,23 @@ k_coarse_apply_mfma2(const float *__restrict__ Ym, const __half *__restrict__ Yh
       a_load(a_nxt, d + 1);
     }
     if (mt < MT) {
+      const float *bcol = Bt + jc * LDK + krow * KS;
 #pragma unroll
-      for (int ks = 0; ks < KS; ks++) {
-        const float a1 = ks < Q ? a_cur[ks] : -a_cur[ks];
-        const float a2 = ks < Q ? a_cur[ks + Q] : a_cur[ks - Q];
-        const float *bcol = Bt + jc * LDK + ks * 4 + krow;
+      for (int k4 = 0; k4 < KS; k4 += 4) {
+        float4 bv[NTR];
 #pragma unroll
-        for (int t = 0; t < NTR; t++) {
-          const float b = bcol[t * 16 * LDK];
-          cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, cr[t], 0, 0, 0);
-          ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b, ci[t], 0, 0, 0);
+        for (int t = 0; t < NTR; t++) bv[t] = *(const float4 *)(bcol + t * 16 * LDK + k4);
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int ks = k4 + u;
+          const float a1 = ks < Q ? a_cur[ks] : -a_cur[ks];
+          const float a2 = ks < Q ? a_cur[ks + Q] : a_cur[ks - Q];
+#pragma unroll
+          for (int t = 0; t < NTR; t++) {
+            const float b = u == 0 ? bv[t].x : (u == 1 ? bv[t].y : (u == 2 ? bv[t].z : bv[t].w));
+            cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, cr[t], 0, 0, 0);
+            ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b, ci[t], 0, 0, 0);
+          }
         }
       }
     }
@@ -834,7 +850,7 @@ static int coarse_apply_mfma_any(const Geom &gc, int n, const float *Ym, const _
   dim3 blk(64 * MT);
   if (n == 32 || n == 40 || n == 48 || n == 64) {
     const int NTR = (rmax + 15) / 16;
-    size_t lds2 = sizeof(float) * NTR * 16 * mfma_ldk(n);
+    size_t lds2 = sizeof(float) * NTR * 16 * mfma2_ldk(n);
 #define N2_CASE(T, NN)                                                                                         \
   if (NTR == T && n == NN) {                                                                                  \
     if (Yh)                                                                                                   \

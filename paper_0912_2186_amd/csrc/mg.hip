@@ -13,6 +13,8 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "wmg_internal.h"
@@ -257,6 +259,7 @@ struct Level {
   int dof_max = 0;
   // transfer to level+1
   int b[4] = {1, 1, 1, 1};
+  int ns = 2;  // parts per site in the blocking: 2 chiralities, or 4 spins (fine level, WMG_SPIN_SPLIT)
   int nv = 0, nv_max = 0;
   double2 *vecs = nullptr;  // null vectors, level vector layout, FP64
   double2 *P64 = nullptr;
@@ -306,6 +309,14 @@ struct wmg_ctx {
   int *flag = nullptr;
   double *hbuf = nullptr;  // pinned host mirror
   GcrBuf gb[2][2];         // [level 0 / level 1][FP64 / FP32 inner precision]
+  // coarse CGNR iteration blocks captured as HIP graphs (WMG_GRAPHS): key ->
+  // (times seen, block of 4 iterations minus the last second half, that half)
+  struct CgGraph {
+    int seen = 0;
+    bool failed = false;
+    hipGraphExec_t blk = nullptr, tail = nullptr;
+  };
+  std::map<std::vector<uintptr_t>, CgGraph> cg_graphs;
   std::vector<int> last_iters;
   double setup_s = 0;
   // solve statistics
@@ -509,7 +520,7 @@ static int transfer_restrict(wmg_ctx *c, int l, int prec, const void *fine, void
   int pp = prec == P64 ? P64 : P16;
   const void *P = prec == P64 ? (const void *)L.P64 : (const void *)L.P16;
   int slot = l == 0 ? prof_begin(c, K_RESTRICT, transfer_bytes(L, prec, nrhs)) : -1;
-  int rc = restrict_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, fine, L.fine ? 1 : 0, coarse, nrhs, c->st);
+  int rc = restrict_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, fine, L.fine ? 1 : 0, coarse, nrhs, c->st, L.ns);
   prof_end(c, slot);
   return rc;
 }
@@ -518,7 +529,7 @@ static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, voi
   int pp = prec == P64 ? P64 : P16;
   const void *P = prec == P64 ? (const void *)L.P64 : (const void *)L.P16;
   int slot = l == 0 ? prof_begin(c, K_PROLONG, transfer_bytes(L, prec, nrhs)) : -1;
-  int rc = prolong_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, coarse, fine, L.fine ? 1 : 0, nrhs, c->st);
+  int rc = prolong_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, coarse, fine, L.fine ? 1 : 0, nrhs, c->st, L.ns);
   prof_end(c, slot);
   return rc;
 }
@@ -756,37 +767,113 @@ static int cgnr(wmg_ctx *c, int l, int prec, const void *b, void *x, int nrhs) {
   TRY(apply_op(c, l, prec, r, s, nrhs, false, 1, c->cg + 1, 8));
   TRY(copy(prec, p, prec, s, L.n, nrhs, c->st));
   int cur = 1;
-  const int check = 4;
+  constexpr int check = 4;
   int it = 0;
   dim3 g = grid_for<double2>(L.n, nrhs);
   double *spart;
   TRY(cpart_get(c, (size_t)nrhs * (g.x > L.g.V ? g.x : L.g.V), &spart));
-  for (; it < c->p.coarse_maxiter; it++) {
-    // u = A p, |u|^2; x += alpha p, r -= alpha u, |r|^2
+  // first half of iteration it (slot cur): u = A p, |u|^2; x += alpha p,
+  // r -= alpha u, |r|^2; convergence flag
+  auto half1 = [&](int cu) -> int {
     TRY(apply_op(c, l, prec, p, u, nrhs, false, 0, c->cg + 0, 8));
     if (prec == P64)
-      hipLaunchKernelGGL(k_cg_step1<double2>, g, dim3(256), 0, c->st, c->cg, cur, (double2 *)x, (double2 *)r,
+      hipLaunchKernelGGL(k_cg_step1<double2>, g, dim3(256), 0, c->st, c->cg, cu, (double2 *)x, (double2 *)r,
                          (const double2 *)p, (const double2 *)u, L.n, nrhs, spart);
     else
-      hipLaunchKernelGGL(k_cg_step1<float2>, g, dim3(256), 0, c->st, c->cg, cur, (float2 *)x, (float2 *)r,
+      hipLaunchKernelGGL(k_cg_step1<float2>, g, dim3(256), 0, c->st, c->cg, cu, (float2 *)x, (float2 *)r,
                          (const float2 *)p, (const float2 *)u, L.n, nrhs, spart);
     TRY(sum_partials(spart, g.x, nrhs, c->cg + 3, 8, c->st));
     hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, c->st, c->cg, nrhs, c->flag);
-    if ((it + 1) % check == 0 || it + 1 == c->p.coarse_maxiter) {
+    WMG_HIP(hipGetLastError());
+    return 0;
+  };
+  // second half: s = A^dag r, |s|^2 (slot nxt); p = s + beta p
+  auto half2 = [&](int cu) -> int {
+    const int nxt = 3 - cu;
+    TRY(apply_op(c, l, prec, r, s, nrhs, false, 1, c->cg + nxt, 8));
+    if (prec == P64)
+      hipLaunchKernelGGL(k_cg_step2<double2>, g, dim3(256), 0, c->st, c->cg, nxt, cu, (const double2 *)s,
+                         (double2 *)p, L.n);
+    else
+      hipLaunchKernelGGL(k_cg_step2<float2>, g, dim3(256), 0, c->st, c->cg, nxt, cu, (const float2 *)s,
+                         (float2 *)p, L.n);
+    WMG_HIP(hipGetLastError());
+    return 0;
+  };
+  // With WMG_GRAPHS the loop runs as HIP graphs of `check` iterations (the
+  // same launches in the same order, so the same results): the graph of a
+  // buffer set is captured the second time the set is used (the first run
+  // fills every lazily allocated buffer and tuner choice), then replayed.
+  wmg_ctx::CgGraph *G = nullptr;
+  if ((c->p.flags & WMG_GRAPHS) && !c->prof && c->p.coarse_maxiter % check == 0) {
+    std::vector<uintptr_t> key = {(uintptr_t)l, (uintptr_t)prec, (uintptr_t)nrhs, (uintptr_t)x, (uintptr_t)r,
+                                  (uintptr_t)s, (uintptr_t)p, (uintptr_t)u, (uintptr_t)spart, (uintptr_t)L.n};
+    G = &c->cg_graphs[key];
+    if (G->failed) G = nullptr;
+    else if (!G->blk && G->seen++ >= 1) {
+      auto capture = [&](auto body, hipGraphExec_t *out) -> int {
+        hipGraph_t graph = nullptr;
+        WMG_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+        int rc = body();
+        hipError_t e = hipStreamEndCapture(c->st, &graph);
+        if (rc || e != hipSuccess || !graph) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return rc ? rc : set_error(WMG_EHIP, "graph capture failed");
+        }
+        e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        return e == hipSuccess ? 0 : set_error(WMG_EHIP, "graph instantiation failed");
+      };
+      int rc = capture([&]() -> int {
+        int cu = 1;
+        for (int k = 0; k < check; k++) {
+          TRY(half1(cu));
+          if (k + 1 < check) {
+            TRY(half2(cu));
+            cu = 3 - cu;
+          }
+        }
+        return 0;
+      }, &G->blk);
+      // the last iteration of a block has slot 1 when check is odd, else 2
+      if (!rc) rc = capture([&]() -> int { return half2(((check - 1) % 2) ? 2 : 1); }, &G->tail);
+      if (rc) {
+        (void)hipGetLastError();
+        G->failed = true;
+        G = nullptr;
+      }
+    } else if (!G->blk) {
+      G = nullptr;
+    }
+  }
+  if (G) {
+    // blocks of `check` iterations; the block ends after the first half of
+    // its last iteration, where the flag is read (an even `check` brings
+    // every block back to slot 1)
+    static_assert(check % 2 == 0, "blocks of an even iteration count start in slot 1");
+    for (; it < c->p.coarse_maxiter; it += check) {
+      WMG_HIP(hipGraphLaunch(G->blk, c->st));
       int done = 0;
       WMG_HIP(hipMemcpyAsync(&done, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
       TRY(sync(c));
-      if (done) { it++; break; }
+      if (done) {
+        it += check;
+        break;
+      }
+      if (it + check < c->p.coarse_maxiter) WMG_HIP(hipGraphLaunch(G->tail, c->st));
     }
-    int nxt = 3 - cur;
-    TRY(apply_op(c, l, prec, r, s, nrhs, false, 1, c->cg + nxt, 8));
-    if (prec == P64)
-      hipLaunchKernelGGL(k_cg_step2<double2>, g, dim3(256), 0, c->st, c->cg, nxt, cur, (const double2 *)s,
-                         (double2 *)p, L.n);
-    else
-      hipLaunchKernelGGL(k_cg_step2<float2>, g, dim3(256), 0, c->st, c->cg, nxt, cur, (const float2 *)s,
-                         (float2 *)p, L.n);
-    cur = nxt;
+  } else {
+    for (; it < c->p.coarse_maxiter; it++) {
+      TRY(half1(cur));
+      if ((it + 1) % check == 0 || it + 1 == c->p.coarse_maxiter) {
+        int done = 0;
+        WMG_HIP(hipMemcpyAsync(&done, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+        TRY(sync(c));
+        if (done) { it++; break; }
+      }
+      TRY(half2(cur));
+      cur = 3 - cur;
+    }
   }
   // effective iterations (max over rhs) for the statistics
   WMG_HIP(hipMemcpyAsync(c->hbuf, c->cg, sizeof(double) * 8 * nrhs, hipMemcpyDeviceToHost, c->st));
@@ -1040,15 +1127,15 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
 static int build_level(wmg_ctx *c, int l, int k) {
   Level &F = c->lv[l], &C = c->lv[l + 1];
   F.nv = k;
-  C.dof = 2 * k;
+  C.dof = F.ns * k;
   C.n = C.g.V * C.dof;
   WMG_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), c->st));
-  TRY(block_orthonormalize(F.g, F.dof, F.b, k, F.vecs, F.fine ? 1 : 0, F.P64, c->flag, c->st));
+  TRY(block_orthonormalize(F.g, F.dof, F.b, k, F.vecs, F.fine ? 1 : 0, F.P64, c->flag, c->st, F.ns));
   int fail = 0;
   WMG_HIP(hipMemcpyAsync(&fail, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
   TRY(sync(c));
   if (fail) return set_error(WMG_ERANK, "block Gram-Schmidt breakdown at level %d (null vectors dependent)", l);
-  TRY(coarse_build(F.g, F.fine ? 0 : 1, F.dof, F.U[P64], F.m, F.Y64, F.b, k, F.P64, C.Y64, nullptr, c->st));
+  TRY(coarse_build(F.g, F.fine ? 0 : 1, F.dof, F.U[P64], F.m, F.Y64, F.b, k, F.P64, C.Y64, nullptr, c->st, F.ns));
   return 0;
 }
 
@@ -1144,6 +1231,10 @@ static void free_ctx(wmg_ctx *c) {
     for (void *p : ps)
       if (p) (void)hipFree(p);
     if (B.prec != P64 && B.rin) (void)hipFree(B.rin);
+  }
+  for (auto &kv : c->cg_graphs) {
+    if (kv.second.blk) (void)hipGraphExecDestroy(kv.second.blk);
+    if (kv.second.tail) (void)hipGraphExecDestroy(kv.second.tail);
   }
   for (auto &e : c->ev_pool) (void)hipEventDestroy(e);
   red_free(c->red);
@@ -1252,11 +1343,13 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
         return set_error(WMG_EINVAL, "level %d: extent %d not divisible by block %d", l, L[i], p.block[l][i]);
       bs *= p.block[l][i];
     }
-    if (p.nvec[l] < 1 || p.nvec[l] > (dof / 2) * bs || p.nvec[l] > 64)
-      return set_error(WMG_EINVAL, "level %d: Nv = %d outside [1, %d]", l, p.nvec[l], (dof / 2) * bs < 64 ? (dof / 2) * bs : 64);
+    const int ns = (l == 0 && (p.flags & WMG_SPIN_SPLIT)) ? 4 : 2;
+    if (p.nvec[l] < 1 || p.nvec[l] > (dof / ns) * bs || p.nvec[l] > 64)
+      return set_error(WMG_EINVAL, "level %d: Nv = %d outside [1, %d]", l, p.nvec[l], (dof / ns) * bs < 64 ? (dof / ns) * bs : 64);
+    if (ns * p.nvec[l] > 128) return set_error(WMG_EINVAL, "level %d: %d coarse dof > 128", l, ns * p.nvec[l]);
     if (l == 0 && bs > 256) return set_error(WMG_EINVAL, "fine aggregate of %d sites > 256", bs);
     for (int i = 0; i < 4; i++) L[i] /= p.block[l][i];
-    dof = 2 * p.nvec[l];
+    dof = ns * p.nvec[l];
   }
   wmg_ctx *c = new wmg_ctx();
   c->p = p;
@@ -1298,13 +1391,14 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
       Level &A = c->lv[l], &C = c->lv[l + 1];
       for (int i = 0; i < 4; i++) A.b[i] = p.block[l][i];
       A.nv_max = A.nv = p.nvec[l];
+      A.ns = (l == 0 && (p.flags & WMG_SPIN_SPLIT)) ? 4 : 2;
       CK(dalloc((void **)&A.vecs, 16 * (size_t)A.nv_max * A.n));
       CK(dalloc((void **)&A.P64, 16 * (size_t)A.nv_max * A.n));
       int Lc[4];
       for (int i = 0; i < 4; i++) Lc[i] = A.g.L[i] / A.b[i];
       C.g = to_geom(Lc);
       C.fine = false;
-      C.dof = C.dof_max = 2 * A.nv_max;
+      C.dof = C.dof_max = A.ns * A.nv_max;
       C.n = C.n_alloc = C.g.V * C.dof;
       C.m = m;
       CK(dalloc((void **)&C.Y64, 16 * (size_t)C.g.V * 9 * C.dof * C.dof));

@@ -72,10 +72,12 @@ struct BlockGeom {
   long V, Vc;
   long Vs;  // fine-lattice site stride
   int bs, dof;
+  int ns;   // parts of the per-site components: 2 chiralities or 4 spins
 };
 
-static BlockGeom make_bg(const Geom &g, int dof, const int b[4]) {
+static BlockGeom make_bg(const Geom &g, int dof, const int b[4], int ns = 2) {
   BlockGeom bg;
+  bg.ns = ns;
   for (int i = 0; i < 4; i++) {
     bg.L[i] = g.L[i];
     bg.b[i] = b[i];
@@ -152,7 +154,7 @@ __global__ void __launch_bounds__(TB) k_block_gs(BlockGeom bg, int nv, const dou
                                                 double2 *__restrict__ P, int *fail) {
   long xh = blockIdx.x;
   int chi = blockIdx.y;
-  int h = bg.dof / 2;
+  int h = bg.dof / bg.ns;
   int E = bg.bs * bg.dof;
   __shared__ double sh[4 * 2 * 8];
   __shared__ double red[2 * 8];
@@ -242,12 +244,13 @@ __global__ void __launch_bounds__(TB) k_block_gs(BlockGeom bg, int nv, const dou
 }
 
 int block_orthonormalize(const Geom &g, int dof, const int b[4], int nv, const double2 *vecs, int fine_soa, double2 *P,
-                         int *fail_dev, hipStream_t st) {
-  BlockGeom bg = make_bg(g, dof, b);
+                         int *fail_dev, hipStream_t st, int ns) {
+  BlockGeom bg = make_bg(g, dof, b, ns);
   int E = bg.bs * dof;
   int ept = (E + TB - 1) / TB;
   if (nv > 64) return set_error(-1, "block_orthonormalize: nv=%d > 64", nv);
-  dim3 grid((unsigned)bg.Vc, 2);
+  if ((ns != 2 && ns != 4) || dof % ns) return set_error(-1, "block_orthonormalize: %d parts of %d", ns, dof);
+  dim3 grid((unsigned)bg.Vc, ns);
 #define GS_CASE(F, N)                                                                                      \
   if (fine_soa == F && ept <= N) {                                                                        \
     hipLaunchKernelGGL((k_block_gs<F, N>), grid, dim3(TB), 0, st, bg, nv, vecs, P, fail_dev);             \
@@ -268,8 +271,9 @@ template <> struct pscale<__half2> {
   static __device__ __forceinline__ float get(const float *s, size_t i) { return s[i]; }
 };
 
-// one workgroup per (coarse site, rhs); alpha processed in chunks of 8
-template <int FINE, int EPT, class TP, class TV>
+// one workgroup per (coarse site, rhs); alpha processed in chunks of 16/NS
+// (NS parts of the per-site components)
+template <int FINE, int EPT, class TP, class TV, int NS>
 __global__ void __launch_bounds__(TB) k_restrict(BlockGeom bg, int nv, const TP *__restrict__ P,
                                                 const float *__restrict__ Pscale, const TV *__restrict__ fine,
                                                 TV *__restrict__ coarse, int nrhs) {
@@ -278,7 +282,10 @@ __global__ void __launch_bounds__(TB) k_restrict(BlockGeom bg, int nv, const TP 
   // from cache, not HBM
   long xh = blockIdx.x / nrhs;
   int r = (int)(blockIdx.x % nrhs);
-  int E = bg.bs * bg.dof, h = bg.dof / 2;
+  int E = bg.bs * bg.dof, h = bg.dof / NS;
+  // 16 accumulators: ACH null vectors per chunk for each of the NS parts
+  constexpr int ACH = 16 / NS;
+  const int nc = NS * nv;
   __shared__ double sh[4 * 2 * 16];
   __shared__ double red[2 * 16];
   cx<R> v[EPT];
@@ -299,12 +306,12 @@ __global__ void __launch_bounds__(TB) k_restrict(BlockGeom bg, int nv, const TP 
       sidx[q] = (size_t)xh * bg.bs + k;
     }
   }
-  for (int a0 = 0; a0 < nv; a0 += 8) {
+  for (int a0 = 0; a0 < nv; a0 += ACH) {
     cx<double> acc[16];
 #pragma unroll
     for (int j = 0; j < 16; j++) acc[j] = czero<double>();
 #pragma unroll
-    for (int jj = 0; jj < 8; jj++) {
+    for (int jj = 0; jj < ACH; jj++) {
       int a = a0 + jj;
       if (a < nv) {
 #pragma unroll
@@ -315,16 +322,17 @@ __global__ void __launch_bounds__(TB) k_restrict(BlockGeom bg, int nv, const TP 
           float sc = pscale<TP>::get(Pscale, (size_t)a * bg.Vc * bg.bs + sidx[q]);
           cx<R> pv = {(R)(sc * p.re), (R)(sc * p.im)};
           cx<R> t = cmulc(pv, v[q]);
-          if (ch[q] == 0) acc[jj] = acc[jj] + cx<double>{t.re, t.im};
-          else acc[8 + jj] = acc[8 + jj] + cx<double>{t.re, t.im};
+#pragma unroll
+          for (int pt = 0; pt < NS; pt++)
+            if (pt == ch[q]) acc[pt * ACH + jj] = acc[pt * ACH + jj] + cx<double>{t.re, t.im};
         }
       }
     }
     wg_csum<16>(acc, sh, red);
     if (threadIdx.x < 16) {
-      int jj = threadIdx.x & 7, chi = threadIdx.x >> 3, a = a0 + jj;
-      if (a < nv)
-        stc(coarse + ((size_t)r * bg.Vc + xh) * (2 * nv) + chi * nv + a,
+      int jj = threadIdx.x % ACH, chi = threadIdx.x / ACH, a = a0 + jj;
+      if (chi < NS && a < nv)
+        stc(coarse + ((size_t)r * bg.Vc + xh) * nc + chi * nv + a,
             cx<double>{red[2 * threadIdx.x], red[2 * threadIdx.x + 1]});
     }
     __syncthreads();
@@ -343,7 +351,7 @@ __global__ void __launch_bounds__(TB) k_prolong(BlockGeom bg, int nv, const TP *
   using R = typename store_traits<TV>::real;
   long xh = xcd_tile(blockIdx.x, gridDim.x);
   if (xh >= bg.Vc) return;
-  const int E = bg.bs * bg.dof, h = bg.dof / 2, n = 2 * nv;
+  const int E = bg.bs * bg.dof, h = bg.dof / bg.ns, n = bg.ns * nv;  // n <= 128
   __shared__ cx<R> cs[RC * 128];
   for (int r0 = 0; r0 < nrhs; r0 += RC) {
     int rc = nrhs - r0 < RC ? nrhs - r0 : RC;
@@ -419,7 +427,7 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, cons
   for (int k = threadIdx.x; k < bg.bs; k += TB) soff[k] = (int)(block_site(bg, xh, k) - origin);
   const int r0 = blockIdx.y * 32;
   const int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
-  const int E = bg.bs * 12, H = bg.bs * 6;
+  const int E = bg.bs * 12, H = E / bg.ns, nc = bg.ns * nv;
   const int MTr = (nv + 15) / 16, NTr = (R + 15) / 16;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // zero the padding rows once (rows nv..31 of A, columns R..31 of B)
@@ -427,7 +435,7 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, cons
   for (int i = threadIdx.x; i < (32 - R) * RLD; i += TB) Bt[R * RLD + i] = 0.f;
   const int mt = w / 2, nt = w % 2;  // wave w: row tile w/2, rhs tile w%2
   const bool mine = mt < MTr && nt < NTr;
-  for (int chi = 0; chi < 2; chi++) {
+  for (int chi = 0; chi < bg.ns; chi++) {
     floatx4 accr = floatx4{0.f, 0.f, 0.f, 0.f}, acci = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int e0 = 0; e0 < H; e0 += RCH) {
       // the chunk lies inside one spin-colour component c0 (bs % RCH == 0)
@@ -464,7 +472,7 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, cons
       for (int v = 0; v < 4; v++) {
         int a = mt * 16 + 4 * (lane >> 4) + v, r = nt * 16 + (lane & 15);
         if (a < nv && r < R)
-          coarse[((size_t)(r0 + r) * bg.Vc + xh) * (2 * nv) + chi * nv + a] = make_float2(accr[v], acci[v]);
+          coarse[((size_t)(r0 + r) * bg.Vc + xh) * nc + chi * nv + a] = make_float2(accr[v], acci[v]);
       }
     }
   }
@@ -507,15 +515,15 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(BlockGeom bg, const __half2
   const int r0 = blockIdx.y * 32;
   const int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
   const int NTr = (R + 15) / 16;
-  const int E = bg.bs * 12, H = bg.bs * 6, nt_el = H / 16;
+  const int E = bg.bs * 12, H = E / bg.ns, nt_el = H / 16, nc = bg.ns * NV;
   float *A = Ac[G == 4 ? w : 0];
-  for (int chi = 0; chi < 2; chi++) {
+  for (int chi = 0; chi < bg.ns; chi++) {
     __syncthreads();  // previous chirality's tiles done
     if (G == 4) {
       for (int i = lane; i < 32 * NV; i += 64) {
         const int r = i / NV, a = i % NV;
         float2 v = make_float2(0.f, 0.f);
-        if (r < R) v = coarse[((size_t)(r0 + r) * bg.Vc + xh) * (2 * NV) + chi * NV + a];
+        if (r < R) v = coarse[((size_t)(r0 + r) * bg.Vc + xh) * nc + chi * NV + a];
         A[r * LDA + a] = v.x;
         A[r * LDA + NV + a] = v.y;
       }
@@ -523,7 +531,7 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(BlockGeom bg, const __half2
       for (int i = threadIdx.x; i < 32 * NV; i += TB) {
         const int r = i / NV, a = i % NV;
         float2 v = make_float2(0.f, 0.f);
-        if (r < R) v = coarse[((size_t)(r0 + r) * bg.Vc + xh) * (2 * NV) + chi * NV + a];
+        if (r < R) v = coarse[((size_t)(r0 + r) * bg.Vc + xh) * nc + chi * NV + a];
         A[r * LDA + a] = v.x;
         A[r * LDA + NV + a] = v.y;
       }
@@ -581,8 +589,11 @@ static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, 
   dim3 grid((unsigned)(bg.Vc * nrhs));
 #define TR_CASE(N)                                                                                         \
   if (ept <= N) {                                                                                         \
-    if (dir == 0)                                                                                          \
-      hipLaunchKernelGGL((k_restrict<FINE, N, TP, TV>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps,  \
+    if (dir == 0 && bg.ns == 4)                                                                            \
+      hipLaunchKernelGGL((k_restrict<FINE, N, TP, TV, 4>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps, \
+                         (const TV *)in, (TV *)out, nrhs);                                                 \
+    else if (dir == 0)                                                                                     \
+      hipLaunchKernelGGL((k_restrict<FINE, N, TP, TV, 2>), grid, dim3(TB), 0, st, bg, nv, (const TP *)P, Ps, \
                          (const TV *)in, (TV *)out, nrhs);                                                 \
     else                                                                                                   \
       hipLaunchKernelGGL((k_prolong<FINE, N, sizeof(TV) == 16 ? 4 : 32, TP, TV>), dim3((unsigned)xcd_grid(bg.Vc)), \
@@ -596,9 +607,11 @@ static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, 
 }
 
 static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P,
-                    const float *Ps, int vprec, const void *in, void *out, int fine_soa, int nrhs, hipStream_t st) {
-  BlockGeom bg = make_bg(g, dof, b);
+                    const float *Ps, int vprec, const void *in, void *out, int fine_soa, int nrhs, hipStream_t st,
+                    int ns) {
+  BlockGeom bg = make_bg(g, dof, b, ns);
   if (nv > 64) return set_error(-1, "transfer: nv=%d > 64", nv);
+  if ((ns != 2 && ns != 4) || dof % ns || ns * nv > 128) return set_error(-1, "transfer: %d parts of %d, nv=%d", ns, dof, nv);
   if (dir == 0 && fine_soa && pprec == P16 && vprec == P32 && nv <= 32 && bg.bs % RCH == 0 && bg.bs <= 256) {
     dim3 grid((unsigned)xcd_grid(bg.Vc), (nrhs + 31) / 32);
     hipLaunchKernelGGL(k_restrict_mfma, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps, (const float2 *)in,
@@ -639,13 +652,13 @@ static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int
 }
 
 int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
-                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st) {
-  return transfer(0, g, dof, b, nv, pprec, P, Pscale, vprec, fine, coarse, fine_soa, nrhs, st);
+                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st, int ns) {
+  return transfer(0, g, dof, b, nv, pprec, P, Pscale, vprec, fine, coarse, fine_soa, nrhs, st, ns);
 }
 
 int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
-               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st) {
-  return transfer(1, g, dof, b, nv, pprec, P, Pscale, vprec, coarse, fine, fine_soa, nrhs, st);
+               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st, int ns) {
+  return transfer(1, g, dof, b, nv, pprec, P, Pscale, vprec, coarse, fine, fine_soa, nrhs, st, ns);
 }
 
 // ------------------------------------------------------------ P precision

@@ -258,12 +258,14 @@ int sigma3(int prec, void *x, long nsite, int dof, int nrhs, hipStream_t st);
 // coarse (AoS): vector stride nsite*dof
 int start_vectors(long nsite, int dof, uint64_t seed, int lvl, int alpha0, int count, double2 *out_soa_or_aos,
                   int fine_soa, long Vs, hipStream_t st);
+// ns: parts of the per-site components in the blocking (2 chiralities; 4
+// Dirac spins on the fine level), coarse dof ns * nv ordered (part, vector)
 int block_orthonormalize(const Geom &g, int dof, const int b[4], int nv, const double2 *vecs, int fine_soa,
-                         double2 *P, int *fail_dev, hipStream_t st);
+                         double2 *P, int *fail_dev, hipStream_t st, int ns = 2);
 int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
-                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st);
+                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st, int ns = 2);
 int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
-               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st);
+               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st, int ns = 2);
 int P_convert(long count, const double2 *P64, int pprec, void *Pout, float *scale, int dof, hipStream_t st);
 int P_convert_half(long nsites_total, int bs, int dof, int fine, const double2 *P64, __half2 *Ph, float *scale,
                    hipStream_t st);
@@ -272,7 +274,7 @@ int P_block_to_vector(const Geom &g, int dof, const int b[4], int nv, const doub
 
 // coarse.hip
 int coarse_build(const Geom &g, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf, const int b[4],
-                 int nv, const double2 *P, double2 *Yc, double2 *work, hipStream_t st);
+                 int nv, const double2 *P, double2 *Yc, double2 *work, hipStream_t st, int ns = 2);
 int coarse_apply(const Geom &gc, int n, int yprec, const void *Y, int vprec, const void *in, void *out, int dagger,
                  int nrhs, hipStream_t st);
 int coarse_shift_diag(long Vc, int n, double2 *Y, double dm, hipStream_t st);

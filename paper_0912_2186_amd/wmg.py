@@ -35,6 +35,8 @@ WMG_X0_GIVEN = 1
 WMG_COARSE_FP32 = 2
 WMG_LINKS18 = 4
 WMG_EO_SMOOTHER = 8
+WMG_GRAPHS = 16
+WMG_SPIN_SPLIT = 32
 
 
 class WmgError(RuntimeError):
