@@ -109,12 +109,15 @@ __device__ __forceinline__ void wilson_hop(const double2 *U, long V, long s, lon
 }
 
 // One workgroup per (coarse site xh, column); fine Wilson level, one thread
-// per fine site of the aggregate (bs <= 256).
+// per fine site of the aggregate (bs <= 256).  NS parts per site (2
+// chiralities or 4 spins), hc = 12 / NS components each.
+template <int NS>
 __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__restrict__ U, double m,
                                                     const double2 *__restrict__ P, double2 *__restrict__ Yc) {
   long xh = blockIdx.x;
   int col = blockIdx.y;
-  int nv = g.nv, n = g.ns * nv, hc = 12 / g.ns;
+  constexpr int hc = 12 / NS;
+  const int nv = g.nv, n = NS * nv;
   int chic = col / nv, al = col % nv;
   __shared__ double sh[4 * 2 * 16];
   __shared__ double red[2 * 16];
@@ -306,7 +309,8 @@ int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, dou
     if (g.bs > TB) return set_error(-1, "coarse_build: aggregate of %d sites > %d", g.bs, TB);
     int rc = upload_gamma();
     if (rc) return rc;
-    hipLaunchKernelGGL(k_build_wilson, grid, dim3(TB), 0, st, g, (const double2 *)U64soa, m, P, Yc);
+    if (g.ns == 4) hipLaunchKernelGGL(k_build_wilson<4>, grid, dim3(TB), 0, st, g, (const double2 *)U64soa, m, P, Yc);
+    else hipLaunchKernelGGL(k_build_wilson<2>, grid, dim3(TB), 0, st, g, (const double2 *)U64soa, m, P, Yc);
   } else {
     long E = (long)g.bs * g.dof;
     int ept = (int)((E + TB - 1) / TB);
