@@ -251,6 +251,17 @@ int mg_apply_fine(wmg_ctx *ctx, int prec, const double *in, double *out, int nrh
  * r and e rounded to FP32, FP16 links, the result stored in FP16 and
  * returned as FP64 (canonical layouts, nrhs <= 64). */
 int mg_smoother_residual(wmg_ctx *ctx, const double *r, const double *e, double *out, int nrhs);
+/* One red/black hopping kernel of the smoother's Schur complement (Sec. 3,
+ * red/black preconditioning): out = a diag + b H_par(hop) on the sites of
+ * parity par = (x+y+z+t) mod 2, where H_par(v) is the hopping sum of Eq. 2.2
+ * at those sites from v on the other parity (D_{par,1-par} = -H_par / 2).
+ * diag (read at parity par; NULL allowed when a == 0), hop (read at the other
+ * parity) and out (zero at the other parity) are canonical FP64 full-lattice
+ * vectors.  prec 0: FP64 links and vectors; 3: FP16 links and FP16 vectors
+ * (the MR steps); 4: FP16 links and diag, FP32 hop input and output (the odd
+ * correction).  Needs every extent even; nrhs <= 64. */
+int mg_hop_eo(wmg_ctx *ctx, int prec, int par, double a, double b, const double *diag, const double *hop,
+              double *out, int nrhs);
 /* One application of the FP64 preconditioner z = M r (one MG cycle). */
 int mg_cycle(wmg_ctx *ctx, const double *r, double *z);
 /* Per-rhs outer iteration counts of the last solve (array of nrhs ints,

@@ -427,6 +427,10 @@ long wilson_red_blocks(const Geom &g) {
         long nb = make_sweep(g.L, nl * lb[i] + sb[i], budget).nblocks;
         m = nb > m ? nb : m;
       }
+  if (g.L[0] % 2 == 0) {
+    const long et = eo_red_tiles(g);
+    m = et > m ? et : m;
+  }
   return m;
 }
 
@@ -470,52 +474,121 @@ int wilson_soa(const Geom &g, int lprec, const void *U, int sprec, double m, con
 // ---------------------------------------------------------------- red/black
 // Even-odd decomposition (Sec. 3, red/black preconditioning).  A site of
 // parity p = (x+y+z+t) mod 2 with lexicographic index s has the compact
-// index h = s / 2 in the half-lattice array of its parity (x extent even):
-// fields [rhs][12][Vhs] per parity, links [parity][4][NR][Vhs].  The hopping
-// term between the sublattices, H_p(v) at sites of parity p from v on the
-// other one, is the sum over mu of (1 - gamma_mu) U_mu(x) v(x+mu) +
-// (1 + gamma_mu) U_mu(x-mu)^dag v(x-mu); D_{p,1-p} = -H_p / 2.
+// index h = s / 2 in the half-lattice array of its parity (x extent even).
+// Half-lattice fields are [rhs][colour][Vhs][spin]: the four spins of one
+// colour at one site are adjacent, so a lane reads them with one 16-byte
+// (FP16), two (FP32) or four (FP64) loads and projects them at once.  Links
+// are [parity][4][NR][Vhs].  The hopping term between the sublattices,
+// H_p(v) at sites of parity p from v on the other one, is the sum over mu of
+// (1 - gamma_mu) U_mu(x) v(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag v(x-mu);
+// D_{p,1-p} = -H_p / 2.
 struct EoGeom {
   int L[4];
+  int hx;        // compact sites per x line (L0 / 2)
   long Vh, Vhs;  // sites per parity, compact array stride
 };
 
-__device__ __forceinline__ void eo_coords(const EoGeom &g, int par, long h, int x[4]) {
-  const int hx = g.L[0] / 2;
-  long r = h / hx;
-  x[1] = (int)(r % g.L[1]);
-  r /= g.L[1];
-  x[2] = (int)(r % g.L[2]);
-  x[3] = (int)(r / g.L[2]);
-  x[0] = 2 * (int)(h % hx) + ((par + x[1] + x[2] + x[3]) & 1);
+// the four spins of one colour (consecutive elements)
+__device__ __forceinline__ void ld4(const __half2 *p, cx<float> o[4]) {
+  const uint4 v = *(const uint4 *)p;
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    __half2 h;
+    __builtin_memcpy(&h, &w[i], 4);
+    const float2 f = __half22float2(h);
+    o[i] = {f.x, f.y};
+  }
+}
+__device__ __forceinline__ void ld4(const float2 *p, cx<float> o[4]) {
+  const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 2);
+  o[0] = {a.x, a.y};
+  o[1] = {a.z, a.w};
+  o[2] = {b.x, b.y};
+  o[3] = {b.z, b.w};
+}
+__device__ __forceinline__ void ld4(const double2 *p, cx<double> o[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; i++) o[i] = ldc(p + i);
+}
+__device__ __forceinline__ void st4(__half2 *p, const cx<float> o[4]) {
+  unsigned w[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const __half2 h = __floats2half2_rn(o[i].re, o[i].im);
+    __builtin_memcpy(&w[i], &h, 4);
+  }
+  *(uint4 *)p = make_uint4(w[0], w[1], w[2], w[3]);
+}
+__device__ __forceinline__ void st4(float2 *p, const cx<float> o[4]) {
+  *(float4 *)p = make_float4(o[0].re, o[0].im, o[1].re, o[1].im);
+  *(float4 *)(p + 2) = make_float4(o[2].re, o[2].im, o[3].re, o[3].im);
+}
+__device__ __forceinline__ void st4(double2 *p, const cx<double> o[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; i++) stc(p + i, o[i]);
+}
+
+// Work order of the hop kernels.  A tile is 256 consecutive compact sites of
+// a slab of zb z-slices at one t (x fastest, then y, then z inside the
+// slab); tiles are numbered slab chunk fastest, then t, then z-slab, and XCD
+// k takes the k-th contiguous range.  The t-neighbours of a tile are then a
+// few tiles away in the XCD's sequence and still in its L2, and all rhs
+// tiles of one site tile run back to back (the links are read once).
+struct EoTiles {
+  int zb;     // z-slices per slab (divides L2)
+  int nch;    // chunks of 256 sites per slab and t
+  int ntile;  // tiles
+  int tpx;    // tiles per XCD
+};
+
+static EoTiles make_eo_tiles(const EoGeom &e, int zb) {
+  EoTiles t;
+  t.zb = zb;
+  const long q = (long)e.hx * e.L[1] * zb;
+  t.nch = (int)((q + 255) / 256);
+  t.ntile = t.nch * e.L[3] * (e.L[2] / zb);
+  t.tpx = (t.ntile + NXCD - 1) / NXCD;
+  return t;
 }
 
 // out = a in_diag + b H_par(in_hop) at the compact sites of parity par, for
 // RT right-hand sides per thread (sharing every link load); with RED, also
-// <out, in_diag> and |out|^2 per workgroup and rhs into red (as stored).
-// Workgroups are ordered so that each XCD runs the rhs tiles of one site
-// tile back to back (links read from HBM once per launch).
+// <out, in_diag> and |out|^2 per tile and rhs into red (as stored).  Site
+// indices are 32-bit (a parity holds fewer than 2^29 sites).
 template <class TL, class TD, class TH, class TO, int RT, int RED, int NR>
 __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const TD *__restrict__ in_diag,
                                                const TH *__restrict__ in_hop, TO *__restrict__ out, EoGeom g, int par,
-                                               double ad, double bd, int nrhs, long ntile, long per_xcd,
-                                               double *__restrict__ red) {
+                                               double ad, double bd, int nrhs, EoTiles tl, double *__restrict__ red) {
   using R = typename store_traits<TO>::real;
-  const long q = (blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
   const int nrt = (nrhs + RT - 1) / RT;
-  const long tile = q / nrt;
-  const int r0 = (int)(q % nrt) * RT;
-  const bool valid_tile = tile < ntile;
-  const long h = tile * 256 + threadIdx.x;
-  const bool valid = valid_tile && h < g.Vh;
+  const int j = (int)(blockIdx.x / NXCD);
+  const int tile = (int)(blockIdx.x % NXCD) * tl.tpx + j / nrt;
+  const int r0 = (j % nrt) * RT;
+  const bool valid_tile = tile < tl.ntile;
+  int x[4] = {0, 0, 0, 0}, h = 0, xh = 0;
+  bool valid = false;
+  if (valid_tile) {
+    const int P = g.hx * g.L[1];
+    int u = tile / tl.nch;
+    const int q = (tile - u * tl.nch) * 256 + (int)threadIdx.x;
+    const int tt = u % g.L[3];
+    const int zi = q / P, hp = q - zi * P;
+    valid = zi < tl.zb;
+    x[1] = hp / g.hx;
+    xh = hp - x[1] * g.hx;
+    x[2] = (u / g.L[3]) * tl.zb + zi;
+    x[3] = tt;
+    x[0] = 2 * xh + ((par + x[1] + x[2] + x[3]) & 1);
+    h = hp + P * (x[2] + g.L[2] * tt);
+  }
   const R a = (R)ad, b = (R)bd;
   double rs[RT][3];
 #pragma unroll
   for (int t = 0; t < RT; t++) rs[t][0] = rs[t][1] = rs[t][2] = 0.0;
   if (valid) {
-    int x[4];
-    eo_coords(g, par, h, x);
-    const long Vs = g.Vhs;
+    const int Vs = (int)g.Vhs;
+    const int hs[4] = {0, g.hx, g.hx * g.L[1], g.hx * g.L[1] * g.L[2]};  // compact strides of y, z, t
     const TL *Uf = Ue + (size_t)par * 4 * NR * Vs;        // links at sites of parity par
     const TL *Ub = Ue + (size_t)(1 - par) * 4 * NR * Vs;  // ... of the other parity
     cx<R> acc[RT][12];
@@ -523,33 +596,35 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
     for (int t = 0; t < RT; t++)
 #pragma unroll
       for (int c = 0; c < 12; c++) acc[t][c] = czero<R>();
-    auto load_link = [&](const TL *Up, int mu, long site, cx<R> u[9]) {
+    auto load_link = [&](const TL *Up, int mu, int site, cx<R> u[9]) {
 #pragma unroll
       for (int e = 0; e < NR; e++) {
-        auto v = ldc(Up + ((size_t)(mu * NR + e)) * Vs + site);
+        auto v = ldc(Up + (size_t)(mu * NR + e) * Vs + (unsigned)site);
         u[e] = {(R)v.re, (R)v.im};
       }
       if (NR == 6) su3_third_row(u);
     };
-    auto half = [&](int r, long site, auto proj, cx<R> hh[6]) {
+    // projected half spinor of the neighbour, colour by colour
+    auto half = [&](int r, int site, auto proj, cx<R> hh[6]) {
 #pragma unroll
       for (int c = 0; c < 3; c++) {
         cx<R> p4[4];
-#pragma unroll
-        for (int sp = 0; sp < 4; sp++) {
-          auto v = ldc(in_hop + ((size_t)r * 12 + sp * 3 + c) * Vs + site);
-          p4[sp] = {(R)v.re, (R)v.im};
-        }
+        ld4(in_hop + ((size_t)r * 3 + c) * Vs * 4 + (unsigned)site * 4, p4);
         proj(p4, hh[c], hh[3 + c]);
       }
     };
 #define EO_DIR(MU)                                                                      \
     {                                                                                   \
-      int y[4] = {x[0], x[1], x[2], x[3]};                                              \
-      y[MU] = x[MU] == g.L[MU] - 1 ? 0 : x[MU] + 1;                                     \
-      const long hf = site_index(g.L, y) >> 1;                                          \
-      y[MU] = x[MU] == 0 ? g.L[MU] - 1 : x[MU] - 1;                                     \
-      const long hb = site_index(g.L, y) >> 1;                                          \
+      int hf, hb;                                                                       \
+      if (MU == 0) {                                                                    \
+        const int xf = x[0] == g.L[0] - 1 ? 0 : x[0] + 1;                               \
+        const int xb = x[0] == 0 ? g.L[0] - 1 : x[0] - 1;                               \
+        hf = h - xh + (xf >> 1);                                                        \
+        hb = h - xh + (xb >> 1);                                                        \
+      } else {                                                                          \
+        hf = x[MU] == g.L[MU] - 1 ? h - (g.L[MU] - 1) * hs[MU] : h + hs[MU];            \
+        hb = x[MU] == 0 ? h + (g.L[MU] - 1) * hs[MU] : h - hs[MU];                      \
+      }                                                                                 \
       cx<R> u[9], hh[6], gg[6];                                                         \
       load_link(Uf, MU, h, u);                                                          \
       _Pragma("unroll") for (int t = 0; t < RT; t++) {                                  \
@@ -577,20 +652,23 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
     for (int t = 0; t < RT; t++) {
       if (r0 + t >= nrhs) continue;
 #pragma unroll
-      for (int c = 0; c < 12; c++) {
-        const size_t i = ((size_t)(r0 + t) * 12 + c) * Vs + h;
-        cx<R> dv = czero<R>();
-        if (ad != 0.0) {
-          auto v = ldc(in_diag + i);
-          dv = {(R)v.re, (R)v.im};
-        }
-        cx<R> o = {a * dv.re + b * acc[t][c].re, a * dv.im + b * acc[t][c].im};
-        stc(out + i, o);
+      for (int c = 0; c < 3; c++) {
+        const size_t i = ((size_t)(r0 + t) * 3 + c) * Vs * 4 + (unsigned)h * 4;
+        cx<R> dv[4] = {czero<R>(), czero<R>(), czero<R>(), czero<R>()};
+        if (ad != 0.0) ld4(in_diag + i, dv);
+        cx<R> o[4];
+#pragma unroll
+        for (int sp = 0; sp < 4; sp++)
+          o[sp] = {a * dv[sp].re + b * acc[t][sp * 3 + c].re, a * dv[sp].im + b * acc[t][sp * 3 + c].im};
+        st4(out + i, o);
         if (RED) {
-          o = as_stored(out, o);
-          rs[t][0] += (double)o.re * dv.re + (double)o.im * dv.im;
-          rs[t][1] += (double)o.re * dv.im - (double)o.im * dv.re;
-          rs[t][2] += (double)o.re * o.re + (double)o.im * o.im;
+#pragma unroll
+          for (int sp = 0; sp < 4; sp++) {
+            const cx<R> os = as_stored(out, o[sp]);
+            rs[t][0] += (double)os.re * dv[sp].re + (double)os.im * dv[sp].im;
+            rs[t][1] += (double)os.re * dv[sp].im - (double)os.im * dv[sp].re;
+            rs[t][2] += (double)os.re * os.re + (double)os.im * os.im;
+          }
         }
       }
     }
@@ -611,7 +689,7 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
     if (valid_tile && threadIdx.x < RT * 3) {
       int t = threadIdx.x / 3, k = threadIdx.x % 3;
       if (r0 + t < nrhs)
-        red[((size_t)(r0 + t) * ntile + tile) * 3 + k] = sh[t][k][0] + sh[t][k][1] + sh[t][k][2] + sh[t][k][3];
+        red[((size_t)(r0 + t) * tl.ntile + tile) * 3 + k] = sh[t][k][0] + sh[t][k][1] + sh[t][k][2] + sh[t][k][3];
     }
   }
 }
@@ -619,6 +697,7 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
 static EoGeom make_eo(const Geom &g) {
   EoGeom e;
   for (int i = 0; i < 4; i++) e.L[i] = g.L[i];
+  e.hx = g.L[0] / 2;
   e.Vh = g.V / 2;
   e.Vhs = fine_stride(e.Vh);
   return e;
@@ -626,25 +705,61 @@ static EoGeom make_eo(const Geom &g) {
 
 long eo_stride(const Geom &g) { return fine_stride(g.V / 2); }
 
+// slab depths the autotuner tries (those dividing L2), the first the default
+static int eo_zb_candidates(const Geom &g, int zb[6]) {
+  const int pref[6] = {4, 8, 2, 1, 16, g.L[2]};
+  int n = 0;
+  for (int i = 0; i < 6; i++) {
+    if (pref[i] < 1 || g.L[2] % pref[i]) continue;
+    bool dup = false;
+    for (int k = 0; k < n; k++) dup |= zb[k] == pref[i];
+    if (!dup) zb[n++] = pref[i];
+  }
+  return n;
+}
+
+long eo_red_tiles(const Geom &g) {
+  EoGeom e = make_eo(g);
+  int zb[6];
+  const int n = eo_zb_candidates(g, zb);
+  long m = 0;
+  for (int i = 0; i < n; i++) {
+    const long t = make_eo_tiles(e, zb[i]).ntile;
+    m = t > m ? t : m;
+  }
+  return m;
+}
+
 template <class TL, class TD, class TH, class TO, int RT, int NR>
 static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, double b, const void *in_diag,
                          const void *in_hop, void *out, int nrhs, double *red, double *red_out, int red_stride,
                          hipStream_t st) {
   EoGeom e = make_eo(g);
-  const long ntile = (e.Vh + 255) / 256;
   const int nrt = (nrhs + RT - 1) / RT;
-  const long grid = xcd_grid(ntile * nrt);
-  if (red) {
-    hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 1, NR>), dim3((unsigned)grid), dim3(256), 0, st, (const TL *)Ue,
-                       (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, ntile, grid / NXCD, red);
-    hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, ntile, red_out, red_stride);
-  } else {
-    hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 0, NR>), dim3((unsigned)grid), dim3(256), 0, st, (const TL *)Ue,
-                       (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, ntile, grid / NXCD,
-                       (double *)nullptr);
-  }
-  WMG_HIP(hipGetLastError());
-  return 0;
+  int zb[6];
+  const int ncand = eo_zb_candidates(g, zb);
+  auto run = [&](int cand) -> int {
+    const EoTiles tl = make_eo_tiles(e, zb[cand]);
+    const dim3 grid((unsigned)((long)NXCD * tl.tpx * nrt));
+    if (red) {
+      hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 1, NR>), grid, dim3(256), 0, st, (const TL *)Ue,
+                         (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl, red);
+      hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)tl.ntile, red_out,
+                         red_stride);
+    } else {
+      hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 0, NR>), grid, dim3(256), 0, st, (const TL *)Ue,
+                         (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl,
+                         (double *)nullptr);
+    }
+    WMG_HIP(hipGetLastError());
+    return 0;
+  };
+  char key[256];
+  std::snprintf(key, sizeof(key), "hop_eo/l%zu-d%zu-h%zu-o%zu-nr%d-red%d-diag%d/%dx%dx%dx%d/rhs%d", sizeof(TL),
+                sizeof(TD), sizeof(TH), sizeof(TO), NR, red ? 1 : 0, a != 0.0 ? 1 : 0, g.L[0], g.L[1], g.L[2],
+                g.L[3], nrhs);
+  int choice = 0;
+  return tune_choice(key, ncand, run, st, &choice);
 }
 
 int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b, int pdiag, const void *in_diag,
@@ -652,6 +767,7 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
            hipStream_t st) {
   const bool c12 = (lprec & LK12) != 0;
   const int lp = lprec & ~LK12;
+  if (g.L[0] % 2 || g.V / 2 >= (1L << 29)) return set_error(-1, "hop_eo: lattice not supported");
 #define HOP(TL, TD, TH, TO, RT)                                                                                    \
   return c12 ? launch_hop_eo<TL, TD, TH, TO, RT, 6>(g, Ue, par, a, b, in_diag, in_hop, out, nrhs, red, red_out,    \
                                                    red_stride, st)                                                \
@@ -664,9 +780,10 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
   return set_error(-1, "hop_eo: unsupported precisions link %d diag %d hop %d out %d", lp, pdiag, phop, pout);
 }
 
-// full lexicographic SoA [rhs][12][Vs] <-> compact halves [rhs][12][Vhs]
+// full lexicographic SoA [rhs][12][Vs] <-> half-lattice [rhs][colour][Vhs][spin]
 template <class TF, class TE>
 __global__ void k_eo_pack(const TF *__restrict__ full, TE *__restrict__ ev, TE *__restrict__ od, EoGeom g, long Vs) {
+  using R = typename store_traits<TE>::real;
   long s = blockIdx.x * 256L + threadIdx.x;
   int r = blockIdx.y;
   if (s >= 2 * g.Vh) return;
@@ -675,15 +792,21 @@ __global__ void k_eo_pack(const TF *__restrict__ full, TE *__restrict__ ev, TE *
   TE *dst = ((x[0] + x[1] + x[2] + x[3]) & 1) ? od : ev;
   const long hh = s >> 1;
 #pragma unroll
-  for (int c = 0; c < 12; c++) {
-    auto v = ldc(full + ((size_t)r * 12 + c) * Vs + s);
-    stc(dst + ((size_t)r * 12 + c) * g.Vhs + hh, v);
+  for (int c = 0; c < 3; c++) {
+    cx<R> o[4];
+#pragma unroll
+    for (int sp = 0; sp < 4; sp++) {
+      auto v = ldc(full + ((size_t)r * 12 + sp * 3 + c) * Vs + s);
+      o[sp] = {(R)v.re, (R)v.im};
+    }
+    st4(dst + (((size_t)r * 3 + c) * g.Vhs + hh) * 4, o);
   }
 }
 // full += (ev, od) (either half may be null: no contribution)
 template <class TF, class TE>
 __global__ void k_eo_unpack_add(TF *__restrict__ full, const TE *__restrict__ ev, const TE *__restrict__ od, EoGeom g,
                                 long Vs) {
+  using R = typename store_traits<TE>::real;
   long s = blockIdx.x * 256L + threadIdx.x;
   int r = blockIdx.y;
   if (s >= 2 * g.Vh) return;
@@ -693,11 +816,15 @@ __global__ void k_eo_unpack_add(TF *__restrict__ full, const TE *__restrict__ ev
   if (!src) return;
   const long hh = s >> 1;
 #pragma unroll
-  for (int c = 0; c < 12; c++) {
-    const size_t i = ((size_t)r * 12 + c) * Vs + s;
-    auto f = ldc(full + i);
-    auto v = ldc(src + ((size_t)r * 12 + c) * g.Vhs + hh);
-    stc(full + i, decltype(f){f.re + v.re, f.im + v.im});
+  for (int c = 0; c < 3; c++) {
+    cx<R> v[4];
+    ld4(src + (((size_t)r * 3 + c) * g.Vhs + hh) * 4, v);
+#pragma unroll
+    for (int sp = 0; sp < 4; sp++) {
+      const size_t i = ((size_t)r * 12 + sp * 3 + c) * Vs + s;
+      auto f = ldc(full + i);
+      stc(full + i, decltype(f){f.re + v[sp].re, f.im + v[sp].im});
+    }
   }
 }
 
@@ -707,6 +834,9 @@ int eo_pack(const Geom &g, int pfull, const void *full, int phalf, void *ev, voi
   if (pfull == P16 && phalf == P16)
     hipLaunchKernelGGL((k_eo_pack<__half2, __half2>), grid, dim3(256), 0, st, (const __half2 *)full, (__half2 *)ev,
                        (__half2 *)od, e, g.Vs);
+  else if (pfull == P32 && phalf == P32)
+    hipLaunchKernelGGL((k_eo_pack<float2, float2>), grid, dim3(256), 0, st, (const float2 *)full, (float2 *)ev,
+                       (float2 *)od, e, g.Vs);
   else if (pfull == P64 && phalf == P64)
     hipLaunchKernelGGL((k_eo_pack<double2, double2>), grid, dim3(256), 0, st, (const double2 *)full, (double2 *)ev,
                        (double2 *)od, e, g.Vs);

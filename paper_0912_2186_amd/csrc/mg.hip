@@ -1882,6 +1882,67 @@ int mg_apply_fine(wmg_ctx *c, int prec, const double *in, double *out, int nrhs)
   return sync(c);
 }
 
+// canonical FP64 full-lattice vectors -> half-lattice arrays (even, odd) of
+// precision p, through the fine level's work vectors VX / VS
+static int canon_to_eo(wmg_ctx *c, int p, const double *canon, void *ev, void *od, int nrhs) {
+  Level &F = c->lv[0];
+  void *a64;
+  TRY(level_vec(c, 0, P64, VX, &a64, nrhs));
+  TRY(spinor_to_soa(F.g, canon, (double2 *)a64, nrhs, c->st));
+  if (p == P64) return eo_pack(F.g, P64, a64, P64, ev, od, nrhs, c->st);
+  void *a32;
+  TRY(level_vec(c, 0, P32, VX, &a32, nrhs));
+  TRY(copy(P32, a32, P64, a64, F.n, nrhs, c->st));
+  if (p == P32) return eo_pack(F.g, P32, a32, P32, ev, od, nrhs, c->st);
+  void *a16;
+  TRY(level_vec(c, 0, P16, VS, &a16, nrhs));
+  TRY(copy(P16, a16, P32, a32, F.n, nrhs, c->st));
+  return eo_pack(F.g, P16, a16, P16, ev, od, nrhs, c->st);
+}
+
+int mg_hop_eo(wmg_ctx *c, int prec, int par, double a, double b, const double *diag, const double *hop, double *out,
+              int nrhs) {
+  if (!c || !hop || !out || (a != 0.0 && !diag) || nrhs < 1 || nrhs > c->p.nrhs_max || nrhs > 64 ||
+      (prec != 0 && prec != 3 && prec != 4) || (par != 0 && par != 1))
+    return set_error(WMG_EINVAL, "bad argument");
+  Level &F = c->lv[0];
+  for (int i = 0; i < 4; i++)
+    if (F.g.L[i] % 2) return set_error(WMG_EINVAL, "red/black sublattices need even extents");
+  const int lp = prec == 0 ? P64 : P16;                        // links
+  const int pd = prec == 0 ? P64 : P16;                        // diag
+  const int ph = prec == 0 ? P64 : (prec == 3 ? P16 : P32);    // hop input and output
+  const void *Ue;
+  TRY(eo_links(c, lp, &Ue));
+  void *de, *dod, *he, *ho, *o;
+  TRY(level_vec(c, 0, pd, VHSE, &de, nrhs));
+  TRY(level_vec(c, 0, pd, VHSO, &dod, nrhs));
+  TRY(level_vec(c, 0, ph, VHDE, &he, nrhs));
+  TRY(level_vec(c, 0, ph, VHDO, &ho, nrhs));
+  TRY(level_vec(c, 0, ph, VHQ, &o, nrhs));
+  if (a != 0.0) TRY(canon_to_eo(c, pd, diag, de, dod, nrhs));
+  TRY(canon_to_eo(c, ph, hop, he, ho, nrhs));
+  TRY(hop_eo(F.g, lp | F.lk, Ue, par, a, b, pd, a != 0.0 ? (par ? dod : de) : nullptr, ph, par ? he : ho, ph, o,
+             nrhs, nullptr, nullptr, 0, c->st));
+  // result (sites of parity par) -> zeroed full lattice -> canonical FP64
+  const long nh = 12 * eo_stride(F.g);
+  const int pf = ph == P64 ? P64 : P32;
+  void *o2 = o, *full, *b64;
+  if (ph == P16) {
+    TRY(level_vec(c, 0, P32, VHQ, &o2, nrhs));
+    TRY(copy(P32, o2, P16, o, nh, nrhs, c->st));
+  }
+  TRY(level_vec(c, 0, pf, VT, &full, nrhs));
+  TRY(zero(pf, full, F.n, nrhs, c->st));
+  TRY(eo_unpack_add(F.g, pf, full, pf, par ? nullptr : o2, par ? o2 : nullptr, nrhs, c->st));
+  b64 = full;
+  if (pf == P32) {
+    TRY(level_vec(c, 0, P64, VT, &b64, nrhs));
+    TRY(copy(P64, b64, P32, full, F.n, nrhs, c->st));
+  }
+  TRY(spinor_from_soa(F.g, (double2 *)b64, out, nrhs, c->st));
+  return sync(c);
+}
+
 int mg_smoother_residual(wmg_ctx *c, const double *r, const double *e, double *out, int nrhs) {
   if (!c || !r || !e || !out || nrhs < 1 || nrhs > c->p.nrhs_max || nrhs > 64) return set_error(WMG_EINVAL, "bad argument");
   Level &F = c->lv[0];

@@ -174,12 +174,15 @@ int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double 
 int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
                    const void *bsub, const double *bnrm2, int bstride, double *red, double *red_out, int red_stride,
                    hipStream_t st, int lflags = 0);
+// partials per rhs that the fused reductions of wilson_soa_fused,
+// wilson_soa_h16 and hop_eo may write (the largest of their tilings)
 long wilson_red_blocks(const Geom &g);
 // ---- red/black (even-odd) sublattices; requires every extent even.
 // Compact half-lattice arrays: site of lexicographic index s, parity p at
-// index s/2 of parity p's array; fields [rhs][12][eo_stride], links
-// [parity][4][NR][eo_stride].
+// index s/2 of parity p's array; fields [rhs][colour][eo_stride][spin],
+// links [parity][4][NR][eo_stride].
 long eo_stride(const Geom &g);
+long eo_red_tiles(const Geom &g);
 // out = a in_diag + b H_par(in_hop) on the sites of parity par (H: the
 // hopping sum of Eq. 2.2 from the other sublattice; D_{p,1-p} = -H/2);
 // with red, <out, in_diag> and |out|^2 per rhs -> red_out[rhs * stride + 0..2]

@@ -116,6 +116,7 @@ _sig = {
     "mg_prolong_f32": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_apply_fine": (_i, [_vp, _i, _vp, _vp, _i]),
     "mg_smoother_residual": (_i, [_vp, _vp, _vp, _vp, _i]),
+    "mg_hop_eo": (_i, [_vp, _i, _i, _d, _d, _vp, _vp, _vp, _i]),
     "mg_link_reals": (_i, [_vp]),
     "mg_save": (_i, [_vp, ctypes.c_char_p]),
     "mg_load": (_i, [ctypes.c_char_p, _P(Geom), _vp, _d, _P(Params), _P(_vp)]),
@@ -315,6 +316,12 @@ class MG:
     def mg_smoother_residual(self, r: torch.Tensor, e: torch.Tensor, out: torch.Tensor, nrhs: int = 1) -> None:
         torch.cuda.synchronize()
         _check(_lib.mg_smoother_residual(self.h, _ptr(r), _ptr(e), _ptr(out), int(nrhs)))
+
+    def mg_hop_eo(self, prec: int, par: int, a: float, b: float, diag, hop: torch.Tensor, out: torch.Tensor,
+                  nrhs: int = 1) -> None:
+        torch.cuda.synchronize()
+        _check(_lib.mg_hop_eo(self.h, int(prec), int(par), float(a), float(b), _ptr(diag) if diag is not None else None,
+                              _ptr(hop), _ptr(out), int(nrhs)))
 
     def mg_link_reals(self) -> int:
         rc = _lib.mg_link_reals(self.h)

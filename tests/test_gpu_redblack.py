@@ -2,7 +2,9 @@
 red/black preconditioning) on the GPU against the oracle: one FP64 cycle
 from identical null vectors, FP64 solve iteration parity, and the
 mixed-precision multi-RHS solve (FP16 sublattice residuals) reaching the
-oracle's 1e-10 in fewer outer iterations than the MR-on-D smoother."""
+oracle's 1e-10 in fewer outer iterations than the MR-on-D smoother; and
+the red/black hopping kernel itself, site by site, in its three precision
+forms."""
 import sys
 
 import numpy as np
@@ -10,7 +12,7 @@ import pytest
 
 import oracle
 from paper_0912_2186_amd import inputs
-from helpers import relerr, vol
+from helpers import local_err, relerr, vol
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +41,73 @@ def empty(shape):
 def rand_vecs(nv, V, dof, seed):
     rng = np.random.default_rng(seed)
     return rng.standard_normal((nv, V, dof)) + 1j * rng.standard_normal((nv, V, dof))
+
+
+def _round(a, dt):
+    return a.real.astype(dt).astype(np.float64) + 1j * a.imag.astype(dt).astype(np.float64)
+
+
+def _decaying(L, site, kappa, seed):
+    rng = np.random.default_rng(seed)
+    V = vol(L)
+    x0 = np.unravel_index(site, (L[3], L[2], L[1], L[0]))
+    grid = np.indices((L[3], L[2], L[1], L[0]))
+    d = np.zeros((L[3], L[2], L[1], L[0]))
+    for ax, n in enumerate((L[3], L[2], L[1], L[0])):
+        a = np.abs(grid[ax] - x0[ax])
+        d = d + np.minimum(a, n - a)
+    return np.exp(-kappa * d).reshape(V, 1) * (rng.standard_normal((V, 12)) + 1j * rng.standard_normal((V, 12)))
+
+
+# (lattice, aggregate): several tiles with a ragged last chunk per slab, and
+# a lattice whose z extent admits only slabs of 1, 2 or 6 z-slices
+@pytest.mark.parametrize("L,block", [((20, 14, 4, 6), (4, 2, 4, 2)), ((8, 8, 6, 12), (4, 4, 2, 4))])
+@pytest.mark.parametrize("prec", [0, 3, 4])
+def test_hop_kernel_per_site(wmg, L, block, prec):
+    """out = a diag + b H_par(hop) from the GPU kernel against the oracle's
+    D_{par,1-par} (H = -2 D_{par,1-par}), both parities, both link formats,
+    three right-hand sides (Gaussian, point source, decaying point source),
+    inputs pre-rounded to the kernel's storage formats so both sides see the
+    same values.  Per-site bound in units of the neighbourhood's largest
+    input component (floor 2^-9 of the largest component for the FP16
+    forms): FP64 256 u64 (|a| + 16 |b|); FP16 forms 64 * 2^-11 (|a| + 16 |b|),
+    the links being FP16 on the GPU and exact in the oracle."""
+    V = vol(L)
+    m = -0.25
+    m4 = 4 + m
+    U = inputs.gauge_field(L, 0.5, 401)
+    par_of = oracle.parity(L)
+    src = np.stack([inputs.gaussian_rhs(L, 402)[0], inputs.point_sources(L)[5], _decaying(L, 17, 1.5, 403)])
+    dg = np.stack([inputs.gaussian_rhs(L, 404)[0], inputs.z4_noise(L, 405, 1)[0], _decaying(L, 3, 1.0, 406)])
+    if prec == 0:
+        hop_in, diag_in = src, dg
+    elif prec == 3:
+        hop_in, diag_in = _round(src, np.float16), _round(dg, np.float16)
+    else:
+        hop_in, diag_in = _round(src, np.float32), _round(dg, np.float16)
+    for flags in (0, wmg.WMG_LINKS18):
+        p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=3, flags=flags)
+        mg = wmg.MG(L, dev(U), m, 4, block, p)
+        for par, a, b in ((1, 0.0, 1.0), (0, m4, -0.25 / m4), (1, 1.0 / m4, 0.5 / m4)):
+            out = empty((3, V, 12))
+            mg.mg_hop_eo(prec, par, a, b, dev(diag_in) if a != 0.0 else None, dev(hop_in), out, 3)
+            oh = host(out)
+            for r in range(3):
+                mask = (par_of == par)[:, None]
+                ref = (a * diag_in[r] + b * (-2.0) * oracle.wilson_hop_parity(L, U, m, hop_in[r], par)) * mask
+                sc_in = np.concatenate([hop_in[r], diag_in[r]], axis=1) if a != 0.0 else hop_in[r]
+                k = abs(a) + 16 * abs(b)
+                if prec == 0:
+                    le = local_err(oh[r], ref, sc_in, L)
+                    bound = 256 * 2.0 ** -52 * k
+                else:
+                    le = local_err(oh[r], ref, sc_in, L, floor=2.0 ** -9 * np.abs(sc_in).max())
+                    bound = 64 * 2.0 ** -11 * k
+                say("  L", L, "prec", prec, "links", mg.mg_link_reals(), "par", par, "rhs", r,
+                    "relerr %.2e site %.2e" % (relerr(oh[r], ref), le))
+                assert le < bound
+                assert np.all(oh[r][~mask[:, 0]] == 0)
+        mg.close()
 
 
 @pytest.mark.parametrize("flags", [0, "links18"])
