@@ -21,6 +21,7 @@
 // is the complex conjugate of the cross product of the first two, and the
 // kernel rebuilds it in registers.
 #include <cstdio>
+#include <type_traits>
 
 #include "wmg_internal.h"
 
@@ -529,6 +530,30 @@ __device__ __forceinline__ void st4(double2 *p, const cx<double> o[4]) {
   for (int i = 0; i < 4; i++) stc(p + i, o[i]);
 }
 
+// One colour of the projection straight from the four FP16 spins as
+// stored: h = p_up - S A_mu p_down with every sum written fma(x, one, y),
+// one = 1 passed at run time, so that the compiler folds the f16 -> f32
+// conversions into the mixed-precision FMA (v_fma_mix_f32) instead of
+// converting first; the values are those of proj_pair.
+template <int MU, int S>
+__device__ __forceinline__ void proj_pair_h16(const __half2 *p, float one, cx<float> &h0, cx<float> &h1) {
+  const uint4 v = *(const uint4 *)p;
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
+  __half2 q[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) __builtin_memcpy(&q[i], &w[i], 4);
+  const float p0r = __low2float(q[0]), p0i = __high2float(q[0]), p1r = __low2float(q[1]), p1i = __high2float(q[1]);
+  const float p2r = __low2float(q[2]), p2i = __high2float(q[2]), p3r = __low2float(q[3]), p3i = __high2float(q[3]);
+  float a0r, a0i, a1r, a1i;  // A_mu p_down
+  if (MU == 0) { a0r = p3i; a0i = -p3r; a1r = p2i; a1i = -p2r; }
+  if (MU == 1) { a0r = -p3r; a0i = -p3i; a1r = p2r; a1i = p2i; }
+  if (MU == 2) { a0r = p2i; a0i = -p2r; a1r = -p3i; a1i = p3r; }
+  if (MU == 3) { a0r = p2r; a0i = p2i; a1r = p3r; a1i = p3i; }
+  if (S > 0) { a0r = -a0r; a0i = -a0i; a1r = -a1r; a1i = -a1i; }
+  h0 = {__builtin_fmaf(a0r, one, p0r), __builtin_fmaf(a0i, one, p0i)};
+  h1 = {__builtin_fmaf(a1r, one, p1r), __builtin_fmaf(a1i, one, p1i)};
+}
+
 // Work order of the hop kernels.  A tile is 256 consecutive compact sites of
 // a slab of zb z-slices at one t (x fastest, then y, then z inside the
 // slab); tiles are numbered slab chunk fastest, then t, then z-slab, and XCD
@@ -559,7 +584,8 @@ static EoTiles make_eo_tiles(const EoGeom &e, int zb) {
 template <class TL, class TD, class TH, class TO, int RT, int RED, int NR>
 __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const TD *__restrict__ in_diag,
                                                const TH *__restrict__ in_hop, TO *__restrict__ out, EoGeom g, int par,
-                                               double ad, double bd, int nrhs, EoTiles tl, double *__restrict__ red) {
+                                               double ad, double bd, int nrhs, EoTiles tl, double *__restrict__ red,
+                                               float one) {
   using R = typename store_traits<TO>::real;
   const int nrt = (nrhs + RT - 1) / RT;
   const int j = (int)(blockIdx.x / NXCD);
@@ -605,12 +631,17 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
       if (NR == 6) su3_third_row(u);
     };
     // projected half spinor of the neighbour, colour by colour
-    auto half = [&](int r, int site, auto proj, cx<R> hh[6]) {
+    auto half = [&](int r, int site, auto proj, auto proj16, cx<R> hh[6]) {
 #pragma unroll
       for (int c = 0; c < 3; c++) {
-        cx<R> p4[4];
-        ld4(in_hop + ((size_t)r * 3 + c) * Vs * 4 + (unsigned)site * 4, p4);
-        proj(p4, hh[c], hh[3 + c]);
+        const TH *p = in_hop + ((size_t)r * 3 + c) * Vs * 4 + (unsigned)site * 4;
+        if constexpr (std::is_same<TH, __half2>::value) {
+          proj16(p, one, hh[c], hh[3 + c]);
+        } else {
+          cx<R> p4[4];
+          ld4(p, p4);
+          proj(p4, hh[c], hh[3 + c]);
+        }
       }
     };
 #define EO_DIR(MU)                                                                      \
@@ -629,7 +660,7 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
       load_link(Uf, MU, h, u);                                                          \
       _Pragma("unroll") for (int t = 0; t < RT; t++) {                                  \
         if (r0 + t < nrhs) {                                                            \
-          half(r0 + t, hf, proj_pair<MU, 1, R>, hh);                                    \
+          half(r0 + t, hf, proj_pair<MU, 1, R>, proj_pair_h16<MU, 1>, hh);              \
           su3_mul<0>(u, hh, gg);                                                        \
           reconstruct<MU, 1>(gg, acc[t]);                                               \
         }                                                                               \
@@ -637,7 +668,7 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
       load_link(Ub, MU, hb, u);                                                         \
       _Pragma("unroll") for (int t = 0; t < RT; t++) {                                  \
         if (r0 + t < nrhs) {                                                            \
-          half(r0 + t, hb, proj_pair<MU, -1, R>, hh);                                   \
+          half(r0 + t, hb, proj_pair<MU, -1, R>, proj_pair_h16<MU, -1>, hh);            \
           su3_mul<1>(u, hh, gg);                                                        \
           reconstruct<MU, -1>(gg, acc[t]);                                              \
         }                                                                               \
@@ -743,13 +774,13 @@ static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, doubl
     const dim3 grid((unsigned)((long)NXCD * tl.tpx * nrt));
     if (red) {
       hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 1, NR>), grid, dim3(256), 0, st, (const TL *)Ue,
-                         (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl, red);
+                         (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl, red, 1.0f);
       hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)tl.ntile, red_out,
                          red_stride);
     } else {
       hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 0, NR>), grid, dim3(256), 0, st, (const TL *)Ue,
                          (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl,
-                         (double *)nullptr);
+                         (double *)nullptr, 1.0f);
     }
     WMG_HIP(hipGetLastError());
     return 0;
@@ -774,7 +805,7 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
              : launch_hop_eo<TL, TD, TH, TO, RT, 9>(g, Ue, par, a, b, in_diag, in_hop, out, nrhs, red, red_out,    \
                                                    red_stride, st)
   if (lp == P64 && pdiag == P64 && phop == P64 && pout == P64) HOP(double2, double2, double2, double2, 1);
-  if (lp == P16 && pdiag == P16 && phop == P16 && pout == P16) HOP(__half2, __half2, __half2, __half2, 2);
+  if (lp == P16 && pdiag == P16 && phop == P16 && pout == P16) HOP(__half2, __half2, __half2, __half2, 3);
   if (lp == P16 && pdiag == P16 && phop == P32 && pout == P32) HOP(__half2, __half2, float2, float2, 2);
 #undef HOP
   return set_error(-1, "hop_eo: unsupported precisions link %d diag %d hop %d out %d", lp, pdiag, phop, pout);
