@@ -259,7 +259,9 @@ int mg_smoother_residual(wmg_ctx *ctx, const double *r, const double *e, double 
  * parity) and out (zero at the other parity) are canonical FP64 full-lattice
  * vectors.  prec 0: FP64 links and vectors; 3: FP16 links and FP16 vectors
  * (the MR steps); 4: FP16 links and diag, FP32 hop input and output (the odd
- * correction).  Needs every extent even; nrhs <= 64. */
+ * correction); 5: as 4 in the smoother's fused last step (par must be 1),
+ * which also returns hop's values at the even sites.  Needs every extent
+ * even; nrhs <= 64. */
 int mg_hop_eo(wmg_ctx *ctx, int prec, int par, double a, double b, const double *diag, const double *hop,
               double *out, int nrhs);
 /* One application of the FP64 preconditioner z = M r (one MG cycle). */

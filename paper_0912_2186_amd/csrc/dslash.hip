@@ -179,18 +179,71 @@ template <class R> __device__ __forceinline__ void su3_third_row(cx<R> u[9]) {
   u[8] = {c2.re, -c2.im};
 }
 
+// the four spins of one colour (consecutive elements)
+__device__ __forceinline__ void ld4(const __half2 *p, cx<float> o[4]) {
+  const uint4 v = *(const uint4 *)p;
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    __half2 h;
+    __builtin_memcpy(&h, &w[i], 4);
+    const float2 f = __half22float2(h);
+    o[i] = {f.x, f.y};
+  }
+}
+__device__ __forceinline__ void ld4(const float2 *p, cx<float> o[4]) {
+  const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 2);
+  o[0] = {a.x, a.y};
+  o[1] = {a.z, a.w};
+  o[2] = {b.x, b.y};
+  o[3] = {b.z, b.w};
+}
+__device__ __forceinline__ void ld4(const double2 *p, cx<double> o[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; i++) o[i] = ldc(p + i);
+}
+__device__ __forceinline__ void st4(__half2 *p, const cx<float> o[4]) {
+  unsigned w[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const __half2 h = __floats2half2_rn(o[i].re, o[i].im);
+    __builtin_memcpy(&w[i], &h, 4);
+  }
+  *(uint4 *)p = make_uint4(w[0], w[1], w[2], w[3]);
+}
+__device__ __forceinline__ void st4(float2 *p, const cx<float> o[4]) {
+  *(float4 *)p = make_float4(o[0].re, o[0].im, o[1].re, o[1].im);
+  *(float4 *)(p + 2) = make_float4(o[2].re, o[2].im, o[3].re, o[3].im);
+}
+__device__ __forceinline__ void st4(double2 *p, const cx<double> o[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; i++) stc(p + i, o[i]);
+}
+// p[0] += lo, p[1] += hi (two adjacent sites of a full-lattice component)
+__device__ __forceinline__ void add_pair(float2 *p, cx<float> lo, cx<float> hi) {
+  float4 v = *(float4 *)p;
+  *(float4 *)p = make_float4(v.x + lo.re, v.y + lo.im, v.z + hi.re, v.w + hi.im);
+}
+__device__ __forceinline__ void add_pair(double2 *p, cx<double> lo, cx<double> hi) {
+  const double2 a = p[0], b = p[1];
+  p[0] = make_double2(a.x + lo.re, a.y + lo.im);
+  p[1] = make_double2(b.x + hi.re, b.y + hi.im);
+}
+
 // ---------------------------------------------------------------- SoA
 // Optional fusions for the smoother: bsub != nullptr gives out = bsub - D in
 // (residual); RED != 0 also reduces <out, in> and |out|^2 over the
 // workgroup into red[(rhs * gridDim.x + block) * 3 + 0..2] for a
 // fixed-order finalisation by k_dslash_red_finalize.
-template <class TL, class TS, class TO, int RT, int RED, int NR>
+// With EO, the output goes to the two half-lattice arrays out (even sites)
+// and out_odd (odd sites) in their [rhs][colour][Vhs][spin] layout instead.
+template <class TL, class TS, class TO, int RT, int RED, int NR, int EO = 0>
 __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, const TS *__restrict__ in,
                                                    TO *__restrict__ out, int L0, int L1, int L2, int L3, long V,
                                                    float diagf, double diagd, int nrhs, SweepMap sm, long Vs,
                                                    const TS *__restrict__ bsub, const double *__restrict__ bnrm2,
                                                    int bstride, double *__restrict__ red, int inner,
-                                                   float2 *__restrict__ out32) {
+                                                   float2 *__restrict__ out32, TO *__restrict__ out_odd, long Vhs) {
   using R = typename store_traits<TS>::real;
   const R diag = sizeof(R) == 8 ? (R)diagd : (R)diagf;
   // one sweep over the lattice per tile of RT right-hand sides (grid.y)
@@ -300,6 +353,7 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
 #pragma unroll
   for (int t = 0; t < RT; t++) {
     if (r0 + t >= nrhs) continue;
+    cx<R> oo[EO ? 12 : 1];
     cx<R> p[12];
 #pragma unroll
     for (int c = 0; c < 12; c++) {
@@ -318,13 +372,22 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
         }
         o = cx<R>{bs * (R)bv.re - o.re, bs * (R)bv.im - o.im};
       }
-      stc(out + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
+      if constexpr (EO) oo[c] = o;
+      else stc(out + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
       if (out32) stc(out32 + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
       if (RED) o = as_stored(out, o);
       if (RED) {
         rs[t][0] += (double)o.re * p[c].re + (double)o.im * p[c].im;
         rs[t][1] += (double)o.re * p[c].im - (double)o.im * p[c].re;
         rs[t][2] += (double)o.re * o.re + (double)o.im * o.im;
+      }
+    }
+    if constexpr (EO) {
+      TO *dst = ((x[0] + x[1] + x[2] + x[3]) & 1) ? out_odd : out;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        const cx<R> q4[4] = {oo[c], oo[3 + c], oo[6 + c], oo[9 + c]};
+        st4(dst + (((size_t)(r0 + t) * 3 + c) * Vhs + (s >> 1)) * 4, q4);
       }
     }
   }
@@ -376,7 +439,9 @@ __global__ void __launch_bounds__(256) k_dslash_red_finalize(const double *__res
 template <class TL, class TS, class TO = TS, int NR = 9>
 static int launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, const void *bsub,
                       double *red, double *red_out, int red_stride, hipStream_t st, const double *bnrm2 = nullptr,
-                      int bstride = 0, void *out32 = nullptr) {
+                      int bstride = 0, void *out32 = nullptr, void *out_odd = nullptr) {
+  if (out_odd && (red || g.L[0] % 2)) return set_error(-1, "wilson_soa: half-lattice output without reductions only");
+  const long Vhs = fine_stride(g.V / 2);
   constexpr int RT = sizeof(TS) == 16 ? 1 : 2;
   const int nrt = (nrhs + RT - 1) / RT;
   // Default order: FP64 and FP32 links (288-576 B per site) would be re-read
@@ -398,21 +463,31 @@ static int launch_soa(const Geom &g, const void *U, double m, const void *in, vo
     if (red) {
       hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1, NR>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
                          (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                         (const TS *)bsub, bnrm2, bstride, red, inner, (float2 *)out32);
+                         (const TS *)bsub, bnrm2, bstride, red, inner, (float2 *)out32, (TO *)nullptr, Vhs);
       hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
                          red_stride);
+    } else if (out_odd) {
+      // instantiated for the smoother's residual form only
+      if constexpr (std::is_same<TO, __half2>::value && std::is_same<TS, float2>::value)
+        hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR, 1>), grid, dim3(256), lds, st, (const TL *)U,
+                           (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
+                           nrhs, sm, g.Vs, (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner,
+                           (float2 *)out32, (TO *)out_odd, Vhs);
+      else
+        return set_error(-1, "wilson_soa: half-lattice output not instantiated for these precisions");
     } else {
       hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
                          (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                         (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner, (float2 *)out32);
+                         (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner, (float2 *)out32, (TO *)nullptr,
+                         Vhs);
     }
     WMG_HIP(hipGetLastError());
     return 0;
   };
   char key[256];
-  std::snprintf(key, sizeof(key), "dslash/l%zu-s%zu-o%zu-nr%d-red%d-b%d-f%d/%dx%dx%dx%d/rhs%d", sizeof(TL),
-                sizeof(TS), sizeof(TO), NR, red ? 1 : 0, bsub ? 1 : 0, out32 ? 1 : 0, g.L[0], g.L[1], g.L[2], g.L[3],
-                nrhs);
+  std::snprintf(key, sizeof(key), "dslash/l%zu-s%zu-o%zu-nr%d-red%d-b%d-f%d-eo%d/%dx%dx%dx%d/rhs%d", sizeof(TL),
+                sizeof(TS), sizeof(TO), NR, red ? 1 : 0, bsub ? 1 : 0, out32 ? 1 : 0, out_odd ? 1 : 0, g.L[0], g.L[1],
+                g.L[2], g.L[3], nrhs);
   int choice = 0;
   return tune_choice(key, nrt > 1 ? 2 * NB : NB, run, st, &choice);
 }
@@ -452,13 +527,14 @@ int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double 
 
 int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
                    const void *bsub, const double *bnrm2, int bstride, double *red, double *red_out, int red_stride,
-                   hipStream_t st, int lflags) {
+                   hipStream_t st, int lflags, void *out_odd) {
   const bool c12 = (lflags & LK12) != 0;
   if (iprec == P32)
     return c12 ? launch_soa<__half2, float2, __half2, 6>(g, U16, m, in, out, nrhs, bsub, red, red_out, red_stride, st,
-                                                         bnrm2, bstride)
+                                                         bnrm2, bstride, nullptr, out_odd)
                : launch_soa<__half2, float2, __half2, 9>(g, U16, m, in, out, nrhs, bsub, red, red_out, red_stride, st,
-                                                         bnrm2, bstride);
+                                                         bnrm2, bstride, nullptr, out_odd);
+  if (out_odd) return set_error(-1, "wilson_soa_h16: half-lattice output only with FP32 input");
   if (iprec == P16 && !bsub)
     return c12 ? launch_soa<__half2, __half2, __half2, 6>(g, U16, m, in, out, nrhs, nullptr, red, red_out, red_stride,
                                                           st)
@@ -487,48 +563,9 @@ struct EoGeom {
   int L[4];
   int hx;        // compact sites per x line (L0 / 2)
   long Vh, Vhs;  // sites per parity, compact array stride
+  long Vsf;      // site stride of full-lattice fields
 };
 
-// the four spins of one colour (consecutive elements)
-__device__ __forceinline__ void ld4(const __half2 *p, cx<float> o[4]) {
-  const uint4 v = *(const uint4 *)p;
-  const unsigned w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int i = 0; i < 4; i++) {
-    __half2 h;
-    __builtin_memcpy(&h, &w[i], 4);
-    const float2 f = __half22float2(h);
-    o[i] = {f.x, f.y};
-  }
-}
-__device__ __forceinline__ void ld4(const float2 *p, cx<float> o[4]) {
-  const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 2);
-  o[0] = {a.x, a.y};
-  o[1] = {a.z, a.w};
-  o[2] = {b.x, b.y};
-  o[3] = {b.z, b.w};
-}
-__device__ __forceinline__ void ld4(const double2 *p, cx<double> o[4]) {
-#pragma unroll
-  for (int i = 0; i < 4; i++) o[i] = ldc(p + i);
-}
-__device__ __forceinline__ void st4(__half2 *p, const cx<float> o[4]) {
-  unsigned w[4];
-#pragma unroll
-  for (int i = 0; i < 4; i++) {
-    const __half2 h = __floats2half2_rn(o[i].re, o[i].im);
-    __builtin_memcpy(&w[i], &h, 4);
-  }
-  *(uint4 *)p = make_uint4(w[0], w[1], w[2], w[3]);
-}
-__device__ __forceinline__ void st4(float2 *p, const cx<float> o[4]) {
-  *(float4 *)p = make_float4(o[0].re, o[0].im, o[1].re, o[1].im);
-  *(float4 *)(p + 2) = make_float4(o[2].re, o[2].im, o[3].re, o[3].im);
-}
-__device__ __forceinline__ void st4(double2 *p, const cx<double> o[4]) {
-#pragma unroll
-  for (int i = 0; i < 4; i++) stc(p + i, o[i]);
-}
 
 // One colour of the projection straight from the four FP16 spins as
 // stored: h = p_up - S A_mu p_down with every sum written fma(x, one, y),
@@ -579,9 +616,13 @@ static EoTiles make_eo_tiles(const EoGeom &e, int zb) {
 
 // out = a in_diag + b H_par(in_hop) at the compact sites of parity par, for
 // RT right-hand sides per thread (sharing every link load); with RED, also
-// <out, in_diag> and |out|^2 per tile and rhs into red (as stored).  Site
-// indices are 32-bit (a parity holds fewer than 2^29 sites).
-template <class TL, class TD, class TH, class TO, int RT, int RED, int NR>
+// <out, in_diag> and |out|^2 per tile and rhs into red (as stored).  With
+// ADD, out is instead a full-lattice field [rhs][12][Vsf] that receives
+// the result at the site of parity par and in_hop's value at the other site
+// of the same x pair (same compact index): the last step of the red/black
+// smoother, e += (d_e, d_o), without a separate pass.  Site indices are
+// 32-bit (a parity holds fewer than 2^29 sites).
+template <class TL, class TD, class TH, class TO, int RT, int RED, int NR, int ADD = 0>
 __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const TD *__restrict__ in_diag,
                                                const TH *__restrict__ in_hop, TO *__restrict__ out, EoGeom g, int par,
                                                double ad, double bd, int nrhs, EoTiles tl, double *__restrict__ red,
@@ -691,7 +732,20 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
 #pragma unroll
         for (int sp = 0; sp < 4; sp++)
           o[sp] = {a * dv[sp].re + b * acc[t][sp * 3 + c].re, a * dv[sp].im + b * acc[t][sp * 3 + c].im};
-        st4(out + i, o);
+        if constexpr (ADD) {
+          // the pair (2h, 2h + 1) of full-lattice sites: this site and its
+          // partner of the other parity
+          cx<R> hv[4];
+          ld4(in_hop + i, hv);
+          const int own = x[0] & 1;
+#pragma unroll
+          for (int sp = 0; sp < 4; sp++) {
+            TO *pp = out + ((size_t)(r0 + t) * 12 + sp * 3 + c) * g.Vsf + 2 * (size_t)(unsigned)h;
+            add_pair(pp, own ? hv[sp] : o[sp], own ? o[sp] : hv[sp]);
+          }
+        } else {
+          st4(out + i, o);
+        }
         if (RED) {
 #pragma unroll
           for (int sp = 0; sp < 4; sp++) {
@@ -731,6 +785,7 @@ static EoGeom make_eo(const Geom &g) {
   e.hx = g.L[0] / 2;
   e.Vh = g.V / 2;
   e.Vhs = fine_stride(e.Vh);
+  e.Vsf = g.Vs;
   return e;
 }
 
@@ -761,7 +816,7 @@ long eo_red_tiles(const Geom &g) {
   return m;
 }
 
-template <class TL, class TD, class TH, class TO, int RT, int NR>
+template <class TL, class TD, class TH, class TO, int RT, int NR, int ADD = 0>
 static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, double b, const void *in_diag,
                          const void *in_hop, void *out, int nrhs, double *red, double *red_out, int red_stride,
                          hipStream_t st) {
@@ -778,7 +833,7 @@ static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, doubl
       hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)tl.ntile, red_out,
                          red_stride);
     } else {
-      hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 0, NR>), grid, dim3(256), 0, st, (const TL *)Ue,
+      hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 0, NR, ADD>), grid, dim3(256), 0, st, (const TL *)Ue,
                          (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl,
                          (double *)nullptr, 1.0f);
     }
@@ -786,11 +841,13 @@ static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, doubl
     return 0;
   };
   char key[256];
-  std::snprintf(key, sizeof(key), "hop_eo/l%zu-d%zu-h%zu-o%zu-nr%d-red%d-diag%d/%dx%dx%dx%d/rhs%d", sizeof(TL),
-                sizeof(TD), sizeof(TH), sizeof(TO), NR, red ? 1 : 0, a != 0.0 ? 1 : 0, g.L[0], g.L[1], g.L[2],
-                g.L[3], nrhs);
+  std::snprintf(key, sizeof(key), "hop_eo/l%zu-d%zu-h%zu-o%zu-nr%d-red%d-diag%d-add%d/%dx%dx%dx%d/rhs%d",
+                sizeof(TL), sizeof(TD), sizeof(TH), sizeof(TO), NR, red ? 1 : 0, a != 0.0 ? 1 : 0, ADD, g.L[0],
+                g.L[1], g.L[2], g.L[3], nrhs);
   int choice = 0;
-  return tune_choice(key, ncand, run, st, &choice);
+  // candidates with ADD accumulate into out: not pure, so no search (slab
+  // depth 4, or the first that divides L2)
+  return ADD ? run(0) : tune_choice(key, ncand, run, st, &choice);
 }
 
 int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b, int pdiag, const void *in_diag,
@@ -809,6 +866,21 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
   if (lp == P16 && pdiag == P16 && phop == P32 && pout == P32) HOP(__half2, __half2, float2, float2, 2);
 #undef HOP
   return set_error(-1, "hop_eo: unsupported precisions link %d diag %d hop %d out %d", lp, pdiag, phop, pout);
+}
+
+int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int pdiag, const void *in_diag,
+               int phop, const void *de, void *full, int nrhs, hipStream_t st) {
+  const bool c12 = (lprec & LK12) != 0;
+  const int lp = lprec & ~LK12;
+  if (g.L[0] % 2 || g.V / 2 >= (1L << 29)) return set_error(-1, "hop_eo_add: lattice not supported");
+#define HOPA(TL, TD, TH, RT)                                                                                      \
+  return c12 ? launch_hop_eo<TL, TD, TH, TH, RT, 6, 1>(g, Ue, 1, a, b, in_diag, de, full, nrhs, nullptr, nullptr, 0, \
+                                                      st)                                                          \
+             : launch_hop_eo<TL, TD, TH, TH, RT, 9, 1>(g, Ue, 1, a, b, in_diag, de, full, nrhs, nullptr, nullptr, 0, st)
+  if (lp == P64 && pdiag == P64 && phop == P64) HOPA(double2, double2, double2, 1);
+  if (lp == P16 && pdiag == P16 && phop == P32) HOPA(__half2, __half2, float2, 2);
+#undef HOPA
+  return set_error(-1, "hop_eo_add: unsupported precisions link %d diag %d field %d", lp, pdiag, phop);
 }
 
 // full lexicographic SoA [rhs][12][Vs] <-> half-lattice [rhs][colour][Vhs][spin]

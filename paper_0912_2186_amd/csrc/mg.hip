@@ -86,7 +86,8 @@ __global__ void k_mr_next(const double *__restrict__ red, int k, const S *__rest
 struct MrVecs {
   const void *s[4];
 };
-template <class S, class SS = S>
+// e (+)= sum_k alpha_k s_k; ACC = 0 overwrites e
+template <class S, class SS = S, int ACC = 1>
 __global__ void k_mr_accum(const double *__restrict__ red, int nsteps, MrVecs v, S *__restrict__ e, long n) {
   using R = typename store_traits<S>::real;
   constexpr int PK = pack_len<S>() > pack_len<SS>() ? pack_len<S>() : pack_len<SS>();
@@ -98,7 +99,12 @@ __global__ void k_mr_accum(const double *__restrict__ red, int nsteps, MrVecs v,
   const long np = n / PK;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
     cx<R> acc[PK];
-    ldp<PK>(e + off + i * PK, acc);
+    if (ACC) {
+      ldp<PK>(e + off + i * PK, acc);
+    } else {
+#pragma unroll
+      for (int q = 0; q < PK; q++) acc[q] = czero<R>();
+    }
 #pragma unroll
     for (int k = 0; k < 4; k++)
       if (k < nsteps) {
@@ -624,46 +630,54 @@ static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, vo
   const void *Ue;
   TRY(eo_links(c, lp, &Ue));
   const int lc = lp | L.lk;
-  void *s, *xk[4] = {nullptr, nullptr, nullptr, nullptr}, *q, *t, *se, *so, *de, *dd;
+  void *s = nullptr, *xk[4] = {nullptr, nullptr, nullptr, nullptr}, *q, *t, *se, *so, *de;
   const int names[4] = {VH0, VH1, VH2, VH3};
-  TRY(level_vec(c, 0, vp, VS, &s, nrhs));
+  if (sp == P64) TRY(level_vec(c, 0, vp, VS, &s, nrhs));
   for (int k = 0; k < nsteps; k++) TRY(level_vec(c, 0, vp, names[k], &xk[k], nrhs));
   TRY(level_vec(c, 0, vp, VHQ, &q, nrhs));
   TRY(level_vec(c, 0, vp, VHT, &t, nrhs));
   TRY(level_vec(c, 0, vp, VHSE, &se, nrhs));
   TRY(level_vec(c, 0, vp, VHSO, &so, nrhs));
   TRY(level_vec(c, 0, dp, VHDE, &de, nrhs));
-  TRY(level_vec(c, 0, dp, VHDO, &dd, nrhs));
   const double m4 = 4.0 + L.m;
   const long nh = 12 * eo_stride(L.g);
   const double vb = (double)L.g.V * fine_link_cx(L) * (lp == P64 ? 16 : 4);  // links of both halves
   const double eb = sp == P64 ? 16 : 4;                                        // sublattice element bytes
+  const double db = sp == P64 ? 16 : 8;                                        // correction element bytes
+  const double hs = (double)L.g.V / 2 * 12 * nrhs;                             // elements of one half field
+  // one red/black hop launch, timed and counted as the cycle's fine operator
+  // (algorithmic bytes: the links of both halves, the input, the output and
+  // the diagonal input when there is one)
+  auto hop = [&](int par, double a, double b, int pdg, const void *dg, int phop, const void *in, int pout, void *out,
+                 double *red, double *red_out, double bytes) -> int {
+    const int slot = prof_begin(c, sp == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE, bytes);
+    const int rc = hop_eo(L.g, lc, Ue, par, a, b, pdg, dg, phop, in, pout, out, nrhs, red, red_out, 4, c->st);
+    prof_end(c, slot);
+    return rc;
+  };
   // s = r - D e (full lattice; FP16 on the normalised problem), split
   c->st_fine++;
   int slot;
   if (sp == P64) {
     TRY(fine_apply_fused(c, P64, e, s, nrhs, r, false));
   } else {
+    // written straight into the two half-lattice arrays
     slot = prof_begin(c, K_DSLASH_RES, vb + (double)L.g.V * 12 * (8 + 8 + 4) * nrhs);
-    int rc = wilson_soa_h16(L.g, fine_links(L, P16), P32, L.m, e, s, nrhs, r, rn2, 4, nullptr, nullptr, 0, c->st,
-                            L.lk);
+    int rc = wilson_soa_h16(L.g, fine_links(L, P16), P32, L.m, e, se, nrhs, r, rn2, 4, nullptr, nullptr, 0, c->st,
+                            L.lk, so);
     prof_end(c, slot);
     TRY(rc);
   }
-  TRY(eo_pack(L.g, vp, s, vp, se, so, nrhs, c->st));
+  if (sp == P64) TRY(eo_pack(L.g, vp, s, vp, se, so, nrhs, c->st));
   // x_0 = s_e + H_e(s_o) / (2 (4+m))
-  TRY(hop_eo(L.g, lc, Ue, 0, 1.0, 0.5 / m4, vp, se, vp, so, vp, xk[0], nrhs, nullptr, nullptr, 0, c->st));
+  TRY(hop(0, 1.0, 0.5 / m4, vp, se, vp, so, vp, xk[0], nullptr, nullptr, vb + 3 * hs * eb));
   dim3 g = sp == P64 ? grid_for<double2>(nh, nrhs) : grid_for<__half2>(nh, nrhs);
   for (int k = 0; k < nsteps; k++) {
     // q = S x_k with <q, x_k>, |q|^2 -> mr_red[k]; x_{k+1} = x_k - alpha_k q
     c->st_fine++;
-    slot = prof_begin(c, K_DSLASH_CYCLE, 2 * vb + (double)L.g.V * 12 * eb * 2 * nrhs);
-    int rc = hop_eo(L.g, lc, Ue, 1, 0.0, 1.0, vp, nullptr, vp, xk[k], vp, t, nrhs, nullptr, nullptr, 0, c->st);
-    if (!rc)
-      rc = hop_eo(L.g, lc, Ue, 0, m4, -0.25 / m4, vp, xk[k], vp, t, vp, q, nrhs, c->dred,
-                  c->mr_red + (size_t)k * 64 * 4, 4, c->st);
-    prof_end(c, slot);
-    TRY(rc);
+    TRY(hop(1, 0.0, 1.0, vp, nullptr, vp, xk[k], vp, t, nullptr, nullptr, vb + 2 * hs * eb));
+    TRY(hop(0, m4, -0.25 / m4, vp, xk[k], vp, t, vp, q, c->dred, c->mr_red + (size_t)k * 64 * 4,
+            vb + 3 * hs * eb));
     if (k + 1 < nsteps) {
       if (sp == P64)
         hipLaunchKernelGGL(k_mr_next<double2>, g, dim3(256), 0, c->st, c->mr_red, k, (const double2 *)xk[k],
@@ -675,16 +689,20 @@ static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, vo
     }
   }
   // d_e = sum_k alpha_k x_k
-  TRY(zero(dp, de, nh, nrhs, c->st));
   MrVecs mv{{xk[0], xk[1], xk[2], xk[3]}};
   if (sp == P64)
-    hipLaunchKernelGGL(k_mr_accum<double2>, g, dim3(256), 0, c->st, c->mr_red, nsteps, mv, (double2 *)de, nh);
+    hipLaunchKernelGGL((k_mr_accum<double2, double2, 0>), g, dim3(256), 0, c->st, c->mr_red, nsteps, mv,
+                       (double2 *)de, nh);
   else
-    hipLaunchKernelGGL((k_mr_accum<float2, __half2>), g, dim3(256), 0, c->st, c->mr_red, nsteps, mv, (float2 *)de, nh);
+    hipLaunchKernelGGL((k_mr_accum<float2, __half2, 0>), g, dim3(256), 0, c->st, c->mr_red, nsteps, mv,
+                       (float2 *)de, nh);
   WMG_HIP(hipGetLastError());
-  // d_o = (s_o + H_o(d_e) / 2) / (4+m); e += d
-  TRY(hop_eo(L.g, lc, Ue, 1, 1.0 / m4, 0.5 / m4, vp, so, dp, de, dp, dd, nrhs, nullptr, nullptr, 0, c->st));
-  return eo_unpack_add(L.g, dp, e, dp, de, dd, nrhs, c->st);
+  // d_o = (s_o + H_o(d_e) / 2) / (4+m) and e += (d_e, d_o) in one kernel
+  // (bytes: links, s_o, d_e, and e read and written)
+  const int slot2 = prof_begin(c, sp == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE, vb + hs * (eb + db + 4 * db));
+  const int rc2 = hop_eo_add(L.g, lc, Ue, 1.0 / m4, 0.5 / m4, vp, so, dp, de, e, nrhs, c->st);
+  prof_end(c, slot2);
+  return rc2;
 }
 
 static int mr_smooth(wmg_ctx *c, int l, int prec, const void *r, void *e, int nsteps, int nrhs,
@@ -1903,7 +1921,7 @@ static int canon_to_eo(wmg_ctx *c, int p, const double *canon, void *ev, void *o
 int mg_hop_eo(wmg_ctx *c, int prec, int par, double a, double b, const double *diag, const double *hop, double *out,
               int nrhs) {
   if (!c || !hop || !out || (a != 0.0 && !diag) || nrhs < 1 || nrhs > c->p.nrhs_max || nrhs > 64 ||
-      (prec != 0 && prec != 3 && prec != 4) || (par != 0 && par != 1))
+      (prec != 0 && prec != 3 && prec != 4 && prec != 5) || (par != 0 && par != 1) || (prec == 5 && par != 1))
     return set_error(WMG_EINVAL, "bad argument");
   Level &F = c->lv[0];
   for (int i = 0; i < 4; i++)
@@ -1921,19 +1939,25 @@ int mg_hop_eo(wmg_ctx *c, int prec, int par, double a, double b, const double *d
   TRY(level_vec(c, 0, ph, VHQ, &o, nrhs));
   if (a != 0.0) TRY(canon_to_eo(c, pd, diag, de, dod, nrhs));
   TRY(canon_to_eo(c, ph, hop, he, ho, nrhs));
-  TRY(hop_eo(F.g, lp | F.lk, Ue, par, a, b, pd, a != 0.0 ? (par ? dod : de) : nullptr, ph, par ? he : ho, ph, o,
-             nrhs, nullptr, nullptr, 0, c->st));
-  // result (sites of parity par) -> zeroed full lattice -> canonical FP64
   const long nh = 12 * eo_stride(F.g);
   const int pf = ph == P64 ? P64 : P32;
-  void *o2 = o, *full, *b64;
-  if (ph == P16) {
-    TRY(level_vec(c, 0, P32, VHQ, &o2, nrhs));
-    TRY(copy(P32, o2, P16, o, nh, nrhs, c->st));
-  }
+  void *full, *b64;
   TRY(level_vec(c, 0, pf, VT, &full, nrhs));
   TRY(zero(pf, full, F.n, nrhs, c->st));
-  TRY(eo_unpack_add(F.g, pf, full, pf, par ? nullptr : o2, par ? o2 : nullptr, nrhs, c->st));
+  if (prec == 5) {
+    // the smoother's last step: full += (hop at the even sites, the odd result)
+    TRY(hop_eo_add(F.g, lp | F.lk, Ue, a, b, pd, a != 0.0 ? dod : nullptr, ph, he, full, nrhs, c->st));
+  } else {
+    TRY(hop_eo(F.g, lp | F.lk, Ue, par, a, b, pd, a != 0.0 ? (par ? dod : de) : nullptr, ph, par ? he : ho, ph, o,
+               nrhs, nullptr, nullptr, 0, c->st));
+    // result (sites of parity par) -> zeroed full lattice
+    void *o2 = o;
+    if (ph == P16) {
+      TRY(level_vec(c, 0, P32, VHQ, &o2, nrhs));
+      TRY(copy(P32, o2, P16, o, nh, nrhs, c->st));
+    }
+    TRY(eo_unpack_add(F.g, pf, full, pf, par ? nullptr : o2, par ? o2 : nullptr, nrhs, c->st));
+  }
   b64 = full;
   if (pf == P32) {
     TRY(level_vec(c, 0, P64, VT, &b64, nrhs));

@@ -170,10 +170,12 @@ int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double 
 // only with iprec P32) is scaled per rhs by 1/sqrt(bnrm2[rhs * bstride])
 // (0 where that norm is 0); red as in wilson_soa_fused, computed from the
 // stored (rounded) output.
-// lflags: LK12 for links stored as two rows.
+// lflags: LK12 for links stored as two rows.  With out_odd (FP32 input, no
+// reductions) the output goes to the half-lattice arrays out (even sites)
+// and out_odd (odd sites) instead of a full-lattice field.
 int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
                    const void *bsub, const double *bnrm2, int bstride, double *red, double *red_out, int red_stride,
-                   hipStream_t st, int lflags = 0);
+                   hipStream_t st, int lflags = 0, void *out_odd = nullptr);
 // partials per rhs that the fused reductions of wilson_soa_fused,
 // wilson_soa_h16 and hop_eo may write (the largest of their tilings)
 long wilson_red_blocks(const Geom &g);
@@ -191,6 +193,12 @@ long eo_red_tiles(const Geom &g);
 int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b, int pdiag, const void *in_diag,
            int phop, const void *in_hop, int pout, void *out, int nrhs, double *red, double *red_out, int red_stride,
            hipStream_t st);
+// full (full-lattice, precision phop) += d_e at the even sites and
+// a in_diag + b H_odd(d_e) at the odd sites, d_e the even half-lattice field
+// (precision phop): all FP64, or FP16 links and in_diag with FP32 d_e and
+// full.
+int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int pdiag, const void *in_diag,
+               int phop, const void *de, void *full, int nrhs, hipStream_t st);
 int eo_pack(const Geom &g, int pfull, const void *full, int phalf, void *ev, void *od, int nrhs, hipStream_t st);
 int eo_unpack_add(const Geom &g, int pfull, void *full, int phalf, const void *ev, const void *od, int nrhs,
                   hipStream_t st);

@@ -62,7 +62,7 @@ def _decaying(L, site, kappa, seed):
 # (lattice, aggregate): several tiles with a ragged last chunk per slab, and
 # a lattice whose z extent admits only slabs of 1, 2 or 6 z-slices
 @pytest.mark.parametrize("L,block", [((20, 14, 4, 6), (4, 2, 4, 2)), ((8, 8, 6, 12), (4, 4, 2, 4))])
-@pytest.mark.parametrize("prec", [0, 3, 4])
+@pytest.mark.parametrize("prec", [0, 3, 4, 5])
 def test_hop_kernel_per_site(wmg, L, block, prec):
     """out = a diag + b H_par(hop) from the GPU kernel against the oracle's
     D_{par,1-par} (H = -2 D_{par,1-par}), both parities, both link formats,
@@ -85,16 +85,23 @@ def test_hop_kernel_per_site(wmg, L, block, prec):
         hop_in, diag_in = _round(src, np.float16), _round(dg, np.float16)
     else:
         hop_in, diag_in = _round(src, np.float32), _round(dg, np.float16)
+    # prec 5 is the fused last step of the smoother: parity 1 only, and the
+    # even sites return hop's own values
+    cases = ((1, 0.0, 1.0), (0, m4, -0.25 / m4), (1, 1.0 / m4, 0.5 / m4))
+    if prec == 5:
+        cases = ((1, 1.0 / m4, 0.5 / m4), (1, 0.0, 1.0))
     for flags in (0, wmg.WMG_LINKS18):
         p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=3, flags=flags)
         mg = wmg.MG(L, dev(U), m, 4, block, p)
-        for par, a, b in ((1, 0.0, 1.0), (0, m4, -0.25 / m4), (1, 1.0 / m4, 0.5 / m4)):
+        for par, a, b in cases:
             out = empty((3, V, 12))
             mg.mg_hop_eo(prec, par, a, b, dev(diag_in) if a != 0.0 else None, dev(hop_in), out, 3)
             oh = host(out)
             for r in range(3):
                 mask = (par_of == par)[:, None]
                 ref = (a * diag_in[r] + b * (-2.0) * oracle.wilson_hop_parity(L, U, m, hop_in[r], par)) * mask
+                if prec == 5:
+                    ref = ref + hop_in[r] * ~mask
                 sc_in = np.concatenate([hop_in[r], diag_in[r]], axis=1) if a != 0.0 else hop_in[r]
                 k = abs(a) + 16 * abs(b)
                 if prec == 0:
@@ -106,7 +113,10 @@ def test_hop_kernel_per_site(wmg, L, block, prec):
                 say("  L", L, "prec", prec, "links", mg.mg_link_reals(), "par", par, "rhs", r,
                     "relerr %.2e site %.2e" % (relerr(oh[r], ref), le))
                 assert le < bound
-                assert np.all(oh[r][~mask[:, 0]] == 0)
+                if prec == 5:
+                    assert np.array_equal(oh[r][~mask[:, 0]], hop_in[r][~mask[:, 0]])
+                else:
+                    assert np.all(oh[r][~mask[:, 0]] == 0)
         mg.close()
 
 
