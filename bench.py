@@ -82,6 +82,13 @@ def measured_traffic(workload, kernel_class):
     return None
 
 
+def solver_flags(args):
+    from paper_0912_2186_amd import wmg
+
+    return ((wmg.WMG_EO_SMOOTHER if args.smoother == "redblack" else 0) |
+            (wmg.WMG_GRAPHS if getattr(args, "graphs", False) else 0))
+
+
 def make_rhs(inputs, L, w):
     import numpy as np
 
@@ -108,7 +115,7 @@ def cpu_info():
     return {"cpu_model": model, "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
 
 
-def cpu_baseline(w):
+def cpu_baseline(w, eo_smoother=True):
     """The FP64 oracle, as it stands, on a bounded sample of the same
     workload: setup + MG-GCR solves of the workload's own right-hand-side
     kinds (2 point sources and 2 Z4 noise vectors) on a 12^3 x 16
@@ -128,7 +135,7 @@ def cpu_baseline(w):
     V = L[0] * L[1] * L[2] * L[3]
     U = inputs.gauge_field(Ls, w["eps"], w["seed_cfg"] * 100 + 1)
     p = oracle.default_params(nlevels=2, nv=(w["nv"],), setup_iters=w["setup_iters"], seed=w["seed_cfg"] * 100 + 50,
-                              coarse_tol=COARSE_TOL_MIXED if w["mixed"] else 1e-8)
+                              coarse_tol=COARSE_TOL_MIXED if w["mixed"] else 1e-8, eo_smoother=eo_smoother)
     mg = oracle.MG(Ls, U, w["m"], p)
     t0 = time.time()
     mg.setup()
@@ -161,7 +168,8 @@ def cpu_baseline(w):
         "cores": nthr,
         "kind": "oracle",
         "estimate": True,
-        "sample": "estimate: FP64 oracle MG-GCR (same N_nu, blocks, eps, m, tol 1e-10) on a 12^3x16 sub-volume, "
+        "sample": "estimate: FP64 oracle MG-GCR (same N_nu, blocks, eps, m, smoother, tol 1e-10) on a 12^3x16 "
+                  "sub-volume, "
                   "2 point + 2 Z4 rhs solved one by one: %.3f s/RHS (outer iterations %s; setup %.1f s not counted), "
                   "scaled by the volume ratio %.2f" % (t, its, ts, V / Vs),
         "oracle_dslash_s": round(td, 4),
@@ -210,7 +218,7 @@ def critical_scan(args, w):
     p = wmg.default_params(setup_iters=w["setup_iters"], seed=w["seed_cfg"] * 100 + 50, nrhs_max=1,
                            precision=wmg.WMG_MIXED,
                            coarse_tol=args.coarse_tol if args.coarse_tol is not None else COARSE_TOL_MIXED,
-                           flags=wmg.WMG_EO_SMOOTHER if args.smoother == "redblack" else 0, **kw)
+                           flags=solver_flags(args), **kw)
     os.environ.setdefault("WMG_VERBOSE", "1")  # the setup reports each null vector
     torch.cuda.synchronize()
     t0 = time.time()
@@ -260,6 +268,8 @@ def main():
     ap.add_argument("--delta", type=float, default=None, help="reliable-update threshold (default: library's)")
     ap.add_argument("--coarse-tol", type=float, default=None,
                     help="coarsest CGNR tolerance (mixed default %g)" % COARSE_TOL_MIXED)
+    ap.add_argument("--graphs", action="store_true",
+                    help="run the coarsest CGNR as captured HIP graphs of 4 iterations (WMG_GRAPHS)")
     ap.add_argument("--smoother", choices=["redblack", "mr"], default="redblack",
                     help="fine-level post-smoother: MR on the red/black Schur complement (default) or MR on D")
     ap.add_argument("--levels", type=int, choices=[2, 3], default=2,
@@ -312,7 +322,7 @@ def main():
         p = wmg.default_params(setup_iters=1, seed=w["seed_cfg"] * 100 + 50, nrhs_max=b.shape[0],
                                precision=wmg.WMG_MIXED if w["mixed"] else wmg.WMG_FP64,
                                coarse_tol=args.coarse_tol if args.coarse_tol is not None else COARSE_TOL_MIXED,
-                               flags=wmg.WMG_EO_SMOOTHER if args.smoother == "redblack" else 0)
+                               flags=solver_flags(args))
         mg = wmg.MG(L, torch.from_numpy(U).cuda(), w["m"], w["nv"], (4, 4, 4, 4), p)
         bd = torch.from_numpy(b).cuda()
         st = mg.mg_solve(bd, torch.zeros_like(bd), 1e-10)
@@ -330,7 +340,7 @@ def main():
     p = wmg.default_params(setup_iters=w["setup_iters"], seed=w["seed_cfg"] * 100 + 50, nrhs_max=nrhs,
                            precision=wmg.WMG_MIXED if w["mixed"] else wmg.WMG_FP64,
                            coarse_tol=COARSE_TOL_MIXED if w["mixed"] else 1e-8,
-                           flags=wmg.WMG_EO_SMOOTHER if args.smoother == "redblack" else 0)
+                           flags=solver_flags(args))
     if args.delta is not None:
         p.reliable_delta = args.delta
     if args.coarse_tol is not None:
@@ -394,16 +404,12 @@ def main():
     kernels = {k: {"launches": v[0], "ms": round(v[1], 2),
                    "GB/s": round(v[2] / max(v[0], 1) / (v[1] / max(v[0], 1) * 1e-3) / 1e9, 1) if v[0] else None}
                for k, v in prof.items()}
-    # true residual of the timed solves through the library's FP64 operator,
-    # and for a sample of rhs (2 point sources, 2 Z4 vectors) through the
-    # oracle's operator
+    # true residual of the timed solves through the library's FP64 operator;
+    # the CPU leg below also checks a sample of rhs (2 point sources, 2 Z4
+    # vectors) with the oracle's operator
     relres = max(s["true_relres"] for s in stats)
     sample = sorted(set(i for i in (0, 1, w.get("npoint", 0), w.get("npoint", 0) + 1) if i < nrhs))
-    xh = {i: xd[i].cpu().numpy() for i in sample}
-    t0 = time.time()
-    orc_res = oracle_residuals(L, U, w["m"], b, xh, sample)
-    log("oracle residuals %.1fs: %s" % (time.time() - t0, orc_res))
-    del xh
+    xh = {i: xd[i].cpu().numpy() for i in sample} if not args.no_cpu else None
     # Dslash bandwidth on internal layouts (algorithmic bytes, HIP events)
     # algorithmic bytes of the operator as stored: 4 links per site in the
     # context's format (12 reals for SU(3) fields: 24 complex per site, else
@@ -431,12 +437,21 @@ def main():
         mg.mg_set_precision(wmg.WMG_MIXED)
         log("fp64 single-rhs: %s" % fp64)
     mg.close()
-    del U
     cpu = None
+    orc_res = {}
     if not args.no_cpu:
+        # the CPU leg: the oracle's FP64 residual of sampled GPU solutions,
+        # then the oracle timed as the CPU baseline
         t0 = time.time()
-        cpu = cpu_baseline(w)
+        orc_res = oracle_residuals(L, U, w["m"], b, xh, sample)
+        log("oracle residuals %.1fs: %s" % (time.time() - t0, orc_res))
+        del xh
+        del U
+        t0 = time.time()
+        cpu = cpu_baseline(w, args.smoother == "redblack")
         log("cpu baseline %.1fs: %s" % (time.time() - t0, cpu))
+    else:
+        del U
     iters = [s["outer_iters"] for s in stats]
     out = {
         "metric": "MG-GCR time-to-solution @1e-10 (s/RHS), mixed+batched vs FP64; Dslash GB/s",
@@ -454,9 +469,10 @@ def main():
         "config": {"workload": args.workload, "lattice": list(L), "eps": w["eps"], "mass": w["m"], "Nv": w["nv"],
                    "block": [4, 4, 4, 4], "nrhs": nrhs, "tol": 1e-10, "levels": 2,
                    "smoother": "MR on the red/black Schur complement" if args.smoother == "redblack" else "MR on D",
+                   "coarse_solve": "CGNR to %g%s" % (p.coarse_tol, ", captured HIP graphs" if args.graphs else ""),
                    "outer_iters": iters[-1], "true_relres_max": relres, "setup_s": round(setup_s, 2)},
         "oracle_relres": {"rhs": sorted(orc_res), "relres": [orc_res[k] for k in sorted(orc_res)],
-                          "max": max(orc_res.values()) if orc_res else None},
+                          "max": max(orc_res.values())} if orc_res else None,
         "ms_per_step_with_events": round(el_prof / nprof * 1e3, 2),
         "roofline": roofline,
         "kernels": kernels,

@@ -27,6 +27,10 @@ struct CGeom {
   long Vs;  // fine-lattice site stride of the links
   int bs, dof, nv;
   int ns;   // parts of the fine site's 12 components: 2 chiralities or 4 spins
+  // storage of the built blocks: coarse index (part, alpha) at part * nld +
+  // alpha of a block with leading dimension ldn (nld = nv, ldn = ns * nv for
+  // the compact layout); columns computed: alpha = al0 .. al0 + gridDim.y/ns - 1
+  int nld, ldn, al0;
 };
 
 __device__ __forceinline__ long cg_block_site(const CGeom &g, long xh, int k, int x[4]) {
@@ -115,10 +119,11 @@ template <int NS>
 __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__restrict__ U, double m,
                                                     const double2 *__restrict__ P, double2 *__restrict__ Yc) {
   long xh = blockIdx.x;
-  int col = blockIdx.y;
   constexpr int hc = 12 / NS;
   const int nv = g.nv, n = NS * nv;
-  int chic = col / nv, al = col % nv;
+  const int nal = gridDim.y / NS;
+  const int chic = blockIdx.y / nal, al = g.al0 + blockIdx.y % nal;
+  const int colS = chic * g.nld + al;
   __shared__ double sh[4 * 2 * 16];
   __shared__ double red[2 * 16];
   int k = threadIdx.x;
@@ -176,8 +181,10 @@ __global__ void __launch_bounds__(TB) k_build_wilson(CGeom g, const double2 *__r
       }
       cg_wsum<16>(acc, sh, red);
       if (threadIdx.x < 16 && r0 + (int)threadIdx.x < n) {
-        int row = r0 + threadIdx.x;
-        Yc[(((size_t)xh * 9 + d) * n + col) * n + row] = make_double2(red[2 * threadIdx.x], red[2 * threadIdx.x + 1]);
+        const int row = r0 + threadIdx.x;
+        const int rowS = (row / nv) * g.nld + row % nv;
+        Yc[(((size_t)xh * 9 + d) * g.ldn + colS) * g.ldn + rowS] =
+            make_double2(red[2 * threadIdx.x], red[2 * threadIdx.x + 1]);
       }
       __syncthreads();
     }
@@ -190,9 +197,10 @@ template <int EPT>
 __global__ void __launch_bounds__(TB) k_build_coarse(CGeom g, const double2 *__restrict__ Yf,
                                                     const double2 *__restrict__ P, double2 *__restrict__ Yc) {
   long xh = blockIdx.x;
-  int col = blockIdx.y;
   int nv = g.nv, n = 2 * nv, f = g.dof, h = f / 2;
-  int chic = col / nv, al = col % nv;
+  const int nal = gridDim.y / 2;
+  const int chic = blockIdx.y / nal, al = g.al0 + blockIdx.y % nal;
+  const int colS = chic * g.nld + al;
   const long E = (long)g.bs * f;
   __shared__ double sh[4 * 2 * 16];
   __shared__ double red[2 * 16];
@@ -250,7 +258,9 @@ __global__ void __launch_bounds__(TB) k_build_coarse(CGeom g, const double2 *__r
       cg_wsum<16>(acc, sh, red);
       if (threadIdx.x < 16 && r0 + (int)threadIdx.x < n) {
         int row = r0 + threadIdx.x;
-        Yc[(((size_t)xh * 9 + d) * n + col) * n + row] = make_double2(red[2 * threadIdx.x], red[2 * threadIdx.x + 1]);
+        const int rowS = (row / nv) * g.nld + row % nv;
+        Yc[(((size_t)xh * 9 + d) * g.ldn + colS) * g.ldn + rowS] =
+            make_double2(red[2 * threadIdx.x], red[2 * threadIdx.x + 1]);
       }
       __syncthreads();
     }
@@ -288,8 +298,11 @@ static int upload_gamma() {
   return gamma_status;
 }
 
-int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf, const int b[4],
-                 int nv, const double2 *P, double2 *Yc, double2 * /*work*/, hipStream_t st, int ns) {
+// columns alpha = al0 .. al0 + nal - 1 of every part, all ns * nv rows, into
+// blocks of leading dimension ns * nld
+static int build_cols(const Geom &gf, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf,
+                      const int b[4], int nv, int nld, int al0, int nal, const double2 *P, double2 *Yc, hipStream_t st,
+                      int ns) {
   CGeom g;
   for (int i = 0; i < 4; i++) {
     g.L[i] = gf.L[i];
@@ -303,8 +316,12 @@ int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, dou
   g.dof = fine_kind == 0 ? 12 : dof;
   g.nv = nv;
   g.ns = fine_kind == 0 ? ns : 2;
+  g.nld = nld;
+  g.ldn = g.ns * nld;
+  g.al0 = al0;
   if (g.ns != 2 && g.ns != 4) return set_error(-1, "coarse_build: %d parts", g.ns);
-  dim3 grid((unsigned)g.Vc, g.ns * nv);
+  if (nv > nld || al0 < 0 || nal < 1 || al0 + nal > nv) return set_error(-1, "coarse_build: columns out of range");
+  dim3 grid((unsigned)g.Vc, g.ns * nal);
   if (fine_kind == 0) {
     if (g.bs > TB) return set_error(-1, "coarse_build: aggregate of %d sites > %d", g.bs, TB);
     int rc = upload_gamma();
@@ -319,6 +336,86 @@ int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, dou
     else if (ept <= 16) hipLaunchKernelGGL((k_build_coarse<16>), grid, dim3(TB), 0, st, g, Yf, P, Yc);
     else return set_error(-1, "coarse_build: aggregate too large (%ld elements)", E);
   }
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
+int coarse_build(const Geom &gf, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf, const int b[4],
+                 int nv, const double2 *P, double2 *Yc, double2 * /*work*/, hipStream_t st, int ns) {
+  return build_cols(gf, fine_kind, dof, U64soa, m, Yf, b, nv, nv, 0, nv, P, Yc, st, ns);
+}
+
+// The rows of the newest vector from the columns just built, by the
+// gamma_5-hermiticity of the coarse operator: sigma_3 D_hat sigma_3 =
+// D_hat^dag (sigma_3 = +1 on the first half of the parts, -1 on the
+// second), block by block D_hat(y, x) = sigma_3 D_hat(x, y)^dag sigma_3, i.e.
+//   X(x)[i][j]        = s_i s_j conj(X(x)[j][i])
+//   Y_{+mu}(x)[i][j]  = s_i s_j conj(Y_{-mu}(x+mu)[j][i])
+//   Y_{-mu}(x)[i][j]  = s_i s_j conj(Y_{+mu}(x-mu)[j][i])
+// for i a row of the newest vector (alpha = knew - 1) and j an older column.
+// One thread per (coarse site, block, part of the new row, older column).
+__global__ void k_mirror_new_rows(double2 *__restrict__ Y, int Lc0, int Lc1, int Lc2, int Lc3, long Vc, int ns,
+                                  int nld, int knew) {
+  const int nold = knew - 1;
+  const long per = 9L * ns * ns * nold;
+  const long i = blockIdx.x * 256L + threadIdx.x;
+  if (nold < 1 || i >= Vc * per) return;
+  const long xh = i / per;
+  long r = i % per;
+  const int d = (int)(r / ((long)ns * ns * nold));
+  r %= (long)ns * ns * nold;
+  const int chr = (int)(r / (ns * nold));
+  r %= ns * nold;
+  const int chj = (int)(r / nold), aj = (int)(r % nold);
+  const int L[4] = {Lc0, Lc1, Lc2, Lc3};
+  int x[4];
+  site_coords(L, xh, x);
+  int dp = 0;
+  if (d >= 1) {
+    const int mu = (d - 1) % 4, sg = d <= 4 ? 1 : -1;
+    x[mu] = (x[mu] + sg + L[mu]) % L[mu];
+    dp = sg > 0 ? 5 + mu : 1 + mu;
+  }
+  const long yh = site_index(L, x);
+  const int ldn = ns * nld;
+  const int rowS = chr * nld + nold, colS = chj * nld + aj;
+  const double2 v = Y[(((size_t)yh * 9 + dp) * ldn + rowS) * ldn + colS];
+  const double sgn = ((chr < ns / 2) == (chj < ns / 2)) ? 1.0 : -1.0;
+  Y[(((size_t)xh * 9 + d) * ldn + colS) * ldn + rowS] = make_double2(sgn * v.x, -sgn * v.y);
+}
+
+// blocks of leading dimension ns * nld -> compact blocks of the first k
+// vectors (n = ns * k)
+__global__ void k_pack_blocks(const double2 *__restrict__ Ys, double2 *__restrict__ Yc, long Vc, int ns, int nld,
+                              int k) {
+  const int n = ns * k, ldn = ns * nld;
+  const long i = blockIdx.x * 256L + threadIdx.x;
+  if (i >= Vc * 9L * n * n) return;
+  const long blk = i / ((long)n * n);
+  const int e = (int)(i % ((long)n * n));
+  const int c = e / n, rr = e % n;
+  const int cS = (c / k) * nld + c % k, rS = (rr / k) * nld + rr % k;
+  Yc[i] = Ys[(blk * ldn + cS) * ldn + rS];
+}
+
+int coarse_build_next(const Geom &gf, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf,
+                      const int b[4], int k, int nld, const double2 *P, double2 *Ys, double2 *Yc, hipStream_t st,
+                      int ns) {
+  if (k < 1 || k > nld) return set_error(-1, "coarse_build_next: %d vectors of %d", k, nld);
+  const int rc = build_cols(gf, fine_kind, dof, U64soa, m, Yf, b, k, nld, k - 1, 1, P, Ys, st, ns);
+  if (rc) return rc;
+  const int nsx = fine_kind == 0 ? ns : 2;
+  int Lc[4];
+  for (int i = 0; i < 4; i++) Lc[i] = gf.L[i] / b[i];
+  const long Vc = (long)Lc[0] * Lc[1] * Lc[2] * Lc[3];
+  if (k > 1) {
+    const long nm = Vc * 9L * nsx * nsx * (k - 1);
+    hipLaunchKernelGGL(k_mirror_new_rows, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, st, Ys, Lc[0], Lc[1],
+                       Lc[2], Lc[3], Vc, nsx, nld, k);
+    WMG_HIP(hipGetLastError());
+  }
+  const long np = Vc * 9L * nsx * k * nsx * k;
+  hipLaunchKernelGGL(k_pack_blocks, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, Ys, Yc, Vc, nsx, nld, k);
   WMG_HIP(hipGetLastError());
   return 0;
 }

@@ -1157,6 +1157,26 @@ static int build_level(wmg_ctx *c, int l, int k) {
   return 0;
 }
 
+// The setup's rebuild after vector k-1 has been added: only that vector's
+// block orthonormalisation and its columns (and, by gamma_5-hermiticity,
+// rows) of the Galerkin operator are computed; the first k-1 stay as built
+// (Ys holds the blocks with room for every vector of the level).
+static int build_level_next(wmg_ctx *c, int l, int k, double2 *Ys) {
+  Level &F = c->lv[l], &C = c->lv[l + 1];
+  F.nv = k;
+  C.dof = F.ns * k;
+  C.n = C.g.V * C.dof;
+  WMG_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), c->st));
+  TRY(block_orthonormalize(F.g, F.dof, F.b, k, F.vecs, F.fine ? 1 : 0, F.P64, c->flag, c->st, F.ns, k - 1));
+  int fail = 0;
+  WMG_HIP(hipMemcpyAsync(&fail, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  TRY(sync(c));
+  if (fail) return set_error(WMG_ERANK, "block Gram-Schmidt breakdown at level %d (null vectors dependent)", l);
+  TRY(coarse_build_next(F.g, F.fine ? 0 : 1, F.dof, F.U[P64], F.m, F.Y64, F.b, k, F.nv_max, F.P64, Ys, C.Y64, c->st,
+                        F.ns));
+  return 0;
+}
+
 // reduced-precision copies used by the mixed-precision cycle
 static int make_low_precision(wmg_ctx *c) {
   if (c->p.precision != WMG_MIXED) return 0;
@@ -1203,9 +1223,21 @@ static int setup_level(wmg_ctx *c, int l) {
   TRY(gcr_buffers(c, l, P64, 1, &B));
   long n = F.n;
   std::vector<int> its;
+  // blocks with room for every vector of the level, for the incremental
+  // rebuilds (freed at the end of the level's setup)
+  double2 *Ys = nullptr;
+  {
+    Level &C = c->lv[l + 1];
+    const size_t nmax = (size_t)F.ns * nv;
+    TRY(dalloc((void **)&Ys, sizeof(double2) * (size_t)C.g.V * 9 * nmax * nmax));
+  }
+  struct YsFree {
+    double2 *p;
+    ~YsFree() { if (p) (void)hipFree(p); }
+  } ys_free{Ys};
   for (int k = 0; k < nv; k++) {
     TRY(start_vectors(F.g.V, F.dof, c->p.seed, l, k, 1, B->x64, F.fine ? 1 : 0, F.g.Vs, c->st));
-    if (k > 0) TRY(build_level(c, l, k));
+    if (k > 0) TRY(build_level_next(c, l, k, Ys));
     TRY(zero(P64, B->b64, n, 1, c->st));
     int rc = gcr_solve(c, l, *B, 1, 0.0, c->p.setup_iters, k > 0 ? 1 : 0, 0.0, true, its, nullptr);
     if (rc < 0) return rc;
@@ -1217,6 +1249,8 @@ static int setup_level(wmg_ctx *c, int l) {
       std::fprintf(stderr, "wmg setup: level %d vector %d/%d done\n", l, k + 1, nv);
     }
   }
+  // the level's operator itself is one full Galerkin build (the same blocks
+  // as every other rebuild: load, refresh, given vectors)
   TRY(build_level(c, l, nv));
   c->nl_cur = c->nl;
   return sync(c);

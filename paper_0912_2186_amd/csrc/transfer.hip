@@ -150,7 +150,7 @@ __device__ __forceinline__ void wg_csum(cx<double> v[NV], double *sh /* [4][2*NV
 // numerically equivalent to modified GS twice), unit norm, positive real
 // diagonal of R.  EPT = elements per thread.
 template <int FINE, int EPT>
-__global__ void __launch_bounds__(TB) k_block_gs(BlockGeom bg, int nv, const double2 *__restrict__ vecs,
+__global__ void __launch_bounds__(TB) k_block_gs(BlockGeom bg, int a0, int nv, const double2 *__restrict__ vecs,
                                                 double2 *__restrict__ P, int *fail) {
   long xh = blockIdx.x;
   int chi = blockIdx.y;
@@ -171,7 +171,8 @@ __global__ void __launch_bounds__(TB) k_block_gs(BlockGeom bg, int nv, const dou
     }
   }
   (void)nmine;
-  for (int a = 0; a < nv; a++) {
+  // vector a depends on vectors 0 .. a-1 only: columns below a0 are kept
+  for (int a = a0; a < nv; a++) {
     cx<double> v[EPT];
     double n0loc = 0;
 #pragma unroll
@@ -244,16 +245,17 @@ __global__ void __launch_bounds__(TB) k_block_gs(BlockGeom bg, int nv, const dou
 }
 
 int block_orthonormalize(const Geom &g, int dof, const int b[4], int nv, const double2 *vecs, int fine_soa, double2 *P,
-                         int *fail_dev, hipStream_t st, int ns) {
+                         int *fail_dev, hipStream_t st, int ns, int a0) {
   BlockGeom bg = make_bg(g, dof, b, ns);
   int E = bg.bs * dof;
   int ept = (E + TB - 1) / TB;
   if (nv > 64) return set_error(-1, "block_orthonormalize: nv=%d > 64", nv);
+  if (a0 < 0 || a0 >= nv) return set_error(-1, "block_orthonormalize: first vector %d of %d", a0, nv);
   if ((ns != 2 && ns != 4) || dof % ns) return set_error(-1, "block_orthonormalize: %d parts of %d", ns, dof);
   dim3 grid((unsigned)bg.Vc, ns);
 #define GS_CASE(F, N)                                                                                      \
   if (fine_soa == F && ept <= N) {                                                                        \
-    hipLaunchKernelGGL((k_block_gs<F, N>), grid, dim3(TB), 0, st, bg, nv, vecs, P, fail_dev);             \
+    hipLaunchKernelGGL((k_block_gs<F, N>), grid, dim3(TB), 0, st, bg, a0, nv, vecs, P, fail_dev);         \
     WMG_HIP(hipGetLastError());                                                                            \
     return 0;                                                                                              \
   }

@@ -271,8 +271,10 @@ int start_vectors(long nsite, int dof, uint64_t seed, int lvl, int alpha0, int c
                   int fine_soa, long Vs, hipStream_t st);
 // ns: parts of the per-site components in the blocking (2 chiralities; 4
 // Dirac spins on the fine level), coarse dof ns * nv ordered (part, vector)
+// vectors a0 .. nv-1 (the earlier columns of P are kept: each vector is
+// orthogonalised against the ones before it only)
 int block_orthonormalize(const Geom &g, int dof, const int b[4], int nv, const double2 *vecs, int fine_soa,
-                         double2 *P, int *fail_dev, hipStream_t st, int ns = 2);
+                         double2 *P, int *fail_dev, hipStream_t st, int ns = 2, int a0 = 0);
 int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
                 int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st, int ns = 2);
 int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
@@ -286,6 +288,15 @@ int P_block_to_vector(const Geom &g, int dof, const int b[4], int nv, const doub
 // coarse.hip
 int coarse_build(const Geom &g, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf, const int b[4],
                  int nv, const double2 *P, double2 *Yc, double2 *work, hipStream_t st, int ns = 2);
+// One step of the adaptive setup's rebuild: with the first k - 1 columns of
+// every part already in Ys (blocks of leading dimension ns * nld), build the
+// columns of vector k - 1, mirror them into its rows (gamma_5-hermiticity of
+// the coarse operator) and write the compact blocks of the first k vectors
+// to Yc.  The prolongator's first k - 1 vectors must be those Ys was built
+// from (block Gram-Schmidt leaves earlier vectors unchanged).
+int coarse_build_next(const Geom &g, int fine_kind, int dof, const void *U64soa, double m, const double2 *Yf,
+                      const int b[4], int k, int nld, const double2 *P, double2 *Ys, double2 *Yc, hipStream_t st,
+                      int ns = 2);
 int coarse_apply(const Geom &gc, int n, int yprec, const void *Y, int vprec, const void *in, void *out, int dagger,
                  int nrhs, hipStream_t st);
 int coarse_shift_diag(long Vc, int n, double2 *Y, double dm, hipStream_t st);
