@@ -5,8 +5,9 @@ size (FP64 true residual, mass independence of the MG iteration count).
 
 Workloads (inputs recipe in the benchmark): 32^3x64 with 28 right-hand sides
 (12 point sources + 16 Z4 vectors) in mixed precision; 24^3x48 three-level
-W-cycle in mixed precision; 16^3x32 FP64 mass scan against BiCGStab; an
-uneven batch of 16 instances (8^4, 12^4, 16^4, 16^3x32, four each)."""
+W-cycle in mixed precision, also near the critical mass; 16^3x32 FP64 mass
+scan against BiCGStab; an uneven batch of 16 instances (8^4, 12^4, 16^4,
+16^3x32, four each)."""
 import sys
 
 import numpy as np
@@ -162,6 +163,44 @@ def test_config3_three_level_mixed(wmg):
         rr = relres(L, U, m, b[r], xh[r])
         say("  rhs", r, "oracle relres", rr)
         assert rr <= 1e-10 * 1.0001
+
+
+def test_three_level_near_critical_mass_independence(wmg):
+    """24^3x48, eps 0.6 (m_crit = -0.865 for fields of this kind), three-level
+    W-cycle in mixed precision with the red/black smoother and the
+    benchmark's coarse tolerance, one setup at m_crit + 0.02 and the exact
+    coarse shift to m_crit + 0.2: as m - m_crit shrinks 10x the MG outer
+    iteration count grows at most 1.5x (the paper's Table 1 criterion) while
+    BiCGStab's grows at least 3x; every solution meets the oracle's 1e-10."""
+    L = (24, 24, 24, 48)
+    m_crit = -0.865
+    say("near-critical three-level", L)
+    U = inputs.gauge_field(L, 0.6, 501)
+    b = inputs.gaussian_rhs(L, 510)
+    p = wmg.default_params(levels=3, block=((4, 4, 4, 4), (2, 2, 2, 2)), nvec=(24, 32), setup_iters=10, seed=550,
+                           precision=wmg.WMG_MIXED, coarse_tol=3e-2, flags=wmg.WMG_EO_SMOOTHER)
+    mg = wmg.MG(L, dev(U), m_crit + 0.02, 24, (4, 4, 4, 4), p)
+    mg_its, bi_its = [], []
+    for dm in (0.2, 0.02):
+        m = m_crit + dm
+        mg.mg_set_mass(m)
+        x = empty((1, vol(L), 12))
+        st = mg.mg_solve(dev(b), x, 1e-10)
+        rr = relres(L, U, m, b[0], host(x)[0])
+        xb = empty((vol(L), 12))
+        sb = wmg.bicgstab_solve(L, dev(U), m, dev(b[0]), xb, 1e-10, maxiter=40000)
+        say("  m - m_crit", dm, "MG", st["outer_iters"], "coarse", st["coarse_iters"], "relres", rr, "BiCGStab",
+            sb["outer_iters"], sb["converged"])
+        assert st["converged"] and rr <= 1e-10 * 1.0001
+        assert sb["converged"]
+        mg_its.append(st["outer_iters"])
+        bi_its.append(sb["outer_iters"])
+    mg.close()
+    g_mg = mg_its[1] / mg_its[0]
+    g_bi = bi_its[1] / bi_its[0]
+    say("  growth MG", g_mg, "BiCGStab", g_bi)
+    assert g_mg <= 1.5
+    assert g_bi >= 3.0
 
 
 def test_config2_mass_scan_against_bicgstab(wmg):
