@@ -95,7 +95,7 @@ typedef struct {
   int nrhs_max;           /* largest nrhs accepted by mg_solve */
   double coarse_tol;      /* coarsest CGNR: relative residual */
   int coarse_maxiter;     /* coarsest CGNR: iteration cap */
-  double reliable_delta;  /* mixed: restart in FP64 when |r_inner| < delta * |r_last_update| */
+  double reliable_delta;  /* mixed: restart in FP64 when |r_inner| < delta * |r_last_update| (default 1e-3) */
   int maxiter;            /* outer GCR iteration cap */
   unsigned long long seed;/* Philox key of the setup's random start vectors */
   int flags;              /* WMG_X0_GIVEN | WMG_COARSE_FP32 */

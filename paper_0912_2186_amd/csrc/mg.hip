@@ -1322,7 +1322,7 @@ int wmg_default_params(wmg_params *p) {
   p->nrhs_max = 1;
   p->coarse_tol = 1e-8;
   p->coarse_maxiter = 500;
-  p->reliable_delta = 0.01;
+  p->reliable_delta = 1e-3;
   p->maxiter = 1000;
   p->seed = 12345;
   p->flags = 0;
