@@ -46,6 +46,12 @@ WORKLOADS = {
     # kind): one setup at the lightest mass, exact coarse shifts to the others
     "48^3x96-critical-scan": dict(L=(48, 48, 48, 96), eps=0.6, m_crit=-0.865, scan=(0.2, 0.1, 0.05, 0.02), nv=24,
                                   npoint=0, nz4=0, ngauss=1, mixed=True, setup_iters=10, seed_cfg=5),
+    # 16 independent instances, four each of 8^4, 12^4, 16^4, 16^3x32: instance
+    # k of size i has eps = 0.3 + 0.1 k, m = -0.1 - 0.2 k / 3, links seeded
+    # 1000 + 10 i + k, one Gaussian rhs seeded 2000 + 10 i + k
+    "uneven-batch-16": dict(L=(16, 16, 16, 32), sizes=((8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16),
+                                                       (16, 16, 16, 32)), nv=24, mixed=True, setup_iters=10,
+                            seed_cfg=6),
 }
 DEFAULT = "32^3x64-28rhs-mixed"
 
@@ -194,6 +200,57 @@ def oracle_residuals(L, U, m, b, x, idx):
     return res
 
 
+def uneven_batch(args, w):
+    """The uneven batch: 16 instances set up and solved together
+    (mg_setup_batch / mg_solve_batch: every instance on its own stream and
+    host thread), mixed precision, tol 1e-10.  Reports seconds per batch
+    solve and per instance, and site-iterations per second (sum over
+    instances of sites x outer iterations, divided by the batch time)."""
+    import torch
+
+    from paper_0912_2186_amd import inputs, wmg
+
+    shapes, Us, ms, bs = [], [], [], []
+    for si, Lb in enumerate(w["sizes"]):
+        for k in range(4):
+            shapes.append(Lb)
+            Us.append(torch.from_numpy(inputs.gauge_field(Lb, 0.3 + 0.1 * k, 1000 + 10 * si + k)).cuda())
+            ms.append(-0.1 - 0.2 * k / 3)
+            bs.append(torch.from_numpy(inputs.gaussian_rhs(Lb, 2000 + 10 * si + k)).cuda())
+    p = wmg.default_params(setup_iters=w["setup_iters"], seed=w["seed_cfg"] * 100 + 50,
+                           precision=wmg.WMG_MIXED if w["mixed"] else wmg.WMG_FP64,
+                           coarse_tol=args.coarse_tol if args.coarse_tol is not None else COARSE_TOL_MIXED,
+                           flags=solver_flags(args))
+    torch.cuda.synchronize()
+    t0 = time.time()
+    batch = wmg.MGBatch(shapes, Us, ms, w["nv"], (4, 4, 4, 4), p)
+    setup_s = time.time() - t0
+    for _ in range(max(args.warmup, 1)):
+        xs = [torch.zeros_like(b) for b in bs]
+        batch.mg_solve_batch(bs, xs, 1e-10)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        xs = [torch.zeros_like(b) for b in bs]
+        sts = batch.mg_solve_batch(bs, xs, 1e-10)
+    torch.cuda.synchronize()
+    el = (time.time() - t0) / args.steps
+    sites = [Lb[0] * Lb[1] * Lb[2] * Lb[3] for Lb in shapes]
+    its = [st["outer_iters"] for st in sts]
+    print(json.dumps({
+        "metric": "uneven batch MG-GCR @1e-10: seconds per batch solve (16 instances, 1 rhs each)",
+        "value": round(el, 5), "unit": "s/batch", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": False, "dtype": "f32 cycle (f16-stored links/null vectors), f64 outer",
+        "data": "synthetic: seeded SU(3) links exp(i eps H), Gaussian rhs",
+        "config": {"workload": args.workload, "instances": [list(Lb) for Lb in shapes], "Nv": w["nv"],
+                   "block": [4, 4, 4, 4], "tol": 1e-10, "setup_s": round(setup_s, 2),
+                   "smoother": "MR on the red/black Schur complement" if args.smoother == "redblack" else "MR on D"},
+        "s_per_instance": round(el / len(shapes), 5),
+        "site_iterations_per_s": round(sum(v * i for v, i in zip(sites, its)) / el, 1),
+        "outer_iters": its, "converged": [st["converged"] for st in sts],
+        "true_relres_max": max(st["true_relres"] for st in sts)}))
+
+
 def critical_scan(args, w):
     """Mixed-precision solves of one Gaussian rhs at m = m_crit + dm for each
     dm of the scan, after one setup at the lightest mass: outer iterations
@@ -295,6 +352,8 @@ def main():
     V = L[0] * L[1] * L[2] * L[3]
     if "scan" in w:
         return critical_scan(args, w)
+    if "sizes" in w:
+        return uneven_batch(args, w)
     if args.only == "copy":
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -27,8 +27,11 @@
  * CUDA tensor's data_ptr()).  The caller owns U, b, x and every array it
  * passes; the library copies what it keeps, so U may be freed after
  * mg_setup returns.  A context owns all its internal buffers until
- * mg_destroy.  A context is not thread safe; its work runs on its own HIP
- * stream and every call returns only after that work has finished.
+ * mg_destroy.  A context is not thread safe; its work runs on its own
+ * non-blocking HIP stream (no implicit ordering with the default stream) and
+ * every call returns only after that work has finished.  Device inputs must
+ * be complete when a call starts (e.g. the device synchronised after the
+ * kernels that wrote them).
  *
  * Return codes: 0 success, WMG_ENOTCONV (1) = not converged (x holds the
  * last iterate, stats filled), negative = error, message via wmg_strerror().
@@ -63,7 +66,9 @@ extern "C" {
                              red/black preconditioning); every extent must be even */
 #define WMG_GRAPHS 16     /* flags: the coarsest CGNR runs its iterations as captured HIP
                              graphs of 4 iterations (same launches, same results; captured
-                             at the second solve of a buffer set, not while profiling) */
+                             at the second solve of a buffer set, not while profiling;
+                             ignored by mg_setup_batch, whose instances run on concurrent
+                             host threads) */
 #define WMG_SPIN_SPLIT 32 /* flags: the fine level's blocking splits each null vector into its
                              four Dirac spins instead of its two chiralities (Sec. 3, exposing
                              the full spin structure on the coarse blocks): 4 Nv coarse dof per

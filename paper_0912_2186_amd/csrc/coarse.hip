@@ -291,6 +291,8 @@ static int upload_gamma_once() {  // chiral basis: gamma_k = [[0, -i sigma_k], [
     G[3][2 + i][i] = make_double2(1, 0);
   }
   WMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gamma), G, sizeof(G)));
+  // complete before any kernel of a (non-blocking) context stream reads it
+  WMG_HIP(hipDeviceSynchronize());
   return 0;
 }
 static int upload_gamma() {

@@ -387,7 +387,10 @@ static int dalloc(void **p, size_t bytes) {
   if (e != hipSuccess) return set_error(WMG_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
   // zero-filled: the site padding of fine-lattice fields must read as zero
   // in every vector kernel that sweeps whole arrays
+  // (on the default stream, waited for here: the contexts' own streams are
+  // non-blocking, so nothing else orders their later kernels after the fill)
   e = hipMemset(*p, 0, bytes);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) return set_error(WMG_EHIP, "hipMemset: %s", hipGetErrorString(e));
   return 0;
 }
@@ -984,8 +987,10 @@ static int gcr_buffers(wmg_ctx *c, int l, int prec, int nrhs, GcrBuf **out) {
     else TRY(dalloc(&B.rin, csize(prec) * nalloc * nrhs));
     TRY(dalloc((void **)&B.zdev, sizeof(void *) * KMAX));
     TRY(dalloc((void **)&B.wdev, sizeof(void *) * KMAX));
-    WMG_HIP(hipMemcpy(B.zdev, B.z, sizeof(void *) * KMAX, hipMemcpyHostToDevice));
-    WMG_HIP(hipMemcpy(B.wdev, B.wv, sizeof(void *) * KMAX, hipMemcpyHostToDevice));
+    // on the context's stream, ahead of the kernels that read the tables
+    WMG_HIP(hipMemcpyAsync(B.zdev, B.z, sizeof(void *) * KMAX, hipMemcpyHostToDevice, c->st));
+    WMG_HIP(hipMemcpyAsync(B.wdev, B.wv, sizeof(void *) * KMAX, hipMemcpyHostToDevice, c->st));
+    WMG_HIP(hipStreamSynchronize(c->st));
   }
   *out = &B;
   return 0;
@@ -1412,7 +1417,11 @@ static int ctx_create(const wmg_geom *g, const double *U, double m, int Nv, cons
     rc = (x);                  \
     if (rc) goto fail;         \
   } while (0)
-  CK(hipStreamCreate(&c->st) == hipSuccess ? 0 : set_error(WMG_EHIP, "hipStreamCreate"));
+  // non-blocking: the default stream (synchronous allocations and fills of
+  // other contexts, e.g. the instances of a batch on other host threads)
+  // neither waits for this stream nor breaks a graph capture on it
+  CK(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) == hipSuccess ? 0
+                                                                           : set_error(WMG_EHIP, "hipStreamCreate"));
   CK(red_init(c->red, p.nrhs_max));
   CK(dalloc((void **)&c->dsc, sizeof(double) * ((size_t)(4 + 8 + GS + 1) * 64 + 4096)));
   {
@@ -2111,13 +2120,18 @@ int mg_setup_batch(int n, const wmg_geom *g, const double *const *U, const doubl
   wmg_ctx *parent = new wmg_ctx();
   if (p) parent->p = *p;
   else wmg_default_params(&parent->p);
+  // the instances run on concurrent host threads, whose allocations and
+  // synchronisations a stream capture on one of them does not tolerate:
+  // no graph capture inside a batch
+  wmg_params pi = parent->p;
+  pi.flags &= ~WMG_GRAPHS;
   std::vector<wmg_ctx *> ctx(n, nullptr);
   std::vector<int> rcs(n, 0);
   std::vector<std::string> msgs(n);
   std::vector<std::thread> th;
   for (int i = 0; i < n; i++)
     th.emplace_back([&, i]() {
-      rcs[i] = mg_setup(&g[i], U[i], m[i], Nv, block, p, &ctx[i]);
+      rcs[i] = mg_setup(&g[i], U[i], m[i], Nv, block, &pi, &ctx[i]);
       if (rcs[i]) msgs[i] = g_err;
     });
   for (auto &t : th) t.join();
