@@ -788,7 +788,7 @@ k_coarse_apply_mfma(const float *__restrict__ Ym, const __half *__restrict__ Yh,
 // writes and reads of the duplicated form, the same MFMA count, and C
 // comes out as (re, im) pairs per lane.
 template <int NTR, int N, bool AH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_coarse_apply_mfma2(const float *__restrict__ Ym, const __half *__restrict__ Yh, const float *__restrict__ Ysc,
                      const float2 *__restrict__ in, float2 *__restrict__ out, int L0, int L1, int L2, int L3, long Vc,
                      int nrhs, int dagger, double *__restrict__ npart) {
