@@ -493,8 +493,9 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, cons
 // and forms both B operands from them.  A lane's results are (re, im) pairs
 // of 16 consecutive elements, i.e. x-runs of 4 sites, per rhs.  A workgroup
 // takes G aggregates adjacent in x, one wave each, which walk their element
-// tiles in step; with G = 4 each tile's results go through LDS (double
-// buffered, one barrier per tile) and the workgroup writes them as 16-site
+// tiles in step; with G = 4 each tile's results go through LDS (two
+// barriers per tile, one buffer: the smaller LDS footprint keeps three
+// workgroups per CU) and the workgroup writes them as 16-site
 // x-runs, whole 128-byte lines of the FP32 output (4-site runs written
 // straight from the lanes were fetched before being written: the line was
 // read in full for every partial write).
@@ -507,9 +508,8 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(BlockGeom bg, const __half2
   constexpr int NW = TB / 64;      // waves
   __shared__ float Ac[G == 4 ? NW : 1][32 * LDA];  // per aggregate: [Cr | Ci] of one chirality
   __shared__ int soff[256];
-  // G = 4: staged results [buffer][aggregate][rhs][element] (+1 pad)
-  __shared__ float2 Ob[G == 4 ? 2 : 1][G == 4 ? NW : 1][G == 4 ? 32 : 1][17];
-  int tcount = 0;
+  // G = 4: staged results [aggregate][rhs][element] (+1 pad)
+  __shared__ float2 Ob[G == 4 ? NW : 1][G == 4 ? 32 : 1][17];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, krow = lane >> 4;
   // G = 4: wave w takes aggregate 4 g + w (x-adjacent); G = 1: one aggregate
   // per workgroup, its element tiles spread over the waves
@@ -575,19 +575,19 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(BlockGeom bg, const __half2
         }
       }
       if constexpr (G == 4) {
-        const int buf = tcount++ & 1;
+        __syncthreads();  // the previous tile's results have been written out
 #pragma unroll
         for (int m = 0; m < 2; m++) {
           if (m >= NTr) break;
 #pragma unroll
-          for (int v = 0; v < 4; v++) Ob[buf][w][m * 16 + 4 * krow + v][col] = make_float2(fr[m][v], fi[m][v]);
+          for (int v = 0; v < 4; v++) Ob[w][m * 16 + 4 * krow + v][col] = make_float2(fr[m][v], fi[m][v]);
         }
         __syncthreads();
         // rhs r, block row y (4), x-run of 16 sites over the 4 aggregates
         const long origin0 = origin - (long)w * bg.b[0];
         for (int i = threadIdx.x; i < R * 64; i += TB) {
           const int r = i >> 6, yl = (i >> 4) & 3, xx = i & 15, wa = xx >> 2, el = (xx & 3) + 4 * yl;
-          fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + origin0 + (long)wa * bg.b[0] + soff[k0 + el]] = Ob[buf][wa][r][el];
+          fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + origin0 + (long)wa * bg.b[0] + soff[k0 + el]] = Ob[wa][r][el];
         }
       } else {
         const long site = origin + soff[k0 + col];
