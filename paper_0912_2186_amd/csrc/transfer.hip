@@ -12,6 +12,8 @@
 // Chirality of component c is c / (dof/2).  In FP16 storage every
 // (alpha, xh, k) site of P carries one FP32 scale (max |re|, |im| of its
 // components), the stored halves being the components divided by it.
+#include <cstdio>
+
 #include "wmg_internal.h"
 
 namespace wmg {
@@ -414,12 +416,13 @@ __global__ void __launch_bounds__(TB) k_prolong(BlockGeom bg, int nv, const TP *
 // rows x 4 k of an MFMA fragment over all banks.  Fine sites of the block
 // come from a per-workgroup offset table (no index arithmetic per element).
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-static constexpr int RCH = 64;            // elements per chunk
-static constexpr int RLD = 2 * RCH + 4;   // LDS row stride
-
+// RCH elements per chunk (32, 64 or 128: the autotuner picks; smaller chunks
+// take less LDS and allow more resident workgroups, larger ones fewer barriers)
+template <int RCH>
 __global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, const __half2 *__restrict__ P,
                                                      const float *__restrict__ Pscale, const float2 *__restrict__ fine,
                                                      float2 *__restrict__ coarse, int nrhs) {
+  constexpr int RLD = 2 * RCH + 4;  // LDS row stride
   __shared__ float As[32 * RLD];
   __shared__ float Bt[32 * RLD];
   __shared__ int soff[256];  // fine-site offset of block element k from the block's first site
@@ -636,12 +639,30 @@ static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int
   BlockGeom bg = make_bg(g, dof, b, ns);
   if (nv > 64) return set_error(-1, "transfer: nv=%d > 64", nv);
   if ((ns != 2 && ns != 4) || dof % ns || ns * nv > 128) return set_error(-1, "transfer: %d parts of %d, nv=%d", ns, dof, nv);
-  if (dir == 0 && fine_soa && pprec == P16 && vprec == P32 && nv <= 32 && bg.bs % RCH == 0 && bg.bs <= 256) {
+  if (dir == 0 && fine_soa && pprec == P16 && vprec == P32 && nv <= 32 && bg.bs % 32 == 0 && bg.bs <= 256) {
     dim3 grid((unsigned)xcd_grid(bg.Vc), (nrhs + 31) / 32);
-    hipLaunchKernelGGL(k_restrict_mfma, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps, (const float2 *)in,
-                       (float2 *)out, nrhs);
-    WMG_HIP(hipGetLastError());
-    return 0;
+    const int chunks[3] = {64, 32, 128};
+    int ncand = 0, cand[3];
+    for (int c : chunks)
+      if (bg.bs % c == 0) cand[ncand++] = c;
+    auto run = [&](int i) -> int {
+      if (cand[i] == 64)
+        hipLaunchKernelGGL(k_restrict_mfma<64>, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps,
+                           (const float2 *)in, (float2 *)out, nrhs);
+      else if (cand[i] == 32)
+        hipLaunchKernelGGL(k_restrict_mfma<32>, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps,
+                           (const float2 *)in, (float2 *)out, nrhs);
+      else
+        hipLaunchKernelGGL(k_restrict_mfma<128>, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps,
+                           (const float2 *)in, (float2 *)out, nrhs);
+      WMG_HIP(hipGetLastError());
+      return 0;
+    };
+    char key[160];
+    std::snprintf(key, sizeof(key), "restrict_mfma/nv%d-ns%d-bs%d/%dx%dx%dx%d/rhs%d", nv, ns, bg.bs, g.L[0], g.L[1],
+                  g.L[2], g.L[3], nrhs);
+    int choice = 0;
+    return tune_choice(key, ncand, run, st, &choice);
   }
   if (dir == 1 && fine_soa && pprec == P16 && vprec == P32 && nv % 4 == 0 && nv <= 32 && bg.bs % 16 == 0 &&
       bg.bs <= 256) {
