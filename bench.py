@@ -240,7 +240,7 @@ def uneven_batch(args, w):
     print(json.dumps({
         "metric": "uneven batch MG-GCR @1e-10: seconds per batch solve (16 instances, 1 rhs each)",
         "value": round(el, 5), "unit": "s/batch", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "higher_is_better": False, "dtype": "f32 cycle (f16-stored links/null vectors), f64 outer",
+        "higher_is_better": False, "dtype": "f32 cycle (f16 smoother hops, f16-stored links/null vectors), f64 outer",
         "data": "synthetic: seeded SU(3) links exp(i eps H), Gaussian rhs",
         "config": {"workload": args.workload, "instances": [list(Lb) for Lb in shapes], "Nv": w["nv"],
                    "block": [4, 4, 4, 4], "tol": 1e-10, "setup_s": round(setup_s, 2),
@@ -523,7 +523,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 cycle (f16-stored links/null vectors), f64 outer" if w["mixed"] else "f64",
+        "dtype": "f32 cycle (f16 smoother hops, f16-stored links/null vectors), f64 outer" if w["mixed"] else "f64",
         "data": "synthetic: seeded SU(3) links exp(i eps H) and seeded right-hand sides",
         "config": {"workload": args.workload, "lattice": list(L), "eps": w["eps"], "mass": w["m"], "Nv": w["nv"],
                    "block": [4, 4, 4, 4], "nrhs": nrhs, "tol": 1e-10, "levels": 2,

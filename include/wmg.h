@@ -263,10 +263,11 @@ int mg_smoother_residual(wmg_ctx *ctx, const double *r, const double *e, double 
  * diag (read at parity par; NULL allowed when a == 0), hop (read at the other
  * parity) and out (zero at the other parity) are canonical FP64 full-lattice
  * vectors.  prec 0: FP64 links and vectors; 3: FP16 links and FP16 vectors
- * (the MR steps); 4: FP16 links and diag, FP32 hop input and output (the odd
- * correction); 5: as 4 in the smoother's fused last step (par must be 1),
- * which also returns hop's values at the even sites.  Needs every extent
- * even; nrhs <= 64. */
+ * (the MR steps: projection and SU(3) products in packed FP16 arithmetic,
+ * the eight directions summed in FP32); 4: FP16 links and diag, FP32 hop
+ * input and output (the odd correction); 5: as 4 in the smoother's fused
+ * last step (par must be 1), which also returns hop's values at the even
+ * sites.  Needs every extent even; nrhs <= 64. */
 int mg_hop_eo(wmg_ctx *ctx, int prec, int par, double a, double b, const double *diag, const double *hop,
               double *out, int nrhs);
 /* One application of the FP64 preconditioner z = M r (one MG cycle). */
@@ -278,6 +279,12 @@ int mg_last_iters(wmg_ctx *ctx, int *iters, int nrhs);
  * layouts, measured with HIP events on the context stream (Dslash
  * bandwidth measurement).  prec as in mg_apply_fine. */
 int mg_time_dslash(wmg_ctx *ctx, int prec, int nrhs, int reps, double *ms);
+
+/* Test hook of the launch-shape autotuner (process-wide): choice >= 0 makes
+ * every tuned launch run candidate `choice` (candidate 0, the default, where
+ * a launch has fewer) with no search and nothing recorded; choice < 0
+ * restores normal tuning.  Returns the previous setting (-1 when off). */
+int wmg_tune_force(int choice);
 
 /* ---- measurement hooks --------------------------------------------- */
 /* Kernel classes timed by mg_profile. */

@@ -219,6 +219,34 @@ __device__ __forceinline__ void st4(double2 *p, const cx<double> o[4]) {
 #pragma unroll
   for (int i = 0; i < 4; i++) stc(p + i, o[i]);
 }
+// the same with the non-temporal hint (data used once: the line is not
+// kept in the caches at the expense of data that is reused)
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void ld4_nt(const __half2 *p, cx<float> o[4]) {
+  const u32x4 v = __builtin_nontemporal_load((const u32x4 *)p);
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    __half2 h;
+    __builtin_memcpy(&h, &w[i], 4);
+    const float2 f = __half22float2(h);
+    o[i] = {f.x, f.y};
+  }
+}
+__device__ __forceinline__ void ld4_nt(const float2 *p, cx<float> o[4]) { ld4(p, o); }
+__device__ __forceinline__ void ld4_nt(const double2 *p, cx<double> o[4]) { ld4(p, o); }
+__device__ __forceinline__ void st4_nt(__half2 *p, const cx<float> o[4]) {
+  unsigned w[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const __half2 h = __floats2half2_rn(o[i].re, o[i].im);
+    __builtin_memcpy(&w[i], &h, 4);
+  }
+  const u32x4 v = {w[0], w[1], w[2], w[3]};
+  __builtin_nontemporal_store(v, (u32x4 *)p);
+}
+__device__ __forceinline__ void st4_nt(float2 *p, const cx<float> o[4]) { st4(p, o); }
+__device__ __forceinline__ void st4_nt(double2 *p, const cx<double> o[4]) { st4(p, o); }
 // p[0] += lo, p[1] += hi (two adjacent sites of a full-lattice component)
 __device__ __forceinline__ void add_pair(float2 *p, cx<float> lo, cx<float> hi) {
   float4 v = *(float4 *)p;
@@ -567,95 +595,189 @@ struct EoGeom {
 };
 
 
-// One colour of the projection straight from the four FP16 spins as
-// stored: h = p_up - S A_mu p_down with every sum written fma(x, one, y),
-// one = 1 passed at run time, so that the compiler folds the f16 -> f32
-// conversions into the mixed-precision FMA (v_fma_mix_f32) instead of
-// converting first; the values are those of proj_pair.
-template <int MU, int S>
-__device__ __forceinline__ void proj_pair_h16(const __half2 *p, float one, cx<float> &h0, cx<float> &h1) {
-  const uint4 v = *(const uint4 *)p;
-  const unsigned w[4] = {v.x, v.y, v.z, v.w};
-  __half2 q[4];
-#pragma unroll
-  for (int i = 0; i < 4; i++) __builtin_memcpy(&q[i], &w[i], 4);
-  const float p0r = __low2float(q[0]), p0i = __high2float(q[0]), p1r = __low2float(q[1]), p1i = __high2float(q[1]);
-  const float p2r = __low2float(q[2]), p2i = __high2float(q[2]), p3r = __low2float(q[3]), p3i = __high2float(q[3]);
-  float a0r, a0i, a1r, a1i;  // A_mu p_down
-  if (MU == 0) { a0r = p3i; a0i = -p3r; a1r = p2i; a1i = -p2r; }
-  if (MU == 1) { a0r = -p3r; a0i = -p3i; a1r = p2r; a1i = p2i; }
-  if (MU == 2) { a0r = p2i; a0i = -p2r; a1r = -p3i; a1i = p3r; }
-  if (MU == 3) { a0r = p2r; a0i = p2i; a1r = p3r; a1i = p3i; }
-  if (S > 0) { a0r = -a0r; a0i = -a0i; a1r = -a1r; a1i = -a1i; }
-  h0 = {__builtin_fmaf(a0r, one, p0r), __builtin_fmaf(a0i, one, p0i)};
-  h1 = {__builtin_fmaf(a1r, one, p1r), __builtin_fmaf(a1i, one, p1i)};
-}
-
 // Work order of the hop kernels.  A tile is 256 consecutive compact sites of
 // a slab of zb z-slices at one t (x fastest, then y, then z inside the
 // slab); tiles are numbered slab chunk fastest, then t, then z-slab, and XCD
 // k takes the k-th contiguous range.  The t-neighbours of a tile are then a
-// few tiles away in the XCD's sequence and still in its L2, and all rhs
-// tiles of one site tile run back to back (the links are read once).
+// few tiles away in the XCD's sequence.  The rhs tiles are swept in groups of
+// grp: an XCD runs its whole range for one group before the next, with the
+// group's rhs tiles of one site tile back to back.  One group holding every
+// rhs tile reads the links once; smaller groups read them once per group but
+// bring the t-neighbours closer in the sequence (8 rhs tiles of 256 sites and
+// three FP16 rhs each already touch about 1 MB, against a 4 MB L2 per XCD).
 struct EoTiles {
   int zb;     // z-slices per slab (divides L2)
   int nch;    // chunks of 256 sites per slab and t
   int ntile;  // tiles
   int tpx;    // tiles per XCD
+  int grp;    // rhs tiles per group
+  int nt;     // FP16 diagonal input and output with the non-temporal hint
 };
 
-static EoTiles make_eo_tiles(const EoGeom &e, int zb) {
+static EoTiles make_eo_tiles(const EoGeom &e, int zb, int grp, int nt = 0) {
   EoTiles t;
   t.zb = zb;
   const long q = (long)e.hx * e.L[1] * zb;
   t.nch = (int)((q + 255) / 256);
   t.ntile = t.nch * e.L[3] * (e.L[2] / zb);
   t.tpx = (t.ntile + NXCD - 1) / NXCD;
+  t.grp = grp < 1 ? 1 : grp;
+  t.nt = nt;
   return t;
 }
 
+// The compact site of one thread of a hop kernel: tile and first rhs from
+// the block (groups of rhs tiles, XCD ranges), coordinates from the lane.
+struct EoSite {
+  int tile, r0;    // tile index, first rhs of the thread
+  int x[4], h, xh; // coordinates, compact index, compact x
+  bool valid_tile, valid;
+};
+
+__device__ __forceinline__ EoSite eo_site(const EoGeom &g, const EoTiles &tl, int par, int nrhs, int RT) {
+  EoSite s;
+  const int nrt = (nrhs + RT - 1) / RT;
+  const int j = (int)(blockIdx.x / NXCD);
+  const int span = tl.tpx * tl.grp;           // blocks of one full group on an XCD
+  const int g0 = (j / span) * tl.grp;         // first rhs tile of this block's group
+  const int gc = min(tl.grp, nrt - g0);       // rhs tiles in the group (the last may be short)
+  const int rem = j - (g0 / tl.grp) * span;
+  s.tile = (int)(blockIdx.x % NXCD) * tl.tpx + rem / gc;
+  s.r0 = (g0 + rem % gc) * RT;
+  s.valid_tile = s.tile < tl.ntile;
+  s.valid = false;
+  s.x[0] = s.x[1] = s.x[2] = s.x[3] = 0;
+  s.h = s.xh = 0;
+  if (s.valid_tile) {
+    const int P = g.hx * g.L[1];
+    const int u = s.tile / tl.nch;
+    const int q = (s.tile - u * tl.nch) * 256 + (int)threadIdx.x;
+    const int tt = u % g.L[3];
+    const int zi = q / P, hp = q - zi * P;
+    s.valid = zi < tl.zb;
+    s.x[1] = hp / g.hx;
+    s.xh = hp - s.x[1] * g.hx;
+    s.x[2] = (u / g.L[3]) * tl.zb + zi;
+    s.x[3] = tt;
+    s.x[0] = 2 * s.xh + ((par + s.x[1] + s.x[2] + s.x[3]) & 1);
+    s.h = hp + P * (s.x[2] + g.L[2] * tt);
+  }
+  return s;
+}
+
+// compact indices of the forward and backward neighbours in direction MU
+template <int MU>
+__device__ __forceinline__ void eo_neighbours(const EoGeom &g, const EoSite &s, int &hf, int &hb) {
+  if (MU == 0) {
+    const int xf = s.x[0] == g.L[0] - 1 ? 0 : s.x[0] + 1;
+    const int xb = s.x[0] == 0 ? g.L[0] - 1 : s.x[0] - 1;
+    hf = s.h - s.xh + (xf >> 1);
+    hb = s.h - s.xh + (xb >> 1);
+  } else {
+    const int hs = MU == 1 ? g.hx : (MU == 2 ? g.hx * g.L[1] : g.hx * g.L[1] * g.L[2]);
+    hf = s.x[MU] == g.L[MU] - 1 ? s.h - (g.L[MU] - 1) * hs : s.h + hs;
+    hb = s.x[MU] == 0 ? s.h + (g.L[MU] - 1) * hs : s.h - hs;
+  }
+}
+
+// out = a in_diag + b acc per rhs of the thread (see k_hop_eo for ADD),
+// with the reduction terms of RED accumulated into rs
+template <class TD, class TH, class TO, int RT, int RED, int ADD, class R>
+__device__ __forceinline__ void eo_store(const EoGeom &g, const EoTiles &tl, const EoSite &st, int nrhs,
+                                         const TD *__restrict__ in_diag, const TH *__restrict__ in_hop,
+                                         TO *__restrict__ out, double ad, R a, R b, cx<R> (&acc)[RT][12],
+                                         double (&rs)[RT][3]) {
+  const int Vs = (int)g.Vhs;
+#pragma unroll
+  for (int t = 0; t < RT; t++) {
+    if (st.r0 + t >= nrhs) continue;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const size_t i = ((size_t)(st.r0 + t) * 3 + c) * Vs * 4 + (unsigned)st.h * 4;
+      cx<R> dv[4] = {czero<R>(), czero<R>(), czero<R>(), czero<R>()};
+      if (ad != 0.0) {
+        if (tl.nt) ld4_nt(in_diag + i, dv);
+        else ld4(in_diag + i, dv);
+      }
+      cx<R> o[4];
+#pragma unroll
+      for (int sp = 0; sp < 4; sp++)
+        o[sp] = {a * dv[sp].re + b * acc[t][sp * 3 + c].re, a * dv[sp].im + b * acc[t][sp * 3 + c].im};
+      if constexpr (ADD) {
+        // the pair (2h, 2h + 1) of full-lattice sites: this site and its
+        // partner of the other parity
+        cx<R> hv[4];
+        ld4(in_hop + i, hv);
+        const int own = st.x[0] & 1;
+#pragma unroll
+        for (int sp = 0; sp < 4; sp++) {
+          TO *pp = out + ((size_t)(st.r0 + t) * 12 + sp * 3 + c) * g.Vsf + 2 * (size_t)(unsigned)st.h;
+          add_pair(pp, own ? hv[sp] : o[sp], own ? o[sp] : hv[sp]);
+        }
+      } else if (tl.nt) {
+        st4_nt(out + i, o);
+      } else {
+        st4(out + i, o);
+      }
+      if (RED) {
+#pragma unroll
+        for (int sp = 0; sp < 4; sp++) {
+          const cx<R> os = as_stored(out, o[sp]);
+          rs[t][0] += (double)os.re * dv[sp].re + (double)os.im * dv[sp].im;
+          rs[t][1] += (double)os.re * dv[sp].im - (double)os.im * dv[sp].re;
+          rs[t][2] += (double)os.re * os.re + (double)os.im * os.im;
+        }
+      }
+    }
+  }
+}
+
+// block sums of the RED terms -> red[(rhs * ntile + tile) * 3 + k]; every
+// thread of the block calls it
+template <int RT>
+__device__ __forceinline__ void eo_reduce(const EoTiles &tl, const EoSite &st, int nrhs, double (&rs)[RT][3],
+                                          double *__restrict__ red) {
+  __shared__ double sh[RT][3][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < RT; t++)
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      double v = rs[t][k];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+      if (lane == 0) sh[t][k][wv] = v;
+    }
+  __syncthreads();
+  if (st.valid_tile && threadIdx.x < RT * 3) {
+    const int t = threadIdx.x / 3, k = threadIdx.x % 3;
+    if (st.r0 + t < nrhs)
+      red[((size_t)(st.r0 + t) * tl.ntile + st.tile) * 3 + k] = sh[t][k][0] + sh[t][k][1] + sh[t][k][2] + sh[t][k][3];
+  }
+}
+
 // out = a in_diag + b H_par(in_hop) at the compact sites of parity par, for
-// RT right-hand sides per thread (sharing every link load); with RED, also
-// <out, in_diag> and |out|^2 per tile and rhs into red (as stored).  With
-// ADD, out is instead a full-lattice field [rhs][12][Vsf] that receives
-// the result at the site of parity par and in_hop's value at the other site
-// of the same x pair (same compact index): the last step of the red/black
-// smoother, e += (d_e, d_o), without a separate pass.  Site indices are
-// 32-bit (a parity holds fewer than 2^29 sites).
+// RT right-hand sides per thread (sharing every link load), with FP32 or
+// FP64 arithmetic; with RED, also <out, in_diag> and |out|^2 per tile and
+// rhs into red (as stored).  With ADD, out is instead a full-lattice field
+// [rhs][12][Vsf] that receives the result at the site of parity par and
+// in_hop's value at the other site of the same x pair (same compact index):
+// the last step of the red/black smoother, e += (d_e, d_o), without a
+// separate pass.  Site indices are 32-bit (a parity holds fewer than 2^29
+// sites).
 template <class TL, class TD, class TH, class TO, int RT, int RED, int NR, int ADD = 0>
 __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const TD *__restrict__ in_diag,
                                                const TH *__restrict__ in_hop, TO *__restrict__ out, EoGeom g, int par,
                                                double ad, double bd, int nrhs, EoTiles tl, double *__restrict__ red,
                                                float one) {
   using R = typename store_traits<TO>::real;
-  const int nrt = (nrhs + RT - 1) / RT;
-  const int j = (int)(blockIdx.x / NXCD);
-  const int tile = (int)(blockIdx.x % NXCD) * tl.tpx + j / nrt;
-  const int r0 = (j % nrt) * RT;
-  const bool valid_tile = tile < tl.ntile;
-  int x[4] = {0, 0, 0, 0}, h = 0, xh = 0;
-  bool valid = false;
-  if (valid_tile) {
-    const int P = g.hx * g.L[1];
-    int u = tile / tl.nch;
-    const int q = (tile - u * tl.nch) * 256 + (int)threadIdx.x;
-    const int tt = u % g.L[3];
-    const int zi = q / P, hp = q - zi * P;
-    valid = zi < tl.zb;
-    x[1] = hp / g.hx;
-    xh = hp - x[1] * g.hx;
-    x[2] = (u / g.L[3]) * tl.zb + zi;
-    x[3] = tt;
-    x[0] = 2 * xh + ((par + x[1] + x[2] + x[3]) & 1);
-    h = hp + P * (x[2] + g.L[2] * tt);
-  }
-  const R a = (R)ad, b = (R)bd;
+  const EoSite st = eo_site(g, tl, par, nrhs, RT);
+  const int r0 = st.r0;
   double rs[RT][3];
 #pragma unroll
   for (int t = 0; t < RT; t++) rs[t][0] = rs[t][1] = rs[t][2] = 0.0;
-  if (valid) {
+  if (st.valid) {
     const int Vs = (int)g.Vhs;
-    const int hs[4] = {0, g.hx, g.hx * g.L[1], g.hx * g.L[1] * g.L[2]};  // compact strides of y, z, t
     const TL *Uf = Ue + (size_t)par * 4 * NR * Vs;        // links at sites of parity par
     const TL *Ub = Ue + (size_t)(1 - par) * 4 * NR * Vs;  // ... of the other parity
     cx<R> acc[RT][12];
@@ -672,36 +794,23 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
       if (NR == 6) su3_third_row(u);
     };
     // projected half spinor of the neighbour, colour by colour
-    auto half = [&](int r, int site, auto proj, auto proj16, cx<R> hh[6]) {
+    auto half = [&](int r, int site, auto proj, cx<R> hh[6]) {
 #pragma unroll
       for (int c = 0; c < 3; c++) {
-        const TH *p = in_hop + ((size_t)r * 3 + c) * Vs * 4 + (unsigned)site * 4;
-        if constexpr (std::is_same<TH, __half2>::value) {
-          proj16(p, one, hh[c], hh[3 + c]);
-        } else {
-          cx<R> p4[4];
-          ld4(p, p4);
-          proj(p4, hh[c], hh[3 + c]);
-        }
+        cx<R> p4[4];
+        ld4(in_hop + ((size_t)r * 3 + c) * Vs * 4 + (unsigned)site * 4, p4);
+        proj(p4, hh[c], hh[3 + c]);
       }
     };
 #define EO_DIR(MU)                                                                      \
     {                                                                                   \
       int hf, hb;                                                                       \
-      if (MU == 0) {                                                                    \
-        const int xf = x[0] == g.L[0] - 1 ? 0 : x[0] + 1;                               \
-        const int xb = x[0] == 0 ? g.L[0] - 1 : x[0] - 1;                               \
-        hf = h - xh + (xf >> 1);                                                        \
-        hb = h - xh + (xb >> 1);                                                        \
-      } else {                                                                          \
-        hf = x[MU] == g.L[MU] - 1 ? h - (g.L[MU] - 1) * hs[MU] : h + hs[MU];            \
-        hb = x[MU] == 0 ? h + (g.L[MU] - 1) * hs[MU] : h - hs[MU];                      \
-      }                                                                                 \
+      eo_neighbours<MU>(g, st, hf, hb);                                                 \
       cx<R> u[9], hh[6], gg[6];                                                         \
-      load_link(Uf, MU, h, u);                                                          \
+      load_link(Uf, MU, st.h, u);                                                       \
       _Pragma("unroll") for (int t = 0; t < RT; t++) {                                  \
         if (r0 + t < nrhs) {                                                            \
-          half(r0 + t, hf, proj_pair<MU, 1, R>, proj_pair_h16<MU, 1>, hh);              \
+          half(r0 + t, hf, proj_pair<MU, 1, R>, hh);                                    \
           su3_mul<0>(u, hh, gg);                                                        \
           reconstruct<MU, 1>(gg, acc[t]);                                               \
         }                                                                               \
@@ -709,7 +818,7 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
       load_link(Ub, MU, hb, u);                                                         \
       _Pragma("unroll") for (int t = 0; t < RT; t++) {                                  \
         if (r0 + t < nrhs) {                                                            \
-          half(r0 + t, hb, proj_pair<MU, -1, R>, proj_pair_h16<MU, -1>, hh);            \
+          half(r0 + t, hb, proj_pair<MU, -1, R>, hh);                                   \
           su3_mul<1>(u, hh, gg);                                                        \
           reconstruct<MU, -1>(gg, acc[t]);                                              \
         }                                                                               \
@@ -720,63 +829,156 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
     EO_DIR(2)
     EO_DIR(3)
 #undef EO_DIR
-#pragma unroll
-    for (int t = 0; t < RT; t++) {
-      if (r0 + t >= nrhs) continue;
-#pragma unroll
-      for (int c = 0; c < 3; c++) {
-        const size_t i = ((size_t)(r0 + t) * 3 + c) * Vs * 4 + (unsigned)h * 4;
-        cx<R> dv[4] = {czero<R>(), czero<R>(), czero<R>(), czero<R>()};
-        if (ad != 0.0) ld4(in_diag + i, dv);
-        cx<R> o[4];
-#pragma unroll
-        for (int sp = 0; sp < 4; sp++)
-          o[sp] = {a * dv[sp].re + b * acc[t][sp * 3 + c].re, a * dv[sp].im + b * acc[t][sp * 3 + c].im};
-        if constexpr (ADD) {
-          // the pair (2h, 2h + 1) of full-lattice sites: this site and its
-          // partner of the other parity
-          cx<R> hv[4];
-          ld4(in_hop + i, hv);
-          const int own = x[0] & 1;
-#pragma unroll
-          for (int sp = 0; sp < 4; sp++) {
-            TO *pp = out + ((size_t)(r0 + t) * 12 + sp * 3 + c) * g.Vsf + 2 * (size_t)(unsigned)h;
-            add_pair(pp, own ? hv[sp] : o[sp], own ? o[sp] : hv[sp]);
-          }
-        } else {
-          st4(out + i, o);
-        }
-        if (RED) {
-#pragma unroll
-          for (int sp = 0; sp < 4; sp++) {
-            const cx<R> os = as_stored(out, o[sp]);
-            rs[t][0] += (double)os.re * dv[sp].re + (double)os.im * dv[sp].im;
-            rs[t][1] += (double)os.re * dv[sp].im - (double)os.im * dv[sp].re;
-            rs[t][2] += (double)os.re * os.re + (double)os.im * os.im;
-          }
-        }
-      }
-    }
+    eo_store<TD, TH, TO, RT, RED, ADD, R>(g, tl, st, nrhs, in_diag, in_hop, out, ad, (R)ad, (R)bd, acc, rs);
   }
-  if (RED) {
-    __shared__ double sh[RT][3][4];
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (RED) eo_reduce<RT>(tl, st, nrhs, rs, red);
+}
+
+// ---- packed FP16 form
+// The all-FP16 hop of the smoother's MR steps computes the spin projection,
+// the SU(3) products and the sum and difference of the forward and backward
+// terms of each direction in packed half precision: two FP16 values per lane
+// and instruction, with the complex broadcasts, swaps and signs folded into
+// the operands' modifiers (a complex multiply-add is two packed FMAs).  The
+// eight directions are accumulated in FP32 (the FP16 -> FP32 conversion
+// folded into the FMA through `one`, as above), and the output is formed and
+// rounded as in k_hop_eo.  The FP16 products round at 2^-11 relative to the
+// link and spinor magnitudes, the size of the FP16 storage rounding of the
+// same fields.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2 pk_i(h2 a) { return (h2){-a.y, a.x}; }   // i a
+__device__ __forceinline__ h2 pk_mi(h2 a) { return (h2){a.y, -a.x}; }  // -i a
+// c + a b and c + conj(a) b
+__device__ __forceinline__ h2 pk_cfma(h2 a, h2 b, h2 c) {
+  const h2 t = __builtin_elementwise_fma(a.xx, b, c);
+  return __builtin_elementwise_fma((h2){-a.y, a.y}, b.yx, t);
+}
+__device__ __forceinline__ h2 pk_cfmac(h2 a, h2 b, h2 c) {
+  const h2 t = __builtin_elementwise_fma(a.xx, b, c);
+  return __builtin_elementwise_fma((h2){a.y, -a.y}, b.yx, t);
+}
+__device__ __forceinline__ h2 pk_cmul(h2 a, h2 b) { return __builtin_elementwise_fma((h2){-a.y, a.y}, b.yx, a.xx * b); }
+__device__ __forceinline__ h2 pk_ld(const __half2 *p) {
+  const unsigned w = *(const unsigned *)p;
+  h2 r;
+  __builtin_memcpy(&r, &w, 4);
+  return r;
+}
+template <int NR>
+__device__ __forceinline__ void pk_link(const __half2 *Up, int mu, unsigned site, int Vs, h2 u[9]) {
+#pragma unroll
+  for (int e = 0; e < NR; e++) u[e] = pk_ld(Up + (size_t)(mu * NR + e) * Vs + site);
+  if (NR == 6) {
+    // third row conj(row0 x row1), conj(a b) - conj(c d) as four packed FMAs
+    auto cc = [](h2 a, h2 b, h2 c, h2 d) {
+      h2 t = a.xx * (h2){b.x, -b.y};
+      t = __builtin_elementwise_fma((h2){-a.y, -a.y}, b.yx, t);
+      t = __builtin_elementwise_fma(-c.xx, (h2){d.x, -d.y}, t);
+      return __builtin_elementwise_fma((h2){c.y, c.y}, d.yx, t);
+    };
+    u[6] = cc(u[1], u[5], u[2], u[4]);
+    u[7] = cc(u[2], u[3], u[0], u[5]);
+    u[8] = cc(u[0], u[4], u[1], u[3]);
+  }
+}
+// one colour of the projection from the four stored spins (as proj_pair)
+template <int MU, int S>
+__device__ __forceinline__ void pk_proj(const __half2 *p, h2 &h0, h2 &h1) {
+  const uint4 v = *(const uint4 *)p;
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
+  h2 q[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) __builtin_memcpy(&q[i], &w[i], 4);
+  h2 a0, a1;  // A_mu p_down
+  if (MU == 0) { a0 = pk_mi(q[3]); a1 = pk_mi(q[2]); }
+  if (MU == 1) { a0 = -q[3]; a1 = q[2]; }
+  if (MU == 2) { a0 = pk_mi(q[2]); a1 = pk_i(q[3]); }
+  if (MU == 3) { a0 = q[2]; a1 = q[3]; }
+  if (S > 0) { h0 = q[0] - a0; h1 = q[1] - a1; }
+  else { h0 = q[0] + a0; h1 = q[1] + a1; }
+}
+__device__ __forceinline__ void pk_acc(cx<float> &acc, h2 x, float one) {
+  acc.re = __builtin_fmaf((float)x.x, one, acc.re);
+  acc.im = __builtin_fmaf((float)x.y, one, acc.im);
+}
+// upper spins += gf + gb, lower spins += A_mu^dag (gb - gf): the forward and
+// backward terms of reconstruct<MU, +1> and reconstruct<MU, -1> together
+template <int MU>
+__device__ __forceinline__ void pk_recon(const h2 gf[6], const h2 gb[6], cx<float> acc[12], float one) {
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    pk_acc(acc[c], gf[c] + gb[c], one);
+    pk_acc(acc[3 + c], gf[3 + c] + gb[3 + c], one);
+    const h2 d0 = gb[c] - gf[c], d1 = gb[3 + c] - gf[3 + c];
+    h2 b0, b1;
+    if (MU == 0) { b0 = pk_i(d1); b1 = pk_i(d0); }
+    if (MU == 1) { b0 = d1; b1 = -d0; }
+    if (MU == 2) { b0 = pk_i(d0); b1 = pk_mi(d1); }
+    if (MU == 3) { b0 = d0; b1 = d1; }
+    pk_acc(acc[6 + c], b0, one);
+    pk_acc(acc[9 + c], b1, one);
+  }
+}
+
+template <int RT, int RED, int NR>
+__global__ void __launch_bounds__(256) k_hop_eo_pk(const __half2 *__restrict__ Ue, const __half2 *__restrict__ in_diag,
+                                                  const __half2 *__restrict__ in_hop, __half2 *__restrict__ out,
+                                                  EoGeom g, int par, double ad, double bd, int nrhs, EoTiles tl,
+                                                  double *__restrict__ red, float one) {
+  const EoSite st = eo_site(g, tl, par, nrhs, RT);
+  const int r0 = st.r0;
+  double rs[RT][3];
+#pragma unroll
+  for (int t = 0; t < RT; t++) rs[t][0] = rs[t][1] = rs[t][2] = 0.0;
+  if (st.valid) {
+    const int Vs = (int)g.Vhs;
+    const __half2 *Uf = Ue + (size_t)par * 4 * NR * Vs;
+    const __half2 *Ub = Ue + (size_t)(1 - par) * 4 * NR * Vs;
+    cx<float> acc[RT][12];
 #pragma unroll
     for (int t = 0; t < RT; t++)
 #pragma unroll
-      for (int k = 0; k < 3; k++) {
-        double v = rs[t][k];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-        if (lane == 0) sh[t][k][wv] = v;
-      }
-    __syncthreads();
-    if (valid_tile && threadIdx.x < RT * 3) {
-      int t = threadIdx.x / 3, k = threadIdx.x % 3;
-      if (r0 + t < nrhs)
-        red[((size_t)(r0 + t) * tl.ntile + tile) * 3 + k] = sh[t][k][0] + sh[t][k][1] + sh[t][k][2] + sh[t][k][3];
+      for (int c = 0; c < 12; c++) acc[t][c] = {0.f, 0.f};
+#define PK_DIR(MU)                                                                                  \
+    {                                                                                               \
+      int hf, hb;                                                                                   \
+      eo_neighbours<MU>(g, st, hf, hb);                                                             \
+      h2 uf[9], ub[9];                                                                              \
+      pk_link<NR>(Uf, MU, (unsigned)st.h, Vs, uf);                                                  \
+      pk_link<NR>(Ub, MU, (unsigned)hb, Vs, ub);                                                    \
+      _Pragma("unroll") for (int t = 0; t < RT; t++) {                                              \
+        if (r0 + t < nrhs) {                                                                        \
+          const __half2 *in_r = in_hop + (size_t)(r0 + t) * 3 * Vs * 4;                             \
+          h2 hh[6], gf[6], gb[6];                                                                   \
+          _Pragma("unroll") for (int c = 0; c < 3; c++)                                             \
+            pk_proj<MU, 1>(in_r + (size_t)c * Vs * 4 + (unsigned)hf * 4, hh[c], hh[3 + c]);         \
+          _Pragma("unroll") for (int sp = 0; sp < 2; sp++)                                          \
+          _Pragma("unroll") for (int a = 0; a < 3; a++) {                                           \
+            h2 v = pk_cmul(uf[3 * a], hh[3 * sp]);                                                  \
+            v = pk_cfma(uf[3 * a + 1], hh[3 * sp + 1], v);                                          \
+            gf[3 * sp + a] = pk_cfma(uf[3 * a + 2], hh[3 * sp + 2], v);                             \
+          }                                                                                         \
+          _Pragma("unroll") for (int c = 0; c < 3; c++)                                             \
+            pk_proj<MU, -1>(in_r + (size_t)c * Vs * 4 + (unsigned)hb * 4, hh[c], hh[3 + c]);        \
+          _Pragma("unroll") for (int sp = 0; sp < 2; sp++)                                          \
+          _Pragma("unroll") for (int a = 0; a < 3; a++) {                                           \
+            h2 v = pk_cfmac(ub[a], hh[3 * sp], (h2){0, 0});                                         \
+            v = pk_cfmac(ub[3 + a], hh[3 * sp + 1], v);                                             \
+            gb[3 * sp + a] = pk_cfmac(ub[6 + a], hh[3 * sp + 2], v);                                \
+          }                                                                                         \
+          pk_recon<MU>(gf, gb, acc[t], one);                                                        \
+        }                                                                                           \
+      }                                                                                             \
     }
+    PK_DIR(0)
+    PK_DIR(1)
+    PK_DIR(2)
+    PK_DIR(3)
+#undef PK_DIR
+    eo_store<__half2, __half2, __half2, RT, RED, 0, float>(g, tl, st, nrhs, in_diag, in_hop, out, ad, (float)ad,
+                                                           (float)bd, acc, rs);
   }
+  if (RED) eo_reduce<RT>(tl, st, nrhs, rs, red);
 }
 
 static EoGeom make_eo(const Geom &g) {
@@ -804,13 +1006,46 @@ static int eo_zb_candidates(const Geom &g, int zb[6]) {
   return n;
 }
 
+// (slab depth, rhs tiles per group, non-temporal hint) triples the
+// autotuner tries for nrt rhs tiles: every slab depth with one group, then
+// slab depths 4 and 2 with groups of 2 to 5 rhs tiles, then slab depths 4, 2
+// and 8 with one group and the hint (FP16 only); the first is the default
+static int eo_tile_candidates(const Geom &g, int nrt, bool h16, int zb[20], int grp[20], int nt[20]) {
+  int z[6];
+  const int nz = eo_zb_candidates(g, z);
+  int n = 0;
+  for (int i = 0; i < nz; i++) {
+    zb[n] = z[i];
+    grp[n] = nrt;
+    nt[n++] = 0;
+  }
+  const int zg[2] = {4, 2}, gs[4] = {4, 3, 2, 5};
+  for (int a = 0; a < 2; a++) {
+    if (zg[a] > g.L[2] || g.L[2] % zg[a]) continue;
+    for (int b = 0; b < 4; b++) {
+      if (gs[b] >= nrt) continue;
+      zb[n] = zg[a];
+      grp[n] = gs[b];
+      nt[n++] = 0;
+    }
+  }
+  const int zn[3] = {4, 2, 8};
+  for (int a = 0; a < 3 && h16; a++) {
+    if (zn[a] > g.L[2] || g.L[2] % zn[a]) continue;
+    zb[n] = zn[a];
+    grp[n] = nrt;
+    nt[n++] = 1;
+  }
+  return n;
+}
+
 long eo_red_tiles(const Geom &g) {
   EoGeom e = make_eo(g);
   int zb[6];
   const int n = eo_zb_candidates(g, zb);
   long m = 0;
   for (int i = 0; i < n; i++) {
-    const long t = make_eo_tiles(e, zb[i]).ntile;
+    const long t = make_eo_tiles(e, zb[i], 1).ntile;
     m = t > m ? t : m;
   }
   return m;
@@ -822,21 +1057,35 @@ static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, doubl
                          hipStream_t st) {
   EoGeom e = make_eo(g);
   const int nrt = (nrhs + RT - 1) / RT;
-  int zb[6];
-  const int ncand = eo_zb_candidates(g, zb);
+  int zb[20], grp[20], nt[20];
+  const int ncand = eo_tile_candidates(g, nrt, std::is_same<TO, __half2>::value, zb, grp, nt);
+  // the all-FP16 form runs the packed-arithmetic kernel
+  constexpr bool pk = std::is_same<TL, __half2>::value && std::is_same<TD, __half2>::value &&
+                      std::is_same<TH, __half2>::value && std::is_same<TO, __half2>::value;
+  static_assert(!(pk && ADD), "no fused full-lattice update in the packed FP16 form");
   auto run = [&](int cand) -> int {
-    const EoTiles tl = make_eo_tiles(e, zb[cand]);
+    const EoTiles tl = make_eo_tiles(e, zb[cand], grp[cand], nt[cand]);
     const dim3 grid((unsigned)((long)NXCD * tl.tpx * nrt));
-    if (red) {
+    if constexpr (pk) {
+      if (red)
+        hipLaunchKernelGGL((k_hop_eo_pk<RT, 1, NR>), grid, dim3(256), 0, st, (const __half2 *)Ue,
+                           (const __half2 *)in_diag, (const __half2 *)in_hop, (__half2 *)out, e, par, a, b, nrhs, tl,
+                           red, 1.0f);
+      else
+        hipLaunchKernelGGL((k_hop_eo_pk<RT, 0, NR>), grid, dim3(256), 0, st, (const __half2 *)Ue,
+                           (const __half2 *)in_diag, (const __half2 *)in_hop, (__half2 *)out, e, par, a, b, nrhs, tl,
+                           (double *)nullptr, 1.0f);
+    } else if (red) {
       hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 1, NR>), grid, dim3(256), 0, st, (const TL *)Ue,
                          (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl, red, 1.0f);
-      hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)tl.ntile, red_out,
-                         red_stride);
     } else {
       hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 0, NR, ADD>), grid, dim3(256), 0, st, (const TL *)Ue,
                          (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl,
                          (double *)nullptr, 1.0f);
     }
+    if (red)
+      hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)tl.ntile, red_out,
+                         red_stride);
     WMG_HIP(hipGetLastError());
     return 0;
   };
@@ -862,7 +1111,7 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
              : launch_hop_eo<TL, TD, TH, TO, RT, 9>(g, Ue, par, a, b, in_diag, in_hop, out, nrhs, red, red_out,    \
                                                    red_stride, st)
   if (lp == P64 && pdiag == P64 && phop == P64 && pout == P64) HOP(double2, double2, double2, double2, 1);
-  if (lp == P16 && pdiag == P16 && phop == P16 && pout == P16) HOP(__half2, __half2, __half2, __half2, 3);
+  if (lp == P16 && pdiag == P16 && phop == P16 && pout == P16) HOP(__half2, __half2, __half2, __half2, 4);
   if (lp == P16 && pdiag == P16 && phop == P32 && pout == P32) HOP(__half2, __half2, float2, float2, 2);
 #undef HOP
   return set_error(-1, "hop_eo: unsupported precisions link %d diag %d hop %d out %d", lp, pdiag, phop, pout);

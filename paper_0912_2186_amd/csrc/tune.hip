@@ -4,7 +4,8 @@
 // process.  With the environment variable WMG_TUNE_CACHE naming a file, the
 // choices are read from it at the first lookup and every new choice is
 // appended, so later processes skip the search.  WMG_TUNE=0 switches the
-// search off (candidate 0, the hand-picked default, everywhere).
+// search off (candidate 0, the hand-picked default, everywhere);
+// WMG_TUNE_VERBOSE=1 prints every candidate's time to stderr.
 //
 // Candidates must be pure launches (outputs overwritten from inputs that the
 // launch does not modify): tune_choice always ends with one launch of the
@@ -30,12 +31,16 @@ std::mutex g_mu;
 std::unordered_map<std::string, Entry> g_table;
 bool g_loaded = false;
 int g_enabled = -1;
+bool g_verbose = false;
+int g_force = -1;  // test hook: run this candidate everywhere, no search
 
 void load_cache_locked() {
   if (g_loaded) return;
   g_loaded = true;
   const char *e = std::getenv("WMG_TUNE");
   g_enabled = !(e && e[0] == '0');
+  const char *v = std::getenv("WMG_TUNE_VERBOSE");
+  g_verbose = v && v[0] == '1';
   const char *path = std::getenv("WMG_TUNE_CACHE");
   if (!path || !*path) return;
   FILE *f = std::fopen(path, "r");
@@ -58,14 +63,19 @@ void append_cache_locked(const std::string &key, const Entry &e) {
 }  // namespace
 
 int tune_choice(const std::string &key, int ncand, const std::function<int(int)> &run, hipStream_t st, int *choice) {
-  int known = -1;
+  int known = -1, forced = -1;
   bool search = true;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache_locked();
+    if (g_force >= 0) forced = g_force < ncand ? g_force : 0;
     auto it = g_table.find(key);
     if (it != g_table.end() && it->second.choice < ncand) known = it->second.choice;
     search = known < 0 && g_enabled && ncand > 1;
+  }
+  if (forced >= 0) {
+    *choice = forced;
+    return run(forced);
   }
   if (search) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -95,6 +105,7 @@ int tune_choice(const std::string &key, int ncand, const std::function<int(int)>
     }
     float ms = 0;
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = set_error(-3, "tune: elapsed time"); break; }
+    if (g_verbose) std::fprintf(stderr, "tune %s candidate %d: %.4f ms\n", key.c_str(), c, ms / reps);
     if (ms / reps < best_ms) {
       best_ms = ms / reps;
       best = c;
@@ -124,3 +135,10 @@ int tune_lookup(const std::string &key) {
 }
 
 }  // namespace wmg
+
+extern "C" int wmg_tune_force(int choice) {
+  std::lock_guard<std::mutex> lk(wmg::g_mu);
+  const int prev = wmg::g_force;
+  wmg::g_force = choice < 0 ? -1 : choice;
+  return prev;
+}

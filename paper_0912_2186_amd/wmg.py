@@ -125,6 +125,7 @@ _sig = {
     "mg_last_iters": (_i, [_vp, _P(_i), _i]),
     "mg_time_dslash": (_i, [_vp, _i, _i, _i, _P(_d)]),
     "mg_profile": (_i, [_vp, _i]),
+    "wmg_tune_force": (_i, [_i]),
     "mg_profile_get": (_i, [_vp, _i, _P(_i), _P(_d), _P(_d)]),
 }
 KERNEL_KINDS = {"dslash_cycle": 0, "dslash_outer32": 1, "dslash_fp64": 2, "coarse_fp32": 3, "coarse_fp64": 4,
@@ -178,6 +179,11 @@ def _stream_ptr(stream) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
     return stream.cuda_stream
+
+
+def tune_force(choice: int) -> int:
+    """Autotuner test hook: run candidate `choice` everywhere (< 0: off)."""
+    return int(_lib.wmg_tune_force(int(choice)))
 
 
 def wilson_apply(L, U: torch.Tensor, m: float, inp: torch.Tensor, out: torch.Tensor, stream=None) -> None:

@@ -198,3 +198,56 @@ def test_red_black_mixed_multi_rhs(wmg):
             say("    rhs", k, "oracle relres", rr)
             assert rr <= 1e-10 * 1.0001
     assert its[wmg.WMG_EO_SMOOTHER] < its[0]
+
+
+@pytest.mark.parametrize("prec", [0, 3, 4])
+def test_hop_kernel_tilings_identical(wmg, prec):
+    """Every work order the autotuner may pick for the red/black hop (slab
+    depth, rhs tiles swept in groups, the last group short) computes each
+    site with the same operations, so the outputs are bit-identical to the
+    default's; the default is checked against the oracle per site on three
+    of the 16 right-hand sides (bounds as in test_hop_kernel_per_site).
+    16^1 x 12 x 8 x 6 gives ragged chunks per slab; 16 rhs give 6, 8 or 16
+    rhs tiles (three, two or one rhs per thread), so groups of 2-5 leave a
+    short last group."""
+    L = (16, 12, 8, 6)
+    V = vol(L)
+    m = -0.25
+    m4 = 4 + m
+    nr = 16
+    U = inputs.gauge_field(L, 0.5, 411)
+    par_of = oracle.parity(L)
+    src = inputs.gaussian_rhs(L, 412, nr)
+    dg = inputs.gaussian_rhs(L, 413, nr)
+    if prec == 3:
+        src, dg = _round(src, np.float16), _round(dg, np.float16)
+    elif prec == 4:
+        src, dg = _round(src, np.float32), _round(dg, np.float16)
+    p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=nr)
+    mg = wmg.MG(L, dev(U), m, 4, (4, 4, 4, 2), p)
+    try:
+        for par, a, b in ((1, 0.0, 1.0), (0, m4, -0.25 / m4)):
+            outs = []
+            for cand in range(16):
+                wmg.tune_force(cand)
+                out = empty((nr, V, 12))
+                mg.mg_hop_eo(prec, par, a, b, dev(dg) if a != 0.0 else None, dev(src), out, nr)
+                outs.append(host(out))
+            wmg.tune_force(-1)
+            for r in (0, 7, 15):
+                mask = (par_of == par)[:, None]
+                ref = (a * dg[r] + b * (-2.0) * oracle.wilson_hop_parity(L, U, m, src[r], par)) * mask
+                sc_in = np.concatenate([src[r], dg[r]], axis=1) if a != 0.0 else src[r]
+                k = abs(a) + 16 * abs(b)
+                if prec == 0:
+                    le, bound = local_err(outs[0][r], ref, sc_in, L), 256 * 2.0 ** -52 * k
+                else:
+                    le = local_err(outs[0][r], ref, sc_in, L, floor=2.0 ** -9 * np.abs(sc_in).max())
+                    bound = 64 * 2.0 ** -11 * k
+                assert le < bound
+            diff = [c for c in range(1, 16) if not np.array_equal(outs[c], outs[0])]
+            say("  prec", prec, "par", par, "tilings differing from the default:", diff)
+            assert not diff
+    finally:
+        wmg.tune_force(-1)
+        mg.close()
