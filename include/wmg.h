@@ -265,9 +265,10 @@ int mg_smoother_residual(wmg_ctx *ctx, const double *r, const double *e, double 
  * vectors.  prec 0: FP64 links and vectors; 3: FP16 links and FP16 vectors
  * (the MR steps: projection and SU(3) products in packed FP16 arithmetic,
  * the eight directions summed in FP32); 4: FP16 links and diag, FP32 hop
- * input and output (the odd correction); 5: as 4 in the smoother's fused
- * last step (par must be 1), which also returns hop's values at the even
- * sites.  Needs every extent even; nrhs <= 64. */
+ * input and output (the odd correction); 5: FP16 links, diag and hop input
+ * with FP32 output, the smoother's fused last step (par must be 1), which
+ * also returns hop's values at the even sites.  Needs every extent even;
+ * nrhs <= 64. */
 int mg_hop_eo(wmg_ctx *ctx, int prec, int par, double a, double b, const double *diag, const double *hop,
               double *out, int nrhs);
 /* One application of the FP64 preconditioner z = M r (one MG cycle). */

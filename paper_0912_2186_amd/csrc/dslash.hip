@@ -688,9 +688,13 @@ __device__ __forceinline__ void eo_store(const EoGeom &g, const EoTiles &tl, con
                                          TO *__restrict__ out, double ad, R a, R b, cx<R> (&acc)[RT][12],
                                          double (&rs)[RT][3]) {
   const int Vs = (int)g.Vhs;
+  // a thread's reduction terms summed in the arithmetic's precision (12
+  // products per rhs), then added to the FP64 block sums
+  using A = typename std::conditional<sizeof(R) == 8, double, float>::type;
 #pragma unroll
   for (int t = 0; t < RT; t++) {
     if (st.r0 + t >= nrhs) continue;
+    A loc[3] = {A(0), A(0), A(0)};
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       const size_t i = ((size_t)(st.r0 + t) * 3 + c) * Vs * 4 + (unsigned)st.h * 4;
@@ -723,11 +727,16 @@ __device__ __forceinline__ void eo_store(const EoGeom &g, const EoTiles &tl, con
 #pragma unroll
         for (int sp = 0; sp < 4; sp++) {
           const cx<R> os = as_stored(out, o[sp]);
-          rs[t][0] += (double)os.re * dv[sp].re + (double)os.im * dv[sp].im;
-          rs[t][1] += (double)os.re * dv[sp].im - (double)os.im * dv[sp].re;
-          rs[t][2] += (double)os.re * os.re + (double)os.im * os.im;
+          loc[0] += (A)os.re * (A)dv[sp].re + (A)os.im * (A)dv[sp].im;
+          loc[1] += (A)os.re * (A)dv[sp].im - (A)os.im * (A)dv[sp].re;
+          loc[2] += (A)os.re * (A)os.re + (A)os.im * (A)os.im;
         }
       }
+    }
+    if (RED) {
+      rs[t][0] += (double)loc[0];
+      rs[t][1] += (double)loc[1];
+      rs[t][2] += (double)loc[2];
     }
   }
 }
@@ -1122,12 +1131,13 @@ int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int
   const bool c12 = (lprec & LK12) != 0;
   const int lp = lprec & ~LK12;
   if (g.L[0] % 2 || g.V / 2 >= (1L << 29)) return set_error(-1, "hop_eo_add: lattice not supported");
-#define HOPA(TL, TD, TH, RT)                                                                                      \
-  return c12 ? launch_hop_eo<TL, TD, TH, TH, RT, 6, 1>(g, Ue, 1, a, b, in_diag, de, full, nrhs, nullptr, nullptr, 0, \
+#define HOPA(TL, TD, TH, TO, RT)                                                                                  \
+  return c12 ? launch_hop_eo<TL, TD, TH, TO, RT, 6, 1>(g, Ue, 1, a, b, in_diag, de, full, nrhs, nullptr, nullptr, 0, \
                                                       st)                                                          \
-             : launch_hop_eo<TL, TD, TH, TH, RT, 9, 1>(g, Ue, 1, a, b, in_diag, de, full, nrhs, nullptr, nullptr, 0, st)
-  if (lp == P64 && pdiag == P64 && phop == P64) HOPA(double2, double2, double2, 1);
-  if (lp == P16 && pdiag == P16 && phop == P32) HOPA(__half2, __half2, float2, 2);
+             : launch_hop_eo<TL, TD, TH, TO, RT, 9, 1>(g, Ue, 1, a, b, in_diag, de, full, nrhs, nullptr, nullptr, 0, st)
+  if (lp == P64 && pdiag == P64 && phop == P64) HOPA(double2, double2, double2, double2, 1);
+  if (lp == P16 && pdiag == P16 && phop == P32) HOPA(__half2, __half2, float2, float2, 2);
+  if (lp == P16 && pdiag == P16 && phop == P16) HOPA(__half2, __half2, __half2, float2, 2);
 #undef HOPA
   return set_error(-1, "hop_eo_add: unsupported precisions link %d diag %d field %d", lp, pdiag, phop);
 }

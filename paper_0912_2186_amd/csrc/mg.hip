@@ -624,12 +624,12 @@ static int eo_links(wmg_ctx *c, int lp, const void **Ue) {
 }
 
 // prec P64: all in FP64.  prec P16: r FP32 used as r/|r| (|r|^2 in rn2),
-// sublattice vectors and MR iterates FP16, corrections and e FP32.
+// sublattice vectors, MR iterates and the even correction d_e FP16, e FP32.
 static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, void *e, int nsteps, int nrhs) {
   Level &L = c->lv[0];
   const int lp = sp == P64 ? P64 : P16;   // link precision
   const int vp = sp == P64 ? P64 : P16;   // sublattice residuals and MR iterates
-  const int dp = sp == P64 ? P64 : P32;   // corrections
+  const int dp = sp == P64 ? P64 : P16;   // even correction d_e
   const void *Ue;
   TRY(eo_links(c, lp, &Ue));
   const int lc = lp | L.lk;
@@ -646,7 +646,8 @@ static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, vo
   const long nh = 12 * eo_stride(L.g);
   const double vb = (double)L.g.V * fine_link_cx(L) * (lp == P64 ? 16 : 4);  // links of both halves
   const double eb = sp == P64 ? 16 : 4;                                        // sublattice element bytes
-  const double db = sp == P64 ? 16 : 8;                                        // correction element bytes
+  const double db = sp == P64 ? 16 : 4;                                        // d_e element bytes
+  const double fb = sp == P64 ? 16 : 8;                                        // e element bytes
   const double hs = (double)L.g.V / 2 * 12 * nrhs;                             // elements of one half field
   // one red/black hop launch, timed and counted as the cycle's fine operator
   // (algorithmic bytes: the links of both halves, the input, the output and
@@ -697,12 +698,12 @@ static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, vo
     hipLaunchKernelGGL((k_mr_accum<double2, double2, 0>), g, dim3(256), 0, c->st, c->mr_red, nsteps, mv,
                        (double2 *)de, nh);
   else
-    hipLaunchKernelGGL((k_mr_accum<float2, __half2, 0>), g, dim3(256), 0, c->st, c->mr_red, nsteps, mv,
-                       (float2 *)de, nh);
+    hipLaunchKernelGGL((k_mr_accum<__half2, __half2, 0>), g, dim3(256), 0, c->st, c->mr_red, nsteps, mv,
+                       (__half2 *)de, nh);
   WMG_HIP(hipGetLastError());
   // d_o = (s_o + H_o(d_e) / 2) / (4+m) and e += (d_e, d_o) in one kernel
   // (bytes: links, s_o, d_e, and e read and written)
-  const int slot2 = prof_begin(c, sp == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE, vb + hs * (eb + db + 4 * db));
+  const int slot2 = prof_begin(c, sp == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE, vb + hs * (eb + db + 4 * fb));
   const int rc2 = hop_eo_add(L.g, lc, Ue, 1.0 / m4, 0.5 / m4, vp, so, dp, de, e, nrhs, c->st);
   prof_end(c, slot2);
   return rc2;
@@ -1971,7 +1972,7 @@ int mg_hop_eo(wmg_ctx *c, int prec, int par, double a, double b, const double *d
     if (F.g.L[i] % 2) return set_error(WMG_EINVAL, "red/black sublattices need even extents");
   const int lp = prec == 0 ? P64 : P16;                        // links
   const int pd = prec == 0 ? P64 : P16;                        // diag
-  const int ph = prec == 0 ? P64 : (prec == 3 ? P16 : P32);    // hop input and output
+  const int ph = prec == 0 ? P64 : (prec == 4 ? P32 : P16);    // hop input (and output, prec 0, 3, 4)
   const void *Ue;
   TRY(eo_links(c, lp, &Ue));
   void *de, *dod, *he, *ho, *o;
@@ -1983,7 +1984,7 @@ int mg_hop_eo(wmg_ctx *c, int prec, int par, double a, double b, const double *d
   if (a != 0.0) TRY(canon_to_eo(c, pd, diag, de, dod, nrhs));
   TRY(canon_to_eo(c, ph, hop, he, ho, nrhs));
   const long nh = 12 * eo_stride(F.g);
-  const int pf = ph == P64 ? P64 : P32;
+  const int pf = prec == 0 ? P64 : P32;
   void *full, *b64;
   TRY(level_vec(c, 0, pf, VT, &full, nrhs));
   TRY(zero(pf, full, F.n, nrhs, c->st));

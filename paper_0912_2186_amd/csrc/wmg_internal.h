@@ -195,8 +195,8 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
            hipStream_t st);
 // full (full-lattice, precision phop) += d_e at the even sites and
 // a in_diag + b H_odd(d_e) at the odd sites, d_e the even half-lattice field
-// (precision phop): all FP64, or FP16 links and in_diag with FP32 d_e and
-// full.
+// (precision phop): all FP64, or FP16 links and in_diag with FP32 or FP16
+// d_e and FP32 full.
 int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int pdiag, const void *in_diag,
                int phop, const void *de, void *full, int nrhs, hipStream_t st);
 int eo_pack(const Geom &g, int pfull, const void *full, int phalf, void *ev, void *od, int nrhs, hipStream_t st);

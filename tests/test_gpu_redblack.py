@@ -81,12 +81,12 @@ def test_hop_kernel_per_site(wmg, L, block, prec):
     dg = np.stack([inputs.gaussian_rhs(L, 404)[0], inputs.z4_noise(L, 405, 1)[0], _decaying(L, 3, 1.0, 406)])
     if prec == 0:
         hop_in, diag_in = src, dg
-    elif prec == 3:
+    elif prec in (3, 5):
         hop_in, diag_in = _round(src, np.float16), _round(dg, np.float16)
     else:
         hop_in, diag_in = _round(src, np.float32), _round(dg, np.float16)
-    # prec 5 is the fused last step of the smoother: parity 1 only, and the
-    # even sites return hop's own values
+    # prec 5 is the fused last step of the smoother (FP16 input, FP32
+    # output): parity 1 only, and the even sites return hop's own values
     cases = ((1, 0.0, 1.0), (0, m4, -0.25 / m4), (1, 1.0 / m4, 0.5 / m4))
     if prec == 5:
         cases = ((1, 1.0 / m4, 0.5 / m4), (1, 0.0, 1.0))
