@@ -278,16 +278,23 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
   const int L[4] = {L0, L1, L2, L3};
   int x[4];
   long s = 0;
-  // site-tile workgroup index tb and first rhs r0: grid (tiles, rhs tiles),
-  // or with `inner` one dimension in which each XCD (blockIdx % 8) takes the
-  // rhs tiles of its site tiles consecutively
+  // site-tile workgroup index tb and first rhs r0: grid (tiles, rhs tiles)
+  // when inner = 0; else one dimension in which each XCD (blockIdx % 8)
+  // sweeps its range of site tiles once per group of `inner` rhs tiles, the
+  // group's rhs tiles of one site tile back to back (the last group may be
+  // short).  One group of all rhs tiles reads the links once; smaller groups
+  // bring the t-neighbours of a tile closer in the XCD's sequence.
   long tb = blockIdx.x;
   int r0 = blockIdx.y * RT;
   if (inner) {
     const int nrt = (nrhs + RT - 1) / RT;
     const long q = (long)blockIdx.x / NXCD;
-    tb = (q / nrt) * NXCD + blockIdx.x % NXCD;
-    r0 = (int)(q % nrt) * RT;
+    const long span = sm.per_xcd * inner;  // blocks of one full group on an XCD
+    const int g0 = (int)(q / span) * inner;
+    const int gc = min(inner, nrt - g0);
+    const long rem = q - (q / span) * span;
+    tb = (rem / gc) * NXCD + blockIdx.x % NXCD;
+    r0 = (g0 + (int)(rem % gc)) * RT;
   }
   const bool valid = sweep_site(sm, L, tb, threadIdx.x, x, s);
   // the tile's own spinors, [t][c][thread] (sized for the right-hand sides
@@ -478,14 +485,25 @@ static int launch_soa(const Geom &g, const void *U, double m, const void *in, vo
   // 14.6 -> 10.4 ms on 32^3x64); FP16 links are cheap to re-read, and one
   // sweep per rhs tile keeps the spinor halo in L2.  The autotuner also
   // tries the other order and other slab sizes.
-  const int inner0 = sizeof(TL) >= 8 && nrt > 1;
+  const int inner0 = sizeof(TL) >= 8 && nrt > 1 ? nrt : 0;
   // bytes a site brings into L2 during one sweep: its links and RT spinors
   const int bps = 4 * NR * (int)sizeof(TL) + 24 * (int)sizeof(TS) / 2 * RT;
   const size_t lds = (size_t)(nrhs < RT ? nrhs : RT) * 12 * 256 * sizeof(TS);
   constexpr int NB = (int)(sizeof(SWEEP_BUDGETS) / sizeof(SWEEP_BUDGETS[0]));
+  // candidates: every slab budget with the default order, then with the
+  // other of (one sweep per rhs tile, all rhs tiles of a site tile back to
+  // back), then with groups of 4, 3 and 2 rhs tiles
+  int cb[6 * NB], cg[6 * NB], ncand = 0;
+  for (int k = 0; k < NB; k++) cb[ncand] = k, cg[ncand++] = inner0;
+  if (nrt > 1) {
+    for (int k = 0; k < NB; k++) cb[ncand] = k, cg[ncand++] = inner0 ? 0 : nrt;
+    for (int gs : {4, 3, 2})
+      if (gs < nrt)
+        for (int k = 0; k < NB; k++) cb[ncand] = k, cg[ncand++] = gs;
+  }
   auto run = [&](int cand) -> int {
-    const long budget = SWEEP_BUDGETS[cand % NB];
-    const int inner = (cand / NB) ? !inner0 : inner0;
+    const long budget = SWEEP_BUDGETS[cb[cand]];
+    const int inner = cg[cand];
     SweepMap sm = make_sweep(g.L, bps, budget);
     dim3 grid = inner ? dim3((unsigned)(sm.nblocks * nrt)) : dim3((unsigned)sm.nblocks, nrt);
     if (red) {
@@ -517,7 +535,7 @@ static int launch_soa(const Geom &g, const void *U, double m, const void *in, vo
                 sizeof(TS), sizeof(TO), NR, red ? 1 : 0, bsub ? 1 : 0, out32 ? 1 : 0, out_odd ? 1 : 0, g.L[0], g.L[1],
                 g.L[2], g.L[3], nrhs);
   int choice = 0;
-  return tune_choice(key, nrt > 1 ? 2 * NB : NB, run, st, &choice);
+  return tune_choice(key, ncand, run, st, &choice);
 }
 
 long wilson_red_blocks(const Geom &g) {

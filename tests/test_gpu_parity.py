@@ -188,6 +188,47 @@ def test_fp16_smoother_residual_kernel(wmg):
     mg.close()
 
 
+def test_dslash_work_orders_identical(wmg):
+    """Every work order the autotuner may pick for the full-lattice Dslash
+    (slab budget, one sweep per rhs tile, all rhs tiles of a site tile back
+    to back, groups of 2-4 rhs tiles with a short last group) computes each
+    site with the same operations: the FP64, FP32, FP16-link and FP16 MR-step
+    forms and the smoother's residual kernel are bit-identical to the
+    default's, which is checked against the oracle on two of the 16
+    right-hand sides."""
+    L = (16, 12, 8, 6)
+    V = vol(L)
+    m = -0.2
+    nr = 16
+    U = inputs.gauge_field(L, 0.5, 311)
+    psi = inputs.gaussian_rhs(L, 312, nr)
+    e = 1e-3 * inputs.gaussian_rhs(L, 313, nr)
+    p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=nr)
+    mg = wmg.MG(L, dev(U), m, 4, (4, 4, 4, 2), p)
+    try:
+        forms = [(f"apply prec {prec}", lambda out, prec=prec: mg.mg_apply_fine(prec, dev(psi), out, nr))
+                 for prec in (0, 1, 2, 3)]
+        forms.append(("smoother residual", lambda out: mg.mg_smoother_residual(dev(psi), dev(e), out, nr)))
+        for name, run in forms:
+            outs = []
+            for cand in range(30):
+                wmg.tune_force(cand)
+                out = empty((nr, V, 12))
+                run(out)
+                outs.append(host(out))
+            wmg.tune_force(-1)
+            diff = [c for c in range(1, 30) if not np.array_equal(outs[c], outs[0])]
+            say("  ", name, "orders differing from the default:", diff)
+            assert not diff
+            if name == "apply prec 1":
+                for r in (0, 15):
+                    ref = oracle.wilson(L, U, m, psi[r])
+                    assert local_err(outs[0][r], ref, psi[r], L) < SITE_BOUND[1]
+    finally:
+        wmg.tune_force(-1)
+        mg.close()
+
+
 def rand_vecs(nv, V, dof, seed):
     rng = np.random.default_rng(seed)
     return rng.standard_normal((nv, V, dof)) + 1j * rng.standard_normal((nv, V, dof))
