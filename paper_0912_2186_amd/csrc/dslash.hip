@@ -1390,17 +1390,34 @@ int su3_recon_err(const Geom &g, const double *Ucanon, double *part, hipStream_t
   return 0;
 }
 
-__global__ void k_spinor_to_soa(const double2 *__restrict__ c, double2 *__restrict__ s, long V, long Vs) {
-  long i = blockIdx.x * 256L + threadIdx.x;
-  int r = blockIdx.y;
-  if (i >= V) return;
-  for (int k = 0; k < 12; k++) s[((size_t)r * 12 + k) * Vs + i] = c[((size_t)r * V + i) * 12 + k];
+// canonical [rhs][V][12] <-> SoA [rhs][12][Vs], 256 sites per workgroup
+// through LDS so that both sides are read and written in contiguous runs
+// (rows padded to 257 elements against bank conflicts)
+__global__ void __launch_bounds__(256) k_spinor_to_soa(const double2 *__restrict__ c, double2 *__restrict__ s, long V,
+                                                      long Vs) {
+  __shared__ double2 t[12 * 257];
+  const long i0 = blockIdx.x * 256L;
+  const int r = blockIdx.y;
+  const int nv = (int)(V - i0 < 256 ? V - i0 : 256);
+  const double2 *src = c + ((size_t)r * V + i0) * 12;
+  for (int q = threadIdx.x; q < nv * 12; q += 256) t[(q % 12) * 257 + q / 12] = src[q];
+  __syncthreads();
+  if ((int)threadIdx.x < nv)
+#pragma unroll
+    for (int k = 0; k < 12; k++) s[((size_t)r * 12 + k) * Vs + i0 + threadIdx.x] = t[k * 257 + threadIdx.x];
 }
-__global__ void k_spinor_from_soa(const double2 *__restrict__ s, double2 *__restrict__ c, long V, long Vs) {
-  long i = blockIdx.x * 256L + threadIdx.x;
-  int r = blockIdx.y;
-  if (i >= V) return;
-  for (int k = 0; k < 12; k++) c[((size_t)r * V + i) * 12 + k] = s[((size_t)r * 12 + k) * Vs + i];
+__global__ void __launch_bounds__(256) k_spinor_from_soa(const double2 *__restrict__ s, double2 *__restrict__ c,
+                                                        long V, long Vs) {
+  __shared__ double2 t[12 * 257];
+  const long i0 = blockIdx.x * 256L;
+  const int r = blockIdx.y;
+  const int nv = (int)(V - i0 < 256 ? V - i0 : 256);
+  if ((int)threadIdx.x < nv)
+#pragma unroll
+    for (int k = 0; k < 12; k++) t[k * 257 + threadIdx.x] = s[((size_t)r * 12 + k) * Vs + i0 + threadIdx.x];
+  __syncthreads();
+  double2 *dst = c + ((size_t)r * V + i0) * 12;
+  for (int q = threadIdx.x; q < nv * 12; q += 256) dst[q] = t[(q % 12) * 257 + q / 12];
 }
 
 int spinor_to_soa(const Geom &g, const double *canon, double2 *soa, int nrhs, hipStream_t st) {

@@ -1044,8 +1044,17 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
   for (int r = 0; r < nrhs; r++) bn[r] = sqrt(c->hbuf[4 * r]);
   int roff = 0;
   bool rin_done = false;  // B.rin already holds the FP32 copy of r
+  // without an initial guess x is zero but not yet written: the first
+  // solution update writes it instead of adding to it
+  bool x_unset = !x0_nonzero;
   if (x0_nonzero) {
     TRY(residual64(c, l, B, nrhs, &roff, &rin_done));
+  } else if (ip != P64) {
+    // r = b: the first inner cycle starts from the FP32 copy of b, |r|^2 =
+    // |b|^2 is already in red_out, and r64 is first written by the reliable
+    // update
+    TRY(copy(ip, B.rin, P64, B.b64, n, nrhs, st));
+    rin_done = true;
   } else {
     TRY(copy(P64, B.r64, P64, B.b64, n, nrhs, st));
     TRY(norm2(c->red, P64, B.r64, n, nrhs, c->red_out, 4, st));
@@ -1123,7 +1132,9 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
       if (allfrozen) break;
     }
     hipLaunchKernelGGL(k_gcr_trisolve2, dim3(1), dim3(64), 0, st, c->gcr, k, nrhs);
-    TRY(multi_caxpy(P64, B.x64, ip, (const void *const *)B.zdev, k, c->gcr + G_C, GS, 1.0, 1, n, nrhs, st));
+    TRY(multi_caxpy(P64, B.x64, ip, (const void *const *)B.zdev, k, c->gcr + G_C, GS, 1.0, x_unset ? 0 : 1, n,
+                    nrhs, st));
+    x_unset = false;
     // reliable update: true residual in FP64
     TRY(residual64(c, l, B, nrhs, &roff, &rin_done));
     c->st_rel++;
@@ -1137,6 +1148,7 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
       any |= (bool)active[r];
     }
   }
+  if (x_unset) TRY(zero(P64, B.x64, n, nrhs, st));
   if (relres_out) {
     double mx = 0;
     for (int r = 0; r < nrhs; r++) mx = fmax(mx, bn[r] > 0 ? rn[r] / bn[r] : rn[r]);
@@ -1516,8 +1528,7 @@ int mg_solve(wmg_ctx *c, const double *b, double *x, double tol, int nrhs, wmg_s
   Level &F = c->lv[0];
   TRY(spinor_to_soa(F.g, b, B->b64, nrhs, c->st));
   bool x0 = (c->p.flags & WMG_X0_GIVEN) != 0;
-  if (x0) TRY(spinor_to_soa(F.g, x, B->x64, nrhs, c->st));
-  else TRY(zero(P64, B->x64, F.n, nrhs, c->st));
+  if (x0) TRY(spinor_to_soa(F.g, x, B->x64, nrhs, c->st));  // else gcr_solve writes x
   double relres = 0;
   double delta = c->p.precision == WMG_MIXED ? c->p.reliable_delta : 0.0;
   int rc = gcr_solve(c, 0, *B, nrhs, tol, c->p.maxiter, 1, delta, x0, c->last_iters, &relres);
