@@ -69,6 +69,10 @@ extern "C" {
                              at the second solve of a buffer set, not while profiling;
                              ignored by mg_setup_batch, whose instances run on concurrent
                              host threads) */
+#define WMG_COARSE_B32 64 /* flags: with FP16 coarse links the matrix-core coarse stencil
+                             multiplies FP32 vectors (default: the vectors rounded to FP16
+                             with one power-of-two scale per rhs, FP16 products, FP32
+                             accumulation, for 32, 48 or 64 coarse dof and <= 64 rhs) */
 #define WMG_SPIN_SPLIT 32 /* flags: the fine level's blocking splits each null vector into its
                              four Dirac spins instead of its two chiralities (Sec. 3, exposing
                              the full spin structure on the coarse blocks): 4 Nv coarse dof per
@@ -103,7 +107,7 @@ typedef struct {
   double reliable_delta;  /* mixed: restart in FP64 when |r_inner| < delta * |r_last_update| (default 1e-3) */
   int maxiter;            /* outer GCR iteration cap */
   unsigned long long seed;/* Philox key of the setup's random start vectors */
-  int flags;              /* WMG_X0_GIVEN | WMG_COARSE_FP32 */
+  int flags;              /* WMG_* flags above */
 } wmg_params;
 
 typedef struct {

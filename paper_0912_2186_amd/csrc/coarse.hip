@@ -941,9 +941,190 @@ k_coarse_apply_mfma2(const float *__restrict__ Ym, const __half *__restrict__ Yh
   }
 }
 
+// ---- FP16 products
+// With FP16 links the stencil can also multiply in FP16
+// (v_mfma_f32_16x16x16f16: one instruction takes the four k-steps a lane
+// holds, 4x fewer matrix instructions than FP32 products), accumulating in
+// FP32.  B = the neighbour vector times the block's link scale, rounded to
+// FP16, with one power-of-two scale per right-hand side that brings its
+// largest |re| or |im| to [1024, 2048): the products keep FP16's 11 bits
+// relative to each rhs's largest entry (the stored links already round at
+// 2^-11 of their block's largest entry) and cannot overflow (link entries
+// scaled to |y| <= 1, block scales of order 1).
+
+// partial maxima of |re|, |im| of each rhs's vector: EMX per rhs
+constexpr int EMX = COARSE_H_PART;
+__global__ void __launch_bounds__(256) k_rhs_absmax(const float2 *__restrict__ v, long len, float *__restrict__ part) {
+  const int r = blockIdx.y, j = blockIdx.x;
+  const float2 *p = v + (size_t)r * len;
+  float m = 0.f;
+  for (long i = (long)j * 256 + threadIdx.x; i < len; i += (long)EMX * 256) {
+    const float2 x = p[i];
+    m = fmaxf(m, fmaxf(fabsf(x.x), fabsf(x.y)));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_down(m, o, 64));
+  __shared__ float sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)r * EMX + j] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+}
+
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+// k_coarse_apply_mfma2 with FP16 products (same tiling, fragments, B order
+// and epilogue): the lane's four consecutive k-steps of A (as stored) and of
+// B (one 8-byte LDS read) are one FP16 fragment; the k order inside the
+// instruction is permuted the same way for both operands.
+template <int NTR, int N>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+k_coarse_apply_mfma2h(const __half *__restrict__ Yh, const float *__restrict__ Ysc, const float2 *__restrict__ in,
+                      float2 *__restrict__ out, int L0, int L1, int L2, int L3, long Vc, int nrhs, int dagger,
+                      double *__restrict__ npart, const float *__restrict__ bpart) {
+  constexpr int KM = (N / 2 + 7) / 8 * 8;
+  constexpr int KS = N / 2, Q = N / 4;
+  constexpr int MT = (N + 15) / 16;
+  constexpr int LDKH = 2 * N + 8;  // halves per B column
+  static_assert(Q % 4 == 0, "the sign switch of [Yr | -Yi] must fall between fragments");
+  extern __shared__ _Float16 Bh[];  // [NTR*16 columns][LDKH], k order of k_coarse_apply_mfma2
+  __shared__ float bsh[32];         // per-rhs scale
+  long xh = blockIdx.x;
+  int r0 = blockIdx.y * 32;
+  int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
+  int mt = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int L[4] = {L0, L1, L2, L3};
+  int x[4];
+  site_coords(L, xh, x);
+  auto nbr = [&](int d) -> long {
+    if (d == 0) return xh;
+    int mu = (d - 1) & 3;
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    y[mu] = d < 5 ? (x[mu] + 1) % L[mu] : (x[mu] - 1 + L[mu]) % L[mu];
+    return site_index(L, y);
+  };
+  constexpr int h = N / 2;
+  if ((int)threadIdx.x < R) {
+    float m = 0.f;
+    for (int j = 0; j < EMX; j++) m = fmaxf(m, bpart[(size_t)(r0 + threadIdx.x) * EMX + j]);
+    int e = 0;
+    (void)frexpf(m, &e);
+    const int k = 11 - e < -126 ? -126 : (11 - e > 126 ? 126 : 11 - e);
+    bsh[threadIdx.x] = m > 0.f ? ldexpf(1.f, k) : 1.f;
+  }
+  for (int idx = threadIdx.x; idx < (NTR * 16 - R) * LDKH; idx += blockDim.x) Bh[R * LDKH + idx] = (_Float16)0.f;
+  constexpr int tpr = 64 * MT / N;
+  const int col = threadIdx.x % N, rg = threadIdx.x / N;
+  const bool stager = rg < tpr;
+  const bool neg = dagger && col >= h;
+  float2 stg[8];
+  auto stage_load = [&](int d) {
+    const float2 *src = in + ((size_t)(r0 + rg) * Vc + nbr(d)) * N + col;
+    const size_t step = (size_t)tpr * Vc * N;
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (stager && rg + q * tpr < R) stg[q] = src[q * step];
+  };
+  // B row k of column r at r*LDKH + (k % 4)*KS + k/4, times the link block
+  // scale and the rhs scale, in FP16
+  auto stage_store = [&](float sc) {
+    _Float16 *dst = Bh + rg * LDKH + (col % 4) * KS + col / 4;
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (stager && rg + q * tpr < R) {
+        const float2 v = stg[q];
+        const float s = (neg ? -sc : sc) * bsh[rg + q * tpr];
+        dst[q * tpr * LDKH] = (_Float16)(v.x * s);
+        dst[q * tpr * LDKH + N / 4] = (_Float16)(v.y * s);
+      }
+  };
+  const int mts = mt < MT ? mt : 0;
+  auto a_load = [&](half4 *a, int d) {
+    const uint2 *Ad = (const uint2 *)(Yh + (((size_t)xh * 9 + d) * MT + mts) * KM * 64) + lane;
+#pragma unroll
+    for (int kq = 0; kq < KS / 4; kq++) {
+      const uint2 v = Ad[kq * 64];
+      __builtin_memcpy(&a[kq], &v, 8);
+    }
+  };
+  floatx4 cr[NTR], ci[NTR];
+#pragma unroll
+  for (int t = 0; t < NTR; t++) cr[t] = ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  half4 a_cur[KS / 4], a_nxt[KS / 4];
+  float sc_cur = Ysc[(size_t)xh * 9], sc_nxt = 0.f;
+  stage_load(0);
+  a_load(a_cur, 0);
+  const int krow = lane >> 4, jc = lane & 15;
+  for (int d = 0; d < 9; d++) {
+    __syncthreads();  // every wave is done reading B of direction d-1 (and bsh is written)
+    stage_store(sc_cur);
+    __syncthreads();
+    if (d + 1 < 9) {
+      stage_load(d + 1);
+      a_load(a_nxt, d + 1);
+      sc_nxt = Ysc[(size_t)xh * 9 + d + 1];
+    }
+    if (mt < MT) {
+      const _Float16 *bcol = Bh + jc * LDKH + krow * KS;
+#pragma unroll
+      for (int b = 0; b < KS / 4; b++) {
+        // [Yr | -Yi] and [Yi | Yr] from the stored [Yr | Yi]
+        const half4 a1 = b < Q / 4 ? a_cur[b] : -a_cur[b];
+        const half4 a2 = b < Q / 4 ? a_cur[b + Q / 4] : a_cur[b - Q / 4];
+#pragma unroll
+        for (int t = 0; t < NTR; t++) {
+          half4 bv;
+          __builtin_memcpy(&bv, bcol + t * 16 * LDKH + 4 * b, 8);
+          cr[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(a1, bv, cr[t], 0, 0, 0);
+          ci[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(a2, bv, ci[t], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int kq = 0; kq < KS / 4; kq++) a_cur[kq] = a_nxt[kq];
+    sc_cur = sc_nxt;
+  }
+#pragma unroll
+  for (int t = 0; t < NTR; t++) {
+    const int r = t * 16 + (lane & 15);
+    const float inv = r < R ? 1.f / bsh[r] : 0.f;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      cr[t][v] *= inv;
+      ci[t][v] *= inv;
+      const int row = mt * 16 + 4 * (lane >> 4) + v;
+      if (row < N && r < R) {
+        float2 val = make_float2(cr[t][v], ci[t][v]);
+        if (dagger && row >= h) { val.x = -val.x; val.y = -val.y; }
+        out[((size_t)(r0 + r) * Vc + xh) * N + row] = val;
+      }
+    }
+  }
+  if (npart) {
+    __shared__ double nsh[MT][NTR * 16];
+#pragma unroll
+    for (int t = 0; t < NTR; t++) {
+      double q = 0;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int row = mt * 16 + 4 * (lane >> 4) + v;
+        if (row < N) q += (double)cr[t][v] * cr[t][v] + (double)ci[t][v] * ci[t][v];
+      }
+      q += __shfl_xor(q, 16, 64);
+      q += __shfl_xor(q, 32, 64);
+      if (lane < 16) nsh[mt][t * 16 + lane] = q;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+      double q = 0;
+#pragma unroll
+      for (int m = 0; m < MT; m++) q += nsh[m][threadIdx.x];
+      npart[(size_t)(r0 + threadIdx.x) * Vc + xh] = q;
+    }
+  }
+}
+
 static int coarse_apply_mfma_any(const Geom &gc, int n, const float *Ym, const __half *Yh, const float *Ysc,
                                  const float2 *in, float2 *out, int dagger, int nrhs, hipStream_t st,
-                                 double *npart = nullptr, bool *fused = nullptr) {
+                                 double *npart = nullptr, bool *fused = nullptr, float *bpart = nullptr) {
   if (fused) *fused = false;
   if (n > 64 || (n & 1)) return set_error(-1, "coarse_apply_mfma: n=%d (even, <= 64)", n);
   int MT = (n + 15) / 16;
@@ -951,6 +1132,24 @@ static int coarse_apply_mfma_any(const Geom &gc, int n, const float *Ym, const _
   int NT = (2 * rmax + 15) / 16;
   dim3 grid((unsigned)gc.V, (nrhs + 31) / 32);
   dim3 blk(64 * MT);
+  // (n / 4 a multiple of 4: the sign switch of [Yr | -Yi] falls between
+  // the four-k-step fragments)
+  if (Yh && bpart && (n == 32 || n == 48 || n == 64)) {
+    const int NTR = (rmax + 15) / 16;
+    const size_t ldsh = sizeof(_Float16) * NTR * 16 * (2 * n + 8);
+    hipLaunchKernelGGL(k_rhs_absmax, dim3(EMX, nrhs), dim3(256), 0, st, in, gc.V * n, bpart);
+#define H_CASE(T, NN)                                                                                        \
+  if (NTR == T && n == NN) {                                                                                \
+    hipLaunchKernelGGL((k_coarse_apply_mfma2h<T, NN>), grid, blk, ldsh, st, Yh, Ysc, in, out, gc.L[0], gc.L[1], \
+                       gc.L[2], gc.L[3], gc.V, nrhs, dagger, npart, (const float *)bpart);                  \
+    WMG_HIP(hipGetLastError());                                                                             \
+    if (fused) *fused = npart != nullptr;                                                                   \
+    return 0;                                                                                               \
+  }
+    H_CASE(1, 32) H_CASE(1, 48) H_CASE(1, 64)
+    H_CASE(2, 32) H_CASE(2, 48) H_CASE(2, 64)
+#undef H_CASE
+  }
   if (n == 32 || n == 40 || n == 48 || n == 64) {
     const int NTR = (rmax + 15) / 16;
     size_t lds2 = sizeof(float) * NTR * 16 * mfma2_ldk(n);
@@ -996,9 +1195,11 @@ int coarse_apply_mfma(const Geom &gc, int n, const float *Ym, const float2 *in, 
 }
 
 int coarse_apply_mfma16(const Geom &gc, int n, const __half *Yh, const float *Ysc, const float2 *in, float2 *out,
-                        int dagger, int nrhs, hipStream_t st, double *npart, bool *fused) {
+                        int dagger, int nrhs, hipStream_t st, double *npart, bool *fused, float *bpart) {
   if (!Yh || !Ysc) return set_error(-1, "coarse_apply_mfma16: null links");
-  return coarse_apply_mfma_any(gc, n, nullptr, Yh, Ysc, in, out, dagger, nrhs, st, npart, fused);
+  if (bpart && nrhs > COARSE_H_MAXRHS) return set_error(-1, "coarse_apply_mfma16: FP16 products for at most %d rhs",
+                                                        COARSE_H_MAXRHS);
+  return coarse_apply_mfma_any(gc, n, nullptr, Yh, Ysc, in, out, dagger, nrhs, st, npart, fused, bpart);
 }
 
 }  // namespace wmg

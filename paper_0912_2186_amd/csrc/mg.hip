@@ -312,6 +312,7 @@ struct wmg_ctx {
   double *dred = nullptr;  // per-workgroup partials of the fused Dslash reductions
   double *cpart = nullptr;  // per-(rhs, site or workgroup) partials of fused coarse norms
   size_t cpart_cap = 0;
+  float *bpart = nullptr;   // per-rhs partial maxima for the FP16 products of the coarse stencil
   int *flag = nullptr;
   double *hbuf = nullptr;  // pinned host mirror
   GcrBuf gb[2][2];         // [level 0 / level 1][FP64 / FP32 inner precision]
@@ -503,7 +504,8 @@ static int apply_op(wmg_ctx *c, int l, int prec, const void *in, void *out, int 
   if (nrm_out && prec == P32 && (L.Ymh || L.Ym)) TRY(cpart_get(c, (size_t)nrhs * L.g.V, &npart));
   if (prec == P32 && L.Ymh)
     rc = coarse_apply_mfma16(L.g, n, L.Ymh, L.Ymsc, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st, npart,
-                             &fused);
+                             &fused,
+                             (c->p.flags & WMG_COARSE_B32) || nrhs > COARSE_H_MAXRHS ? nullptr : c->bpart);
   else if (prec == P32 && L.Ym)
     rc = coarse_apply_mfma(L.g, n, L.Ym, (const float2 *)in, (float2 *)out, dagger, nrhs, c->st, npart, &fused);
   else
@@ -1215,6 +1217,7 @@ static int make_low_precision(wmg_ctx *c) {
         TRY(dalloc((void **)&C.Ymh, sizeof(__half) * coarse_mfma_halfs(C.g.V, C.dof_max)));
         TRY(dalloc((void **)&C.Ymsc, sizeof(float) * 9 * (size_t)C.g.V));
       }
+      if (!c->bpart) TRY(dalloc((void **)&c->bpart, sizeof(float) * COARSE_H_PART * COARSE_H_MAXRHS));
       TRY(coarse_to_mfma16(C.g.V, C.dof, C.Y64, C.Ymh, C.Ymsc, c->st));
     } else if (C.dof_max <= 64) {
       if (!C.Ym) TRY(dalloc((void **)&C.Ym, sizeof(float) * coarse_mfma_floats(C.g.V, C.dof_max)));
@@ -1311,6 +1314,7 @@ static void free_ctx(wmg_ctx *c) {
   if (c->dsc) (void)hipFree(c->dsc);
   if (c->dred) (void)hipFree(c->dred);
   if (c->cpart) (void)hipFree(c->cpart);
+  if (c->bpart) (void)hipFree(c->bpart);
   if (c->flag) (void)hipFree(c->flag);
   if (c->hbuf) (void)hipHostFree(c->hbuf);
   if (c->st) (void)hipStreamDestroy(c->st);

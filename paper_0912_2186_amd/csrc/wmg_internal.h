@@ -315,7 +315,14 @@ size_t coarse_mfma_halfs(long Vc, int n);
 // write |out|^2 of every (rhs, site) to npart[rhs * Vc + site] and set
 // *fused (sum them with sum_partials); otherwise *fused = false.  The same
 // holds for coarse_apply_mfma above.
+// With bpart != nullptr (scratch of COARSE_H_PART floats per rhs, nrhs <=
+// COARSE_H_MAXRHS) and n = 32, 48 or 64 the products are FP16
+// (v_mfma_f32_16x16x16f16) on the neighbour vectors scaled by the link block
+// scale and one power-of-two scale per rhs, accumulated in FP32.
+constexpr int COARSE_H_PART = 32;
+constexpr int COARSE_H_MAXRHS = 64;
 int coarse_apply_mfma16(const Geom &gc, int n, const __half *Yh, const float *Ysc, const float2 *in, float2 *out,
-                        int dagger, int nrhs, hipStream_t st, double *npart = nullptr, bool *fused = nullptr);
+                        int dagger, int nrhs, hipStream_t st, double *npart = nullptr, bool *fused = nullptr,
+                        float *bpart = nullptr);
 
 }  // namespace wmg

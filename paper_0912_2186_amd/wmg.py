@@ -37,6 +37,7 @@ WMG_LINKS18 = 4
 WMG_EO_SMOOTHER = 8
 WMG_GRAPHS = 16
 WMG_SPIN_SPLIT = 32
+WMG_COARSE_B32 = 64
 
 
 class WmgError(RuntimeError):

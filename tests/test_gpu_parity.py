@@ -274,12 +274,13 @@ def test_transfer_and_galerkin_from_given_vectors(wmg, L, block):
 
 
 @pytest.mark.parametrize("fp32_links", [False, True])
-@pytest.mark.parametrize("nv,nrhs", [(5, 1), (8, 7), (20, 28), (24, 28), (24, 40), (32, 3)])
+@pytest.mark.parametrize("nv,nrhs", [(5, 1), (8, 7), (16, 9), (20, 28), (24, 28), (24, 40), (32, 3)])
 def test_mfma_coarse_apply_multi_rhs(wmg, nv, nrhs, fp32_links):
     """Matrix-core coarse stencil (and its sigma_3 adjoint) for many
     right-hand sides against the oracle's FP64 stencil: FP32 links (FP32
     rounding) and the default FP16 links with one scale per site and
-    direction (a few 2^-11 relative)."""
+    direction and, for 32, 48 and 64 coarse dof, FP16 products (a few
+    2^-11 relative)."""
     L = (8, 8, 8, 16) if nv <= 8 else (8, 8, 8, 8)
     block = (4, 4, 4, 4) if nv <= 8 else (2, 2, 4, 4)
     say("mfma coarse", nv, nrhs, L, block)
@@ -306,15 +307,20 @@ def test_mfma_coarse_apply_multi_rhs(wmg, nv, nrhs, fp32_links):
         assert e < (2e-6 if fp32_links else 1.5e-3)
 
 
-def test_mfma16_coarse_apply_dynamic_range(wmg):
+@pytest.mark.parametrize("fp16_products", [False, True])
+def test_mfma16_coarse_apply_dynamic_range(wmg, fp16_products):
     """FP16-link matrix-core stencil on vectors whose sites span 12 decades
     (each site and rhs scaled by 10^u, u uniform in [-8, 4]), one zero rhs
     and one of size 1e-30: per rhs, the result matches the oracle applying
-    the same stored FP16 links to FP32 precision."""
+    the same stored FP16 links, to FP32 precision with FP32 products
+    (WMG_COARSE_B32) and to 2e-3 with the default FP16 products (vectors
+    rounded to FP16 after one power-of-two scale per rhs, 2^-11 relative to
+    the rhs's largest entry); the zero rhs gives exact zeros either way."""
     L, block, nv, nrhs = (8, 8, 8, 8), (4, 4, 4, 4), 24, 6
-    say("mfma16 dynamic range", L, nv, nrhs)
+    say("mfma16 dynamic range", L, nv, nrhs, "fp16 products", fp16_products)
     U = inputs.gauge_field(L, 0.5, 309)
-    p = wmg.default_params(setup_iters=0, seed=2, nrhs_max=nrhs, precision=wmg.WMG_MIXED)
+    p = wmg.default_params(setup_iters=0, seed=2, nrhs_max=nrhs, precision=wmg.WMG_MIXED,
+                           flags=0 if fp16_products else wmg.WMG_COARSE_B32)
     mg = wmg.MG(L, dev(U), -0.1, nv, block, p)
     vecs = rand_vecs(nv, vol(L), 12, 84)
     mg.mg_set_null_vectors(0, dev(vecs))
@@ -343,7 +349,10 @@ def test_mfma16_coarse_apply_dynamic_range(wmg):
                 continue
             e = relerr(oh[r], ref)
             say("  dagger", dag, "rhs", r, "relerr", e)
-            assert e < 5e-6
+            assert e < (2e-3 if fp16_products else 5e-6)
+            if fp16_products:
+                # and not merely the FP32 result: the products are FP16
+                assert e > 1e-6
 
 
 @pytest.mark.parametrize("L,block,nv,nrhs", [((8, 8, 8, 16), (4, 4, 4, 4), 24, 28), ((8, 8, 8, 8), (4, 4, 4, 4), 6, 1),
