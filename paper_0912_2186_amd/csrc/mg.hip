@@ -526,12 +526,17 @@ static double transfer_bytes(const Level &L, int prec, int nrhs) {
   if (prec != P64) b += 4.0 * L.nv * L.g.V;
   return b;
 }
-static int transfer_restrict(wmg_ctx *c, int l, int prec, const void *fine, void *coarse, int nrhs) {
+// rn2: |fine|^2 per rhs (device, stride 4) for FP16 products on the fine
+// level of the mixed cycle (nullptr, or WMG_COARSE_B32: FP32 products)
+static int transfer_restrict(wmg_ctx *c, int l, int prec, const void *fine, void *coarse, int nrhs,
+                             const double *rn2 = nullptr) {
   Level &L = c->lv[l];
   int pp = prec == P64 ? P64 : P16;
   const void *P = prec == P64 ? (const void *)L.P64 : (const void *)L.P16;
+  if (prec != P32 || !L.fine || (c->p.flags & WMG_COARSE_B32)) rn2 = nullptr;
   int slot = l == 0 ? prof_begin(c, K_RESTRICT, transfer_bytes(L, prec, nrhs)) : -1;
-  int rc = restrict_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, fine, L.fine ? 1 : 0, coarse, nrhs, c->st, L.ns);
+  int rc = restrict_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, fine, L.fine ? 1 : 0, coarse, nrhs, c->st, L.ns,
+                       rn2, 4);
   prof_end(c, slot);
   return rc;
 }
@@ -929,7 +934,7 @@ static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int n
     else
       TRY(norm2(c->red, P32, r, c->lv[0].n, nrhs, c->cyc_nrm, 4, c->st));
   }
-  TRY(transfer_restrict(c, l, prec, r, rc, nrhs));
+  TRY(transfer_restrict(c, l, prec, r, rc, nrhs, h16 ? c->cyc_nrm : nullptr));
   if (h16) TRY(scale_inv_sqrt(P32, rc, c->cyc_nrm, 4, C.n, nrhs, c->st));
   if (l + 1 == c->nl_cur - 1) {
     TRY(cgnr(c, l + 1, prec, rc, ec, nrhs));
@@ -1881,7 +1886,13 @@ static int transfer_f32(wmg_ctx *c, int level, int dir, const double *in, double
   if (dir == 0) {
     TRY(to_internal(c, level, in, (double2 *)f64, nrhs));
     TRY(copy(P32, f32, P64, f64, F.n, nrhs, c->st));
-    TRY(transfer_restrict(c, level, P32, f32, c32, nrhs));
+    // as the mixed cycle runs it: on the fine level with |in|^2 per rhs
+    double *nrm = nullptr;
+    if (F.fine) {
+      TRY(cpart_get(c, 4 * (size_t)nrhs, &nrm));
+      TRY(norm2(c->red, P32, f32, F.n, nrhs, nrm, 4, c->st));
+    }
+    TRY(transfer_restrict(c, level, P32, f32, c32, nrhs, nrm));
     TRY(copy(P64, out, P32, c32, C.n, nrhs, c->st));
   } else {
     TRY(copy(P32, c32, P64, in, C.n, nrhs, c->st));

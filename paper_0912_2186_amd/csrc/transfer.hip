@@ -483,6 +483,100 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(BlockGeom bg, int nv, cons
   }
 }
 
+// The same restriction with FP16 products (v_mfma_f32_16x16x16f16, FP32
+// accumulation): the P chunk as P16 x scale rounded to FP16, the vectors
+// times one power-of-two scale per rhs that brings its 2-norm (rn2, the
+// squared norm per rhs at stride rstride) to [1024, 2048), so every entry
+// stays below 2048 and the rounding is 2^-11 relative.  Each lane's four
+// consecutive k of A and of B (8-byte LDS reads) form one fragment; the
+// imaginary part's A = [-Pi | Pr] is read from the same tile at the other
+// half with a sign (RCH a multiple of 16: the switch falls between
+// fragments).
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+template <int RCH>
+__global__ void __launch_bounds__(TB) k_restrict_mfma_h(BlockGeom bg, int nv, const __half2 *__restrict__ P,
+                                                       const float *__restrict__ Pscale,
+                                                       const float2 *__restrict__ fine, float2 *__restrict__ coarse,
+                                                       int nrhs, const double *__restrict__ rn2, int rstride) {
+  static_assert(RCH % 16 == 0, "fragments of 16 k");
+  constexpr int RLDH = 2 * RCH + 8;  // LDS row stride in halves
+  __shared__ _Float16 Ah[32 * RLDH];
+  __shared__ _Float16 Bh[32 * RLDH];
+  __shared__ int soff[256];
+  __shared__ float bsh[32];
+  long xh = xcd_tile(blockIdx.x, gridDim.x);
+  if (xh >= bg.Vc) return;
+  const long origin = block_site(bg, xh, 0);
+  for (int k = threadIdx.x; k < bg.bs; k += TB) soff[k] = (int)(block_site(bg, xh, k) - origin);
+  const int r0 = blockIdx.y * 32;
+  const int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
+  if ((int)threadIdx.x < R) {
+    const double q = rn2[(size_t)(r0 + threadIdx.x) * rstride];
+    int e = 0;
+    (void)frexp(sqrt(q > 0 ? q : 0.0), &e);
+    const int k = 11 - e < -126 ? -126 : (11 - e > 126 ? 126 : 11 - e);
+    bsh[threadIdx.x] = q > 0 ? ldexpf(1.f, k) : 1.f;
+  }
+  const int E = bg.bs * 12, H = E / bg.ns, nc = bg.ns * nv;
+  const int MTr = (nv + 15) / 16, NTr = (R + 15) / 16;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < (32 - nv) * RLDH; i += TB) Ah[nv * RLDH + i] = (_Float16)0.f;
+  for (int i = threadIdx.x; i < (32 - R) * RLDH; i += TB) Bh[R * RLDH + i] = (_Float16)0.f;
+  const int mt = w / 2, nt = w % 2;
+  const bool mine = mt < MTr && nt < NTr;
+  const int krow = lane >> 4;
+  for (int chi = 0; chi < bg.ns; chi++) {
+    floatx4 accr = floatx4{0.f, 0.f, 0.f, 0.f}, acci = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int e0 = 0; e0 < H; e0 += RCH) {
+      const int g0 = chi * H + e0, c0 = g0 / bg.bs, k0 = g0 % bg.bs;
+      __syncthreads();  // the previous chunk is consumed (and bsh is written)
+      for (int i = threadIdx.x; i < nv * RCH; i += TB) {
+        int a = i / RCH, e = i % RCH;
+        float2 pv = __half22float2(P[((size_t)a * bg.Vc + xh) * E + g0 + e]);
+        float sc = Pscale[((size_t)a * bg.Vc + xh) * bg.bs + k0 + e];
+        Ah[a * RLDH + e] = (_Float16)(sc * pv.x);
+        Ah[a * RLDH + RCH + e] = (_Float16)(sc * pv.y);
+      }
+      for (int i = threadIdx.x; i < R * RCH; i += TB) {
+        int r = i / RCH, e = i % RCH;
+        float2 v = fine[((size_t)(r0 + r) * 12 + c0) * bg.Vs + origin + soff[k0 + e]];
+        const float bs = bsh[r];
+        Bh[r * RLDH + e] = (_Float16)(v.x * bs);
+        Bh[r * RLDH + RCH + e] = (_Float16)(v.y * bs);
+      }
+      __syncthreads();
+      if (mine) {
+        const _Float16 *ar = Ah + (mt * 16 + (lane & 15)) * RLDH + 4 * krow;
+        const _Float16 *br = Bh + (nt * 16 + (lane & 15)) * RLDH + 4 * krow;
+#pragma unroll
+        for (int b = 0; b < 2 * RCH / 16; b++) {
+          half4 a1, a2, bv;
+          __builtin_memcpy(&a1, ar + 16 * b, 8);
+          __builtin_memcpy(&bv, br + 16 * b, 8);
+          if (b < RCH / 16) {
+            __builtin_memcpy(&a2, ar + 16 * b + RCH, 8);
+            a2 = -a2;
+          } else {
+            __builtin_memcpy(&a2, ar + 16 * b - RCH, 8);
+          }
+          accr = __builtin_amdgcn_mfma_f32_16x16x16f16(a1, bv, accr, 0, 0, 0);
+          acci = __builtin_amdgcn_mfma_f32_16x16x16f16(a2, bv, acci, 0, 0, 0);
+        }
+      }
+    }
+    if (mine) {
+      const int r = nt * 16 + (lane & 15);
+      const float inv = r < R ? 1.f / bsh[r] : 0.f;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        int a = mt * 16 + 4 * (lane >> 4) + v;
+        if (a < nv && r < R)
+          coarse[((size_t)(r0 + r) * bg.Vc + xh) * nc + chi * nv + a] = make_float2(accr[v] * inv, acci[v] * inv);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------ MFMA prolongation
 // Fine-level prolongation of many right-hand sides on the matrix cores:
 // per aggregate xh and chirality chi, for 16 block elements e at a time,
@@ -635,7 +729,7 @@ static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, 
 
 static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P,
                     const float *Ps, int vprec, const void *in, void *out, int fine_soa, int nrhs, hipStream_t st,
-                    int ns) {
+                    int ns, const double *rn2 = nullptr, int rstride = 0) {
   BlockGeom bg = make_bg(g, dof, b, ns);
   if (nv > 64) return set_error(-1, "transfer: nv=%d > 64", nv);
   if ((ns != 2 && ns != 4) || dof % ns || ns * nv > 128) return set_error(-1, "transfer: %d parts of %d, nv=%d", ns, dof, nv);
@@ -645,6 +739,27 @@ static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int
     int ncand = 0, cand[3];
     for (int c : chunks)
       if (bg.bs % c == 0) cand[ncand++] = c;
+    if (rn2) {
+      // FP16 products: the chunk size candidates as for the FP32 form
+      auto runh = [&](int i) -> int {
+        if (cand[i] == 64)
+          hipLaunchKernelGGL(k_restrict_mfma_h<64>, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps,
+                             (const float2 *)in, (float2 *)out, nrhs, rn2, rstride);
+        else if (cand[i] == 32)
+          hipLaunchKernelGGL(k_restrict_mfma_h<32>, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps,
+                             (const float2 *)in, (float2 *)out, nrhs, rn2, rstride);
+        else
+          hipLaunchKernelGGL(k_restrict_mfma_h<128>, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps,
+                             (const float2 *)in, (float2 *)out, nrhs, rn2, rstride);
+        WMG_HIP(hipGetLastError());
+        return 0;
+      };
+      char keyh[160];
+      std::snprintf(keyh, sizeof(keyh), "restrict_mfma_h/nv%d-ns%d-bs%d/%dx%dx%dx%d/rhs%d", nv, ns, bg.bs, g.L[0],
+                    g.L[1], g.L[2], g.L[3], nrhs);
+      int choiceh = 0;
+      return tune_choice(keyh, ncand, runh, st, &choiceh);
+    }
     auto run = [&](int i) -> int {
       if (cand[i] == 64)
         hipLaunchKernelGGL(k_restrict_mfma<64>, grid, dim3(TB), 0, st, bg, nv, (const __half2 *)P, Ps,
@@ -697,8 +812,9 @@ static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int
 }
 
 int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
-                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st, int ns) {
-  return transfer(0, g, dof, b, nv, pprec, P, Pscale, vprec, fine, coarse, fine_soa, nrhs, st, ns);
+                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st, int ns,
+                const double *rn2, int rstride) {
+  return transfer(0, g, dof, b, nv, pprec, P, Pscale, vprec, fine, coarse, fine_soa, nrhs, st, ns, rn2, rstride);
 }
 
 int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,

@@ -275,8 +275,11 @@ int start_vectors(long nsite, int dof, uint64_t seed, int lvl, int alpha0, int c
 // orthogonalised against the ones before it only)
 int block_orthonormalize(const Geom &g, int dof, const int b[4], int nv, const double2 *vecs, int fine_soa,
                          double2 *P, int *fail_dev, hipStream_t st, int ns = 2, int a0 = 0);
+// rn2 != nullptr (|fine|^2 per rhs at stride rstride): the fine-level
+// matrix-core restriction with FP16 products (transfer.hip)
 int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
-                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st, int ns = 2);
+                int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st, int ns = 2,
+                const double *rn2 = nullptr, int rstride = 0);
 int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
                int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st, int ns = 2);
 int P_convert(long count, const double2 *P64, int pprec, void *Pout, float *scale, int dof, hipStream_t st);
