@@ -70,10 +70,11 @@ extern "C" {
                              ignored by mg_setup_batch, whose instances run on concurrent
                              host threads) */
 #define WMG_COARSE_B32 64 /* flags: the mixed cycle's matrix-core coarse stencil (FP16 links)
-                             and fine-level restriction multiply FP32 vectors (default: the
-                             vectors rounded to FP16 with one power-of-two scale per rhs,
-                             FP16 products, FP32 accumulation; stencil for 32, 48 or 64
-                             coarse dof and <= 64 rhs) */
+                             and fine-level restriction and prolongation multiply FP32
+                             vectors (default: the vectors rounded to FP16 with one
+                             power-of-two scale per rhs, FP16 products, FP32 accumulation;
+                             stencil for 32, 48 or 64 coarse dof, prolongation for Nv a
+                             multiple of 8, <= 64 rhs) */
 #define WMG_SPIN_SPLIT 32 /* flags: the fine level's blocking splits each null vector into its
                              four Dirac spins instead of its two chiralities (Sec. 3, exposing
                              the full spin structure on the coarse blocks): 4 Nv coarse dof per
@@ -246,8 +247,8 @@ int mg_prolong(wmg_ctx *ctx, int level, const double *coarse, double *fine, int 
 int mg_coarse_apply(wmg_ctx *ctx, int level, const double *in, double *out, int dagger, int nrhs);
 /* Restriction / prolongation through the FP32 vectors and the FP16-stored
  * prolongator of a mixed-precision context, as the mixed cycle runs them
- * (the fine-level restriction with FP16 products unless WMG_COARSE_B32);
- * canonical FP64 in/out. */
+ * (on the fine level with FP16 products unless WMG_COARSE_B32); canonical
+ * FP64 in/out. */
 int mg_restrict_f32(wmg_ctx *ctx, int level, const double *fine, double *coarse, int nrhs);
 int mg_prolong_f32(wmg_ctx *ctx, int level, const double *coarse, double *fine, int nrhs);
 /* The same through the FP32 coarse operator of a mixed-precision context

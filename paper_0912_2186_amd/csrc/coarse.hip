@@ -970,6 +970,12 @@ __global__ void __launch_bounds__(256) k_rhs_absmax(const float2 *__restrict__ v
   if (threadIdx.x == 0) part[(size_t)r * EMX + j] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
 }
 
+int rhs_absmax(const float2 *v, long len, int nrhs, float *part, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_absmax, dim3(EMX, nrhs), dim3(256), 0, st, v, len, part);
+  WMG_HIP(hipGetLastError());
+  return 0;
+}
+
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 // k_coarse_apply_mfma2 with FP16 products (same tiling, fragments, B order
 // and epilogue): the lane's four consecutive k-steps of A (as stored) and of

@@ -540,12 +540,18 @@ static int transfer_restrict(wmg_ctx *c, int l, int prec, const void *fine, void
   prof_end(c, slot);
   return rc;
 }
+// on the fine level of the mixed cycle with FP16 products (per-rhs scales
+// from partial maxima in c->bpart) unless WMG_COARSE_B32
 static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, void *fine, int nrhs) {
   Level &L = c->lv[l];
   int pp = prec == P64 ? P64 : P16;
   const void *P = prec == P64 ? (const void *)L.P64 : (const void *)L.P16;
+  float *cpart = prec == P32 && L.fine && c->bpart && nrhs <= COARSE_H_MAXRHS && !(c->p.flags & WMG_COARSE_B32)
+                     ? c->bpart
+                     : nullptr;
   int slot = l == 0 ? prof_begin(c, K_PROLONG, transfer_bytes(L, prec, nrhs)) : -1;
-  int rc = prolong_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, coarse, fine, L.fine ? 1 : 0, nrhs, c->st, L.ns);
+  int rc = prolong_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, coarse, fine, L.fine ? 1 : 0, nrhs, c->st, L.ns,
+                      cpart);
   prof_end(c, slot);
   return rc;
 }

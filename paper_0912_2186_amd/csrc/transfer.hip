@@ -702,6 +702,146 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(BlockGeom bg, const __half2
   }
 }
 
+// The same prolongation with FP16 products (v_mfma_f32_16x16x16f16, FP32
+// accumulation) for NV a multiple of 8: the coarse values scaled per rhs by
+// a power of two (from the partial maxima cpart of their |re|, |im|, as for
+// the coarse stencil) and the P entries times their site scale, both rounded
+// to FP16; K is ordered as (alpha, re/im) pairs so that each lane's fragment
+// holds two alphas' pairs.
+template <int NV, int G>
+__global__ void __launch_bounds__(TB) k_prolong_mfma_h(BlockGeom bg, const __half2 *__restrict__ P,
+                                                      const float *__restrict__ Pscale, const float2 *__restrict__ coarse,
+                                                      float2 *__restrict__ fine, int nrhs,
+                                                      const float *__restrict__ cpart) {
+  static_assert(NV % 8 == 0, "fragments of four alphas' (re, im) pairs");
+  constexpr int NB = NV / 8;        // fragments of 16 k per K = 2 NV
+  constexpr int LDA = 2 * NV + 8;   // LDS row stride (halves) of the (re, im)-interleaved coarse values
+  constexpr int NW = TB / 64;       // waves
+  __shared__ _Float16 Ac[G == 4 ? NW : 1][32 * LDA];  // per aggregate: C of one chirality, scaled per rhs
+  __shared__ float bsh[32];                           // per-rhs scale
+  __shared__ int soff[256];
+  // G = 4: staged results [aggregate][rhs][element] (+1 pad)
+  __shared__ float2 Ob[G == 4 ? NW : 1][G == 4 ? 32 : 1][17];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, krow = lane >> 4;
+  // G = 4: wave w takes aggregate 4 g + w (x-adjacent); G = 1: one aggregate
+  // per workgroup, its element tiles spread over the waves
+  const long grp = xcd_tile(blockIdx.x, gridDim.x);
+  const long xh = G == 4 ? grp * 4 + w : grp;
+  const long ngrp = G == 4 ? bg.Vc / 4 : bg.Vc;
+  if (grp >= ngrp) return;
+  for (int k = threadIdx.x; k < bg.bs; k += TB) soff[k] = (int)(block_site(bg, 0, k) - block_site(bg, 0, 0));
+  const long origin = block_site(bg, xh, 0);
+  const int r0 = blockIdx.y * 32;
+  const int R = nrhs - r0 < 32 ? nrhs - r0 : 32;
+  if ((int)threadIdx.x < R) {
+    float m = 0.f;
+    for (int j = 0; j < COARSE_H_PART; j++) m = fmaxf(m, cpart[(size_t)(r0 + threadIdx.x) * COARSE_H_PART + j]);
+    int e = 0;
+    (void)frexpf(m, &e);
+    const int kx = 11 - e < -126 ? -126 : (11 - e > 126 ? 126 : 11 - e);
+    bsh[threadIdx.x] = m > 0.f ? ldexpf(1.f, kx) : 1.f;
+  }
+  const int NTr = (R + 15) / 16;
+  const int E = bg.bs * 12, H = E / bg.ns, nt_el = H / 16, nc = bg.ns * NV;
+  _Float16 *A = Ac[G == 4 ? w : 0];
+  for (int chi = 0; chi < bg.ns; chi++) {
+    __syncthreads();  // previous chirality's tiles done
+    if (G == 4) {
+      for (int i = lane; i < 32 * NV; i += 64) {
+        const int r = i / NV, a = i % NV;
+        float2 v = make_float2(0.f, 0.f);
+        if (r < R) v = coarse[((size_t)(r0 + r) * bg.Vc + xh) * nc + chi * NV + a];
+        const float bs = r < R ? bsh[r] : 0.f;
+        A[r * LDA + 2 * a] = (_Float16)(v.x * bs);
+        A[r * LDA + 2 * a + 1] = (_Float16)(v.y * bs);
+      }
+    } else {
+      for (int i = threadIdx.x; i < 32 * NV; i += TB) {
+        const int r = i / NV, a = i % NV;
+        float2 v = make_float2(0.f, 0.f);
+        if (r < R) v = coarse[((size_t)(r0 + r) * bg.Vc + xh) * nc + chi * NV + a];
+        const float bs = r < R ? bsh[r] : 0.f;
+        A[r * LDA + 2 * a] = (_Float16)(v.x * bs);
+        A[r * LDA + 2 * a + 1] = (_Float16)(v.y * bs);
+      }
+    }
+    __syncthreads();
+    for (int t = G == 4 ? 0 : w; t < nt_el; t += G == 4 ? 1 : NW) {
+      const int e0 = chi * H + t * 16;
+      const int c = e0 / bg.bs, k0 = e0 % bg.bs;  // 16 elements inside one component (bs % 16 == 0)
+      // k slot 16 b + 4 krow + u holds (alpha 8 b + 2 krow + u / 2, re if u
+      // even else im) in both operands: the lane's B fragments come from the
+      // P entries of two alphas of element e0 + col
+      half4 b1[NB], b2[NB];
+#pragma unroll
+      for (int bb = 0; bb < NB; bb++) {
+        float pr[2], pi[2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+          const int a = 8 * bb + 2 * krow + u;
+          const size_t pa = (size_t)a * bg.Vc + xh;
+          const float2 pv = __half22float2(P[pa * E + e0 + col]);
+          const float sc = Pscale[pa * bg.bs + k0 + col];
+          pr[u] = sc * pv.x;
+          pi[u] = sc * pv.y;
+        }
+        b1[bb] = half4{(_Float16)pr[0], (_Float16)(-pi[0]), (_Float16)pr[1], (_Float16)(-pi[1])};
+        b2[bb] = half4{(_Float16)pi[0], (_Float16)pr[0], (_Float16)pi[1], (_Float16)pr[1]};
+      }
+      floatx4 fr[2], fi[2];
+#pragma unroll
+      for (int m = 0; m < 2; m++) fr[m] = fi[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int m = 0; m < 2; m++) {
+        if (m >= NTr) break;
+        const _Float16 *ar = A + (m * 16 + col) * LDA + 4 * krow;
+#pragma unroll
+        for (int bb = 0; bb < NB; bb++) {
+          half4 a;
+          __builtin_memcpy(&a, ar + 16 * bb, 8);
+          fr[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b1[bb], fr[m], 0, 0, 0);
+          fi[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b2[bb], fi[m], 0, 0, 0);
+        }
+        // undo the rhs scale (rows 4 krow + v of the tile are rhs m 16 + 4 krow + v)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int r = m * 16 + 4 * krow + v;
+          const float inv = r < R ? 1.f / bsh[r] : 0.f;
+          fr[m][v] *= inv;
+          fi[m][v] *= inv;
+        }
+      }
+      if constexpr (G == 4) {
+        __syncthreads();  // the previous tile's results have been written out
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+          if (m >= NTr) break;
+#pragma unroll
+          for (int v = 0; v < 4; v++) Ob[w][m * 16 + 4 * krow + v][col] = make_float2(fr[m][v], fi[m][v]);
+        }
+        __syncthreads();
+        // rhs r, block row y (4), x-run of 16 sites over the 4 aggregates
+        const long origin0 = origin - (long)w * bg.b[0];
+        for (int i = threadIdx.x; i < R * 64; i += TB) {
+          const int r = i >> 6, yl = (i >> 4) & 3, xx = i & 15, wa = xx >> 2, el = (xx & 3) + 4 * yl;
+          fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + origin0 + (long)wa * bg.b[0] + soff[k0 + el]] = Ob[wa][r][el];
+        }
+      } else {
+        const long site = origin + soff[k0 + col];
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+          if (m >= NTr) break;
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            const int r = m * 16 + 4 * krow + v;
+            if (r < R) fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + site] = make_float2(fr[m][v], fi[m][v]);
+          }
+        }
+      }
+    }
+  }
+}
+
 template <int FINE, class TP, class TV>
 static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, const float *Ps, const void *in,
                            void *out, int nrhs, hipStream_t st) {
@@ -729,7 +869,7 @@ static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, 
 
 static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P,
                     const float *Ps, int vprec, const void *in, void *out, int fine_soa, int nrhs, hipStream_t st,
-                    int ns, const double *rn2 = nullptr, int rstride = 0) {
+                    int ns, const double *rn2 = nullptr, int rstride = 0, float *cpart = nullptr) {
   BlockGeom bg = make_bg(g, dof, b, ns);
   if (nv > 64) return set_error(-1, "transfer: nv=%d > 64", nv);
   if ((ns != 2 && ns != 4) || dof % ns || ns * nv > 128) return set_error(-1, "transfer: %d parts of %d, nv=%d", ns, dof, nv);
@@ -785,6 +925,23 @@ static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int
     // tile 128-byte lines
     const bool g4 = bg.b[0] == 4 && bg.Lc[0] % 4 == 0;
     dim3 grid((unsigned)xcd_grid(g4 ? bg.Vc / 4 : bg.Vc), (nrhs + 31) / 32);
+    if (cpart && nv % 8 == 0) {
+      const int rc = rhs_absmax((const float2 *)in, bg.Vc * (long)ns * nv, nrhs, cpart, st);
+      if (rc) return rc;
+#define PH_CASE(N)                                                                                           \
+  if (nv == N) {                                                                                            \
+    if (g4)                                                                                                 \
+      hipLaunchKernelGGL((k_prolong_mfma_h<N, 4>), grid, dim3(TB), 0, st, bg, (const __half2 *)P, Ps,       \
+                         (const float2 *)in, (float2 *)out, nrhs, (const float *)cpart);                    \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_prolong_mfma_h<N, 1>), grid, dim3(TB), 0, st, bg, (const __half2 *)P, Ps,       \
+                         (const float2 *)in, (float2 *)out, nrhs, (const float *)cpart);                    \
+    WMG_HIP(hipGetLastError());                                                                             \
+    return 0;                                                                                               \
+  }
+      PH_CASE(8) PH_CASE(16) PH_CASE(24) PH_CASE(32)
+#undef PH_CASE
+    }
 #define PM_CASE(N)                                                                                           \
   if (nv == N) {                                                                                            \
     if (g4)                                                                                                 \
@@ -818,8 +975,9 @@ int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const
 }
 
 int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
-               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st, int ns) {
-  return transfer(1, g, dof, b, nv, pprec, P, Pscale, vprec, coarse, fine, fine_soa, nrhs, st, ns);
+               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st, int ns,
+               float *cpart) {
+  return transfer(1, g, dof, b, nv, pprec, P, Pscale, vprec, coarse, fine, fine_soa, nrhs, st, ns, nullptr, 0, cpart);
 }
 
 // ------------------------------------------------------------ P precision

@@ -280,8 +280,11 @@ int block_orthonormalize(const Geom &g, int dof, const int b[4], int nv, const d
 int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
                 int vprec, const void *fine, int fine_soa, void *coarse, int nrhs, hipStream_t st, int ns = 2,
                 const double *rn2 = nullptr, int rstride = 0);
+// cpart != nullptr (COARSE_H_PART floats per rhs, nrhs <= COARSE_H_MAXRHS):
+// the fine-level matrix-core prolongation with FP16 products when Nv % 8 == 0
 int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
-               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st, int ns = 2);
+               int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st, int ns = 2,
+               float *cpart = nullptr);
 int P_convert(long count, const double2 *P64, int pprec, void *Pout, float *scale, int dof, hipStream_t st);
 int P_convert_half(long nsites_total, int bs, int dof, int fine, const double2 *P64, __half2 *Ph, float *scale,
                    hipStream_t st);
@@ -324,6 +327,9 @@ size_t coarse_mfma_halfs(long Vc, int n);
 // scale and one power-of-two scale per rhs, accumulated in FP32.
 constexpr int COARSE_H_PART = 32;
 constexpr int COARSE_H_MAXRHS = 64;
+// partial maxima of |re|, |im| of each rhs's vector (len complex per rhs):
+// COARSE_H_PART per rhs into part
+int rhs_absmax(const float2 *v, long len, int nrhs, float *part, hipStream_t st);
 int coarse_apply_mfma16(const Geom &gc, int n, const __half *Yh, const float *Ysc, const float2 *in, float2 *out,
                         int dagger, int nrhs, hipStream_t st, double *npart = nullptr, bool *fused = nullptr,
                         float *bpart = nullptr);
