@@ -261,8 +261,11 @@ int mg_coarse_apply_f32(wmg_ctx *ctx, int level, const double *in, double *out, 
  * in/out, nrhs <= 64. */
 int mg_apply_fine(wmg_ctx *ctx, int prec, const double *in, double *out, int nrhs);
 /* The mixed cycle's smoother residual kernel: out = r/|r| - D e per rhs,
- * r and e rounded to FP32, FP16 links, the result stored in FP16 and
- * returned as FP64 (canonical layouts, nrhs <= 64). */
+ * r rounded to FP32 and e to FP32 (or, in a mixed context with
+ * WMG_EO_SMOOTHER whose prolongation writes FP16, to FP16, the output in
+ * the two half-lattice arrays as the red/black smoother reads it), FP16
+ * links, the result stored in FP16 and returned as FP64 (canonical layouts,
+ * nrhs <= 64). */
 int mg_smoother_residual(wmg_ctx *ctx, const double *r, const double *e, double *out, int nrhs);
 /* One red/black hopping kernel of the smoother's Schur complement (Sec. 3,
  * red/black preconditioning): out = a diag + b H_par(hop) on the sites of

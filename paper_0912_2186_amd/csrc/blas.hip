@@ -493,6 +493,11 @@ template <class S> __global__ void k_zero(S *__restrict__ x, long n) {
 }
 
 int zero(int prec, void *x, long n, int nrhs, hipStream_t st) {
+  if (prec == P16) {
+    // n FP16 complex numbers per rhs are n / 2 FP32 complex numbers
+    if (n % 4) return set_error(-1, "zero: FP16 length %ld not a multiple of 4", n);
+    return zero(P32, x, n / 2, nrhs, st);
+  }
   TRY_PK(prec, n, "zero");
   dim3 g = ew_grid(n / (prec == P64 ? 1 : 2), nrhs);
   if (prec == P64) hipLaunchKernelGGL((k_zero<double2>), g, dim3(256), 0, st, (double2 *)x, n);

@@ -247,6 +247,16 @@ __device__ __forceinline__ void st4_nt(__half2 *p, const cx<float> o[4]) {
 }
 __device__ __forceinline__ void st4_nt(float2 *p, const cx<float> o[4]) { st4(p, o); }
 __device__ __forceinline__ void st4_nt(double2 *p, const cx<double> o[4]) { st4(p, o); }
+// p[0] = b[0] + lo, p[1] = b[1] + hi, b an FP16 full-lattice component
+__device__ __forceinline__ void set_pair_base(float2 *p, const __half2 *b, cx<float> lo, cx<float> hi) {
+  const uint2 w = *(const uint2 *)b;
+  __half2 h0, h1;
+  __builtin_memcpy(&h0, &w.x, 4);
+  __builtin_memcpy(&h1, &w.y, 4);
+  const float2 f0 = __half22float2(h0), f1 = __half22float2(h1);
+  *(float4 *)p = make_float4(f0.x + lo.re, f0.y + lo.im, f1.x + hi.re, f1.y + hi.im);
+}
+__device__ __forceinline__ void set_pair_base(double2 *, const __half2 *, cx<double>, cx<double>) {}
 // p[0] += lo, p[1] += hi (two adjacent sites of a full-lattice component)
 __device__ __forceinline__ void add_pair(float2 *p, cx<float> lo, cx<float> hi) {
   float4 v = *(float4 *)p;
@@ -265,11 +275,11 @@ __device__ __forceinline__ void add_pair(double2 *p, cx<double> lo, cx<double> h
 // fixed-order finalisation by k_dslash_red_finalize.
 // With EO, the output goes to the two half-lattice arrays out (even sites)
 // and out_odd (odd sites) in their [rhs][colour][Vhs][spin] layout instead.
-template <class TL, class TS, class TO, int RT, int RED, int NR, int EO = 0>
+template <class TL, class TS, class TO, int RT, int RED, int NR, int EO = 0, class TB = TS>
 __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, const TS *__restrict__ in,
                                                    TO *__restrict__ out, int L0, int L1, int L2, int L3, long V,
                                                    float diagf, double diagd, int nrhs, SweepMap sm, long Vs,
-                                                   const TS *__restrict__ bsub, const double *__restrict__ bnrm2,
+                                                   const TB *__restrict__ bsub, const double *__restrict__ bnrm2,
                                                    int bstride, double *__restrict__ red, int inner,
                                                    float2 *__restrict__ out32, TO *__restrict__ out_odd, long Vhs) {
   using R = typename store_traits<TS>::real;
@@ -471,7 +481,7 @@ __global__ void __launch_bounds__(256) k_dslash_red_finalize(const double *__res
                                                                    sh[threadIdx.x][2] + sh[threadIdx.x][3];
 }
 
-template <class TL, class TS, class TO = TS, int NR = 9>
+template <class TL, class TS, class TO = TS, int NR = 9, class TB = TS>
 static int launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, const void *bsub,
                       double *red, double *red_out, int red_stride, hipStream_t st, const double *bnrm2 = nullptr,
                       int bstride = 0, void *out32 = nullptr, void *out_odd = nullptr) {
@@ -507,33 +517,35 @@ static int launch_soa(const Geom &g, const void *U, double m, const void *in, vo
     SweepMap sm = make_sweep(g.L, bps, budget);
     dim3 grid = inner ? dim3((unsigned)(sm.nblocks * nrt)) : dim3((unsigned)sm.nblocks, nrt);
     if (red) {
-      hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1, NR>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
-                         (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                         (const TS *)bsub, bnrm2, bstride, red, inner, (float2 *)out32, (TO *)nullptr, Vhs);
+      hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1, NR, 0, TB>), grid, dim3(256), lds, st, (const TL *)U,
+                         (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
+                         nrhs, sm, g.Vs, (const TB *)bsub, bnrm2, bstride, red, inner, (float2 *)out32, (TO *)nullptr,
+                         Vhs);
       hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
                          red_stride);
     } else if (out_odd) {
-      // instantiated for the smoother's residual form only
-      if constexpr (std::is_same<TO, __half2>::value && std::is_same<TS, float2>::value)
-        hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR, 1>), grid, dim3(256), lds, st, (const TL *)U,
+      // instantiated for the smoother's residual forms only (FP32 or FP16
+      // input, FP32 bsub)
+      if constexpr (std::is_same<TO, __half2>::value && std::is_same<TB, float2>::value)
+        hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR, 1, TB>), grid, dim3(256), lds, st, (const TL *)U,
                            (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
-                           nrhs, sm, g.Vs, (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner,
+                           nrhs, sm, g.Vs, (const TB *)bsub, bnrm2, bstride, (double *)nullptr, inner,
                            (float2 *)out32, (TO *)out_odd, Vhs);
       else
         return set_error(-1, "wilson_soa: half-lattice output not instantiated for these precisions");
     } else {
-      hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR>), grid, dim3(256), lds, st, (const TL *)U, (const TS *)in,
-                         (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m, nrhs, sm, g.Vs,
-                         (const TS *)bsub, bnrm2, bstride, (double *)nullptr, inner, (float2 *)out32, (TO *)nullptr,
-                         Vhs);
+      hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR, 0, TB>), grid, dim3(256), lds, st, (const TL *)U,
+                         (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
+                         nrhs, sm, g.Vs, (const TB *)bsub, bnrm2, bstride, (double *)nullptr, inner, (float2 *)out32,
+                         (TO *)nullptr, Vhs);
     }
     WMG_HIP(hipGetLastError());
     return 0;
   };
   char key[256];
   std::snprintf(key, sizeof(key), "dslash/l%zu-s%zu-o%zu-nr%d-red%d-b%d-f%d-eo%d/%dx%dx%dx%d/rhs%d", sizeof(TL),
-                sizeof(TS), sizeof(TO), NR, red ? 1 : 0, bsub ? 1 : 0, out32 ? 1 : 0, out_odd ? 1 : 0, g.L[0], g.L[1],
-                g.L[2], g.L[3], nrhs);
+                sizeof(TS), sizeof(TO), NR, red ? 1 : 0, bsub ? (int)sizeof(TB) : 0, out32 ? 1 : 0, out_odd ? 1 : 0,
+                g.L[0], g.L[1], g.L[2], g.L[3], nrhs);
   int choice = 0;
   return tune_choice(key, ncand, run, st, &choice);
 }
@@ -580,7 +592,12 @@ int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const vo
                                                          bnrm2, bstride, nullptr, out_odd)
                : launch_soa<__half2, float2, __half2, 9>(g, U16, m, in, out, nrhs, bsub, red, red_out, red_stride, st,
                                                          bnrm2, bstride, nullptr, out_odd);
-  if (out_odd) return set_error(-1, "wilson_soa_h16: half-lattice output only with FP32 input");
+  if (iprec == P16 && bsub && out_odd)
+    return c12 ? launch_soa<__half2, __half2, __half2, 6, float2>(g, U16, m, in, out, nrhs, bsub, red, red_out,
+                                                                  red_stride, st, bnrm2, bstride, nullptr, out_odd)
+               : launch_soa<__half2, __half2, __half2, 9, float2>(g, U16, m, in, out, nrhs, bsub, red, red_out,
+                                                                  red_stride, st, bnrm2, bstride, nullptr, out_odd);
+  if (out_odd) return set_error(-1, "wilson_soa_h16: half-lattice output only with FP32 bsub");
   if (iprec == P16 && !bsub)
     return c12 ? launch_soa<__half2, __half2, __half2, 6>(g, U16, m, in, out, nrhs, nullptr, red, red_out, red_stride,
                                                           st)
@@ -704,7 +721,7 @@ template <class TD, class TH, class TO, int RT, int RED, int ADD, class R>
 __device__ __forceinline__ void eo_store(const EoGeom &g, const EoTiles &tl, const EoSite &st, int nrhs,
                                          const TD *__restrict__ in_diag, const TH *__restrict__ in_hop,
                                          TO *__restrict__ out, double ad, R a, R b, cx<R> (&acc)[RT][12],
-                                         double (&rs)[RT][3]) {
+                                         double (&rs)[RT][3], const __half2 *__restrict__ ebase = nullptr) {
   const int Vs = (int)g.Vhs;
   // a thread's reduction terms summed in the arithmetic's precision (12
   // products per rhs), then added to the FP64 block sums
@@ -733,8 +750,9 @@ __device__ __forceinline__ void eo_store(const EoGeom &g, const EoTiles &tl, con
         const int own = st.x[0] & 1;
 #pragma unroll
         for (int sp = 0; sp < 4; sp++) {
-          TO *pp = out + ((size_t)(st.r0 + t) * 12 + sp * 3 + c) * g.Vsf + 2 * (size_t)(unsigned)st.h;
-          add_pair(pp, own ? hv[sp] : o[sp], own ? o[sp] : hv[sp]);
+          const size_t fi = ((size_t)(st.r0 + t) * 12 + sp * 3 + c) * g.Vsf + 2 * (size_t)(unsigned)st.h;
+          if constexpr (ADD == 2) set_pair_base(out + fi, ebase + fi, own ? hv[sp] : o[sp], own ? o[sp] : hv[sp]);
+          else add_pair(out + fi, own ? hv[sp] : o[sp], own ? o[sp] : hv[sp]);
         }
       } else if (tl.nt) {
         st4_nt(out + i, o);
@@ -789,14 +807,15 @@ __device__ __forceinline__ void eo_reduce(const EoTiles &tl, const EoSite &st, i
 // rhs into red (as stored).  With ADD, out is instead a full-lattice field
 // [rhs][12][Vsf] that receives the result at the site of parity par and
 // in_hop's value at the other site of the same x pair (same compact index):
-// the last step of the red/black smoother, e += (d_e, d_o), without a
-// separate pass.  Site indices are 32-bit (a parity holds fewer than 2^29
-// sites).
+// the last step of the red/black smoother, e += (d_e, d_o) (ADD = 1), or
+// out = ebase + (d_e, d_o) with ebase an FP16 full-lattice field (ADD = 2),
+// without a separate pass.  Site indices are 32-bit (a parity holds fewer
+// than 2^29 sites).
 template <class TL, class TD, class TH, class TO, int RT, int RED, int NR, int ADD = 0>
 __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const TD *__restrict__ in_diag,
                                                const TH *__restrict__ in_hop, TO *__restrict__ out, EoGeom g, int par,
                                                double ad, double bd, int nrhs, EoTiles tl, double *__restrict__ red,
-                                               float one) {
+                                               float one, const __half2 *__restrict__ ebase) {
   using R = typename store_traits<TO>::real;
   const EoSite st = eo_site(g, tl, par, nrhs, RT);
   const int r0 = st.r0;
@@ -856,7 +875,7 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
     EO_DIR(2)
     EO_DIR(3)
 #undef EO_DIR
-    eo_store<TD, TH, TO, RT, RED, ADD, R>(g, tl, st, nrhs, in_diag, in_hop, out, ad, (R)ad, (R)bd, acc, rs);
+    eo_store<TD, TH, TO, RT, RED, ADD, R>(g, tl, st, nrhs, in_diag, in_hop, out, ad, (R)ad, (R)bd, acc, rs, ebase);
   }
   if (RED) eo_reduce<RT>(tl, st, nrhs, rs, red);
 }
@@ -1081,7 +1100,7 @@ long eo_red_tiles(const Geom &g) {
 template <class TL, class TD, class TH, class TO, int RT, int NR, int ADD = 0>
 static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, double b, const void *in_diag,
                          const void *in_hop, void *out, int nrhs, double *red, double *red_out, int red_stride,
-                         hipStream_t st) {
+                         hipStream_t st, const void *ebase = nullptr) {
   EoGeom e = make_eo(g);
   const int nrt = (nrhs + RT - 1) / RT;
   int zb[20], grp[20], nt[20];
@@ -1104,11 +1123,12 @@ static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, doubl
                            (double *)nullptr, 1.0f);
     } else if (red) {
       hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 1, NR>), grid, dim3(256), 0, st, (const TL *)Ue,
-                         (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl, red, 1.0f);
+                         (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl, red, 1.0f,
+                         (const __half2 *)nullptr);
     } else {
       hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 0, NR, ADD>), grid, dim3(256), 0, st, (const TL *)Ue,
                          (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl,
-                         (double *)nullptr, 1.0f);
+                         (double *)nullptr, 1.0f, (const __half2 *)ebase);
     }
     if (red)
       hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)tl.ntile, red_out,
@@ -1145,7 +1165,7 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
 }
 
 int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int pdiag, const void *in_diag,
-               int phop, const void *de, void *full, int nrhs, hipStream_t st) {
+               int phop, const void *de, void *full, int nrhs, hipStream_t st, const void *ebase) {
   const bool c12 = (lprec & LK12) != 0;
   const int lp = lprec & ~LK12;
   if (g.L[0] % 2 || g.V / 2 >= (1L << 29)) return set_error(-1, "hop_eo_add: lattice not supported");
@@ -1155,6 +1175,11 @@ int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int
              : launch_hop_eo<TL, TD, TH, TO, RT, 9, 1>(g, Ue, 1, a, b, in_diag, de, full, nrhs, nullptr, nullptr, 0, st)
   if (lp == P64 && pdiag == P64 && phop == P64) HOPA(double2, double2, double2, double2, 1);
   if (lp == P16 && pdiag == P16 && phop == P32) HOPA(__half2, __half2, float2, float2, 2);
+  if (lp == P16 && pdiag == P16 && phop == P16 && ebase)
+    return c12 ? launch_hop_eo<__half2, __half2, __half2, float2, 2, 6, 2>(g, Ue, 1, a, b, in_diag, de, full, nrhs,
+                                                                          nullptr, nullptr, 0, st, ebase)
+               : launch_hop_eo<__half2, __half2, __half2, float2, 2, 9, 2>(g, Ue, 1, a, b, in_diag, de, full, nrhs,
+                                                                          nullptr, nullptr, 0, st, ebase);
   if (lp == P16 && pdiag == P16 && phop == P16) HOPA(__half2, __half2, __half2, float2, 2);
 #undef HOPA
   return set_error(-1, "hop_eo_add: unsupported precisions link %d diag %d field %d", lp, pdiag, phop);

@@ -242,7 +242,9 @@ using namespace wmg;
 // ------------------------------------------------------------ context
 enum { VR, VE, VT, VE2, VS, VQ, VCR, VCS, VCP, VCU, VX, VS1, VS2, VS3,
        // red/black smoother: sublattice residuals, MR iterates, corrections
-       VH0, VH1, VH2, VH3, VHQ, VHT, VHSE, VHSO, VHDE, VHDO, NVW };
+       VH0, VH1, VH2, VH3, VHQ, VHT, VHSE, VHSO, VHDE, VHDO,
+       VEH,  // FP16 copy of the prolonged correction (red/black smoother of the mixed cycle)
+       NVW };
 
 struct Level {
   Geom g;
@@ -542,7 +544,9 @@ static int transfer_restrict(wmg_ctx *c, int l, int prec, const void *fine, void
 }
 // on the fine level of the mixed cycle with FP16 products (per-rhs scales
 // from partial maxima in c->bpart) unless WMG_COARSE_B32
-static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, void *fine, int nrhs) {
+static bool prolong16_ok(wmg_ctx *c, int l, int nrhs);
+static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, void *fine, int nrhs,
+                            bool out16 = false) {
   Level &L = c->lv[l];
   int pp = prec == P64 ? P64 : P16;
   const void *P = prec == P64 ? (const void *)L.P64 : (const void *)L.P16;
@@ -550,10 +554,19 @@ static int transfer_prolong(wmg_ctx *c, int l, int prec, const void *coarse, voi
                      ? c->bpart
                      : nullptr;
   int slot = l == 0 ? prof_begin(c, K_PROLONG, transfer_bytes(L, prec, nrhs)) : -1;
+  if (out16 && !(cpart && prolong16_ok(c, l, nrhs))) return set_error(-1, "prolong: no FP16 output here");
   int rc = prolong_op(L.g, L.dof, L.b, L.nv, pp, P, L.Ps, prec, coarse, fine, L.fine ? 1 : 0, nrhs, c->st, L.ns,
-                      cpart);
+                      cpart, out16);
   prof_end(c, slot);
   return rc;
+}
+
+// the fine-level prolongation of the mixed cycle can write FP16 (FP16
+// products enabled, Nv a multiple of 8, the blocking of the MFMA kernel)
+static bool prolong16_ok(wmg_ctx *c, int l, int nrhs) {
+  Level &L = c->lv[l];
+  return l == 0 && L.fine && c->bpart && nrhs <= COARSE_H_MAXRHS && !(c->p.flags & WMG_COARSE_B32) &&
+         prolong_h_supported(L.g, L.dof, L.b, L.nv, P16, P32, 1, L.ns);
 }
 
 // fine operator with the smoother's fusions: out = [bsub -] D in, and with
@@ -638,7 +651,11 @@ static int eo_links(wmg_ctx *c, int lp, const void **Ue) {
 
 // prec P64: all in FP64.  prec P16: r FP32 used as r/|r| (|r|^2 in rn2),
 // sublattice vectors, MR iterates and the even correction d_e FP16, e FP32.
-static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, void *e, int nsteps, int nrhs) {
+// e16 (prec P16 only): the prolonged correction in FP16 as the residual's
+// input and the base of the last step, which then writes e = e16 + d
+// without reading e.
+static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, void *e, int nsteps, int nrhs,
+                        const void *e16 = nullptr) {
   Level &L = c->lv[0];
   const int lp = sp == P64 ? P64 : P16;   // link precision
   const int vp = sp == P64 ? P64 : P16;   // sublattice residuals and MR iterates
@@ -679,9 +696,9 @@ static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, vo
     TRY(fine_apply_fused(c, P64, e, s, nrhs, r, false));
   } else {
     // written straight into the two half-lattice arrays
-    slot = prof_begin(c, K_DSLASH_RES, vb + (double)L.g.V * 12 * (8 + 8 + 4) * nrhs);
-    int rc = wilson_soa_h16(L.g, fine_links(L, P16), P32, L.m, e, se, nrhs, r, rn2, 4, nullptr, nullptr, 0, c->st,
-                            L.lk, so);
+    slot = prof_begin(c, K_DSLASH_RES, vb + (double)L.g.V * 12 * ((e16 ? 4 : 8) + 8 + 4) * nrhs);
+    int rc = wilson_soa_h16(L.g, fine_links(L, P16), e16 ? P16 : P32, L.m, e16 ? e16 : e, se, nrhs, r, rn2, 4,
+                            nullptr, nullptr, 0, c->st, L.lk, so);
     prof_end(c, slot);
     TRY(rc);
   }
@@ -715,9 +732,11 @@ static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, vo
                        (__half2 *)de, nh);
   WMG_HIP(hipGetLastError());
   // d_o = (s_o + H_o(d_e) / 2) / (4+m) and e += (d_e, d_o) in one kernel
-  // (bytes: links, s_o, d_e, and e read and written)
-  const int slot2 = prof_begin(c, sp == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE, vb + hs * (eb + db + 4 * fb));
-  const int rc2 = hop_eo_add(L.g, lc, Ue, 1.0 / m4, 0.5 / m4, vp, so, dp, de, e, nrhs, c->st);
+  // (bytes: links, s_o, d_e, and e read and written; with e16 the FP16 base
+  // read and e written)
+  const int slot2 = prof_begin(c, sp == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE,
+                               vb + hs * (eb + db + (e16 ? 2 * 4 + 2 * fb : 4 * fb)));
+  const int rc2 = hop_eo_add(L.g, lc, Ue, 1.0 / m4, 0.5 / m4, vp, so, dp, de, e, nrhs, c->st, e16);
   prof_end(c, slot2);
   return rc2;
 }
@@ -955,6 +974,14 @@ static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int n
       TRY(mg_cycle_l(c, l + 1, prec, t, e2, nrhs));
       TRY(axpby(prec, 1.0, e2, 1.0, ec, C.n, nrhs, c->st));  // ec += e2
     }
+  }
+  if (h16 && (c->p.flags & WMG_EO_SMOOTHER) && prolong16_ok(c, l, nrhs)) {
+    // the red/black smoother reads the prolonged correction in FP16 and
+    // writes e = P ec + d
+    void *eh;
+    TRY(level_vec(c, 0, P16, VEH, &eh, nrhs));
+    TRY(transfer_prolong(c, l, prec, ec, eh, nrhs, true));
+    return mr_smooth_eo(c, P16, r, c->cyc_nrm, e, c->p.post_smooth, nrhs, eh);
   }
   TRY(transfer_prolong(c, l, prec, ec, e, nrhs));
   if (h16 && (c->p.flags & WMG_EO_SMOOTHER)) return mr_smooth_eo(c, P16, r, c->cyc_nrm, e, c->p.post_smooth, nrhs);
@@ -2021,8 +2048,12 @@ int mg_hop_eo(wmg_ctx *c, int prec, int par, double a, double b, const double *d
   TRY(level_vec(c, 0, pf, VT, &full, nrhs));
   TRY(zero(pf, full, F.n, nrhs, c->st));
   if (prec == 5) {
-    // the smoother's last step: full += (hop at the even sites, the odd result)
-    TRY(hop_eo_add(F.g, lp | F.lk, Ue, a, b, pd, a != 0.0 ? dod : nullptr, ph, he, full, nrhs, c->st));
+    // the smoother's last step as the mixed cycle runs it: full = base +
+    // (hop at the even sites, the odd result), here with a zero FP16 base
+    void *base;
+    TRY(level_vec(c, 0, P16, VEH, &base, nrhs));
+    TRY(zero(P16, base, F.n, nrhs, c->st));
+    TRY(hop_eo_add(F.g, lp | F.lk, Ue, a, b, pd, a != 0.0 ? dod : nullptr, ph, he, full, nrhs, c->st, base));
   } else {
     TRY(hop_eo(F.g, lp | F.lk, Ue, par, a, b, pd, a != 0.0 ? (par ? dod : de) : nullptr, ph, par ? he : ho, ph, o,
                nrhs, nullptr, nullptr, 0, c->st));
@@ -2059,8 +2090,28 @@ int mg_smoother_residual(wmg_ctx *c, const double *r, const double *e, double *o
   TRY(copy(P32, e32, P64, a64, F.n, nrhs, c->st));
   double *rn2 = c->cyc_nrm;
   TRY(norm2(c->red, P32, r32, F.n, nrhs, rn2, 4, c->st));
-  TRY(wilson_soa_h16(F.g, fine_links(F, P16), P32, F.m, e32, h0, nrhs, r32, rn2, 4, nullptr, nullptr, 0, c->st, F.lk));
-  TRY(copy(P32, b32, P16, h0, F.n, nrhs, c->st));
+  if ((c->p.flags & WMG_EO_SMOOTHER) && prolong16_ok(c, 0, nrhs)) {
+    // the red/black smoother's form: e in FP16, the result in the two
+    // half-lattice arrays
+    void *eh, *se, *so, *se32, *so32;
+    TRY(level_vec(c, 0, P16, VEH, &eh, nrhs));
+    TRY(level_vec(c, 0, P16, VHSE, &se, nrhs));
+    TRY(level_vec(c, 0, P16, VHSO, &so, nrhs));
+    TRY(level_vec(c, 0, P32, VHSE, &se32, nrhs));
+    TRY(level_vec(c, 0, P32, VHSO, &so32, nrhs));
+    const long nh = 12 * eo_stride(F.g);
+    TRY(copy(P16, eh, P32, e32, F.n, nrhs, c->st));
+    TRY(wilson_soa_h16(F.g, fine_links(F, P16), P16, F.m, eh, se, nrhs, r32, rn2, 4, nullptr, nullptr, 0, c->st,
+                       F.lk, so));
+    TRY(copy(P32, se32, P16, se, nh, nrhs, c->st));
+    TRY(copy(P32, so32, P16, so, nh, nrhs, c->st));
+    TRY(zero(P32, b32, F.n, nrhs, c->st));
+    TRY(eo_unpack_add(F.g, P32, b32, P32, se32, so32, nrhs, c->st));
+  } else {
+    TRY(wilson_soa_h16(F.g, fine_links(F, P16), P32, F.m, e32, h0, nrhs, r32, rn2, 4, nullptr, nullptr, 0, c->st,
+                       F.lk));
+    TRY(copy(P32, b32, P16, h0, F.n, nrhs, c->st));
+  }
   TRY(copy(P64, a64, P32, b32, F.n, nrhs, c->st));
   TRY(spinor_from_soa(F.g, (double2 *)a64, out, nrhs, c->st));
   return sync(c);

@@ -707,11 +707,15 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(BlockGeom bg, const __half2
 // a power of two (from the partial maxima cpart of their |re|, |im|, as for
 // the coarse stencil) and the P entries times their site scale, both rounded
 // to FP16; K is ordered as (alpha, re/im) pairs so that each lane's fragment
-// holds two alphas' pairs.
-template <int NV, int G>
+// holds two alphas' pairs.  The fine field is written in FP32 or, for the
+// red/black smoother's residual and last step, in FP16.
+// output of the FP16-product prolongation: FP32 or FP16 fine fields
+__device__ __forceinline__ void st_fine(float2 *p, float2 v) { *p = v; }
+__device__ __forceinline__ void st_fine(__half2 *p, float2 v) { *p = __floats2half2_rn(v.x, v.y); }
+template <int NV, int G, class TOUT>
 __global__ void __launch_bounds__(TB) k_prolong_mfma_h(BlockGeom bg, const __half2 *__restrict__ P,
                                                       const float *__restrict__ Pscale, const float2 *__restrict__ coarse,
-                                                      float2 *__restrict__ fine, int nrhs,
+                                                      TOUT *__restrict__ fine, int nrhs,
                                                       const float *__restrict__ cpart) {
   static_assert(NV % 8 == 0, "fragments of four alphas' (re, im) pairs");
   constexpr int NB = NV / 8;        // fragments of 16 k per K = 2 NV
@@ -824,7 +828,8 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma_h(BlockGeom bg, const __hal
         const long origin0 = origin - (long)w * bg.b[0];
         for (int i = threadIdx.x; i < R * 64; i += TB) {
           const int r = i >> 6, yl = (i >> 4) & 3, xx = i & 15, wa = xx >> 2, el = (xx & 3) + 4 * yl;
-          fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + origin0 + (long)wa * bg.b[0] + soff[k0 + el]] = Ob[wa][r][el];
+          st_fine(fine + ((size_t)(r0 + r) * 12 + c) * bg.Vs + origin0 + (long)wa * bg.b[0] + soff[k0 + el],
+                  Ob[wa][r][el]);
         }
       } else {
         const long site = origin + soff[k0 + col];
@@ -834,7 +839,7 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma_h(BlockGeom bg, const __hal
 #pragma unroll
           for (int v = 0; v < 4; v++) {
             const int r = m * 16 + 4 * krow + v;
-            if (r < R) fine[((size_t)(r0 + r) * 12 + c) * bg.Vs + site] = make_float2(fr[m][v], fi[m][v]);
+            if (r < R) st_fine(fine + ((size_t)(r0 + r) * 12 + c) * bg.Vs + site, make_float2(fr[m][v], fi[m][v]));
           }
         }
       }
@@ -869,7 +874,8 @@ static int launch_transfer(int dir, const BlockGeom &bg, int nv, const void *P, 
 
 static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P,
                     const float *Ps, int vprec, const void *in, void *out, int fine_soa, int nrhs, hipStream_t st,
-                    int ns, const double *rn2 = nullptr, int rstride = 0, float *cpart = nullptr) {
+                    int ns, const double *rn2 = nullptr, int rstride = 0, float *cpart = nullptr,
+                    bool out16 = false) {
   BlockGeom bg = make_bg(g, dof, b, ns);
   if (nv > 64) return set_error(-1, "transfer: nv=%d > 64", nv);
   if ((ns != 2 && ns != 4) || dof % ns || ns * nv > 128) return set_error(-1, "transfer: %d parts of %d, nv=%d", ns, dof, nv);
@@ -928,20 +934,25 @@ static int transfer(int dir, const Geom &g, int dof, const int b[4], int nv, int
     if (cpart && nv % 8 == 0) {
       const int rc = rhs_absmax((const float2 *)in, bg.Vc * (long)ns * nv, nrhs, cpart, st);
       if (rc) return rc;
-#define PH_CASE(N)                                                                                           \
+#define PH_CASE(N, TO)                                                                                       \
   if (nv == N) {                                                                                            \
     if (g4)                                                                                                 \
-      hipLaunchKernelGGL((k_prolong_mfma_h<N, 4>), grid, dim3(TB), 0, st, bg, (const __half2 *)P, Ps,       \
-                         (const float2 *)in, (float2 *)out, nrhs, (const float *)cpart);                    \
+      hipLaunchKernelGGL((k_prolong_mfma_h<N, 4, TO>), grid, dim3(TB), 0, st, bg, (const __half2 *)P, Ps,   \
+                         (const float2 *)in, (TO *)out, nrhs, (const float *)cpart);                        \
     else                                                                                                    \
-      hipLaunchKernelGGL((k_prolong_mfma_h<N, 1>), grid, dim3(TB), 0, st, bg, (const __half2 *)P, Ps,       \
-                         (const float2 *)in, (float2 *)out, nrhs, (const float *)cpart);                    \
+      hipLaunchKernelGGL((k_prolong_mfma_h<N, 1, TO>), grid, dim3(TB), 0, st, bg, (const __half2 *)P, Ps,   \
+                         (const float2 *)in, (TO *)out, nrhs, (const float *)cpart);                        \
     WMG_HIP(hipGetLastError());                                                                             \
     return 0;                                                                                               \
   }
-      PH_CASE(8) PH_CASE(16) PH_CASE(24) PH_CASE(32)
+      if (out16) {
+        PH_CASE(8, __half2) PH_CASE(16, __half2) PH_CASE(24, __half2) PH_CASE(32, __half2)
+      } else {
+        PH_CASE(8, float2) PH_CASE(16, float2) PH_CASE(24, float2) PH_CASE(32, float2)
+      }
 #undef PH_CASE
     }
+    if (out16) return set_error(-1, "prolong: FP16 output only with FP16 products (Nv a multiple of 8)");
 #define PM_CASE(N)                                                                                           \
   if (nv == N) {                                                                                            \
     if (g4)                                                                                                 \
@@ -976,8 +987,17 @@ int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const
 
 int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
                int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st, int ns,
-               float *cpart) {
-  return transfer(1, g, dof, b, nv, pprec, P, Pscale, vprec, coarse, fine, fine_soa, nrhs, st, ns, nullptr, 0, cpart);
+               float *cpart, bool out16) {
+  if (out16 && !prolong_h_supported(g, dof, b, nv, pprec, vprec, fine_soa, ns))
+    return set_error(-1, "prolong: FP16 output not supported for this blocking");
+  return transfer(1, g, dof, b, nv, pprec, P, Pscale, vprec, coarse, fine, fine_soa, nrhs, st, ns, nullptr, 0, cpart,
+                  out16);
+}
+
+bool prolong_h_supported(const Geom &g, int dof, const int b[4], int nv, int pprec, int vprec, int fine_soa, int ns) {
+  BlockGeom bg = make_bg(g, dof, b, ns);
+  return fine_soa && pprec == P16 && vprec == P32 && nv % 8 == 0 && nv <= 32 && bg.bs % 16 == 0 && bg.bs <= 256 &&
+         (ns == 2 || ns == 4) && dof % ns == 0;
 }
 
 // ------------------------------------------------------------ P precision

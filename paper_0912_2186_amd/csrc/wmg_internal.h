@@ -166,13 +166,13 @@ int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double 
                      const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st,
                      void *out32 = nullptr);
 // Smoother variant with FP16 links and FP16 output storage: in is FP32
-// (iprec P32) or FP16 (P16); out (FP16) = [b/|b| -] D in, where bsub (FP32,
-// only with iprec P32) is scaled per rhs by 1/sqrt(bnrm2[rhs * bstride])
-// (0 where that norm is 0); red as in wilson_soa_fused, computed from the
-// stored (rounded) output.
-// lflags: LK12 for links stored as two rows.  With out_odd (FP32 input, no
+// (iprec P32) or FP16 (P16); out (FP16) = [b/|b| -] D in, where bsub (FP32)
+// is scaled per rhs by 1/sqrt(bnrm2[rhs * bstride]) (0 where that norm is
+// 0); red as in wilson_soa_fused, computed from the stored (rounded) output.
+// lflags: LK12 for links stored as two rows.  With out_odd (bsub given, no
 // reductions) the output goes to the half-lattice arrays out (even sites)
-// and out_odd (odd sites) instead of a full-lattice field.
+// and out_odd (odd sites) instead of a full-lattice field.  FP16 input with
+// bsub only with out_odd.
 int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
                    const void *bsub, const double *bnrm2, int bstride, double *red, double *red_out, int red_stride,
                    hipStream_t st, int lflags = 0, void *out_odd = nullptr);
@@ -196,9 +196,10 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
 // full (full-lattice, precision phop) += d_e at the even sites and
 // a in_diag + b H_odd(d_e) at the odd sites, d_e the even half-lattice field
 // (precision phop): all FP64, or FP16 links and in_diag with FP32 or FP16
-// d_e and FP32 full.
+// d_e and FP32 full.  With ebase (FP16 d_e only: an FP16 full-lattice field)
+// full = ebase + (d_e, d_o) instead, full not read.
 int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int pdiag, const void *in_diag,
-               int phop, const void *de, void *full, int nrhs, hipStream_t st);
+               int phop, const void *de, void *full, int nrhs, hipStream_t st, const void *ebase = nullptr);
 int eo_pack(const Geom &g, int pfull, const void *full, int phalf, void *ev, void *od, int nrhs, hipStream_t st);
 int eo_unpack_add(const Geom &g, int pfull, void *full, int phalf, const void *ev, const void *od, int nrhs,
                   hipStream_t st);
@@ -282,9 +283,11 @@ int restrict_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const
                 const double *rn2 = nullptr, int rstride = 0);
 // cpart != nullptr (COARSE_H_PART floats per rhs, nrhs <= COARSE_H_MAXRHS):
 // the fine-level matrix-core prolongation with FP16 products when Nv % 8 == 0
+// out16: the fine field in FP16 (FP16 products only; prolong_h_supported)
 int prolong_op(const Geom &g, int dof, const int b[4], int nv, int pprec, const void *P, const float *Pscale,
                int vprec, const void *coarse, void *fine, int fine_soa, int nrhs, hipStream_t st, int ns = 2,
-               float *cpart = nullptr);
+               float *cpart = nullptr, bool out16 = false);
+bool prolong_h_supported(const Geom &g, int dof, const int b[4], int nv, int pprec, int vprec, int fine_soa, int ns);
 int P_convert(long count, const double2 *P64, int pprec, void *Pout, float *scale, int dof, hipStream_t st);
 int P_convert_half(long nsites_total, int bs, int dof, int fine, const double2 *P64, __half2 *Ph, float *scale,
                    hipStream_t st);

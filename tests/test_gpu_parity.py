@@ -163,18 +163,27 @@ def test_fp16_spinor_mr_step_operator(wmg):
         mg.close()
 
 
-def test_fp16_smoother_residual_kernel(wmg):
+@pytest.mark.parametrize("red_black", [False, True])
+def test_fp16_smoother_residual_kernel(wmg, red_black):
     """The smoother's fused residual kernel out = r/|r| - D e (FP16 links,
     FP16 output) against the oracle, Gaussian and point-source r, per-site
-    bound against the neighbourhood scale of e and r/|r|."""
+    bound against the neighbourhood scale of e and r/|r|: e in FP32 into a
+    full-lattice output, and (red/black smoother of the mixed cycle) e in
+    FP16 into the two half-lattice arrays."""
     L = (8, 8, 8, 12)
     V = vol(L)
     m = -0.2
     U = inputs.gauge_field(L, 0.5, 301)
     r = np.stack([inputs.gaussian_rhs(L, 208)[0], inputs.point_sources(L)[7]])
     e = 1e-3 * np.stack([inputs.gaussian_rhs(L, 209)[0], _decaying_source(L, 0, 1.0, 210)])
-    p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=2)
-    mg = wmg.MG(L, dev(U), m, 4, (4, 4, 4, 4), p)
+    if red_black:
+        e = e.real.astype(np.float16).astype(np.float64) + 1j * e.imag.astype(np.float16).astype(np.float64)
+        p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=2, precision=wmg.WMG_MIXED,
+                               flags=wmg.WMG_EO_SMOOTHER)
+        mg = wmg.MG(L, dev(U), m, 8, (4, 4, 4, 4), p)
+    else:
+        p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=2)
+        mg = wmg.MG(L, dev(U), m, 4, (4, 4, 4, 4), p)
     out = empty((2, V, 12))
     mg.mg_smoother_residual(dev(r), dev(e), out, 2)
     oh = host(out)
