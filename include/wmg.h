@@ -75,6 +75,10 @@ extern "C" {
                              power-of-two scale per rhs, FP16 products, FP32 accumulation;
                              stencil for 32, 48 or 64 coarse dof, prolongation for Nv a
                              multiple of 8, <= 64 rhs) */
+#define WMG_Z32 128        /* flags: the mixed solve stores the cycle's output z in FP32 (default
+                             with WMG_EO_SMOOTHER, FP16 prolongation and <= 64 rhs: FP16, the
+                             flexible GCR taking any preconditioner output; A z and the
+                             solution update read the same FP16 values) */
 #define WMG_SPIN_SPLIT 32 /* flags: the fine level's blocking splits each null vector into its
                              four Dirac spins instead of its two chiralities (Sec. 3, exposing
                              the full spin structure on the coarse blocks): 4 Nv coarse dof per
@@ -257,8 +261,10 @@ int mg_coarse_apply_f32(wmg_ctx *ctx, int level, const double *in, double *out, 
 /* Fine operator through the internal kernels: prec 0 FP64, 1 FP32 links and
  * spinors, 2 FP16 links with FP32 spinors, 3 the smoother's MR-step form
  * (in/|in| per rhs stored in FP16 by the smoother's residual kernel, FP16
- * links on FP16 spinors, FP16 output, returned times |in|); canonical FP64
- * in/out, nrhs <= 64. */
+ * links on FP16 spinors, FP16 output, returned times |in|), 4 the inner
+ * GCR's operator on the FP16-stored preconditioner output (in rounded to
+ * FP16, FP32 links and arithmetic, FP32 output); canonical FP64 in/out,
+ * nrhs <= 64. */
 int mg_apply_fine(wmg_ctx *ctx, int prec, const double *in, double *out, int nrhs);
 /* The mixed cycle's smoother residual kernel: out = r/|r| - D e per rhs,
  * r rounded to FP32 and e to FP32 (or, in a mixed context with
@@ -278,8 +284,8 @@ int mg_smoother_residual(wmg_ctx *ctx, const double *r, const double *e, double 
  * the eight directions summed in FP32); 4: FP16 links and diag, FP32 hop
  * input and output (the odd correction); 5: FP16 links, diag and hop input
  * with FP32 output, the smoother's fused last step (par must be 1), which
- * also returns hop's values at the even sites.  Needs every extent even;
- * nrhs <= 64. */
+ * also returns hop's values at the even sites; 6: as 5 with the output
+ * stored in FP16.  Needs every extent even; nrhs <= 64. */
 int mg_hop_eo(wmg_ctx *ctx, int prec, int par, double a, double b, const double *diag, const double *hop,
               double *out, int nrhs);
 /* One application of the FP64 preconditioner z = M r (one MG cycle). */

@@ -596,6 +596,15 @@ int multi_caxpy(int py, void *y, int px, const void *const *xs_dev, int k, const
                 int accumulate, long n, int nrhs, hipStream_t st) {
   if (k < 0 || k > 16) return set_error(-1, "multi_caxpy k=%d", k);
   if (k == 0 && accumulate) return 0;
+  if (py == P64 && px == P16) {
+    // FP16 x_j (the mixed solve's preconditioner outputs), four per lane
+    if (int e_ = check_packs<__half2>(n, "multi_caxpy")) return e_;
+    dim3 g = ew_grid(n / 4, nrhs);
+    KT_SWITCH(k, hipLaunchKernelGGL((k_multi_caxpy<double2, __half2, KT>), g, dim3(256), 0, st, (double2 *)y,
+                                    (const __half2 *const *)xs_dev, k, c, cstride, sgn, accumulate, n))
+    WMG_HIP(hipGetLastError());
+    return 0;
+  }
   const int pk = (py == P64 && px == P64) ? 1 : 2;
   TRY_PK(pk == 1 ? P64 : P32, n, "multi_caxpy");
   dim3 g = ew_grid(n / pk, nrhs);

@@ -256,6 +256,20 @@ __device__ __forceinline__ void set_pair_base(float2 *p, const __half2 *b, cx<fl
   const float2 f0 = __half22float2(h0), f1 = __half22float2(h1);
   *(float4 *)p = make_float4(f0.x + lo.re, f0.y + lo.im, f1.x + hi.re, f1.y + hi.im);
 }
+// the same with the pair stored in FP16 (sums formed in FP32, rounded once)
+__device__ __forceinline__ void set_pair_base(__half2 *p, const __half2 *b, cx<float> lo, cx<float> hi) {
+  const uint2 w = *(const uint2 *)b;
+  __half2 h0, h1;
+  __builtin_memcpy(&h0, &w.x, 4);
+  __builtin_memcpy(&h1, &w.y, 4);
+  const float2 f0 = __half22float2(h0), f1 = __half22float2(h1);
+  h0 = __floats2half2_rn(f0.x + lo.re, f0.y + lo.im);
+  h1 = __floats2half2_rn(f1.x + hi.re, f1.y + hi.im);
+  uint2 o;
+  __builtin_memcpy(&o.x, &h0, 4);
+  __builtin_memcpy(&o.y, &h1, 4);
+  *(uint2 *)p = o;
+}
 __device__ __forceinline__ void set_pair_base(double2 *, const __half2 *, cx<double>, cx<double>) {}
 // p[0] += lo, p[1] += hi (two adjacent sites of a full-lattice component)
 __device__ __forceinline__ void add_pair(float2 *p, cx<float> lo, cx<float> hi) {
@@ -418,7 +432,7 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
         o = cx<R>{bs * (R)bv.re - o.re, bs * (R)bv.im - o.im};
       }
       if constexpr (EO) oo[c] = o;
-      else stc(out + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
+      else if (out) stc(out + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
       if (out32) stc(out32 + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
       if (RED) o = as_stored(out, o);
       if (RED) {
@@ -571,6 +585,7 @@ long wilson_red_blocks(const Geom &g) {
 int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
                      const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st, void *out32) {
   if (out32 && sprec != P64) return set_error(-1, "wilson_soa: FP32 copy of the output only for FP64 spinors");
+  if (!out && !out32) return set_error(-1, "wilson_soa: no output");
   const bool c12 = (lprec & LK12) != 0;
   const int lp = lprec & ~LK12;
 #define WS_LAUNCH(TL, TS, ...)                                                                                  \
@@ -581,6 +596,14 @@ int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double 
   if (sprec == P32 && lp == P16) WS_LAUNCH(__half2, float2, nullptr, 0, nullptr);
 #undef WS_LAUNCH
   return set_error(-1, "wilson_soa: unsupported precision pair link=%d spinor=%d", lp, sprec);
+}
+
+int wilson_soa_in16(const Geom &g, int lprec, const void *U, double m, const void *in, void *out, int nrhs,
+                    hipStream_t st) {
+  const bool c12 = (lprec & LK12) != 0;
+  if ((lprec & ~LK12) != P32) return set_error(-1, "wilson_soa_in16: FP32 links only");
+  return c12 ? launch_soa<float2, __half2, float2, 6>(g, U, m, in, out, nrhs, nullptr, nullptr, nullptr, 0, st)
+             : launch_soa<float2, __half2, float2, 9>(g, U, m, in, out, nrhs, nullptr, nullptr, nullptr, 0, st);
 }
 
 int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
@@ -1105,10 +1128,10 @@ static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, doubl
   const int nrt = (nrhs + RT - 1) / RT;
   int zb[20], grp[20], nt[20];
   const int ncand = eo_tile_candidates(g, nrt, std::is_same<TO, __half2>::value, zb, grp, nt);
-  // the all-FP16 form runs the packed-arithmetic kernel
+  // the all-FP16 form on the half lattice runs the packed-arithmetic kernel
+  // (the fused full-lattice update, ADD, the product-form kernel)
   constexpr bool pk = std::is_same<TL, __half2>::value && std::is_same<TD, __half2>::value &&
-                      std::is_same<TH, __half2>::value && std::is_same<TO, __half2>::value;
-  static_assert(!(pk && ADD), "no fused full-lattice update in the packed FP16 form");
+                      std::is_same<TH, __half2>::value && std::is_same<TO, __half2>::value && ADD == 0;
   auto run = [&](int cand) -> int {
     const EoTiles tl = make_eo_tiles(e, zb[cand], grp[cand], nt[cand]);
     const dim3 grid((unsigned)((long)NXCD * tl.tpx * nrt));
@@ -1165,10 +1188,19 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
 }
 
 int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int pdiag, const void *in_diag,
-               int phop, const void *de, void *full, int nrhs, hipStream_t st, const void *ebase) {
+               int phop, const void *de, void *full, int nrhs, hipStream_t st, const void *ebase, int pfull) {
   const bool c12 = (lprec & LK12) != 0;
   const int lp = lprec & ~LK12;
   if (g.L[0] % 2 || g.V / 2 >= (1L << 29)) return set_error(-1, "hop_eo_add: lattice not supported");
+  if (pfull == P16) {
+    if (!(lp == P16 && pdiag == P16 && phop == P16 && ebase))
+      return set_error(-1, "hop_eo_add: FP16 full-lattice output only from an FP16 base with FP16 fields");
+    return c12 ? launch_hop_eo<__half2, __half2, __half2, __half2, 2, 6, 2>(g, Ue, 1, a, b, in_diag, de, full, nrhs,
+                                                                            nullptr, nullptr, 0, st, ebase)
+               : launch_hop_eo<__half2, __half2, __half2, __half2, 2, 9, 2>(g, Ue, 1, a, b, in_diag, de, full, nrhs,
+                                                                            nullptr, nullptr, 0, st, ebase);
+  }
+  if (pfull != P32 && pfull != P64) return set_error(-1, "hop_eo_add: output precision %d", pfull);
 #define HOPA(TL, TD, TH, TO, RT)                                                                                  \
   return c12 ? launch_hop_eo<TL, TD, TH, TO, RT, 6, 1>(g, Ue, 1, a, b, in_diag, de, full, nrhs, nullptr, nullptr, 0, \
                                                       st)                                                          \

@@ -287,6 +287,10 @@ struct GcrBuf {
   void **zdev = nullptr, **wdev = nullptr;  // device arrays of the pointers
   void *rin = nullptr;                      // inner residual (aliases r64 in FP64 mode)
   double2 *x64 = nullptr, *r64 = nullptr, *b64 = nullptr, *t64 = nullptr;
+  // storage precision the z[k] last held (-1: as allocated, zero); the
+  // vector kernels sweep whole arrays, so the site padding of the other
+  // view is cleared when it changes
+  int zfmt = -1;
 };
 
 // links the fine operator reads at precision lp, and the precision code
@@ -578,8 +582,10 @@ static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int
   c->st_fine++;
   if (prec == P64) c->st_fine64++;
   double lb = lp == P64 ? 16 : 4, sb = prec == P64 ? 16 : 8;
+  // input, bsub, output and its FP32 copy
+  const double vb = ((bsub ? 24.0 : 12.0) * sb + (out ? 12.0 * sb : 0.0) + (out32 ? 96.0 : 0.0)) * nrhs;
   int slot = prof_begin(c, prec == P64 ? K_DSLASH_64 : (bsub ? K_DSLASH_RES : K_DSLASH_CYCLE),
-                        (double)L.g.V * (fine_link_cx(L) * lb + (bsub ? 36.0 : 24.0) * sb * nrhs));
+                        (double)L.g.V * (fine_link_cx(L) * lb + vb));
   int rc = wilson_soa_fused(L.g, fine_lcode(L, lp), fine_links(L, lp), prec, L.m, in, out, nrhs, bsub, reduce ? c->dred : nullptr,
                             red_dst ? red_dst : c->red_out, 4, c->st, out32);
   prof_end(c, slot);
@@ -655,7 +661,7 @@ static int eo_links(wmg_ctx *c, int lp, const void **Ue) {
 // input and the base of the last step, which then writes e = e16 + d
 // without reading e.
 static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, void *e, int nsteps, int nrhs,
-                        const void *e16 = nullptr) {
+                        const void *e16 = nullptr, int ep = P32) {
   Level &L = c->lv[0];
   const int lp = sp == P64 ? P64 : P16;   // link precision
   const int vp = sp == P64 ? P64 : P16;   // sublattice residuals and MR iterates
@@ -677,7 +683,7 @@ static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, vo
   const double vb = (double)L.g.V * fine_link_cx(L) * (lp == P64 ? 16 : 4);  // links of both halves
   const double eb = sp == P64 ? 16 : 4;                                        // sublattice element bytes
   const double db = sp == P64 ? 16 : 4;                                        // d_e element bytes
-  const double fb = sp == P64 ? 16 : 8;                                        // e element bytes
+  const double fb = sp == P64 ? 16 : (ep == P16 ? 4 : 8);                      // e element bytes
   const double hs = (double)L.g.V / 2 * 12 * nrhs;                             // elements of one half field
   // one red/black hop launch, timed and counted as the cycle's fine operator
   // (algorithmic bytes: the links of both halves, the input, the output and
@@ -736,7 +742,8 @@ static int mr_smooth_eo(wmg_ctx *c, int sp, const void *r, const double *rn2, vo
   // read and e written)
   const int slot2 = prof_begin(c, sp == P64 ? K_DSLASH_64 : K_DSLASH_CYCLE,
                                vb + hs * (eb + db + (e16 ? 2 * 4 + 2 * fb : 4 * fb)));
-  const int rc2 = hop_eo_add(L.g, lc, Ue, 1.0 / m4, 0.5 / m4, vp, so, dp, de, e, nrhs, c->st, e16);
+  const int rc2 = hop_eo_add(L.g, lc, Ue, 1.0 / m4, 0.5 / m4, vp, so, dp, de, e, nrhs, c->st, e16,
+                             sp == P64 ? P64 : ep);
   prof_end(c, slot2);
   return rc2;
 }
@@ -942,7 +949,18 @@ static int cgnr(wmg_ctx *c, int l, int prec, const void *b, void *x, int nrhs) {
 // e = M_l r: restrict, coarse correction (CGNR at the coarsest level, else
 // one or two recursive cycles), prolong, post-smooth (no pre-smoothing).
 // rn2: |r|^2 per rhs (device, stride 4) when the caller already has it
-static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int nrhs, const double *rn2 = nullptr) {
+// The fine-level cycle of a mixed solve can write its output e in FP16
+// (e16out): with the red/black smoother, FP16 prolongation, 1-4 MR steps,
+// at most 64 rhs, unless WMG_Z32.
+static bool z16_ok(wmg_ctx *c, int l, int prec, int nrhs) {
+  return l == 0 && prec == P32 && c->lv[0].fine && c->nl_cur > 1 && c->p.post_smooth >= 1 &&
+         c->p.post_smooth <= 4 && nrhs <= 64 && (c->p.flags & WMG_EO_SMOOTHER) && !(c->p.flags & WMG_Z32) &&
+         prolong16_ok(c, 0, nrhs);
+}
+
+static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int nrhs, const double *rn2 = nullptr,
+                      bool e16out = false) {
+  if (e16out && !z16_ok(c, l, prec, nrhs)) return set_error(-1, "mg_cycle: FP16 output not available here");
   Level &C = c->lv[l + 1];
   void *rc, *ec;
   TRY(level_vec(c, l + 1, prec, VR, &rc, nrhs));
@@ -981,7 +999,7 @@ static int mg_cycle_l(wmg_ctx *c, int l, int prec, const void *r, void *e, int n
     void *eh;
     TRY(level_vec(c, 0, P16, VEH, &eh, nrhs));
     TRY(transfer_prolong(c, l, prec, ec, eh, nrhs, true));
-    return mr_smooth_eo(c, P16, r, c->cyc_nrm, e, c->p.post_smooth, nrhs, eh);
+    return mr_smooth_eo(c, P16, r, c->cyc_nrm, e, c->p.post_smooth, nrhs, eh, e16out ? P16 : P32);
   }
   TRY(transfer_prolong(c, l, prec, ec, e, nrhs));
   if (h16 && (c->p.flags & WMG_EO_SMOOTHER)) return mr_smooth_eo(c, P16, r, c->cyc_nrm, e, c->p.post_smooth, nrhs);
@@ -1051,15 +1069,17 @@ static int gcr_buffers(wmg_ctx *c, int l, int prec, int nrhs, GcrBuf **out) {
 // the fine level one fused operator launch (residual and norm in its
 // epilogue), elsewhere operator, subtraction and norm.
 // r = b - A x in FP64 and |r|^2 (at red_out[4 rhs + *off]); on the fine level
-// of a mixed solve the same kernel also writes the FP32 copy of r into B.rin
-// (*rin_done = true)
+// of a mixed solve the kernel writes r only as the FP32 copy in B.rin
+// (*rin_done = true), which is all the inner cycle reads, and the norm from
+// the FP64 values
 static int residual64(wmg_ctx *c, int l, GcrBuf &B, int nrhs, int *off, bool *rin_done) {
   Level &L = c->lv[l];
   *rin_done = false;
   if (L.fine) {
     *off = 2;
     *rin_done = B.prec == P32;
-    return fine_apply_fused(c, P64, B.x64, B.r64, nrhs, B.b64, true, nullptr, B.prec == P32 ? B.rin : nullptr);
+    return B.prec == P32 ? fine_apply_fused(c, P64, B.x64, nullptr, nrhs, B.b64, true, nullptr, B.rin)
+                         : fine_apply_fused(c, P64, B.x64, B.r64, nrhs, B.b64, true);
   }
   *off = 0;
   TRY(apply_op(c, l, P64, B.x64, B.t64, nrhs, false));
@@ -1067,13 +1087,31 @@ static int residual64(wmg_ctx *c, int l, GcrBuf &B, int nrhs, int *off, bool *ri
   return norm2(c->red, P64, B.r64, L.n, nrhs, c->red_out, 4, c->st);
 }
 
+// w = A z on the fine level from the FP16-stored preconditioner output z:
+// FP32 links and arithmetic, FP32 w
+static int apply_outer_z16(wmg_ctx *c, const void *z, void *w, int nrhs) {
+  Level &L = c->lv[0];
+  c->st_fine++;
+  const int slot = prof_begin(c, K_DSLASH_OUTER32, (double)L.g.V * (fine_link_cx(L) * 8 + (12.0 * 4 + 12.0 * 8) * nrhs));
+  const int rc = wilson_soa_in16(L.g, fine_lcode(L, P32), fine_links(L, P32), L.m, z, w, nrhs, c->st);
+  prof_end(c, slot);
+  return rc;
+}
+
 static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int maxiter, int precond, double delta,
                      bool x0_nonzero, std::vector<int> &iters, double *relres_out) {
   Level &L = c->lv[l];
   const int ip = B.prec;
+  // The flexible GCR takes any preconditioner output: where the cycle can
+  // write z in FP16, z is stored so, and A z and the solution update read the
+  // same FP16 values (z is the cycle's output for r/|r|, O(1)).
+  const int zp = precond == 1 && z16_ok(c, l, ip, nrhs) ? P16 : ip;
   const int K = c->p.gcr_restart;
   const long n = L.n;
   hipStream_t st = c->st;
+  if (B.zfmt >= 0 && B.zfmt != zp)
+    for (int k = 0; k < K; k++) TRY(zero(ip, B.z[k], n, B.nrhs, st));
+  B.zfmt = zp;
   std::vector<double> bn(nrhs), rn(nrhs), rn_last(nrhs);
   std::vector<char> active(nrhs), frozen(nrhs);
   iters.assign(nrhs, 0);
@@ -1126,12 +1164,13 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
       if (precond == 1) {
         // |r_in|^2 is at hand: from the last reliable update (k = 0) or
         // from the previous step's r_in update
-        TRY(mg_cycle_l(c, l, ip, B.rin, z, nrhs, c->red_out + (k == 0 ? roff : 0)));
+        TRY(mg_cycle_l(c, l, ip, B.rin, z, nrhs, c->red_out + (k == 0 ? roff : 0), zp == P16));
       } else {
         TRY(zero(ip, z, n, nrhs, st));
         TRY(mr_smooth(c, l, ip, B.rin, z, c->p.post_smooth, nrhs));
       }
-      TRY(apply_op(c, l, ip, z, w, nrhs, false));
+      if (zp == P16) TRY(apply_outer_z16(c, z, w, nrhs));
+      else TRY(apply_op(c, l, ip, z, w, nrhs, false));
       // classical Gram-Schmidt against the unnormalised w_j, fused: dots |
       // project + <w, r> + |w|^2 (FP64: dots | project + new dots | project
       // + <w, r> + |w|^2)
@@ -1172,7 +1211,7 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
       if (allfrozen) break;
     }
     hipLaunchKernelGGL(k_gcr_trisolve2, dim3(1), dim3(64), 0, st, c->gcr, k, nrhs);
-    TRY(multi_caxpy(P64, B.x64, ip, (const void *const *)B.zdev, k, c->gcr + G_C, GS, 1.0, x_unset ? 0 : 1, n,
+    TRY(multi_caxpy(P64, B.x64, zp, (const void *const *)B.zdev, k, c->gcr + G_C, GS, 1.0, x_unset ? 0 : 1, n,
                     nrhs, st));
     x_unset = false;
     // reliable update: true residual in FP64
@@ -1959,7 +1998,7 @@ int mg_coarse_apply_f32(wmg_ctx *c, int level, const double *in, double *out, in
 }
 
 int mg_apply_fine(wmg_ctx *c, int prec, const double *in, double *out, int nrhs) {
-  if (!c || !in || !out || nrhs < 1 || nrhs > c->p.nrhs_max || nrhs > 64 || prec < 0 || prec > 3)
+  if (!c || !in || !out || nrhs < 1 || nrhs > c->p.nrhs_max || nrhs > 64 || prec < 0 || prec > 4)
     return set_error(WMG_EINVAL, "bad argument");
   Level &F = c->lv[0];
   void *a64, *b64;
@@ -1968,6 +2007,18 @@ int mg_apply_fine(wmg_ctx *c, int prec, const double *in, double *out, int nrhs)
   TRY(spinor_to_soa(F.g, in, (double2 *)a64, nrhs, c->st));
   if (prec == 0) {
     TRY(wilson_soa(F.g, fine_lcode(F, P64), fine_links(F, P64), P64, F.m, a64, b64, nrhs, c->st));
+  } else if (prec == 4) {
+    // the inner GCR's operator on an FP16-stored field: in rounded to FP16,
+    // FP32 links and arithmetic, FP32 output
+    if (F.n % 4) return set_error(WMG_EINVAL, "length not a multiple of 4");
+    void *a32, *h, *b32;
+    TRY(level_vec(c, 0, P32, VX, &a32, nrhs));
+    TRY(level_vec(c, 0, P32, VT, &b32, nrhs));
+    TRY(level_vec(c, 0, P16, VS, &h, nrhs));
+    TRY(copy(P32, a32, P64, a64, F.n, nrhs, c->st));
+    TRY(copy(P16, h, P32, a32, F.n, nrhs, c->st));
+    TRY(wilson_soa_in16(F.g, fine_lcode(F, P32), fine_links(F, P32), F.m, h, b32, nrhs, c->st));
+    TRY(copy(P64, b64, P32, b32, F.n, nrhs, c->st));
   } else if (prec < 3) {
     void *a32, *b32;
     TRY(level_vec(c, 0, P32, VX, &a32, nrhs));
@@ -2024,7 +2075,8 @@ static int canon_to_eo(wmg_ctx *c, int p, const double *canon, void *ev, void *o
 int mg_hop_eo(wmg_ctx *c, int prec, int par, double a, double b, const double *diag, const double *hop, double *out,
               int nrhs) {
   if (!c || !hop || !out || (a != 0.0 && !diag) || nrhs < 1 || nrhs > c->p.nrhs_max || nrhs > 64 ||
-      (prec != 0 && prec != 3 && prec != 4 && prec != 5) || (par != 0 && par != 1) || (prec == 5 && par != 1))
+      (prec != 0 && prec != 3 && prec != 4 && prec != 5 && prec != 6) || (par != 0 && par != 1) ||
+      (prec >= 5 && par != 1))
     return set_error(WMG_EINVAL, "bad argument");
   Level &F = c->lv[0];
   for (int i = 0; i < 4; i++)
@@ -2047,13 +2099,21 @@ int mg_hop_eo(wmg_ctx *c, int prec, int par, double a, double b, const double *d
   void *full, *b64;
   TRY(level_vec(c, 0, pf, VT, &full, nrhs));
   TRY(zero(pf, full, F.n, nrhs, c->st));
-  if (prec == 5) {
+  if (prec >= 5) {
     // the smoother's last step as the mixed cycle runs it: full = base +
-    // (hop at the even sites, the odd result), here with a zero FP16 base
+    // (hop at the even sites, the odd result), here with a zero FP16 base;
+    // prec 6 stores full in FP16
     void *base;
     TRY(level_vec(c, 0, P16, VEH, &base, nrhs));
     TRY(zero(P16, base, F.n, nrhs, c->st));
-    TRY(hop_eo_add(F.g, lp | F.lk, Ue, a, b, pd, a != 0.0 ? dod : nullptr, ph, he, full, nrhs, c->st, base));
+    if (prec == 6) {
+      void *f16;
+      TRY(level_vec(c, 0, P16, VS, &f16, nrhs));
+      TRY(hop_eo_add(F.g, lp | F.lk, Ue, a, b, pd, a != 0.0 ? dod : nullptr, ph, he, f16, nrhs, c->st, base, P16));
+      TRY(copy(P32, full, P16, f16, F.n, nrhs, c->st));
+    } else {
+      TRY(hop_eo_add(F.g, lp | F.lk, Ue, a, b, pd, a != 0.0 ? dod : nullptr, ph, he, full, nrhs, c->st, base));
+    }
   } else {
     TRY(hop_eo(F.g, lp | F.lk, Ue, par, a, b, pd, a != 0.0 ? (par ? dod : de) : nullptr, ph, par ? he : ho, ph, o,
                nrhs, nullptr, nullptr, 0, c->st));

@@ -161,10 +161,16 @@ int wilson_soa(const Geom &g, int lprec, const void *U, int sprec, double m, con
                hipStream_t st);
 // out = [bsub -] D in; with red != nullptr also <out, in>, |out|^2 per rhs ->
 // red_out[rhs * red_stride + 0..2] (red: scratch of nrhs * wilson_red_blocks * 3);
-// with out32 != nullptr (FP64 spinors only) out is also written as FP32 there
+// with out32 != nullptr (FP64 spinors only) out is also written as FP32 there,
+// and out may then be nullptr (FP32 copy only; the reductions stay FP64)
 int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double m, const void *in, void *out, int nrhs,
                      const void *bsub, double *red, double *red_out, int red_stride, hipStream_t st,
                      void *out32 = nullptr);
+// out (FP32) = D in with FP32 links (lprec may carry LK12) on an FP16 input
+// field (FP32 arithmetic): the inner GCR's operator on the FP16-stored
+// preconditioner output.
+int wilson_soa_in16(const Geom &g, int lprec, const void *U, double m, const void *in, void *out, int nrhs,
+                    hipStream_t st);
 // Smoother variant with FP16 links and FP16 output storage: in is FP32
 // (iprec P32) or FP16 (P16); out (FP16) = [b/|b| -] D in, where bsub (FP32)
 // is scaled per rhs by 1/sqrt(bnrm2[rhs * bstride]) (0 where that norm is
@@ -197,9 +203,11 @@ int hop_eo(const Geom &g, int lprec, const void *Ue, int par, double a, double b
 // a in_diag + b H_odd(d_e) at the odd sites, d_e the even half-lattice field
 // (precision phop): all FP64, or FP16 links and in_diag with FP32 or FP16
 // d_e and FP32 full.  With ebase (FP16 d_e only: an FP16 full-lattice field)
-// full = ebase + (d_e, d_o) instead, full not read.
+// full = ebase + (d_e, d_o) instead, full not read; full is then FP32, or
+// FP16 with pfull = P16 (sums in FP32, rounded once).
 int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int pdiag, const void *in_diag,
-               int phop, const void *de, void *full, int nrhs, hipStream_t st, const void *ebase = nullptr);
+               int phop, const void *de, void *full, int nrhs, hipStream_t st, const void *ebase = nullptr,
+               int pfull = P32);
 int eo_pack(const Geom &g, int pfull, const void *full, int phalf, void *ev, void *od, int nrhs, hipStream_t st);
 int eo_unpack_add(const Geom &g, int pfull, void *full, int phalf, const void *ev, const void *od, int nrhs,
                   hipStream_t st);

@@ -38,6 +38,7 @@ WMG_EO_SMOOTHER = 8
 WMG_GRAPHS = 16
 WMG_SPIN_SPLIT = 32
 WMG_COARSE_B32 = 64
+WMG_Z32 = 128
 
 
 class WmgError(RuntimeError):

@@ -75,7 +75,7 @@ def test_internal_dslash_precisions(wmg):
 
 # per-site error bounds, in units of the largest input component in the
 # site's neighbourhood: c * unit roundoff of the storage format
-SITE_BOUND = {0: 256 * 2.0 ** -52, 1: 256 * 2.0 ** -24, 2: 64 * 2.0 ** -11}
+SITE_BOUND = {0: 256 * 2.0 ** -52, 1: 256 * 2.0 ** -24, 2: 64 * 2.0 ** -11, 4: 256 * 2.0 ** -24}
 
 
 def test_link_formats_two_rows_and_whole(wmg):
@@ -88,16 +88,20 @@ def test_link_formats_two_rows_and_whole(wmg):
     U = inputs.gauge_field(L, 0.5, 301)
     psi = inputs.gaussian_rhs(L, 203, 2)
     ref = [oracle.wilson(L, U, -0.2, psi[r]) for r in range(2)]
+    # prec 4 reads its input in FP16: the oracle sees the same rounded values
+    psi16 = _fp16_round(psi)
+    ref16 = [oracle.wilson(L, U, -0.2, psi16[r]) for r in range(2)]
     for flags, reals in ((0, 12), (wmg.WMG_LINKS18, 18)):
         p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=2, flags=flags)
         mg = wmg.MG(L, dev(U), -0.2, 4, (4, 4, 4, 4), p)
         assert mg.mg_link_reals() == reals
-        for prec, tol in [(0, 1e-14), (1, 1e-6), (2, 2e-3)]:
+        for prec, tol in [(0, 1e-14), (1, 1e-6), (2, 2e-3), (4, 1e-6)]:
+            src, rf = (psi16, ref16) if prec == 4 else (psi, ref)
             out = empty((2, V, 12))
-            mg.mg_apply_fine(prec, dev(psi), out, 2)
+            mg.mg_apply_fine(prec, dev(src), out, 2)
             oh = host(out)
             for r in range(2):
-                e, le = relerr(oh[r], ref[r]), local_err(oh[r], ref[r], psi[r], L)
+                e, le = relerr(oh[r], rf[r]), local_err(oh[r], rf[r], src[r], L)
                 say("  reals", reals, "prec", prec, "rhs", r, "relerr %.2e site %.2e" % (e, le))
                 assert e < tol and le < SITE_BOUND[prec]
         mg.close()
@@ -201,8 +205,8 @@ def test_dslash_work_orders_identical(wmg):
     """Every work order the autotuner may pick for the full-lattice Dslash
     (slab budget, one sweep per rhs tile, all rhs tiles of a site tile back
     to back, groups of 2-4 rhs tiles with a short last group) computes each
-    site with the same operations: the FP64, FP32, FP16-link and FP16 MR-step
-    forms and the smoother's residual kernel are bit-identical to the
+    site with the same operations: the FP64, FP32, FP16-link, FP16 MR-step
+    and FP16-input forms and the smoother's residual kernel are bit-identical to the
     default's, which is checked against the oracle on two of the 16
     right-hand sides."""
     L = (16, 12, 8, 6)
@@ -216,7 +220,7 @@ def test_dslash_work_orders_identical(wmg):
     mg = wmg.MG(L, dev(U), m, 4, (4, 4, 4, 2), p)
     try:
         forms = [(f"apply prec {prec}", lambda out, prec=prec: mg.mg_apply_fine(prec, dev(psi), out, nr))
-                 for prec in (0, 1, 2, 3)]
+                 for prec in (0, 1, 2, 3, 4)]
         forms.append(("smoother residual", lambda out: mg.mg_smoother_residual(dev(psi), dev(e), out, nr)))
         for name, run in forms:
             outs = []
