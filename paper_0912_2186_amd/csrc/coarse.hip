@@ -1043,11 +1043,14 @@ k_coarse_apply_mfma2h(const __half *__restrict__ Yh, const float *__restrict__ Y
       }
   };
   const int mts = mt < MT ? mt : 0;
+  // the links stream through once per launch: non-temporal loads leave L2
+  // to the neighbour vectors, which nine workgroups read
   auto a_load = [&](half4 *a, int d) {
-    const uint2 *Ad = (const uint2 *)(Yh + (((size_t)xh * 9 + d) * MT + mts) * KM * 64) + lane;
+    typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+    const u32x2_t *Ad = (const u32x2_t *)(Yh + (((size_t)xh * 9 + d) * MT + mts) * KM * 64) + lane;
 #pragma unroll
     for (int kq = 0; kq < KS / 4; kq++) {
-      const uint2 v = Ad[kq * 64];
+      const u32x2_t v = __builtin_nontemporal_load(Ad + kq * 64);
       __builtin_memcpy(&a[kq], &v, 8);
     }
   };
