@@ -282,6 +282,92 @@ __device__ __forceinline__ void add_pair(double2 *p, cx<double> lo, cx<double> h
   p[1] = make_double2(b.x + hi.re, b.y + hi.im);
 }
 
+// ---------------------------------------------------------------- packed FP16
+// Packed half-precision arithmetic of the all-FP16 hopping terms: two FP16
+// values per lane and instruction, the complex broadcasts, swaps and signs
+// folded into the operands' modifiers (a complex multiply-add is two packed
+// FMAs); the FP16 -> FP32 conversion of a term is folded into its FP32
+// accumulation through a multiplier `one` the compiler cannot see.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2 pk_i(h2 a) { return (h2){-a.y, a.x}; }   // i a
+__device__ __forceinline__ h2 pk_mi(h2 a) { return (h2){a.y, -a.x}; }  // -i a
+// c + a b and c + conj(a) b
+__device__ __forceinline__ h2 pk_cfma(h2 a, h2 b, h2 c) {
+  const h2 t = __builtin_elementwise_fma(a.xx, b, c);
+  return __builtin_elementwise_fma((h2){-a.y, a.y}, b.yx, t);
+}
+__device__ __forceinline__ h2 pk_cfmac(h2 a, h2 b, h2 c) {
+  const h2 t = __builtin_elementwise_fma(a.xx, b, c);
+  return __builtin_elementwise_fma((h2){a.y, -a.y}, b.yx, t);
+}
+__device__ __forceinline__ h2 pk_cmul(h2 a, h2 b) { return __builtin_elementwise_fma((h2){-a.y, a.y}, b.yx, a.xx * b); }
+__device__ __forceinline__ h2 pk_ld(const __half2 *p) {
+  const unsigned w = *(const unsigned *)p;
+  h2 r;
+  __builtin_memcpy(&r, &w, 4);
+  return r;
+}
+template <int NR>
+__device__ __forceinline__ void pk_link(const __half2 *Up, int mu, unsigned site, int Vs, h2 u[9]) {
+#pragma unroll
+  for (int e = 0; e < NR; e++) u[e] = pk_ld(Up + (size_t)(mu * NR + e) * Vs + site);
+  if (NR == 6) {
+    // third row conj(row0 x row1), conj(a b) - conj(c d) as four packed FMAs
+    auto cc = [](h2 a, h2 b, h2 c, h2 d) {
+      h2 t = a.xx * (h2){b.x, -b.y};
+      t = __builtin_elementwise_fma((h2){-a.y, -a.y}, b.yx, t);
+      t = __builtin_elementwise_fma(-c.xx, (h2){d.x, -d.y}, t);
+      return __builtin_elementwise_fma((h2){c.y, c.y}, d.yx, t);
+    };
+    u[6] = cc(u[1], u[5], u[2], u[4]);
+    u[7] = cc(u[2], u[3], u[0], u[5]);
+    u[8] = cc(u[0], u[4], u[1], u[3]);
+  }
+}
+// one colour of the projection from the four stored spins (as proj_pair)
+template <int MU, int S>
+__device__ __forceinline__ void pk_proj_q(const h2 q[4], h2 &h0, h2 &h1) {
+  h2 a0, a1;  // A_mu p_down
+  if (MU == 0) { a0 = pk_mi(q[3]); a1 = pk_mi(q[2]); }
+  if (MU == 1) { a0 = -q[3]; a1 = q[2]; }
+  if (MU == 2) { a0 = pk_mi(q[2]); a1 = pk_i(q[3]); }
+  if (MU == 3) { a0 = q[2]; a1 = q[3]; }
+  if (S > 0) { h0 = q[0] - a0; h1 = q[1] - a1; }
+  else { h0 = q[0] + a0; h1 = q[1] + a1; }
+}
+// the same from the four spins stored together (half-lattice layout)
+template <int MU, int S>
+__device__ __forceinline__ void pk_proj(const __half2 *p, h2 &h0, h2 &h1) {
+  const uint4 v = *(const uint4 *)p;
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
+  h2 q[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) __builtin_memcpy(&q[i], &w[i], 4);
+  pk_proj_q<MU, S>(q, h0, h1);
+}
+__device__ __forceinline__ void pk_acc(cx<float> &acc, h2 x, float one) {
+  acc.re = __builtin_fmaf((float)x.x, one, acc.re);
+  acc.im = __builtin_fmaf((float)x.y, one, acc.im);
+}
+// upper spins += gf + gb, lower spins += A_mu^dag (gb - gf): the forward and
+// backward terms of reconstruct<MU, +1> and reconstruct<MU, -1> together
+template <int MU>
+__device__ __forceinline__ void pk_recon(const h2 gf[6], const h2 gb[6], cx<float> acc[12], float one) {
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    pk_acc(acc[c], gf[c] + gb[c], one);
+    pk_acc(acc[3 + c], gf[3 + c] + gb[3 + c], one);
+    const h2 d0 = gb[c] - gf[c], d1 = gb[3 + c] - gf[3 + c];
+    h2 b0, b1;
+    if (MU == 0) { b0 = pk_i(d1); b1 = pk_i(d0); }
+    if (MU == 1) { b0 = d1; b1 = -d0; }
+    if (MU == 2) { b0 = pk_i(d0); b1 = pk_mi(d1); }
+    if (MU == 3) { b0 = d0; b1 = d1; }
+    pk_acc(acc[6 + c], b0, one);
+    pk_acc(acc[9 + c], b1, one);
+  }
+}
+
 // ---------------------------------------------------------------- SoA
 // Optional fusions for the smoother: bsub != nullptr gives out = bsub - D in
 // (residual); RED != 0 also reduces <out, in> and |out|^2 over the
@@ -295,7 +381,8 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
                                                    float diagf, double diagd, int nrhs, SweepMap sm, long Vs,
                                                    const TB *__restrict__ bsub, const double *__restrict__ bnrm2,
                                                    int bstride, double *__restrict__ red, int inner,
-                                                   float2 *__restrict__ out32, TO *__restrict__ out_odd, long Vhs) {
+                                                   float2 *__restrict__ out32, TO *__restrict__ out_odd, long Vhs,
+                                                   float one) {
   using R = typename store_traits<TS>::real;
   const R diag = sizeof(R) == 8 ? (R)diagd : (R)diagf;
   // one sweep over the lattice per tile of RT right-hand sides (grid.y)
@@ -403,10 +490,65 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
       }                                                                                        \
     }                                                                                          \
   }
-  WILSON_DIR(0)
-  WILSON_DIR(1)
-  WILSON_DIR(2)
-  WILSON_DIR(3)
+  // FP16 links and spinors: projection, SU(3) products and the sum and
+  // difference of each direction's forward and backward terms in packed
+  // FP16, the directions summed in FP32 (as in the packed red/black hop)
+#define WILSON_DIR_PK(MU)                                                                      \
+  {                                                                                            \
+    long fw = x[MU] == L[MU] - 1 ? s - (long)(L[MU] - 1) * stride[MU] : s + stride[MU];        \
+    long bw = x[MU] == 0 ? s + (long)(L[MU] - 1) * stride[MU] : s - stride[MU];                \
+    int yf[4] = {x[0], x[1], x[2], x[3]}, yb[4] = {x[0], x[1], x[2], x[3]};                    \
+    yf[MU] = x[MU] == L[MU] - 1 ? 0 : x[MU] + 1;                                               \
+    yb[MU] = x[MU] == 0 ? L[MU] - 1 : x[MU] - 1;                                               \
+    const int lf = local_of(yf), lb = local_of(yb);                                            \
+    h2 uf[9], ub[9];                                                                           \
+    pk_link<NR>((const __half2 *)U, MU, (unsigned)s, (int)Vs, uf);                             \
+    pk_link<NR>((const __half2 *)U, MU, (unsigned)bw, (int)Vs, ub);                            \
+    _Pragma("unroll") for (int t = 0; t < RT; t++) {                                           \
+      if (r0 + t < nrhs) {                                                                     \
+        h2 hh[6], gf[6], gb[6];                                                                \
+        _Pragma("unroll") for (int c = 0; c < 3; c++) {                                        \
+          h2 q[4];                                                                             \
+          _Pragma("unroll") for (int sp = 0; sp < 4; sp++)                                     \
+            q[sp] = pk_ld(lf >= 0 ? (const __half2 *)Sh + (t * 12 + sp * 3 + c) * 256 + lf     \
+                                  : (const __half2 *)in + ((size_t)(r0 + t) * 12 + sp * 3 + c) * Vs + fw); \
+          pk_proj_q<MU, 1>(q, hh[c], hh[3 + c]);                                               \
+        }                                                                                      \
+        _Pragma("unroll") for (int sp = 0; sp < 2; sp++)                                       \
+        _Pragma("unroll") for (int a = 0; a < 3; a++) {                                        \
+          h2 v = pk_cmul(uf[3 * a], hh[3 * sp]);                                               \
+          v = pk_cfma(uf[3 * a + 1], hh[3 * sp + 1], v);                                       \
+          gf[3 * sp + a] = pk_cfma(uf[3 * a + 2], hh[3 * sp + 2], v);                          \
+        }                                                                                      \
+        _Pragma("unroll") for (int c = 0; c < 3; c++) {                                        \
+          h2 q[4];                                                                             \
+          _Pragma("unroll") for (int sp = 0; sp < 4; sp++)                                     \
+            q[sp] = pk_ld(lb >= 0 ? (const __half2 *)Sh + (t * 12 + sp * 3 + c) * 256 + lb     \
+                                  : (const __half2 *)in + ((size_t)(r0 + t) * 12 + sp * 3 + c) * Vs + bw); \
+          pk_proj_q<MU, -1>(q, hh[c], hh[3 + c]);                                              \
+        }                                                                                      \
+        _Pragma("unroll") for (int sp = 0; sp < 2; sp++)                                       \
+        _Pragma("unroll") for (int a = 0; a < 3; a++) {                                        \
+          h2 v = pk_cfmac(ub[a], hh[3 * sp], (h2){0, 0});                                      \
+          v = pk_cfmac(ub[3 + a], hh[3 * sp + 1], v);                                          \
+          gb[3 * sp + a] = pk_cfmac(ub[6 + a], hh[3 * sp + 2], v);                             \
+        }                                                                                      \
+        pk_recon<MU>(gf, gb, acc[t], one);                                                     \
+      }                                                                                        \
+    }                                                                                          \
+  }
+  if constexpr (std::is_same<TL, __half2>::value && std::is_same<TS, __half2>::value) {
+    WILSON_DIR_PK(0)
+    WILSON_DIR_PK(1)
+    WILSON_DIR_PK(2)
+    WILSON_DIR_PK(3)
+  } else {
+    WILSON_DIR(0)
+    WILSON_DIR(1)
+    WILSON_DIR(2)
+    WILSON_DIR(3)
+  }
+#undef WILSON_DIR_PK
 #undef WILSON_DIR
 
 #pragma unroll
@@ -534,7 +676,7 @@ static int launch_soa(const Geom &g, const void *U, double m, const void *in, vo
       hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1, NR, 0, TB>), grid, dim3(256), lds, st, (const TL *)U,
                          (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
                          nrhs, sm, g.Vs, (const TB *)bsub, bnrm2, bstride, red, inner, (float2 *)out32, (TO *)nullptr,
-                         Vhs);
+                         Vhs, 1.0f);
       hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
                          red_stride);
     } else if (out_odd) {
@@ -544,14 +686,14 @@ static int launch_soa(const Geom &g, const void *U, double m, const void *in, vo
         hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR, 1, TB>), grid, dim3(256), lds, st, (const TL *)U,
                            (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
                            nrhs, sm, g.Vs, (const TB *)bsub, bnrm2, bstride, (double *)nullptr, inner,
-                           (float2 *)out32, (TO *)out_odd, Vhs);
+                           (float2 *)out32, (TO *)out_odd, Vhs, 1.0f);
       else
         return set_error(-1, "wilson_soa: half-lattice output not instantiated for these precisions");
     } else {
       hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR, 0, TB>), grid, dim3(256), lds, st, (const TL *)U,
                          (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
                          nrhs, sm, g.Vs, (const TB *)bsub, bnrm2, bstride, (double *)nullptr, inner, (float2 *)out32,
-                         (TO *)nullptr, Vhs);
+                         (TO *)nullptr, Vhs, 1.0f);
     }
     WMG_HIP(hipGetLastError());
     return 0;
@@ -914,81 +1056,6 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
 // rounded as in k_hop_eo.  The FP16 products round at 2^-11 relative to the
 // link and spinor magnitudes, the size of the FP16 storage rounding of the
 // same fields.
-typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ h2 pk_i(h2 a) { return (h2){-a.y, a.x}; }   // i a
-__device__ __forceinline__ h2 pk_mi(h2 a) { return (h2){a.y, -a.x}; }  // -i a
-// c + a b and c + conj(a) b
-__device__ __forceinline__ h2 pk_cfma(h2 a, h2 b, h2 c) {
-  const h2 t = __builtin_elementwise_fma(a.xx, b, c);
-  return __builtin_elementwise_fma((h2){-a.y, a.y}, b.yx, t);
-}
-__device__ __forceinline__ h2 pk_cfmac(h2 a, h2 b, h2 c) {
-  const h2 t = __builtin_elementwise_fma(a.xx, b, c);
-  return __builtin_elementwise_fma((h2){a.y, -a.y}, b.yx, t);
-}
-__device__ __forceinline__ h2 pk_cmul(h2 a, h2 b) { return __builtin_elementwise_fma((h2){-a.y, a.y}, b.yx, a.xx * b); }
-__device__ __forceinline__ h2 pk_ld(const __half2 *p) {
-  const unsigned w = *(const unsigned *)p;
-  h2 r;
-  __builtin_memcpy(&r, &w, 4);
-  return r;
-}
-template <int NR>
-__device__ __forceinline__ void pk_link(const __half2 *Up, int mu, unsigned site, int Vs, h2 u[9]) {
-#pragma unroll
-  for (int e = 0; e < NR; e++) u[e] = pk_ld(Up + (size_t)(mu * NR + e) * Vs + site);
-  if (NR == 6) {
-    // third row conj(row0 x row1), conj(a b) - conj(c d) as four packed FMAs
-    auto cc = [](h2 a, h2 b, h2 c, h2 d) {
-      h2 t = a.xx * (h2){b.x, -b.y};
-      t = __builtin_elementwise_fma((h2){-a.y, -a.y}, b.yx, t);
-      t = __builtin_elementwise_fma(-c.xx, (h2){d.x, -d.y}, t);
-      return __builtin_elementwise_fma((h2){c.y, c.y}, d.yx, t);
-    };
-    u[6] = cc(u[1], u[5], u[2], u[4]);
-    u[7] = cc(u[2], u[3], u[0], u[5]);
-    u[8] = cc(u[0], u[4], u[1], u[3]);
-  }
-}
-// one colour of the projection from the four stored spins (as proj_pair)
-template <int MU, int S>
-__device__ __forceinline__ void pk_proj(const __half2 *p, h2 &h0, h2 &h1) {
-  const uint4 v = *(const uint4 *)p;
-  const unsigned w[4] = {v.x, v.y, v.z, v.w};
-  h2 q[4];
-#pragma unroll
-  for (int i = 0; i < 4; i++) __builtin_memcpy(&q[i], &w[i], 4);
-  h2 a0, a1;  // A_mu p_down
-  if (MU == 0) { a0 = pk_mi(q[3]); a1 = pk_mi(q[2]); }
-  if (MU == 1) { a0 = -q[3]; a1 = q[2]; }
-  if (MU == 2) { a0 = pk_mi(q[2]); a1 = pk_i(q[3]); }
-  if (MU == 3) { a0 = q[2]; a1 = q[3]; }
-  if (S > 0) { h0 = q[0] - a0; h1 = q[1] - a1; }
-  else { h0 = q[0] + a0; h1 = q[1] + a1; }
-}
-__device__ __forceinline__ void pk_acc(cx<float> &acc, h2 x, float one) {
-  acc.re = __builtin_fmaf((float)x.x, one, acc.re);
-  acc.im = __builtin_fmaf((float)x.y, one, acc.im);
-}
-// upper spins += gf + gb, lower spins += A_mu^dag (gb - gf): the forward and
-// backward terms of reconstruct<MU, +1> and reconstruct<MU, -1> together
-template <int MU>
-__device__ __forceinline__ void pk_recon(const h2 gf[6], const h2 gb[6], cx<float> acc[12], float one) {
-#pragma unroll
-  for (int c = 0; c < 3; c++) {
-    pk_acc(acc[c], gf[c] + gb[c], one);
-    pk_acc(acc[3 + c], gf[3 + c] + gb[3 + c], one);
-    const h2 d0 = gb[c] - gf[c], d1 = gb[3 + c] - gf[3 + c];
-    h2 b0, b1;
-    if (MU == 0) { b0 = pk_i(d1); b1 = pk_i(d0); }
-    if (MU == 1) { b0 = d1; b1 = -d0; }
-    if (MU == 2) { b0 = pk_i(d0); b1 = pk_mi(d1); }
-    if (MU == 3) { b0 = d0; b1 = d1; }
-    pk_acc(acc[6 + c], b0, one);
-    pk_acc(acc[9 + c], b1, one);
-  }
-}
-
 template <int RT, int RED, int NR>
 __global__ void __launch_bounds__(256) k_hop_eo_pk(const __half2 *__restrict__ Ue, const __half2 *__restrict__ in_diag,
                                                   const __half2 *__restrict__ in_hop, __half2 *__restrict__ out,

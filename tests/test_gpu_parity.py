@@ -167,19 +167,27 @@ def test_fp16_spinor_mr_step_operator(wmg):
         mg.close()
 
 
+@pytest.mark.parametrize("e_kind", ["small", "cancel"])
 @pytest.mark.parametrize("red_black", [False, True])
-def test_fp16_smoother_residual_kernel(wmg, red_black):
+def test_fp16_smoother_residual_kernel(wmg, red_black, e_kind):
     """The smoother's fused residual kernel out = r/|r| - D e (FP16 links,
     FP16 output) against the oracle, Gaussian and point-source r, per-site
     bound against the neighbourhood scale of e and r/|r|: e in FP32 into a
     full-lattice output, and (red/black smoother of the mixed cycle) e in
-    FP16 into the two half-lattice arrays."""
+    FP16 into the two half-lattice arrays, whose hopping sum runs in packed
+    FP16 arithmetic.  As for the prolonged correction, D e can cancel much of
+    r/|r|: e_kind "cancel" takes
+    e = (r/|r|) / (4 + m), whose diagonal term cancels r/|r| exactly and
+    leaves the hopping sum alone."""
     L = (8, 8, 8, 12)
     V = vol(L)
     m = -0.2
     U = inputs.gauge_field(L, 0.5, 301)
     r = np.stack([inputs.gaussian_rhs(L, 208)[0], inputs.point_sources(L)[7]])
-    e = 1e-3 * np.stack([inputs.gaussian_rhs(L, 209)[0], _decaying_source(L, 0, 1.0, 210)])
+    if e_kind == "small":
+        e = 1e-3 * np.stack([inputs.gaussian_rhs(L, 209)[0], _decaying_source(L, 0, 1.0, 210)])
+    else:
+        e = np.stack([r[k] / np.linalg.norm(r[k]) for k in range(2)]) / (4 + m)
     if red_black:
         e = e.real.astype(np.float16).astype(np.float64) + 1j * e.imag.astype(np.float16).astype(np.float64)
         p = wmg.default_params(setup_iters=1, seed=7, nrhs_max=2, precision=wmg.WMG_MIXED,
