@@ -1056,11 +1056,12 @@ __global__ void __launch_bounds__(256) k_hop_eo(const TL *__restrict__ Ue, const
 // rounded as in k_hop_eo.  The FP16 products round at 2^-11 relative to the
 // link and spinor magnitudes, the size of the FP16 storage rounding of the
 // same fields.
-template <int RT, int RED, int NR>
+template <int RT, int RED, int NR, int ADD = 0>
 __global__ void __launch_bounds__(256) k_hop_eo_pk(const __half2 *__restrict__ Ue, const __half2 *__restrict__ in_diag,
                                                   const __half2 *__restrict__ in_hop, __half2 *__restrict__ out,
                                                   EoGeom g, int par, double ad, double bd, int nrhs, EoTiles tl,
-                                                  double *__restrict__ red, float one) {
+                                                  double *__restrict__ red, float one,
+                                                  const __half2 *__restrict__ ebase) {
   const EoSite st = eo_site(g, tl, par, nrhs, RT);
   const int r0 = st.r0;
   double rs[RT][3];
@@ -1111,8 +1112,8 @@ __global__ void __launch_bounds__(256) k_hop_eo_pk(const __half2 *__restrict__ U
     PK_DIR(2)
     PK_DIR(3)
 #undef PK_DIR
-    eo_store<__half2, __half2, __half2, RT, RED, 0, float>(g, tl, st, nrhs, in_diag, in_hop, out, ad, (float)ad,
-                                                           (float)bd, acc, rs);
+    eo_store<__half2, __half2, __half2, RT, RED, ADD, float>(g, tl, st, nrhs, in_diag, in_hop, out, ad, (float)ad,
+                                                             (float)bd, acc, rs, ebase);
   }
   if (RED) eo_reduce<RT>(tl, st, nrhs, rs, red);
 }
@@ -1195,10 +1196,10 @@ static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, doubl
   const int nrt = (nrhs + RT - 1) / RT;
   int zb[20], grp[20], nt[20];
   const int ncand = eo_tile_candidates(g, nrt, std::is_same<TO, __half2>::value, zb, grp, nt);
-  // the all-FP16 form on the half lattice runs the packed-arithmetic kernel
-  // (the fused full-lattice update, ADD, the product-form kernel)
+  // the all-FP16 form runs the packed-arithmetic kernel (also the fused
+  // full-lattice write from an FP16 base, ADD 2, with FP16 output)
   constexpr bool pk = std::is_same<TL, __half2>::value && std::is_same<TD, __half2>::value &&
-                      std::is_same<TH, __half2>::value && std::is_same<TO, __half2>::value && ADD == 0;
+                      std::is_same<TH, __half2>::value && std::is_same<TO, __half2>::value && ADD != 1;
   auto run = [&](int cand) -> int {
     const EoTiles tl = make_eo_tiles(e, zb[cand], grp[cand], nt[cand]);
     const dim3 grid((unsigned)((long)NXCD * tl.tpx * nrt));
@@ -1206,11 +1207,11 @@ static int launch_hop_eo(const Geom &g, const void *Ue, int par, double a, doubl
       if (red)
         hipLaunchKernelGGL((k_hop_eo_pk<RT, 1, NR>), grid, dim3(256), 0, st, (const __half2 *)Ue,
                            (const __half2 *)in_diag, (const __half2 *)in_hop, (__half2 *)out, e, par, a, b, nrhs, tl,
-                           red, 1.0f);
+                           red, 1.0f, (const __half2 *)nullptr);
       else
-        hipLaunchKernelGGL((k_hop_eo_pk<RT, 0, NR>), grid, dim3(256), 0, st, (const __half2 *)Ue,
+        hipLaunchKernelGGL((k_hop_eo_pk<RT, 0, NR, ADD>), grid, dim3(256), 0, st, (const __half2 *)Ue,
                            (const __half2 *)in_diag, (const __half2 *)in_hop, (__half2 *)out, e, par, a, b, nrhs, tl,
-                           (double *)nullptr, 1.0f);
+                           (double *)nullptr, 1.0f, (const __half2 *)ebase);
     } else if (red) {
       hipLaunchKernelGGL((k_hop_eo<TL, TD, TH, TO, RT, 1, NR>), grid, dim3(256), 0, st, (const TL *)Ue,
                          (const TD *)in_diag, (const TH *)in_hop, (TO *)out, e, par, a, b, nrhs, tl, red, 1.0f,
@@ -1262,9 +1263,9 @@ int hop_eo_add(const Geom &g, int lprec, const void *Ue, double a, double b, int
   if (pfull == P16) {
     if (!(lp == P16 && pdiag == P16 && phop == P16 && ebase))
       return set_error(-1, "hop_eo_add: FP16 full-lattice output only from an FP16 base with FP16 fields");
-    return c12 ? launch_hop_eo<__half2, __half2, __half2, __half2, 2, 6, 2>(g, Ue, 1, a, b, in_diag, de, full, nrhs,
+    return c12 ? launch_hop_eo<__half2, __half2, __half2, __half2, 4, 6, 2>(g, Ue, 1, a, b, in_diag, de, full, nrhs,
                                                                             nullptr, nullptr, 0, st, ebase)
-               : launch_hop_eo<__half2, __half2, __half2, __half2, 2, 9, 2>(g, Ue, 1, a, b, in_diag, de, full, nrhs,
+               : launch_hop_eo<__half2, __half2, __half2, __half2, 4, 9, 2>(g, Ue, 1, a, b, in_diag, de, full, nrhs,
                                                                             nullptr, nullptr, 0, st, ebase);
   }
   if (pfull != P32 && pfull != P64) return set_error(-1, "hop_eo_add: output precision %d", pfull);
