@@ -594,7 +594,8 @@ static int fine_apply_fused(wmg_ctx *c, int prec, const void *in, void *out, int
 
 // ------------------------------------------------------------ MR smoother
 // Fine-level smoother of the mixed-precision cycle with the MR residuals
-// s_k and q_k = A s_k stored in FP16 (FP32 arithmetic, FP16 links).  The
+// s_k and q_k = A s_k stored in FP16 (FP16 links; the hopping sums of the
+// MR steps in packed FP16 arithmetic, everything else FP32).  The
 // cycle input r is used as r/|r| (|r|^2 per rhs in rn2, stride 4): the cycle
 // is homogeneous in r, the restricted residual was scaled the same way, so
 // e here belongs to r/|r| and every stored residual is O(1).

@@ -178,7 +178,10 @@ int wilson_soa_in16(const Geom &g, int lprec, const void *U, double m, const voi
 // lflags: LK12 for links stored as two rows.  With out_odd (bsub given, no
 // reductions) the output goes to the half-lattice arrays out (even sites)
 // and out_odd (odd sites) instead of a full-lattice field.  FP16 input with
-// bsub only with out_odd.
+// bsub only with out_odd.  With FP16 input the hopping sum runs in packed
+// FP16 arithmetic (projection, SU(3) products, each direction's forward
+// and backward terms combined), the directions summed in FP32; with FP32
+// input, and the diagonal and bsub terms always, in FP32.
 int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,
                    const void *bsub, const double *bnrm2, int bstride, double *red, double *red_out, int red_stride,
                    hipStream_t st, int lflags = 0, void *out_odd = nullptr);
