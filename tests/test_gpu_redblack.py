@@ -257,3 +257,35 @@ def test_hop_kernel_tilings_identical(wmg, prec):
     finally:
         wmg.tune_force(-1)
         mg.close()
+
+
+def test_red_black_mixed_max_rhs_then_fewer(wmg):
+    """One mixed red/black context solving the maximum of 64 right-hand
+    sides, then 3, then 64 again in the same buffers (the cycle's FP16
+    output z, the FP16 smoother fields, the coarse stencil's FP16 products
+    with their per-rhs scales at 64 rhs, two rhs tiles of 32): every solve
+    converges and the oracle's FP64 residual of a sample of each is below
+    1e-10."""
+    L = (8, 8, 8, 8)
+    V = vol(L)
+    say("red/black mixed, 64 rhs then 3 then 64", L)
+    U = inputs.gauge_field(L, 0.5, 3401)
+    m = -0.2
+    p = wmg.default_params(setup_iters=6, seed=3402, nrhs_max=64, precision=wmg.WMG_MIXED, coarse_tol=1e-5,
+                           flags=wmg.WMG_EO_SMOOTHER)
+    mg = wmg.MG(L, dev(U), m, 24, (4, 4, 4, 4), p)
+    b64 = np.concatenate([inputs.point_sources(L), inputs.gaussian_rhs(L, 3403, 52)])
+    b3 = np.concatenate([inputs.point_sources(L)[3:4], inputs.z4_noise(L, 3404, 2)])
+    try:
+        for b, sample in ((b64, (0, 11, 40, 63)), (b3, (0, 1, 2)), (b64, (5, 63))):
+            n = b.shape[0]
+            x = empty((n, V, 12))
+            st = mg.mg_solve(dev(b), x, 1e-10)
+            say("  nrhs", n, st)
+            assert st["converged"] and st["true_relres"] <= 1e-10
+            xh = host(x)
+            for r in sample:
+                res = np.linalg.norm(b[r] - oracle.wilson(L, U, m, xh[r])) / np.linalg.norm(b[r])
+                assert res <= 1e-10 * 1.0001, (n, r, res)
+    finally:
+        mg.close()
