@@ -39,6 +39,25 @@ def test_every_declared_symbol_is_exported(lib):
     assert not missing, missing
 
 
+def test_binding_constants_match_header(lib):
+    """Every WMG_* constant of the Python binding has the value the header
+    defines (flags, precisions, cycle types, error codes, profile slots)."""
+    from paper_0912_2186_amd import wmg
+
+    src = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    defs = {}
+    for name, val in re.findall(r"^\s*#define\s+(WMG_[A-Z0-9_]+)\s+(\(?-?[0-9][0-9a-fA-Fx]*\)?)", src, flags=re.M):
+        defs[name] = int(val.strip("()"), 0)
+    ours = {k: v for k, v in vars(wmg).items() if k.startswith("WMG_") and isinstance(v, int)}
+    assert "WMG_Z32" in ours and "WMG_EO_SMOOTHER" in ours
+    wrong = {k: (v, defs.get(k)) for k, v in ours.items() if k in defs and defs[k] != v}
+    assert not wrong, wrong
+    # flags are distinct bits
+    flags = [defs[k] for k in ("WMG_X0_GIVEN", "WMG_COARSE_FP32", "WMG_LINKS18", "WMG_EO_SMOOTHER", "WMG_GRAPHS",
+                               "WMG_SPIN_SPLIT", "WMG_COARSE_B32", "WMG_Z32")]
+    assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)
+
+
 class Geom(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int * 4)]
 
