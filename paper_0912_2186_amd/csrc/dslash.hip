@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
                                                    const TB *__restrict__ bsub, const double *__restrict__ bnrm2,
                                                    int bstride, double *__restrict__ red, int inner,
                                                    float2 *__restrict__ out32, TO *__restrict__ out_odd, long Vhs,
-                                                   float one) {
+                                                   float one, const float2 *__restrict__ dotv) {
   using R = typename store_traits<TS>::real;
   const R diag = sizeof(R) == 8 ? (R)diagd : (R)diagf;
   // one sweep over the lattice per tile of RT right-hand sides (grid.y)
@@ -578,8 +578,14 @@ __global__ void __launch_bounds__(256) k_wilson_soa(const TL *__restrict__ U, co
       if (out32) stc(out32 + ((size_t)(r0 + t) * 12 + c) * Vs + s, o);
       if (RED) o = as_stored(out, o);
       if (RED) {
-        rs[t][0] += (double)o.re * p[c].re + (double)o.im * p[c].im;
-        rs[t][1] += (double)o.re * p[c].im - (double)o.im * p[c].re;
+        // <out, in> (or <out, dotv> with a partner field) and |out|^2
+        cx<R> q = p[c];
+        if (dotv) {
+          const float2 d = dotv[((size_t)(r0 + t) * 12 + c) * Vs + s];
+          q = {(R)d.x, (R)d.y};
+        }
+        rs[t][0] += (double)o.re * q.re + (double)o.im * q.im;
+        rs[t][1] += (double)o.re * q.im - (double)o.im * q.re;
         rs[t][2] += (double)o.re * o.re + (double)o.im * o.im;
       }
     }
@@ -640,7 +646,7 @@ __global__ void __launch_bounds__(256) k_dslash_red_finalize(const double *__res
 template <class TL, class TS, class TO = TS, int NR = 9, class TB = TS>
 static int launch_soa(const Geom &g, const void *U, double m, const void *in, void *out, int nrhs, const void *bsub,
                       double *red, double *red_out, int red_stride, hipStream_t st, const double *bnrm2 = nullptr,
-                      int bstride = 0, void *out32 = nullptr, void *out_odd = nullptr) {
+                      int bstride = 0, void *out32 = nullptr, void *out_odd = nullptr, const float2 *dotv = nullptr) {
   if (out_odd && (red || g.L[0] % 2)) return set_error(-1, "wilson_soa: half-lattice output without reductions only");
   const long Vhs = fine_stride(g.V / 2);
   constexpr int RT = sizeof(TS) == 16 ? 1 : 2;
@@ -676,7 +682,7 @@ static int launch_soa(const Geom &g, const void *U, double m, const void *in, vo
       hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 1, NR, 0, TB>), grid, dim3(256), lds, st, (const TL *)U,
                          (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
                          nrhs, sm, g.Vs, (const TB *)bsub, bnrm2, bstride, red, inner, (float2 *)out32, (TO *)nullptr,
-                         Vhs, 1.0f);
+                         Vhs, 1.0f, dotv);
       hipLaunchKernelGGL(k_dslash_red_finalize, dim3(nrhs), dim3(256), 0, st, red, (long)sm.nblocks, red_out,
                          red_stride);
     } else if (out_odd) {
@@ -686,21 +692,22 @@ static int launch_soa(const Geom &g, const void *U, double m, const void *in, vo
         hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR, 1, TB>), grid, dim3(256), lds, st, (const TL *)U,
                            (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
                            nrhs, sm, g.Vs, (const TB *)bsub, bnrm2, bstride, (double *)nullptr, inner,
-                           (float2 *)out32, (TO *)out_odd, Vhs, 1.0f);
+                           (float2 *)out32, (TO *)out_odd, Vhs, 1.0f, (const float2 *)nullptr);
       else
         return set_error(-1, "wilson_soa: half-lattice output not instantiated for these precisions");
     } else {
       hipLaunchKernelGGL((k_wilson_soa<TL, TS, TO, RT, 0, NR, 0, TB>), grid, dim3(256), lds, st, (const TL *)U,
                          (const TS *)in, (TO *)out, g.L[0], g.L[1], g.L[2], g.L[3], g.V, (float)(4.0 + m), 4.0 + m,
                          nrhs, sm, g.Vs, (const TB *)bsub, bnrm2, bstride, (double *)nullptr, inner, (float2 *)out32,
-                         (TO *)nullptr, Vhs, 1.0f);
+                         (TO *)nullptr, Vhs, 1.0f, (const float2 *)nullptr);
     }
     WMG_HIP(hipGetLastError());
     return 0;
   };
   char key[256];
   std::snprintf(key, sizeof(key), "dslash/l%zu-s%zu-o%zu-nr%d-red%d-b%d-f%d-eo%d/%dx%dx%dx%d/rhs%d", sizeof(TL),
-                sizeof(TS), sizeof(TO), NR, red ? 1 : 0, bsub ? (int)sizeof(TB) : 0, out32 ? 1 : 0, out_odd ? 1 : 0,
+                sizeof(TS), sizeof(TO), NR, red ? (dotv ? 2 : 1) : 0, bsub ? (int)sizeof(TB) : 0, out32 ? 1 : 0,
+                out_odd ? 1 : 0,
                 g.L[0], g.L[1], g.L[2], g.L[3], nrhs);
   int choice = 0;
   return tune_choice(key, ncand, run, st, &choice);
@@ -709,9 +716,9 @@ static int launch_soa(const Geom &g, const void *U, double m, const void *in, vo
 long wilson_red_blocks(const Geom &g) {
   // every (link, spinor) storage pair launch_soa instantiates, links whole
   // (36 complex per site) or compressed (24)
-  const int lb[4] = {16, 8, 4, 4}, sb[4] = {24 * 8, 24 * 4 * 2, 24 * 4 * 2, 24 * 2 * 2};
+  const int lb[5] = {16, 8, 4, 4, 8}, sb[5] = {24 * 8, 24 * 4 * 2, 24 * 4 * 2, 24 * 2 * 2, 24 * 2 * 2};
   long m = 0;
-  for (int i = 0; i < 4; i++)
+  for (int i = 0; i < 5; i++)
     for (int nl : {36, 24})
       for (long budget : SWEEP_BUDGETS) {
         long nb = make_sweep(g.L, nl * lb[i] + sb[i], budget).nblocks;
@@ -741,11 +748,14 @@ int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double 
 }
 
 int wilson_soa_in16(const Geom &g, int lprec, const void *U, double m, const void *in, void *out, int nrhs,
-                    hipStream_t st) {
+                    hipStream_t st, double *red, double *red_out, int red_stride, const void *dotv) {
   const bool c12 = (lprec & LK12) != 0;
   if ((lprec & ~LK12) != P32) return set_error(-1, "wilson_soa_in16: FP32 links only");
-  return c12 ? launch_soa<float2, __half2, float2, 6>(g, U, m, in, out, nrhs, nullptr, nullptr, nullptr, 0, st)
-             : launch_soa<float2, __half2, float2, 9>(g, U, m, in, out, nrhs, nullptr, nullptr, nullptr, 0, st);
+  if (dotv && !red) return set_error(-1, "wilson_soa_in16: a dot partner needs the reductions");
+  return c12 ? launch_soa<float2, __half2, float2, 6>(g, U, m, in, out, nrhs, nullptr, red, red_out, red_stride, st,
+                                                      nullptr, 0, nullptr, nullptr, (const float2 *)dotv)
+             : launch_soa<float2, __half2, float2, 9>(g, U, m, in, out, nrhs, nullptr, red, red_out, red_stride, st,
+                                                      nullptr, 0, nullptr, nullptr, (const float2 *)dotv);
 }
 
 int wilson_soa_h16(const Geom &g, const void *U16, int iprec, double m, const void *in, void *out, int nrhs,

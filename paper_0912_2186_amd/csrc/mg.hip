@@ -1089,12 +1089,15 @@ static int residual64(wmg_ctx *c, int l, GcrBuf &B, int nrhs, int *off, bool *ri
 }
 
 // w = A z on the fine level from the FP16-stored preconditioner output z:
-// FP32 links and arithmetic, FP32 w
-static int apply_outer_z16(wmg_ctx *c, const void *z, void *w, int nrhs) {
+// FP32 links and arithmetic, FP32 w; with r (FP32) also <w, r> and |w|^2
+// per rhs into c->red_out[4 rhs + 0..2] (the first step of a restart)
+static int apply_outer_z16(wmg_ctx *c, const void *z, void *w, int nrhs, const void *r = nullptr) {
   Level &L = c->lv[0];
   c->st_fine++;
-  const int slot = prof_begin(c, K_DSLASH_OUTER32, (double)L.g.V * (fine_link_cx(L) * 8 + (12.0 * 4 + 12.0 * 8) * nrhs));
-  const int rc = wilson_soa_in16(L.g, fine_lcode(L, P32), fine_links(L, P32), L.m, z, w, nrhs, c->st);
+  const double vb = (12.0 * 4 + 12.0 * 8 + (r ? 12.0 * 8 : 0.0)) * nrhs;  // z, w and r
+  const int slot = prof_begin(c, K_DSLASH_OUTER32, (double)L.g.V * (fine_link_cx(L) * 8 + vb));
+  const int rc = wilson_soa_in16(L.g, fine_lcode(L, P32), fine_links(L, P32), L.m, z, w, nrhs, c->st,
+                                 r ? c->dred : nullptr, r ? c->red_out : nullptr, 4, r);
   prof_end(c, slot);
   return rc;
 }
@@ -1170,13 +1173,15 @@ static int gcr_solve(wmg_ctx *c, int l, GcrBuf &B, int nrhs, double tol, int max
         TRY(zero(ip, z, n, nrhs, st));
         TRY(mr_smooth(c, l, ip, B.rin, z, c->p.post_smooth, nrhs));
       }
-      if (zp == P16) TRY(apply_outer_z16(c, z, w, nrhs));
+      // the first step's <w, r> and |w|^2 come from the operator's epilogue
+      // when z is FP16
+      if (zp == P16) TRY(apply_outer_z16(c, z, w, nrhs, k == 0 ? B.rin : nullptr));
       else TRY(apply_op(c, l, ip, z, w, nrhs, false));
       // classical Gram-Schmidt against the unnormalised w_j, fused: dots |
       // project + <w, r> + |w|^2 (FP64: dots | project + new dots | project
       // + <w, r> + |w|^2)
       if (k == 0) {
-        TRY(dot_norm(c->red, ip, w, B.rin, n, nrhs, c->red_out, 4, st));
+        if (zp != P16) TRY(dot_norm(c->red, ip, w, B.rin, n, nrhs, c->red_out, 4, st));
       } else {
         TRY(multi_dot(c->red, ip, (const void *const *)B.wdev, k, w, n, nrhs, c->gcr + G_TMP, GS, st));
         // FP32 inner solve: one projection pass (on the 32^3x64, 28-rhs

@@ -168,9 +168,12 @@ int wilson_soa_fused(const Geom &g, int lprec, const void *U, int sprec, double 
                      void *out32 = nullptr);
 // out (FP32) = D in with FP32 links (lprec may carry LK12) on an FP16 input
 // field (FP32 arithmetic): the inner GCR's operator on the FP16-stored
-// preconditioner output.
+// preconditioner output.  With red, <out, dotv> (dotv an FP32 field of the
+// same layout; <out, in> without it) and |out|^2 per rhs -> red_out as in
+// wilson_soa_fused.
 int wilson_soa_in16(const Geom &g, int lprec, const void *U, double m, const void *in, void *out, int nrhs,
-                    hipStream_t st);
+                    hipStream_t st, double *red = nullptr, double *red_out = nullptr, int red_stride = 0,
+                    const void *dotv = nullptr);
 // Smoother variant with FP16 links and FP16 output storage: in is FP32
 // (iprec P32) or FP16 (P16); out (FP16) = [b/|b| -] D in, where bsub (FP32)
 // is scaled per rhs by 1/sqrt(bnrm2[rhs * bstride]) (0 where that norm is
